@@ -1,0 +1,30 @@
+"""CPU FP64 oracle for the HDG trace operator and its nested multigrid solver.
+
+TEST INFRASTRUCTURE ONLY.  Nothing in the product (the HIP library and its
+Python binding) imports, links or executes this package; only ``tests/``,
+``__graft_entry__.smoke()`` and the ``cpu_baseline`` leg of ``bench.py`` use
+it.  It shares no code, tables or constants with the HIP path.
+
+The oracle follows Fabien, Knepley, Mills, Riviere, "Manycore parallel
+computing for a hybridizable discontinuous Galerkin nested multigrid method"
+(arXiv:1705.09907).  Every function cites the section / equation / algorithm
+it restates.  It is written plainly: explicit local HDG systems (Sec. 3,
+eqs. static_1/static_2), static condensation (eq. shur0) substituted into the
+transmission condition (eq. shur1), an assembled sparse trace matrix, a sparse
+direct solve, and the nested p/h V-cycle (Algs. algo_1/algo_2) step by step.
+
+Modules
+  quadrature  1D Gauss-Legendre / Gauss-Lobatto rules, barycentric Lagrange
+              evaluation and differentiation (Sec. 4).
+  mesh        numbering of elements, interior faces and trace DoFs.
+  hdg         local matrices, condensed blocks, global assembly, RHS, direct
+              solve, reconstruction and L2 errors (Secs. 3 and 5).
+  mg          p-transfers, h-transfers, Galerkin Q1 hierarchy, smoothers and
+              the V-cycle / solve driver (Secs. 6 and 7).
+
+Every function listed here is pinned by a ``-m "not gpu"`` test in
+``tests/test_oracle_*.py`` against values the paper prints, closed forms,
+invariants or library routines; none is "parity unpinned" except the
+multigrid convergence factor, which the paper reports only for a different
+smoother (see mg.py).
+"""
