@@ -1,0 +1,170 @@
+/*
+ * hdggmg.h -- C ABI of the MI355X (gfx950) HDG trace-operator library.
+ *
+ * Method: Fabien, Knepley, Mills, Riviere, "Manycore parallel computing for a
+ * hybridizable discontinuous Galerkin nested multigrid method"
+ * (arXiv:1705.09907).  The library discretizes -div(K grad u) = f on the unit
+ * square, u = g_D on the boundary, with the LDG-H hybridizable DG method of
+ * Sec. 3 (eqs. eq_h1-eq_h3, tau constant on every edge) on a uniform n x n
+ * mesh of squares, condenses the element unknowns (eq. shur0) into the
+ * statically condensed trace system S Lambda = b (eq. shur1), applies S
+ * matrix-free face by face (Sec. 8, Alg. algo_mv) and solves it with the
+ * nested p -> h multigrid of Secs. 6-7 (Algs. algo_1 / algo_2).
+ *
+ * Conventions (all vectors are FP64, contiguous, caller-owned DEVICE memory
+ * unless a name ends in _host):
+ *   element (i, j), e = i + n j, K = [i h, (i+1) h] x [j h, (j+1) h], h = 1/n
+ *   interior faces: vertical between (i-1, j) and (i, j): f = (i-1) + (n-1) j;
+ *                   horizontal between (i, j-1) and (i, j): f = n(n-1) + i + n(j-1)
+ *   trace vector at degree p: N(p) = 2 n (n-1) (p+1) entries, DoF f (p+1) + a,
+ *     a = Gauss-Lobatto node index in increasing y (vertical faces) or x
+ *     (horizontal faces); p = 0 uses one value per face.
+ *   local faces of an element: 0 left, 1 right, 2 bottom, 3 top.
+ *   Q1 levels: interior vertices (i, j), 1 <= i, j <= m-1, v = (i-1) + (m-1)(j-1).
+ *
+ * Every call is stream-ordered and asynchronous on the stream given to
+ * hdg_create, except calls that return host scalars (they synchronize that
+ * stream).  A handle is not thread safe; use one handle per host thread.
+ * Every function returns an hdg_status_t; on failure hdg_last_error(handle)
+ * returns a message.  Arguments are validated before any launch.
+ */
+#ifndef HDGGMG_H
+#define HDGGMG_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct hdg_ctx* hdg_handle_t;
+
+typedef enum {
+  HDG_OK = 0,
+  HDG_ERR_INVALID_ARG = -1,   /* bad size, degree, pointer, coefficient or config field */
+  HDG_ERR_OOM = -2,           /* device or host allocation failed                      */
+  HDG_ERR_HIP = -3,           /* a HIP runtime call failed (message has the HIP error)  */
+  HDG_ERR_NOT_CONVERGED = -4, /* maxit reached; x, iters, relres are still valid        */
+  HDG_ERR_NONFINITE = -5,     /* NaN or Inf met in a residual norm                       */
+  HDG_ERR_STATE = -6          /* call not valid for this handle (e.g. level missing)     */
+} hdg_status_t;
+
+enum { HDG_SMOOTH_CHAIN = 0, HDG_SMOOTH_FACE = 1 };
+enum { HDG_COARSE_GALERKIN = 0, HDG_COARSE_REDISCRETIZE = 1 };
+enum { HDG_SOLVE_PCG = 0, HDG_SOLVE_VCYCLE = 1 };
+
+#define HDG_MAX_DEGREE 8
+#define HDG_MAX_HLEVELS 24
+
+/* Solver configuration.  Fill with hdg_config_default, then override. */
+typedef struct {
+  int32_t n;            /* elements per direction, n >= 2                                  */
+  int32_t k;            /* finest trace degree, 0 <= k <= HDG_MAX_DEGREE                   */
+  double tau;           /* HDG stabilization, > 0 (Sec. 5 uses 1)                           */
+  int32_t nu1, nu2;     /* pre/post smoothing steps per level (Sec. 7 uses 2, 2)           */
+  int32_t smoother;     /* HDG_SMOOTH_CHAIN: additive Schwarz with one subdomain per chain
+                           of faces (vertical faces of an element row / horizontal faces
+                           of an element column); HDG_SMOOTH_FACE: one subdomain per facet
+                           (Sec. 6, additive Schwarz relaxation, zero overlap)           */
+  int32_t coarse;       /* p-level coarse operators: HDG_COARSE_GALERKIN (element-wise
+                           P^T K P) or HDG_COARSE_REDISCRETIZE (degree-p HDG, Sec. 6)     */
+  double omega[HDG_MAX_DEGREE + 1]; /* Schwarz damping per p; <= 0: 0.8 (chain) or
+                           4 / (3 lambda_max(D^-1 S_p)) estimated on the device (face)    */
+  double cheb_lo, cheb_hi;          /* Chebyshev interval [lo, hi] * lambda_max on Q1 levels */
+  double cheb_lmax[HDG_MAX_HLEVELS];/* lambda_max(diag^-1 A) per Q1 level (0 = finest Q1);
+                                       <= 0: estimated with Lanczos at setup              */
+  int32_t coarse_max;   /* coarsest Q1 level: first with <= coarse_max unknowns (default 2000) */
+  int32_t nq;           /* Gauss-Legendre points per direction of f input (default k + 2) */
+  int32_t reserved[8];
+} hdg_config_t;
+
+/* Defaults: tau 1, V(2,2), chain smoother, Galerkin p-levels, omega/lmax estimated,
+ * Chebyshev interval [0.1, 1.1], coarse_max 2000, nq = k + 2. */
+hdg_status_t hdg_config_default(int32_t n, int32_t k, hdg_config_t* cfg);
+
+/* Setup (Sec. 3 steps (i)-(ii) and the multigrid hierarchy of Sec. 6).
+ * kappa_host: [n*n] per-element coefficient K_e > 0 (host memory, read only,
+ * not retained).  hip_stream: a hipStream_t (NULL = default stream).  Builds on
+ * the host the condensed element blocks of every level, uploads face-major
+ * blocks, smoother factors, transfer tables, Q1 stencils and the coarsest
+ * inverse, then estimates any missing omega / lambda_max on the device.
+ * Errors: INVALID_ARG (n < 2, k out of range, tau or any kappa not > 0 and
+ * finite, bad config), OOM, HIP. */
+hdg_status_t hdg_create(const hdg_config_t* cfg, const double* kappa_host, void* hip_stream,
+                        hdg_handle_t* out);
+hdg_status_t hdg_destroy(hdg_handle_t h);
+
+/* N(p) = 2 n (n-1) (p+1), the trace-vector length at degree p (0 <= p <= k). */
+hdg_status_t hdg_num_dofs(hdg_handle_t h, int32_t p, int64_t* n_lambda);
+
+/* Number of Q1 h-levels and the mesh size m of each (level 0 = the Q1 space on
+ * the finest mesh; the last one is solved directly). */
+hdg_status_t hdg_num_hlevels(hdg_handle_t h, int32_t* nlev);
+hdg_status_t hdg_hlevel_mesh(hdg_handle_t h, int32_t level, int32_t* m);
+/* Damping and lambda_max actually used (after estimation). */
+hdg_status_t hdg_get_params(hdg_handle_t h, double* omega_out /*[k+1]*/,
+                            double* lmax_out /*[num_hlevels]*/);
+
+/* Copy the condensed block of element e at level p (4(p+1) x 4(p+1), row major,
+ * local faces left, right, bottom, top) to host memory: Sec. 3, eqs. shur0
+ * substituted into shur1, K_e = [C^T, -E^T] Abb^{-1} [C; E] + tau M; for p < k
+ * with Galerkin coarsening the block is P4^T K_e^{(p+1)} P4. */
+hdg_status_t hdg_get_element_block(hdg_handle_t h, int32_t p, int64_t e, double* out_host);
+
+/* Same block without a handle or device (host computation only): mesh n, finest
+ * degree k, requested degree p <= k, coefficient kappa_e of the element, coarse =
+ * HDG_COARSE_GALERKIN (chain of P4^T K P4 from degree k) or HDG_COARSE_REDISCRETIZE. */
+hdg_status_t hdg_element_block_host(int32_t n, int32_t k, int32_t p, double tau, double kappa_e,
+                                    int32_t coarse, double* out_host);
+
+/* Gauss-Legendre nodes on [-1, 1] used for the source input (nq of them). */
+hdg_status_t hdg_quadrature_nodes(int32_t nq, double* x_host);
+
+/* Right-hand side at the finest degree (Sec. 3, steps (i)-(ii)):
+ * b = sum_K R_K^T (g_K - K_K[:, bdry] Lambda_bdry), g_K = [C^T, -E^T] Abb^{-1} [0; F_K],
+ * F_K = (f, w)_K.  f_qp_host: [n*n][nq*nq] source values at the Gauss-Legendre
+ * points of each element, point (a, b) -> a + nq b with a along x.  gD_qp_host:
+ * [4n][nq] Dirichlet data at the nq Gauss-Legendre points of each boundary face
+ * (faces ordered bottom, right, top, left, each by increasing coordinate), or
+ * NULL for g_D = 0; it is L2-projected onto Q_k(e) (Sec. 3).  b: device [N(k)].
+ * Computed on the host, copied asynchronously. */
+hdg_status_t hdg_assemble_rhs(hdg_handle_t h, const double* f_qp_host, const double* gD_qp_host,
+                              double* b);
+
+/* y = S_p x, the assembly-free trace operator of Sec. 8 (Alg. algo_mv): every
+ * interior face gathers the blocks of its two elements.  x, y: device [N(p)],
+ * must not alias. */
+hdg_status_t hdg_apply_trace_operator(hdg_handle_t h, int32_t p, const double* x, double* y);
+
+/* r = b - S_p x; if norm2_host != NULL, *norm2_host = ||r||_2 (synchronizes;
+ * deterministic reduction order).  r must not alias x. */
+hdg_status_t hdg_residual(hdg_handle_t h, int32_t p, const double* b, const double* x, double* r,
+                          double* norm2_host);
+
+/* sweeps of the level-p Schwarz smoother x <- x + omega M^{-1} (b - S_p x) in place. */
+hdg_status_t hdg_smooth(hdg_handle_t h, int32_t p, const double* b, double* x, int32_t sweeps);
+
+/* p-transfers (eqs. eq_mg_res / eq_mg_pro), face local, 1 <= p_fine <= k:
+ * r_coarse = P^T r_fine;  x_fine += P e_coarse. */
+hdg_status_t hdg_restrict(hdg_handle_t h, int32_t p_fine, const double* r_fine, double* r_coarse);
+hdg_status_t hdg_prolong(hdg_handle_t h, int32_t p_fine, const double* e_coarse, double* x_fine);
+
+/* One V(nu1, nu2) cycle for S_k x = b starting from x (in place). */
+hdg_status_t hdg_vcycle(hdg_handle_t h, const double* b, double* x);
+
+/* Solve S_k x = b to ||b - S x||_2 <= rtol ||b||_2, x in: initial guess, out:
+ * solution.  mode HDG_SOLVE_PCG (conjugate gradients preconditioned by one
+ * V-cycle) or HDG_SOLVE_VCYCLE (repeated V-cycles, the paper's stationary
+ * solver).  iters, relres: host outputs (nullable); history_host: nullable
+ * [maxit + 1] residual norms (entry 0 = initial).  Returns NOT_CONVERGED if
+ * maxit is reached (outputs still valid), NONFINITE on NaN/Inf. */
+hdg_status_t hdg_solve(hdg_handle_t h, const double* b, double* x, double rtol, int32_t maxit,
+                       int32_t mode, int32_t* iters, double* relres, double* history_host);
+
+const char* hdg_last_error(hdg_handle_t h);
+const char* hdg_status_string(hdg_status_t s);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* HDGGMG_H */

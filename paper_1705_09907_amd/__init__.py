@@ -1,0 +1,257 @@
+"""MI355X-native HDG trace operator and nested p/h multigrid (arXiv:1705.09907).
+
+Thin ctypes binding over the C ABI of ``libhdggmg.so`` (include/hdggmg.h):
+argument marshalling only -- every step runs in the library's HIP kernels.
+PyTorch supplies device memory (float64 CUDA tensors) and the stream.  There is
+no CPU fallback: importing this package without the built library raises.
+"""
+import ctypes
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libhdggmg.so")
+
+HDG_MAX_DEGREE = 8
+HDG_MAX_HLEVELS = 24
+SMOOTHERS = {"chain": 0, "face": 1}
+COARSE = {"galerkin": 0, "rediscretize": 1}
+MODES = {"pcg": 0, "vcycle": 1}
+STATUS = {0: "ok", -1: "invalid argument", -2: "out of memory", -3: "HIP error",
+          -4: "not converged", -5: "non-finite value", -6: "invalid state"}
+
+
+class Config(ctypes.Structure):
+    _fields_ = [("n", ctypes.c_int32), ("k", ctypes.c_int32), ("tau", ctypes.c_double),
+                ("nu1", ctypes.c_int32), ("nu2", ctypes.c_int32),
+                ("smoother", ctypes.c_int32), ("coarse", ctypes.c_int32),
+                ("omega", ctypes.c_double * (HDG_MAX_DEGREE + 1)),
+                ("cheb_lo", ctypes.c_double), ("cheb_hi", ctypes.c_double),
+                ("cheb_lmax", ctypes.c_double * HDG_MAX_HLEVELS),
+                ("coarse_max", ctypes.c_int32), ("nq", ctypes.c_int32),
+                ("reserved", ctypes.c_int32 * 8)]
+
+
+_P = ctypes.c_void_p
+_I32, _I64, _D = ctypes.c_int32, ctypes.c_int64, ctypes.c_double
+_PD = ctypes.POINTER(ctypes.c_double)
+_PI32, _PI64 = ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_int64)
+
+# name -> argtypes; every function returns hdg_status_t (int) unless listed in _RESTYPES
+SIGNATURES = {
+    "hdg_config_default": [_I32, _I32, ctypes.POINTER(Config)],
+    "hdg_create": [ctypes.POINTER(Config), _PD, _P, ctypes.POINTER(_P)],
+    "hdg_destroy": [_P],
+    "hdg_num_dofs": [_P, _I32, _PI64],
+    "hdg_num_hlevels": [_P, _PI32],
+    "hdg_hlevel_mesh": [_P, _I32, _PI32],
+    "hdg_get_params": [_P, _PD, _PD],
+    "hdg_get_element_block": [_P, _I32, _I64, _PD],
+    "hdg_element_block_host": [_I32, _I32, _I32, _D, _D, _I32, _PD],
+    "hdg_quadrature_nodes": [_I32, _PD],
+    "hdg_assemble_rhs": [_P, _PD, _PD, _P],
+    "hdg_apply_trace_operator": [_P, _I32, _P, _P],
+    "hdg_residual": [_P, _I32, _P, _P, _P, _PD],
+    "hdg_smooth": [_P, _I32, _P, _P, _I32],
+    "hdg_restrict": [_P, _I32, _P, _P],
+    "hdg_prolong": [_P, _I32, _P, _P],
+    "hdg_vcycle": [_P, _P, _P],
+    "hdg_solve": [_P, _P, _P, _D, _I32, _I32, _PI32, _PD, _PD],
+    "hdg_last_error": [_P],
+    "hdg_status_string": [_I32],
+}
+_RESTYPES = {"hdg_last_error": ctypes.c_char_p, "hdg_status_string": ctypes.c_char_p}
+
+
+def load_library(path=LIB_PATH):
+    if not os.path.exists(path):
+        raise ImportError(f"{path} is missing: build it with `python -m paper_1705_09907_amd.build` "
+                          "(there is no CPU fallback)")
+    lib = ctypes.CDLL(path)
+    for name, args in SIGNATURES.items():
+        fn = getattr(lib, name)
+        fn.argtypes = args
+        fn.restype = _RESTYPES.get(name, ctypes.c_int)
+    return lib
+
+
+lib = load_library()
+
+
+class HDGError(RuntimeError):
+    def __init__(self, status, msg):
+        super().__init__(f"{STATUS.get(status, status)}: {msg}")
+        self.status = status
+
+
+def _dptr(t, name, numel=None):
+    import torch
+    if not isinstance(t, torch.Tensor) or not t.is_cuda or t.dtype != torch.float64 or not t.is_contiguous():
+        raise TypeError(f"{name} must be a contiguous float64 CUDA tensor")
+    if numel is not None and t.numel() != numel:
+        raise ValueError(f"{name} has {t.numel()} entries, expected {numel}")
+    return ctypes.c_void_p(t.data_ptr())
+
+
+def _host(a, name, size=None):
+    a = np.ascontiguousarray(a, dtype=np.float64)
+    if size is not None and a.size != size:
+        raise ValueError(f"{name} has {a.size} entries, expected {size}")
+    return a, a.ctypes.data_as(_PD)
+
+
+def element_block_host(n, k, p, kappa_e, tau=1.0, coarse="galerkin"):
+    """Condensed block of one element computed by the library's host setup (no device)."""
+    out = np.zeros((4 * (p + 1), 4 * (p + 1)))
+    st = lib.hdg_element_block_host(n, k, p, tau, kappa_e, COARSE[coarse], out.ctypes.data_as(_PD))
+    if st != 0:
+        raise HDGError(st, "hdg_element_block_host: bad arguments")
+    return out
+
+
+def quadrature_nodes(nq):
+    x = np.zeros(nq)
+    st = lib.hdg_quadrature_nodes(nq, x.ctypes.data_as(_PD))
+    if st != 0:
+        raise HDGError(st, "bad nq")
+    return x
+
+
+class Solver:
+    """Handle over hdg_create: one n x n mesh, degree k, per-element kappa."""
+
+    def __init__(self, n, k, kappa, tau=1.0, nu1=2, nu2=2, smoother="chain", coarse="galerkin",
+                 omega=None, cheb_lmax=None, cheb=(0.1, 1.1), coarse_max=2000, nq=None, stream=None):
+        import torch
+        cfg = Config()
+        lib.hdg_config_default(n, k, ctypes.byref(cfg))
+        cfg.tau, cfg.nu1, cfg.nu2 = tau, nu1, nu2
+        cfg.smoother, cfg.coarse = SMOOTHERS[smoother], COARSE[coarse]
+        if omega is not None:
+            om = omega if isinstance(omega, dict) else {p: omega for p in range(k + 1)}
+            for p, v in om.items():
+                cfg.omega[p] = v
+        if cheb_lmax is not None:
+            for l, v in enumerate(cheb_lmax):
+                cfg.cheb_lmax[l] = v
+        cfg.cheb_lo, cfg.cheb_hi = cheb
+        cfg.coarse_max = coarse_max
+        if nq is not None:
+            cfg.nq = nq
+        self.n, self.k, self.nq = n, k, cfg.nq
+        kap, kp = _host(kappa, "kappa", n * n)
+        if stream is None:
+            stream = torch.cuda.current_stream()
+        self.stream = stream
+        h = ctypes.c_void_p()
+        st = lib.hdg_create(ctypes.byref(cfg), kp, ctypes.c_void_p(stream.cuda_stream), ctypes.byref(h))
+        if st != 0:
+            raise HDGError(st, "hdg_create failed (see arguments)")
+        self._h = h
+
+    # ---------------------------------------------------------------- helpers
+    def _check(self, st):
+        if st != 0:
+            raise HDGError(st, lib.hdg_last_error(self._h).decode())
+
+    def close(self):
+        if getattr(self, "_h", None):
+            lib.hdg_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def num_dofs(self, p=None):
+        p = self.k if p is None else p
+        v = ctypes.c_int64()
+        self._check(lib.hdg_num_dofs(self._h, p, ctypes.byref(v)))
+        return v.value
+
+    def num_hlevels(self):
+        v = ctypes.c_int32()
+        self._check(lib.hdg_num_hlevels(self._h, ctypes.byref(v)))
+        return v.value
+
+    def hlevel_mesh(self, level):
+        v = ctypes.c_int32()
+        self._check(lib.hdg_hlevel_mesh(self._h, level, ctypes.byref(v)))
+        return v.value
+
+    def params(self):
+        om = np.zeros(self.k + 1)
+        lm = np.zeros(self.num_hlevels())
+        self._check(lib.hdg_get_params(self._h, om.ctypes.data_as(_PD), lm.ctypes.data_as(_PD)))
+        return om, lm
+
+    def element_block(self, p, e):
+        out = np.zeros((4 * (p + 1), 4 * (p + 1)))
+        self._check(lib.hdg_get_element_block(self._h, p, e, out.ctypes.data_as(_PD)))
+        return out
+
+    def _empty(self, p):
+        import torch
+        return torch.empty(self.num_dofs(p), dtype=torch.float64, device="cuda")
+
+    # ------------------------------------------------------------- operations
+    def assemble_rhs(self, f_qp, gD_qp=None, out=None):
+        f, fp = _host(f_qp, "f_qp", self.n * self.n * self.nq * self.nq)
+        gp = None
+        if gD_qp is not None:
+            g, gp = _host(gD_qp, "gD_qp", 4 * self.n * self.nq)
+        out = self._empty(self.k) if out is None else out
+        self._check(lib.hdg_assemble_rhs(self._h, fp, gp, _dptr(out, "b", self.num_dofs())))
+        return out
+
+    def apply(self, p, x, y=None):
+        N = self.num_dofs(p)
+        y = self._empty(p) if y is None else y
+        self._check(lib.hdg_apply_trace_operator(self._h, p, _dptr(x, "x", N), _dptr(y, "y", N)))
+        return y
+
+    def residual(self, p, b, x, r=None, norm=False):
+        N = self.num_dofs(p)
+        r = self._empty(p) if r is None else r
+        nv = ctypes.c_double()
+        self._check(lib.hdg_residual(self._h, p, _dptr(b, "b", N), _dptr(x, "x", N), _dptr(r, "r", N),
+                                     ctypes.byref(nv) if norm else None))
+        return (r, nv.value) if norm else r
+
+    def smooth(self, p, b, x, sweeps=1):
+        N = self.num_dofs(p)
+        self._check(lib.hdg_smooth(self._h, p, _dptr(b, "b", N), _dptr(x, "x", N), sweeps))
+        return x
+
+    def restrict(self, p_fine, r_fine, out=None):
+        out = self._empty(p_fine - 1) if out is None else out
+        self._check(lib.hdg_restrict(self._h, p_fine, _dptr(r_fine, "r_fine", self.num_dofs(p_fine)),
+                                     _dptr(out, "r_coarse", self.num_dofs(p_fine - 1))))
+        return out
+
+    def prolong(self, p_fine, e_coarse, x_fine):
+        self._check(lib.hdg_prolong(self._h, p_fine, _dptr(e_coarse, "e_coarse", self.num_dofs(p_fine - 1)),
+                                    _dptr(x_fine, "x_fine", self.num_dofs(p_fine))))
+        return x_fine
+
+    def vcycle(self, b, x):
+        N = self.num_dofs()
+        self._check(lib.hdg_vcycle(self._h, _dptr(b, "b", N), _dptr(x, "x", N)))
+        return x
+
+    def solve(self, b, x=None, rtol=1e-10, maxit=200, mode="pcg", raise_on_fail=True):
+        import torch
+        N = self.num_dofs()
+        if x is None:
+            x = torch.zeros(N, dtype=torch.float64, device="cuda")
+        it = ctypes.c_int32()
+        rr = ctypes.c_double()
+        hist = np.zeros(maxit + 1)
+        st = lib.hdg_solve(self._h, _dptr(b, "b", N), _dptr(x, "x", N), rtol, maxit, MODES[mode],
+                           ctypes.byref(it), ctypes.byref(rr), hist.ctypes.data_as(_PD))
+        if st != 0 and (raise_on_fail or st not in (-4,)):
+            self._check(st)
+        return x, it.value, rr.value, hist[:it.value + 1]

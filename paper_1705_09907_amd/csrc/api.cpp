@@ -1,0 +1,915 @@
+// C ABI of the HDG trace-operator library: setup, operator, smoothers,
+// transfers, V-cycle and solvers (Secs. 3, 6-8 of arXiv:1705.09907).
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <memory>
+#include <stdexcept>
+#include <string>
+#include <vector>
+
+#include "../../include/hdggmg.h"
+#include "kernels.hpp"
+#include "setup.hpp"
+
+using hdg::Vec;
+
+namespace {
+
+struct PLevel {
+  int p = 0, P = 1;
+  int64_t N = 0;
+  double* slab = nullptr;
+  double* dinv = nullptr;                                         // facet Schwarz
+  double *clmul = nullptr, *cdtinv = nullptr, *cupper = nullptr;  // chain Schwarz
+  double* pmat = nullptr;                                         // P_p (p >= 1)
+  double omega = 0.8;
+  double *x = nullptr, *b = nullptr, *r = nullptr, *t = nullptr;
+};
+
+struct QLevel {
+  int m = 0;
+  int64_t Nv = 0;
+  bool coarsest = false;
+  double* st = nullptr;
+  double* dinv = nullptr;
+  double* inv = nullptr;
+  double lmax = 0.0;
+  double *x = nullptr, *b = nullptr, *r = nullptr, *d = nullptr, *t = nullptr;
+};
+
+}  // namespace
+
+struct hdg_ctx {
+  hdg_config_t cfg{};
+  hipStream_t stream = nullptr;
+  std::string err;
+  int n = 0, k = 0;
+  int64_t nf = 0, ntiles = 0;
+  std::vector<double> kappa;
+  std::vector<PLevel> pl;      // index = p
+  std::vector<QLevel> ql;
+  std::vector<void*> allocs;
+  double* partial = nullptr;
+  int npartial = 0;
+  double* scal = nullptr;      // device scalar
+  double* scal_h = nullptr;    // pinned host scalar
+  double *vr = nullptr, *vz = nullptr, *vd = nullptr, *vq = nullptr;  // solver vectors
+  int nq = 0;
+};
+
+namespace {
+
+struct HipError : std::runtime_error {
+  using std::runtime_error::runtime_error;
+};
+struct ArgError : std::runtime_error {
+  using std::runtime_error::runtime_error;
+};
+
+inline void hipchk(hipError_t e, const char* what) {
+  if (e != hipSuccess) throw HipError(std::string(what) + ": " + hipGetErrorString(e));
+}
+
+double* dalloc(hdg_ctx* h, int64_t n) {
+  void* p = nullptr;
+  if (n <= 0) n = 1;
+  if (hipMalloc(&p, (size_t)n * sizeof(double)) != hipSuccess) {
+    (void)hipGetLastError();
+    throw std::bad_alloc();
+  }
+  h->allocs.push_back(p);
+  return (double*)p;
+}
+
+double* upload(hdg_ctx* h, const Vec& v) {
+  double* d = dalloc(h, (int64_t)v.size());
+  hipchk(hipMemcpy(d, v.data(), v.size() * sizeof(double), hipMemcpyHostToDevice), "upload");
+  return d;
+}
+
+template <typename F>
+hdg_status_t guarded(hdg_ctx* h, F&& body) {
+  try {
+    return body();
+  } catch (const ArgError& e) {
+    if (h) h->err = e.what();
+    return HDG_ERR_INVALID_ARG;
+  } catch (const HipError& e) {
+    if (h) h->err = e.what();
+    return HDG_ERR_HIP;
+  } catch (const std::bad_alloc&) {
+    if (h) h->err = "allocation failed";
+    return HDG_ERR_OOM;
+  } catch (const std::exception& e) {
+    if (h) h->err = e.what();
+    return HDG_ERR_STATE;
+  }
+}
+
+// Tile-pair layout (setup.hpp) of per-face data with NE entries per face.
+inline int64_t tp_index(int64_t f, int e, int NE) {
+  const int64_t NQ = (NE + 1) / 2;
+  const int64_t tile = f >> 6, lane = f & 63;
+  return ((tile * NQ + (e >> 1)) * 64 + lane) * 2 + (e & 1);
+}
+
+// ------------------------------------------------------- element blocks, host
+// All condensed blocks of level k, [n*n][4P][4P].
+Vec blocks_finest(hdg_ctx* h, int p) {
+  const int P = p + 1, F4 = 4 * P, P2 = P * P;
+  hdg::RefDegree ref;
+  ref.build(p, 1.0 / h->n, h->cfg.tau);
+  const int64_t ne = (int64_t)h->n * h->n;
+  Vec out((size_t)ne * F4 * F4);
+  hdg::parallel_for(ne, [&](int64_t a, int64_t b) {
+    Vec work((size_t)P2 * P2 + (size_t)P2 * F4);
+    for (int64_t e = a; e < b; ++e)
+      hdg::element_block(ref, h->kappa[e], out.data() + (size_t)e * F4 * F4, work.data());
+  });
+  return out;
+}
+
+Vec blocks_galerkin(hdg_ctx* h, int p_fine, const Vec& fine) {
+  const Vec Pp = hdg::p_prolongation(p_fine);
+  const int Ff = 4 * (p_fine + 1), Fc = 4 * p_fine;
+  const int64_t ne = (int64_t)h->n * h->n;
+  Vec out((size_t)ne * Fc * Fc);
+  hdg::parallel_for(ne, [&](int64_t a, int64_t b) {
+    for (int64_t e = a; e < b; ++e)
+      hdg::galerkin_block(Pp, p_fine, fine.data() + (size_t)e * Ff * Ff, out.data() + (size_t)e * Fc * Fc);
+  });
+  return out;
+}
+
+// block (P x P) of the element block coupling local faces (lr, lc)
+inline double blk(const double* K, int P, int lr, int lc, int a, int c) {
+  return K[(size_t)(lr * P + a) * 4 * P + lc * P + c];
+}
+
+// Face-major 7-block layout, summed diagonal blocks, and the facet inverses.
+void build_face_data(hdg_ctx* h, PLevel& L, const Vec& blocks) {
+  const int n = h->n, P = L.P, P2 = P * P, F4 = 4 * P, NE = 7 * P2;
+  const int64_t nf = h->nf;
+  Vec slab((size_t)hdg::slab_doubles(n, P), 0.0);
+  const bool face = h->cfg.smoother == HDG_SMOOTH_FACE;
+  const int NQD = (P2 + 1) / 2;
+  Vec dinv(face ? (size_t)h->ntiles * NQD * 128 : 0, 0.0);
+  Vec diag(h->cfg.smoother == HDG_SMOOTH_CHAIN ? (size_t)nf * P2 : 0, 0.0);
+  hdg::parallel_for(nf, [&](int64_t a0, int64_t a1) {
+    Vec D(P2);
+    for (int64_t f = a0; f < a1; ++f) {
+      int64_t lo, hi;
+      int llo, lhi;
+      hdg::face_elements(n, f, lo, hi, llo, lhi);
+      const double* Klo = blocks.data() + (size_t)lo * F4 * F4;
+      const double* Khi = blocks.data() + (size_t)hi * F4 * F4;
+      const int ilo = (int)(lo % n), jlo = (int)(lo / n), ihi = (int)(hi % n), jhi = (int)(hi / n);
+      int olo[3], ohi[3];
+      hdg::other_faces(llo, olo);
+      hdg::other_faces(lhi, ohi);
+      for (int a = 0; a < P; ++a)
+        for (int c = 0; c < P; ++c) {
+          D[a * P + c] = blk(Klo, P, llo, llo, a, c) + blk(Khi, P, lhi, lhi, a, c);
+          slab[tp_index(f, a * P + c, NE)] = D[a * P + c];
+          for (int s = 0; s < 3; ++s) {
+            const bool in_lo = hdg::element_face(n, ilo, jlo, olo[s]) >= 0;
+            const bool in_hi = hdg::element_face(n, ihi, jhi, ohi[s]) >= 0;
+            slab[tp_index(f, (1 + s) * P2 + a * P + c, NE)] = in_lo ? blk(Klo, P, llo, olo[s], a, c) : 0.0;
+            slab[tp_index(f, (4 + s) * P2 + a * P + c, NE)] = in_hi ? blk(Khi, P, lhi, ohi[s], a, c) : 0.0;
+          }
+        }
+      if (face) {
+        Vec Di(D);
+        if (!hdg::cholesky_inverse(P, Di)) throw std::runtime_error("face block not SPD");
+        for (int e = 0; e < P2; ++e) dinv[tp_index(f, e, P2)] = Di[e];
+      } else {
+        std::copy(D.begin(), D.end(), diag.begin() + (size_t)f * P2);
+      }
+    }
+  });
+  L.slab = upload(h, slab);
+  if (face) {
+    L.dinv = upload(h, dinv);
+    return;
+  }
+  // chain Schwarz: block-tridiagonal LU of every chain of faces (no pivoting;
+  // the chain matrices are SPD principal submatrices of S).
+  const int64_t nch = 2LL * n, m = n - 1, nv = (int64_t)n * (n - 1);
+  Vec lmul((size_t)m * P2 * nch, 0.0), dtinv((size_t)m * P2 * nch, 0.0), upper((size_t)m * P2 * nch, 0.0);
+  hdg::parallel_for(nch, [&](int64_t c0, int64_t c1) {
+    Vec Dt(P2), Dprev_inv(P2), Lm(P2), Up(P2), Uprev(P2), tmp(P2);
+    for (int64_t c = c0; c < c1; ++c) {
+      const bool vert = c < n;
+      const int64_t base = vert ? c * (n - 1) : nv + (c - n);
+      const int64_t stride = vert ? 1 : n;
+      const int sub = vert ? 1 : 3, sup = vert ? 4 : 6;   // slots coupling to previous / next in chain
+      for (int64_t i = 0; i < m; ++i) {
+        const int64_t f = base + stride * i;
+        for (int e = 0; e < P2; ++e) {
+          Dt[e] = diag[(size_t)f * P2 + e];
+          Up[e] = (i + 1 < m) ? slab[tp_index(f, sup * P2 + e, NE)] : 0.0;
+        }
+        if (i > 0) {
+          // L_i = A_{i,i-1} Dt_{i-1}^{-1};  Dt_i = A_ii - L_i A_{i-1,i}
+          for (int a = 0; a < P; ++a)
+            for (int b2 = 0; b2 < P; ++b2) {
+              double s = 0.0;
+              for (int q = 0; q < P; ++q) s += slab[tp_index(f, sub * P2 + a * P + q, NE)] * Dprev_inv[q * P + b2];
+              Lm[a * P + b2] = s;
+            }
+          for (int a = 0; a < P; ++a)
+            for (int b2 = 0; b2 < P; ++b2) {
+              double s = 0.0;
+              for (int q = 0; q < P; ++q) s += Lm[a * P + q] * Uprev[q * P + b2];
+              Dt[a * P + b2] -= s;
+            }
+        } else {
+          std::fill(Lm.begin(), Lm.end(), 0.0);
+        }
+        Vec Dinv(Dt);
+        if (!hdg::cholesky_inverse(P, Dinv)) throw std::runtime_error("chain pivot block not SPD");
+        for (int e = 0; e < P2; ++e) {
+          const size_t idx = ((size_t)i * P2 + e) * nch + c;
+          lmul[idx] = Lm[e];
+          dtinv[idx] = Dinv[e];
+          upper[idx] = Up[e];
+        }
+        Dprev_inv = Dinv;
+        Uprev = Up;
+      }
+    }
+  });
+  L.clmul = upload(h, lmul);
+  L.cdtinv = upload(h, dtinv);
+  L.cupper = upload(h, upper);
+}
+
+// Q1 stencil of P_J^T S0 P_J from the p = 0 element blocks (4 x 4).
+Vec q1_from_p0(hdg_ctx* h, const Vec& b0) {
+  const int n = h->n;
+  const int64_t Nv = (int64_t)(n - 1) * (n - 1);
+  Vec st((size_t)9 * Nv, 0.0);
+  auto vid = [n](int i, int j) -> int64_t {
+    if (i <= 0 || j <= 0 || i >= n || j >= n) return -1;
+    return (int64_t)(i - 1) + (int64_t)(n - 1) * (j - 1);
+  };
+  for (int j = 0; j < n; ++j)
+    for (int i = 0; i < n; ++i) {
+      const double* K = b0.data() + (size_t)(i + (int64_t)n * j) * 16;
+      // local faces l, r, b, t and their end vertices
+      const int ends[4][2][2] = {{{i, j}, {i, j + 1}}, {{i + 1, j}, {i + 1, j + 1}},
+                                 {{i, j}, {i + 1, j}}, {{i, j + 1}, {i + 1, j + 1}}};
+      bool interior[4];
+      for (int lf = 0; lf < 4; ++lf) interior[lf] = hdg::element_face(n, i, j, lf) >= 0;
+      for (int f1 = 0; f1 < 4; ++f1) {
+        if (!interior[f1]) continue;
+        for (int f2 = 0; f2 < 4; ++f2) {
+          if (!interior[f2]) continue;
+          const double kv = K[f1 * 4 + f2];
+          for (int a = 0; a < 2; ++a) {
+            const int vi = ends[f1][a][0], vj = ends[f1][a][1];
+            const int64_t v = vid(vi, vj);
+            if (v < 0) continue;
+            for (int b = 0; b < 2; ++b) {
+              const int wi = ends[f2][b][0], wj = ends[f2][b][1];
+              if (vid(wi, wj) < 0) continue;
+              const int s = (wi - vi + 1) + 3 * (wj - vj + 1);
+              st[(size_t)s * Nv + v] += 0.25 * kv;
+            }
+          }
+        }
+      }
+    }
+  return st;
+}
+
+void build_hlevels(hdg_ctx* h, const Vec& b0) {
+  Vec st = q1_from_p0(h, b0);
+  int m = h->n;
+  int lev = 0;
+  while (true) {
+    QLevel Q;
+    Q.m = m;
+    Q.Nv = (int64_t)(m - 1) * (m - 1);
+    hdg::Csr A = hdg::stencil_to_csr(m, st);
+    const bool last = Q.Nv <= h->cfg.coarse_max || (m % 2) == 1 || m < 4 || lev + 1 >= HDG_MAX_HLEVELS;
+    if (last) {
+      if (Q.Nv > 20000) throw ArgError("coarsest Q1 level too large; use a mesh size with more factors of 2");
+      Q.coarsest = true;
+      Vec dense((size_t)Q.Nv * Q.Nv, 0.0);
+      for (int64_t r = 0; r < A.nrows; ++r)
+        for (int64_t kk = A.ptr[r]; kk < A.ptr[r + 1]; ++kk) dense[(size_t)r * Q.Nv + A.col[kk]] = A.val[kk];
+      if (!hdg::cholesky_inverse((int)Q.Nv, dense)) throw std::runtime_error("coarsest Q1 matrix not SPD");
+      Q.inv = upload(h, dense);
+      Q.x = dalloc(h, Q.Nv);
+      Q.b = dalloc(h, Q.Nv);
+      h->ql.push_back(Q);
+      break;
+    }
+    Vec dinv(Q.Nv);
+    for (int64_t v = 0; v < Q.Nv; ++v) dinv[v] = 1.0 / st[(size_t)4 * Q.Nv + v];
+    Q.lmax = h->cfg.cheb_lmax[lev] > 0 ? h->cfg.cheb_lmax[lev] : hdg::lanczos_lmax(A, dinv, 30);
+    Q.st = upload(h, st);
+    Q.dinv = upload(h, dinv);
+    for (double** p : {&Q.x, &Q.b, &Q.r, &Q.d, &Q.t}) *p = dalloc(h, Q.Nv);
+    h->ql.push_back(Q);
+    const hdg::Csr I = hdg::q1_bilinear(m);
+    const hdg::Csr It = hdg::csr_transpose(I);
+    const hdg::Csr Ac = hdg::csr_multiply(It, hdg::csr_multiply(A, I));
+    m /= 2;
+    st = hdg::csr_to_stencil(m, Ac);
+    ++lev;
+  }
+}
+
+// ------------------------------------------------------------ device helpers
+double reduce_scalar(hdg_ctx* h, int np) {
+  hipchk(hdg::launch_sum_partials(h->partial, np, h->scal, h->stream), "sum");
+  hipchk(hipMemcpyAsync(h->scal_h, h->scal, sizeof(double), hipMemcpyDeviceToHost, h->stream), "d2h");
+  hipchk(hipStreamSynchronize(h->stream), "sync");
+  return *h->scal_h;
+}
+
+double dot(hdg_ctx* h, const double* a, const double* b, int64_t n) {
+  hipchk(hdg::launch_dot_partials(a, b, n, h->partial, h->stream), "dot");
+  return reduce_scalar(h, hdg::reduce_grid(n));
+}
+
+hdg::TraceArgs targs(hdg_ctx* h, const PLevel& L) {
+  hdg::TraceArgs a{};
+  a.slab = L.slab;
+  a.dinv = L.dinv;
+  a.pmat = L.pmat;
+  a.omega = L.omega;
+  a.n = h->n;
+  a.nf = h->nf;
+  a.ntiles = h->ntiles;
+  return a;
+}
+
+void apply(hdg_ctx* h, int p, const double* x, double* y) {
+  hdg::TraceArgs a = targs(h, h->pl[p]);
+  a.x = x;
+  a.y = y;
+  hipchk(hdg::launch_trace(h->pl[p].P, hdg::TM_APPLY, a, h->stream), "trace apply");
+}
+
+// r = b - S x, optionally the squared norm partials
+void residual(hdg_ctx* h, int p, const double* b, const double* x, double* r, bool norm) {
+  hdg::TraceArgs a = targs(h, h->pl[p]);
+  a.x = x;
+  a.b = b;
+  a.y = r;
+  a.partial = norm ? h->partial : nullptr;
+  hipchk(hdg::launch_trace(h->pl[p].P, hdg::TM_RESID, a, h->stream), "trace residual");
+}
+
+double residual_norm(hdg_ctx* h, int p, const double* b, const double* x, double* r) {
+  residual(h, p, b, x, r, true);
+  return std::sqrt(reduce_scalar(h, hdg::trace_grid(h->ntiles)));
+}
+
+// nu sweeps of the level-p Schwarz smoother on x (in place); zero: x == 0 on entry
+void smooth(hdg_ctx* h, int p, const double* b, double* x, int nu, bool zero) {
+  PLevel& L = h->pl[p];
+  for (int s = 0; s < nu; ++s) {
+    const bool z = zero && s == 0;
+    if (h->cfg.smoother == HDG_SMOOTH_FACE) {
+      if (z) {
+        hipchk(hdg::launch_dinv_apply(L.P, L.dinv, b, L.omega, x, h->nf, h->stream), "dinv");
+      } else {
+        hdg::TraceArgs a = targs(h, L);
+        a.x = x;
+        a.b = b;
+        a.y = L.t;
+        hipchk(hdg::launch_trace(L.P, hdg::TM_FACE_SWEEP, a, h->stream), "face sweep");
+        hipchk(hdg::launch_copy(L.t, x, L.N, h->stream), "copy");
+      }
+    } else {
+      hdg::ChainArgs c{};
+      c.lmul = L.clmul;
+      c.dtinv = L.cdtinv;
+      c.upper = L.cupper;
+      c.omega = L.omega;
+      c.n = h->n;
+      c.nf = h->nf;
+      c.work = L.t;
+      c.out = x;
+      if (z) {
+        c.r = b;
+        c.x = nullptr;
+      } else {
+        residual(h, p, b, x, L.r, false);
+        c.r = L.r;
+        c.x = x;
+      }
+      hipchk(hdg::launch_chain_solve(L.P, c, h->stream), "chain solve");
+    }
+  }
+}
+
+// Chebyshev on Q1 level Q; result in Q.x.  zero: initial guess 0.
+void chebyshev(hdg_ctx* h, QLevel& Q, const double* b, int nu, bool zero) {
+  const double a = h->cfg.cheb_lo * Q.lmax, c = h->cfg.cheb_hi * Q.lmax;
+  const double theta = 0.5 * (c + a), delta = 0.5 * (c - a), sigma = theta / delta;
+  double rho = 1.0 / sigma;
+  double* cur = Q.x;
+  double* nxt = Q.t;
+  for (int s = 0; s < nu; ++s) {
+    double c1, c2;
+    if (s == 0) {
+      c1 = 0.0;
+      c2 = 1.0 / theta;
+    } else {
+      const double rn = 1.0 / (2.0 * sigma - rho);
+      c1 = rn * rho;
+      c2 = 2.0 * rn / delta;
+      rho = rn;
+    }
+    const double* xin = (zero && s == 0) ? nullptr : cur;
+    hipchk(hdg::launch_q1_cheb(Q.st, Q.dinv, b, xin, Q.d, nxt, c1, c2, Q.m, h->stream), "chebyshev");
+    std::swap(cur, nxt);
+  }
+  if (cur != Q.x) hipchk(hdg::launch_copy(cur, Q.x, Q.Nv, h->stream), "copy");
+}
+
+void qcycle(hdg_ctx* h, int l) {
+  QLevel& Q = h->ql[l];
+  if (Q.coarsest) {
+    hipchk(hdg::launch_dense_gemv(Q.inv, Q.b, Q.x, (int)Q.Nv, h->stream), "coarse solve");
+    return;
+  }
+  chebyshev(h, Q, Q.b, h->cfg.nu1, true);
+  hipchk(hdg::launch_q1_resid(Q.st, Q.b, Q.x, Q.r, Q.m, h->stream), "q1 resid");
+  QLevel& C = h->ql[l + 1];
+  hipchk(hdg::launch_q1_restrict(Q.r, C.b, Q.m, h->stream), "q1 restrict");
+  qcycle(h, l + 1);
+  hipchk(hdg::launch_q1_prolong_add(C.x, Q.x, Q.m, h->stream), "q1 prolong");
+  chebyshev(h, Q, Q.b, h->cfg.nu2, false);
+}
+
+// V-cycle at p-level p for S_p x = b; zero: x == 0 on entry (its content is ignored)
+void pcycle(hdg_ctx* h, int p, const double* b, double* x, bool zero) {
+  PLevel& L = h->pl[p];
+  smooth(h, p, b, x, h->cfg.nu1, zero);
+  if (p >= 1) {
+    PLevel& C = h->pl[p - 1];
+    hdg::TraceArgs a = targs(h, L);
+    a.x = x;
+    a.b = b;
+    a.y = C.b;
+    hipchk(hdg::launch_trace(L.P, hdg::TM_RESID_RESTRICT, a, h->stream), "resid restrict");
+    pcycle(h, p - 1, C.b, C.x, true);
+    hipchk(hdg::launch_p_prolong_add(L.P, L.pmat, C.x, x, h->nf, h->stream), "p prolong");
+  } else {
+    residual(h, 0, b, x, L.r, false);
+    QLevel& Q = h->ql[0];
+    hipchk(hdg::launch_pj_restrict(L.r, Q.b, h->n, h->stream), "pj restrict");
+    qcycle(h, 0);
+    hipchk(hdg::launch_pj_prolong_add(Q.x, x, h->n, h->stream), "pj prolong");
+  }
+  smooth(h, p, b, x, h->cfg.nu2, false);
+}
+
+// Largest eigenvalue of D^{-1} S_p (facet blocks) by Lanczos in the D inner product.
+double estimate_face_lmax(hdg_ctx* h, int p, int steps) {
+  PLevel& L = h->pl[p];
+  const int64_t N = L.N;
+  double *v = L.x, *z = L.b, *w = L.r, *vold = L.t;
+  Vec hv(N);
+  for (int64_t i = 0; i < N; ++i) hv[i] = 1.0 + 0.25 * std::cos(0.37 * (double)i);
+  hipchk(hipMemcpyAsync(v, hv.data(), N * sizeof(double), hipMemcpyHostToDevice, h->stream), "h2d");
+  hipchk(hdg::launch_fill(0.0, vold, N, h->stream), "fill");
+  hipchk(hdg::launch_dinv_apply(L.P, L.dinv, v, 1.0, z, h->nf, h->stream), "dinv");
+  double beta = std::sqrt(dot(h, v, z, N));
+  hipchk(hdg::launch_xpby(v, 1.0 / beta - 1.0, v, N, h->stream), "scale");  // v <- v / beta
+  hipchk(hdg::launch_xpby(z, 1.0 / beta - 1.0, z, N, h->stream), "scale");
+  std::vector<double> al, be;
+  double bprev = 0.0;
+  for (int s = 0; s < steps; ++s) {
+    apply(h, p, z, w);
+    const double alpha = dot(h, w, z, N);
+    hipchk(hdg::launch_axpy(-alpha, v, w, N, h->stream), "axpy");
+    hipchk(hdg::launch_axpy(-bprev, vold, w, N, h->stream), "axpy");
+    hipchk(hdg::launch_dinv_apply(L.P, L.dinv, w, 1.0, z, h->nf, h->stream), "dinv");
+    const double bn = std::sqrt(std::max(dot(h, w, z, N), 0.0));
+    al.push_back(alpha);
+    if (bn < 1e-14 * std::fabs(alpha)) break;
+    be.push_back(bn);
+    hipchk(hdg::launch_copy(v, vold, N, h->stream), "copy");
+    hipchk(hdg::launch_fill(0.0, v, N, h->stream), "fill");
+    hipchk(hdg::launch_axpy(1.0 / bn, w, v, N, h->stream), "axpy");
+    hipchk(hdg::launch_xpby(z, 1.0 / bn - 1.0, z, N, h->stream), "scale");
+    bprev = bn;
+  }
+  // tridiagonal eigen-bound by bisection
+  const int m = (int)al.size();
+  double lo = 1e300, hi = -1e300;
+  for (int i = 0; i < m; ++i) {
+    const double r = (i > 0 ? std::fabs(be[i - 1]) : 0.0) + (i < m - 1 ? std::fabs(be[i]) : 0.0);
+    lo = std::min(lo, al[i] - r);
+    hi = std::max(hi, al[i] + r);
+  }
+  for (int it = 0; it < 200; ++it) {
+    const double mid = 0.5 * (lo + hi);
+    int c = 0;
+    double d = 1.0;
+    for (int i = 0; i < m; ++i) {
+      d = al[i] - mid - (i > 0 ? be[i - 1] * be[i - 1] / d : 0.0);
+      if (d == 0.0) d = 1e-300;
+      if (d < 0) ++c;
+    }
+    if (c >= m) hi = mid; else lo = mid;
+  }
+  return hi;
+}
+
+void validate_config(const hdg_config_t* c) {
+  if (!c) throw ArgError("cfg is NULL");
+  if (c->n < 2) throw ArgError("n must be >= 2");
+  if (c->k < 0 || c->k > HDG_MAX_DEGREE) throw ArgError("k out of range [0, 8]");
+  if (!(c->tau > 0.0) || !std::isfinite(c->tau)) throw ArgError("tau must be > 0 and finite");
+  if (c->nu1 < 1 || c->nu2 < 1 || c->nu1 > 64 || c->nu2 > 64) throw ArgError("nu1, nu2 must be in [1, 64]");
+  if (c->smoother != HDG_SMOOTH_CHAIN && c->smoother != HDG_SMOOTH_FACE) throw ArgError("bad smoother");
+  if (c->coarse != HDG_COARSE_GALERKIN && c->coarse != HDG_COARSE_REDISCRETIZE) throw ArgError("bad coarse");
+  if (!(c->cheb_lo > 0.0) || !(c->cheb_hi > c->cheb_lo)) throw ArgError("need 0 < cheb_lo < cheb_hi");
+  if (c->coarse_max < 1) throw ArgError("coarse_max must be >= 1");
+  if (c->nq < 1 || c->nq > 32) throw ArgError("nq must be in [1, 32]");
+  if ((int64_t)c->n * c->n > (int64_t)1 << 31) throw ArgError("n too large");
+}
+
+}  // namespace
+
+// =================================================================== C ABI
+extern "C" {
+
+const char* hdg_status_string(hdg_status_t s) {
+  switch (s) {
+    case HDG_OK: return "ok";
+    case HDG_ERR_INVALID_ARG: return "invalid argument";
+    case HDG_ERR_OOM: return "out of memory";
+    case HDG_ERR_HIP: return "HIP error";
+    case HDG_ERR_NOT_CONVERGED: return "not converged";
+    case HDG_ERR_NONFINITE: return "non-finite value";
+    case HDG_ERR_STATE: return "invalid state";
+  }
+  return "unknown";
+}
+
+const char* hdg_last_error(hdg_handle_t h) { return h ? h->err.c_str() : "null handle"; }
+
+hdg_status_t hdg_config_default(int32_t n, int32_t k, hdg_config_t* cfg) {
+  if (!cfg) return HDG_ERR_INVALID_ARG;
+  std::memset(cfg, 0, sizeof(*cfg));
+  cfg->n = n;
+  cfg->k = k;
+  cfg->tau = 1.0;
+  cfg->nu1 = cfg->nu2 = 2;
+  cfg->smoother = HDG_SMOOTH_CHAIN;
+  cfg->coarse = HDG_COARSE_GALERKIN;
+  cfg->cheb_lo = 0.1;
+  cfg->cheb_hi = 1.1;
+  cfg->coarse_max = 2000;
+  cfg->nq = k + 2;
+  return HDG_OK;
+}
+
+hdg_status_t hdg_quadrature_nodes(int32_t nq, double* x_host) {
+  if (nq < 1 || nq > 32 || !x_host) return HDG_ERR_INVALID_ARG;
+  Vec x, w;
+  hdg::gauss_legendre(nq, x, w);
+  std::copy(x.begin(), x.end(), x_host);
+  return HDG_OK;
+}
+
+hdg_status_t hdg_create(const hdg_config_t* cfg, const double* kappa_host, void* hip_stream,
+                        hdg_handle_t* out) {
+  if (!out) return HDG_ERR_INVALID_ARG;
+  *out = nullptr;
+  std::unique_ptr<hdg_ctx> h(new hdg_ctx());
+  hdg_status_t st = guarded(h.get(), [&]() -> hdg_status_t {
+    validate_config(cfg);
+    if (!kappa_host) throw ArgError("kappa_host is NULL");
+    h->cfg = *cfg;
+    h->n = cfg->n;
+    h->k = cfg->k;
+    h->nq = cfg->nq;
+    h->stream = (hipStream_t)hip_stream;
+    const int64_t ne = (int64_t)h->n * h->n;
+    h->kappa.assign(kappa_host, kappa_host + ne);
+    for (double v : h->kappa)
+      if (!(v > 0.0) || !std::isfinite(v)) throw ArgError("kappa must be > 0 and finite");
+    h->nf = hdg::n_faces(h->n);
+    h->ntiles = (h->nf + 63) / 64;
+    h->pl.resize(h->k + 1);
+    Vec blocks;
+    for (int p = h->k; p >= 0; --p) {
+      PLevel& L = h->pl[p];
+      L.p = p;
+      L.P = p + 1;
+      L.N = h->nf * L.P;
+      if (p == h->k || cfg->coarse == HDG_COARSE_REDISCRETIZE) blocks = blocks_finest(h.get(), p);
+      else blocks = blocks_galerkin(h.get(), p + 1, blocks);
+      build_face_data(h.get(), L, blocks);
+      if (p >= 1) L.pmat = upload(h.get(), hdg::p_prolongation(p));
+      L.omega = cfg->omega[p] > 0 ? cfg->omega[p] : 0.8;
+      for (double** q : {&L.x, &L.b, &L.r, &L.t}) *q = dalloc(h.get(), L.N);
+      if (p == 0) build_hlevels(h.get(), blocks);
+    }
+    const int64_t Nk = h->pl[h->k].N;
+    h->npartial = std::max(hdg::trace_grid(h->ntiles), 1024);
+    h->partial = dalloc(h.get(), h->npartial);
+    h->scal = dalloc(h.get(), 1);
+    hipchk(hipHostMalloc((void**)&h->scal_h, sizeof(double), hipHostMallocDefault), "pinned");
+    h->vr = dalloc(h.get(), Nk);
+    h->vz = dalloc(h.get(), Nk);
+    h->vd = dalloc(h.get(), Nk);
+    h->vq = dalloc(h.get(), Nk);
+    if (cfg->smoother == HDG_SMOOTH_FACE)
+      for (int p = 0; p <= h->k; ++p)
+        if (!(cfg->omega[p] > 0)) h->pl[p].omega = 4.0 / (3.0 * estimate_face_lmax(h.get(), p, 30));
+    hipchk(hipStreamSynchronize(h->stream), "setup sync");
+    return HDG_OK;
+  });
+  if (st != HDG_OK) {
+    for (void* p : h->allocs) (void)hipFree(p);
+    if (h->scal_h) (void)hipHostFree(h->scal_h);
+    // keep the message reachable: report through stderr-free path by returning status only
+    return st;
+  }
+  *out = h.release();
+  return HDG_OK;
+}
+
+hdg_status_t hdg_destroy(hdg_handle_t h) {
+  if (!h) return HDG_ERR_INVALID_ARG;
+  (void)hipStreamSynchronize(h->stream);
+  for (void* p : h->allocs) (void)hipFree(p);
+  if (h->scal_h) (void)hipHostFree(h->scal_h);
+  delete h;
+  return HDG_OK;
+}
+
+hdg_status_t hdg_num_dofs(hdg_handle_t h, int32_t p, int64_t* n_lambda) {
+  if (!h || !n_lambda || p < 0 || p > h->k) return HDG_ERR_INVALID_ARG;
+  *n_lambda = h->pl[p].N;
+  return HDG_OK;
+}
+
+hdg_status_t hdg_num_hlevels(hdg_handle_t h, int32_t* nlev) {
+  if (!h || !nlev) return HDG_ERR_INVALID_ARG;
+  *nlev = (int32_t)h->ql.size();
+  return HDG_OK;
+}
+
+hdg_status_t hdg_hlevel_mesh(hdg_handle_t h, int32_t level, int32_t* m) {
+  if (!h || !m || level < 0 || level >= (int)h->ql.size()) return HDG_ERR_INVALID_ARG;
+  *m = h->ql[level].m;
+  return HDG_OK;
+}
+
+hdg_status_t hdg_get_params(hdg_handle_t h, double* omega_out, double* lmax_out) {
+  if (!h) return HDG_ERR_INVALID_ARG;
+  if (omega_out)
+    for (int p = 0; p <= h->k; ++p) omega_out[p] = h->pl[p].omega;
+  if (lmax_out)
+    for (size_t l = 0; l < h->ql.size(); ++l) lmax_out[l] = h->ql[l].lmax;
+  return HDG_OK;
+}
+
+hdg_status_t hdg_element_block_host(int32_t n, int32_t k, int32_t p, double tau, double kappa_e,
+                                    int32_t coarse, double* out_host) {
+  if (n < 2 || k < 0 || k > HDG_MAX_DEGREE || p < 0 || p > k || !(tau > 0) || !(kappa_e > 0) ||
+      !std::isfinite(kappa_e) || !out_host || (coarse != HDG_COARSE_GALERKIN && coarse != HDG_COARSE_REDISCRETIZE))
+    return HDG_ERR_INVALID_ARG;
+  try {
+    const int top = coarse == HDG_COARSE_REDISCRETIZE ? p : k;
+    hdg::RefDegree ref;
+    ref.build(top, 1.0 / n, tau);
+    const int P = top + 1, F4 = 4 * P, P2 = P * P;
+    Vec K((size_t)F4 * F4), work((size_t)P2 * P2 + (size_t)P2 * F4);
+    hdg::element_block(ref, kappa_e, K.data(), work.data());
+    for (int q = top; q > p; --q) {
+      const Vec Pp = hdg::p_prolongation(q);
+      Vec Kc((size_t)16 * q * q);
+      hdg::galerkin_block(Pp, q, K.data(), Kc.data());
+      K.swap(Kc);
+    }
+    std::copy(K.begin(), K.end(), out_host);
+  } catch (const std::exception&) {
+    return HDG_ERR_STATE;
+  }
+  return HDG_OK;
+}
+
+hdg_status_t hdg_get_element_block(hdg_handle_t h, int32_t p, int64_t e, double* out_host) {
+  if (!h || !out_host || p < 0 || p > h->k || e < 0 || e >= (int64_t)h->n * h->n) return HDG_ERR_INVALID_ARG;
+  return hdg_element_block_host(h->n, h->k, p, h->cfg.tau, h->kappa[e], h->cfg.coarse, out_host);
+}
+
+hdg_status_t hdg_assemble_rhs(hdg_handle_t h, const double* f_qp_host, const double* gD_qp_host,
+                              double* b) {
+  if (!h || !f_qp_host || !b) return HDG_ERR_INVALID_ARG;
+  return guarded(h, [&]() -> hdg_status_t {
+    const int n = h->n, p = h->k, P = p + 1, P2 = P * P, F4 = 4 * P, nq = h->nq;
+    const double hh = 1.0 / n;
+    hdg::RefDegree ref;
+    ref.build(p, hh, h->cfg.tau);
+    Vec xq, wq;
+    hdg::gauss_legendre(nq, xq, wq);
+    const Vec nodes = hdg::trace_nodes(p);
+    Vec Lq((size_t)nq * P);
+    for (int q = 0; q < nq; ++q) hdg::lagrange_eval(nodes, xq[q], Lq.data() + (size_t)q * P);
+    // boundary traces: L2 projection onto Q_p(e) of the data at the GL points
+    Vec lam_bd((size_t)4 * n * P, 0.0);
+    if (gD_qp_host) {
+      Vec M1inv(ref.M1);
+      if (!hdg::cholesky_inverse(P, M1inv)) throw std::runtime_error("mass");
+      for (int nb = 0; nb < 4 * n; ++nb) {
+        Vec mom(P, 0.0);
+        for (int q = 0; q < nq; ++q)
+          for (int a = 0; a < P; ++a) mom[a] += wq[q] * gD_qp_host[(size_t)nb * nq + q] * Lq[(size_t)q * P + a];
+        for (int a = 0; a < P; ++a) {
+          double s = 0.0;
+          for (int c = 0; c < P; ++c) s += M1inv[a * P + c] * mom[c];
+          lam_bd[(size_t)nb * P + a] = s;
+        }
+      }
+    }
+    const int64_t ne = (int64_t)n * n;
+    Vec g((size_t)ne * F4);
+    hdg::parallel_for(ne, [&](int64_t e0, int64_t e1) {
+      Vec F(P2), work((size_t)P2 * P2 + (size_t)P2 * F4), K((size_t)F4 * F4);
+      for (int64_t e = e0; e < e1; ++e) {
+        const double* fq = f_qp_host + (size_t)e * nq * nq;
+        for (int i2 = 0; i2 < P; ++i2)
+          for (int i1 = 0; i1 < P; ++i1) {
+            double s = 0.0;
+            for (int bq = 0; bq < nq; ++bq)
+              for (int aq = 0; aq < nq; ++aq)
+                s += wq[aq] * wq[bq] * fq[aq + nq * bq] * Lq[(size_t)aq * P + i1] * Lq[(size_t)bq * P + i2];
+            F[i1 + P * i2] = 0.25 * hh * hh * s;
+          }
+        double* ge = g.data() + (size_t)e * F4;
+        hdg::element_source(ref, h->kappa[e], F.data(), ge, work.data());
+        const int i = (int)(e % n), j = (int)(e / n);
+        const bool touches = i == 0 || j == 0 || i == n - 1 || j == n - 1;
+        if (touches && gD_qp_host) {
+          hdg::element_block(ref, h->kappa[e], K.data(), work.data());
+          int nbf[4] = {i == 0 ? 3 * n + j : -1, i == n - 1 ? n + j : -1, j == 0 ? i : -1,
+                        j == n - 1 ? 2 * n + i : -1};
+          for (int r = 0; r < F4; ++r) {
+            double s = 0.0;
+            for (int lf = 0; lf < 4; ++lf)
+              if (nbf[lf] >= 0)
+                for (int c = 0; c < P; ++c) s += K[(size_t)r * F4 + lf * P + c] * lam_bd[(size_t)nbf[lf] * P + c];
+            ge[r] -= s;
+          }
+        }
+      }
+    });
+    Vec bh((size_t)h->nf * P);
+    hdg::parallel_for(h->nf, [&](int64_t f0, int64_t f1) {
+      for (int64_t f = f0; f < f1; ++f) {
+        int64_t lo, hi;
+        int llo, lhi;
+        hdg::face_elements(n, f, lo, hi, llo, lhi);
+        for (int a = 0; a < P; ++a)
+          bh[(size_t)f * P + a] = g[(size_t)lo * F4 + llo * P + a] + g[(size_t)hi * F4 + lhi * P + a];
+      }
+    });
+    hipchk(hipMemcpyAsync(b, bh.data(), bh.size() * sizeof(double), hipMemcpyHostToDevice, h->stream), "h2d");
+    hipchk(hipStreamSynchronize(h->stream), "sync");
+    return HDG_OK;
+  });
+}
+
+hdg_status_t hdg_apply_trace_operator(hdg_handle_t h, int32_t p, const double* x, double* y) {
+  if (!h || !x || !y || p < 0 || p > h->k || x == y) return HDG_ERR_INVALID_ARG;
+  return guarded(h, [&]() -> hdg_status_t {
+    apply(h, p, x, y);
+    return HDG_OK;
+  });
+}
+
+hdg_status_t hdg_residual(hdg_handle_t h, int32_t p, const double* b, const double* x, double* r,
+                          double* norm2_host) {
+  if (!h || !b || !x || !r || p < 0 || p > h->k || r == x) return HDG_ERR_INVALID_ARG;
+  return guarded(h, [&]() -> hdg_status_t {
+    if (norm2_host) {
+      const double v = residual_norm(h, p, b, x, r);
+      *norm2_host = v;
+      if (!std::isfinite(v)) {
+        h->err = "non-finite residual norm";
+        return HDG_ERR_NONFINITE;
+      }
+    } else {
+      residual(h, p, b, x, r, false);
+    }
+    return HDG_OK;
+  });
+}
+
+hdg_status_t hdg_smooth(hdg_handle_t h, int32_t p, const double* b, double* x, int32_t sweeps) {
+  if (!h || !b || !x || p < 0 || p > h->k || sweeps < 0) return HDG_ERR_INVALID_ARG;
+  return guarded(h, [&]() -> hdg_status_t {
+    smooth(h, p, b, x, sweeps, false);
+    return HDG_OK;
+  });
+}
+
+hdg_status_t hdg_restrict(hdg_handle_t h, int32_t p_fine, const double* r_fine, double* r_coarse) {
+  if (!h || !r_fine || !r_coarse || p_fine < 1 || p_fine > h->k) return HDG_ERR_INVALID_ARG;
+  return guarded(h, [&]() -> hdg_status_t {
+    hipchk(hdg::launch_p_restrict(p_fine + 1, h->pl[p_fine].pmat, r_fine, r_coarse, h->nf, h->stream),
+           "restrict");
+    return HDG_OK;
+  });
+}
+
+hdg_status_t hdg_prolong(hdg_handle_t h, int32_t p_fine, const double* e_coarse, double* x_fine) {
+  if (!h || !e_coarse || !x_fine || p_fine < 1 || p_fine > h->k) return HDG_ERR_INVALID_ARG;
+  return guarded(h, [&]() -> hdg_status_t {
+    hipchk(hdg::launch_p_prolong_add(p_fine + 1, h->pl[p_fine].pmat, e_coarse, x_fine, h->nf, h->stream),
+           "prolong");
+    return HDG_OK;
+  });
+}
+
+hdg_status_t hdg_vcycle(hdg_handle_t h, const double* b, double* x) {
+  if (!h || !b || !x || b == x) return HDG_ERR_INVALID_ARG;
+  return guarded(h, [&]() -> hdg_status_t {
+    pcycle(h, h->k, b, x, false);
+    return HDG_OK;
+  });
+}
+
+hdg_status_t hdg_solve(hdg_handle_t h, const double* b, double* x, double rtol, int32_t maxit,
+                       int32_t mode, int32_t* iters, double* relres, double* history_host) {
+  if (!h || !b || !x || b == x || maxit < 0 || !(rtol >= 0.0) ||
+      (mode != HDG_SOLVE_PCG && mode != HDG_SOLVE_VCYCLE))
+    return HDG_ERR_INVALID_ARG;
+  return guarded(h, [&]() -> hdg_status_t {
+    const int k = h->k;
+    const int64_t N = h->pl[k].N;
+    const double nb = std::sqrt(dot(h, b, b, N));
+    double rn = residual_norm(h, k, b, x, h->vr);
+    int it = 0;
+    if (history_host) history_host[0] = rn;
+    auto finish = [&](hdg_status_t s) {
+      if (iters) *iters = it;
+      if (relres) *relres = nb > 0 ? rn / nb : rn;
+      return s;
+    };
+    if (!std::isfinite(rn) || !std::isfinite(nb)) {
+      h->err = "non-finite residual";
+      return finish(HDG_ERR_NONFINITE);
+    }
+    const double tol = rtol * nb;
+    if (mode == HDG_SOLVE_VCYCLE) {
+      while (rn > tol && it < maxit) {
+        pcycle(h, k, b, x, false);
+        rn = residual_norm(h, k, b, x, h->vr);
+        ++it;
+        if (history_host) history_host[it] = rn;
+        if (!std::isfinite(rn)) {
+          h->err = "non-finite residual";
+          return finish(HDG_ERR_NONFINITE);
+        }
+      }
+    } else if (rn > tol && maxit > 0) {
+      pcycle(h, k, h->vr, h->vz, true);
+      hipchk(hdg::launch_copy(h->vz, h->vd, N, h->stream), "copy");
+      double rz = dot(h, h->vr, h->vz, N);
+      while (rn > tol && it < maxit) {
+        apply(h, k, h->vd, h->vq);
+        const double dq = dot(h, h->vd, h->vq, N);
+        const double alpha = rz / dq;
+        hipchk(hdg::launch_axpy(alpha, h->vd, x, N, h->stream), "axpy");
+        hipchk(hdg::launch_axpy_norm(alpha, h->vq, h->vr, N, h->partial, h->stream), "axpy norm");
+        rn = std::sqrt(reduce_scalar(h, hdg::reduce_grid(N)));
+        ++it;
+        if (history_host) history_host[it] = rn;
+        if (!std::isfinite(rn)) {
+          h->err = "non-finite residual";
+          return finish(HDG_ERR_NONFINITE);
+        }
+        if (rn <= tol) break;
+        pcycle(h, k, h->vr, h->vz, true);
+        const double rz_new = dot(h, h->vr, h->vz, N);
+        hipchk(hdg::launch_xpby(h->vz, rz_new / rz, h->vd, N, h->stream), "xpby");
+        rz = rz_new;
+      }
+    }
+    if (rn > tol) {
+      h->err = "maximum number of iterations reached";
+      return finish(HDG_ERR_NOT_CONVERGED);
+    }
+    return finish(HDG_OK);
+  });
+}
+
+}  // extern "C"

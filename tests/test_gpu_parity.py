@@ -1,0 +1,286 @@
+"""GPU parity: the HIP path (through the C ABI) against the CPU oracle.
+
+Tolerances (FP64): operator, residual, smoothers and transfers 1e-12 relative
+(max norm); V-cycle iterates 1e-11 relative after up to 3 cycles; solutions
+1e-10 relative to the oracle's direct solve.
+"""
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+import paper_1705_09907_amd as H  # noqa: E402
+from oracle import hdg, mg, mesh as ms, quadrature as qd  # noqa: E402
+from workloads import (SinSin, PolyProblem, kappa_lognormal, kappa_const,  # noqa: E402
+                       normal_vector)
+
+CASES = [(2, 1, None), (16, 1, None), (24, 3, 1.0), (40, 4, 1.0), (64, 2, 2.0), (16, 0, 1.0)]
+
+
+def _kappa(n, sigma, seed=12):
+    return kappa_const(n) if sigma is None else kappa_lognormal(n, sigma, seed)
+
+
+def dev(a):
+    return torch.tensor(np.asarray(a), dtype=torch.float64, device="cuda")
+
+
+def host(t):
+    torch.cuda.synchronize()
+    return t.detach().cpu().numpy()
+
+
+def rel_inf(a, b):
+    return np.abs(a - b).max() / max(np.abs(b).max(), 1e-300)
+
+
+def oracle_hier(n, k, kap, smoother, omega=0.8):
+    return mg.Hierarchy(n, k, kap, smoother=smoother, omega=omega)
+
+
+def gpu_solver(n, k, kap, Ho, smoother):
+    lmax = [Ho.lmax[L.name] for L in Ho.levels if L.kind == 'q' and not L.coarsest]
+    return H.Solver(n, k, kap, smoother=smoother, omega=Ho.omega, cheb_lmax=lmax)
+
+
+@pytest.mark.parametrize("n,k,sigma", CASES)
+def test_apply_and_residual_every_level(n, k, sigma):
+    print(f"case apply n={n} k={k} sigma={sigma}", flush=True)
+    kap = _kappa(n, sigma)
+    Ho = oracle_hier(n, k, kap, "face")
+    S = H.Solver(n, k, kap, smoother="face", omega=0.7)
+    try:
+        for lev, L in enumerate(Ho.levels):
+            if L.kind != 'p':
+                break
+            p = L.p
+            N = ms.n_trace_dofs(n, p)
+            assert S.num_dofs(p) == N
+            x = normal_vector(N, 100 + p)
+            b = normal_vector(N, 200 + p)
+            y = host(S.apply(p, dev(x)))
+            yo = L.A @ x
+            assert rel_inf(y, yo) <= 1e-12, (p, rel_inf(y, yo))
+            r, nrm = S.residual(p, dev(b), dev(x), norm=True)
+            ro = b - yo
+            assert rel_inf(host(r), ro) <= 1e-12
+            assert abs(nrm - np.linalg.norm(ro)) <= 1e-12 * np.linalg.norm(ro)
+    finally:
+        S.close()
+
+
+def test_apply_is_deterministic():
+    n, k = 40, 3
+    kap = _kappa(n, 1.0)
+    S = H.Solver(n, k, kap, smoother="face", omega=0.7)
+    x = dev(normal_vector(S.num_dofs(), 5))
+    y1, y2 = host(S.apply(k, x)), host(S.apply(k, x))
+    assert np.array_equal(y1, y2)
+    b = dev(normal_vector(S.num_dofs(), 6))
+    n1 = S.residual(k, b, x, norm=True)[1]
+    n2 = S.residual(k, b, x, norm=True)[1]
+    assert n1 == n2
+    S.close()
+
+
+@pytest.mark.parametrize("n,k,sigma", [(16, 1, None), (24, 3, 1.0), (40, 4, 1.0)])
+@pytest.mark.parametrize("smoother", ["face", "chain"])
+def test_smoother_sweeps(n, k, sigma, smoother):
+    print(f"case smooth {smoother} n={n} k={k}", flush=True)
+    kap = _kappa(n, sigma)
+    Ho = oracle_hier(n, k, kap, smoother, omega=0.75)
+    S = gpu_solver(n, k, kap, Ho, smoother)
+    try:
+        for L in Ho.levels:
+            if L.kind != 'p':
+                break
+            N = ms.n_trace_dofs(n, L.p)
+            b = normal_vector(N, 300 + L.p)
+            x0 = normal_vector(N, 400 + L.p)
+            xo = Ho.smooth(L, b, x0.copy(), 3)
+            xg = dev(x0)
+            S.smooth(L.p, dev(b), xg, 3)
+            assert rel_inf(host(xg), xo) <= 1e-12, (L.p, rel_inf(host(xg), xo))
+    finally:
+        S.close()
+
+
+@pytest.mark.parametrize("k", [1, 2, 3, 4, 6, 8])
+def test_p_transfers(k):
+    n = 12
+    S = H.Solver(n, k, kappa_const(n), smoother="face", omega=0.7)
+    try:
+        for p in range(k, 0, -1):
+            Pm = mg.p_prolongation(n, p)
+            r = normal_vector(ms.n_trace_dofs(n, p), 7 + p)
+            e = normal_vector(ms.n_trace_dofs(n, p - 1), 8 + p)
+            x = normal_vector(ms.n_trace_dofs(n, p), 9 + p)
+            assert rel_inf(host(S.restrict(p, dev(r))), Pm.T @ r) <= 1e-13
+            xg = dev(x)
+            S.prolong(p, dev(e), xg)
+            assert rel_inf(host(xg), x + Pm @ e) <= 1e-13
+    finally:
+        S.close()
+
+
+@pytest.mark.parametrize("n,k,sigma", [(16, 1, None), (24, 3, 1.0), (64, 2, 2.0), (16, 0, 1.0), (2, 1, None)])
+@pytest.mark.parametrize("smoother", ["face", "chain"])
+def test_vcycle_iterates(n, k, sigma, smoother):
+    print(f"case vcycle {smoother} n={n} k={k}", flush=True)
+    kap = _kappa(n, sigma)
+    Ho = oracle_hier(n, k, kap, smoother, omega=0.8)
+    S = gpu_solver(n, k, kap, Ho, smoother)
+    try:
+        N = ms.n_trace_dofs(n, k)
+        b = normal_vector(N, 11)
+        xo = np.zeros(N)
+        xg = torch.zeros(N, dtype=torch.float64, device="cuda")
+        bg = dev(b)
+        for cyc in range(3):
+            xo = Ho.vcycle(b, xo)
+            S.vcycle(bg, xg)
+            assert rel_inf(host(xg), xo) <= 1e-11, (cyc, rel_inf(host(xg), xo))
+    finally:
+        S.close()
+
+
+def _gpu_rhs(S, n, k, nq, f, gD=None):
+    x = H.quadrature_nodes(nq)
+    h = 1.0 / n
+    fq = np.zeros((n * n, nq * nq))
+    for e in range(n * n):
+        i, j = e % n, e // n
+        X = np.tile((i + 0.5 * (1 + x)) * h, nq)
+        Y = np.repeat((j + 0.5 * (1 + x)) * h, nq)
+        fq[e] = f(X, Y)
+    gq = None
+    if gD is not None:
+        gq = np.zeros((4 * n, nq))
+        for nb in range(4 * n):
+            side, t = divmod(nb, n)
+            s = (t + 0.5 * (1 + x)) * h
+            X, Y = [(s, 0 * s), (0 * s + 1, s), (s, 0 * s + 1), (0 * s, s)][side]
+            gq[nb] = gD(X, Y)
+    return S.assemble_rhs(fq, gq)
+
+
+@pytest.mark.parametrize("n,k,kind", [(16, 1, "sinsin"), (8, 3, "poly"), (12, 2, "lognormal")])
+def test_rhs_assembly(n, k, kind):
+    if kind == "sinsin":
+        kap, f, gD = kappa_const(n), SinSin.f, None
+    elif kind == "poly":
+        prob = PolyProblem(k, 2.5)
+        kap, f, gD = kappa_const(n, 2.5), prob.f, prob.gD
+    else:
+        kap, f, gD = _kappa(n, 1.0), (lambda X, Y: 1.0 + 0 * X), None
+    S = H.Solver(n, k, kap, smoother="face", omega=0.7)
+    pr = hdg.Problem(n, k, kap)
+    bo = pr.rhs(pr.f_at_points(f), gD=gD)
+    bg = host(_gpu_rhs(S, n, k, S.nq, f, gD))
+    assert rel_inf(bg, bo) <= 1e-12
+    S.close()
+
+
+@pytest.mark.parametrize("n,k,sigma,mode,smoother", [
+    (16, 1, None, "vcycle", "chain"), (16, 1, None, "pcg", "chain"), (24, 3, 1.0, "pcg", "chain"),
+    (40, 4, 1.0, "pcg", "chain"), (64, 2, 2.0, "pcg", "chain"), (24, 3, 1.0, "pcg", "face"),
+    (24, 2, 1.0, "vcycle", "face")])
+def test_solve_matches_direct(n, k, sigma, mode, smoother):
+    print(f"case solve {mode} {smoother} n={n} k={k}", flush=True)
+    kap = _kappa(n, sigma)
+    pr = hdg.Problem(n, k, kap)
+    b = pr.rhs(np.ones((n * n, pr.ref.nq ** 2))) if sigma else pr.rhs(pr.f_at_points(SinSin.f))
+    xd = pr.solve_direct(b)
+    S = H.Solver(n, k, kap, smoother=smoother)
+    x, it, rr, hist = S.solve(dev(b), rtol=1e-10, maxit=300, mode=mode)
+    S.close()
+    assert rr <= 1e-10 and hist[-1] <= 1e-10 * np.linalg.norm(b)
+    assert np.linalg.norm(host(x) - xd) <= 1e-9 * np.linalg.norm(xd)
+
+
+def test_polynomial_solution_end_to_end():
+    """u in Q_k, K constant: the GPU solve reproduces the exact face values."""
+    n, k = 8, 3
+    prob = PolyProblem(k, 2.5)
+    S = H.Solver(n, k, kappa_const(n, 2.5))
+    b = _gpu_rhs(S, n, k, S.nq, prob.f, prob.gD)
+    x, it, rr, hist = S.solve(b, rtol=1e-13, maxit=100)
+    S.close()
+    uex = np.zeros(ms.n_trace_dofs(n, k))
+    for f in range(ms.n_faces(n)):
+        mid, t = ms.face_midpoint_and_direction(n, f)
+        pts = mid[None, :] + np.outer(qd.trace_nodes(k) * 0.5 / n, t)
+        uex[f * (k + 1):(f + 1) * (k + 1)] = prob.u(pts[:, 0], pts[:, 1])
+    assert np.abs(host(x) - uex).max() <= 1e-10 * np.abs(uex).max()
+
+
+def test_solver_reports_not_converged_and_nonfinite():
+    n, k = 16, 2
+    S = H.Solver(n, k, _kappa(n, 1.0))
+    b = dev(normal_vector(S.num_dofs(), 3))
+    x, it, rr, hist = S.solve(b, rtol=1e-14, maxit=2, raise_on_fail=False)
+    assert it == 2 and rr > 1e-14
+    with pytest.raises(H.HDGError) as ei:
+        S.solve(b, rtol=1e-14, maxit=2)
+    assert ei.value.status == -4
+    bad = b.clone()
+    bad[5] = float("nan")
+    with pytest.raises(H.HDGError) as ei:
+        S.solve(bad, rtol=1e-10, maxit=5)
+    assert ei.value.status == -5
+    S.close()
+
+
+def _oracle_face_rows(n, k, kap, faces, x):
+    """(S x)_f for the sampled faces from the two elements' oracle blocks."""
+    P = k + 1
+    ref_cache = {}
+    out = []
+    for f in faces:
+        lo, hi, o = ms.face_elements(n, f)
+        llo, lhi = ms.face_local_index(n, f)
+        y = np.zeros(P)
+        for e, lf in ((lo, llo), (hi, lhi)):
+            if e not in ref_cache:
+                ref_cache[e] = hdg.condensed_block(*hdg.local_matrices(
+                    hdg.RefOps(k), 1.0 / n, 1.0, np.full((k + 2) ** 2, 1.0 / kap[e])), 1.0)
+            K = ref_cache[e]
+            i, j = e % n, e // n
+            for g, gf in enumerate(ms.element_faces(n, i, j)):
+                if gf >= 0:
+                    y += K[lf * P:(lf + 1) * P, g * P:(g + 1) * P] @ x[gf * P:(gf + 1) * P]
+        out.append(y)
+    return np.concatenate(out)
+
+
+@pytest.mark.parametrize("name,n,k,sigma,seed", [("lognormal_n256_k4", 256, 4, 1.0, 2),
+                                                  ("lognormal_n1024_k3", 1024, 3, 2.0, 3)])
+def test_full_size_apply_sampled(name, n, k, sigma, seed):
+    """Full-size workloads in the benchmark's launch configuration: sampled faces
+    (first, last, boundary-adjacent, ragged tail, random) against the oracle rows."""
+    print(f"case full-size apply {name}", flush=True)
+    kap = kappa_lognormal(n, sigma, seed)
+    S = H.Solver(n, k, kap, smoother="chain")
+    try:
+        N = S.num_dofs()
+        x = normal_vector(N, 21)
+        y = host(S.apply(k, dev(x)))
+        nf = ms.n_faces(n)
+        nv = n * (n - 1)
+        rng = np.random.default_rng(5)
+        faces = sorted(set([0, 1, n - 2, nv - 1, nv, nv + n - 1, nf - 1, nf - 2, nf - 64, (nf // 64) * 64 - 1]
+                           + list(rng.integers(0, nf, 120))))
+        yo = _oracle_face_rows(n, k, kap, faces, x)
+        yg = np.concatenate([y[f * (k + 1):(f + 1) * (k + 1)] for f in faces])
+        assert rel_inf(yg, yo) <= 1e-12
+        # property at any size: S is symmetric, <S x, z> = <x, S z>
+        z = normal_vector(N, 22)
+        sz = host(S.apply(k, dev(z)))
+        assert abs(y @ z - x @ sz) <= 1e-12 * np.linalg.norm(y) * np.linalg.norm(z)
+        # constants on interior faces: (S 1)_f = 0 for faces whose elements touch no boundary
+        one = host(S.apply(k, torch.ones(N, dtype=torch.float64, device="cuda")))
+        f_int = nv // 2 + n // 2
+        assert np.abs(one[f_int * (k + 1):(f_int + 1) * (k + 1)]).max() < 1e-10 * np.abs(y).max()
+    finally:
+        S.close()
