@@ -1,0 +1,177 @@
+"""Benchmark: matrix-free HDG trace apply (trace-DoF/s) and GMG solve time to 1e-10.
+
+Workload (default): lognormal_n256_k4 -- 256 x 256 squares, HDG degree k = 4,
+tau = 1, K_e = exp(z_e), z ~ N(0, 1) (seed 2), f = 1, zero Dirichlet data, FP64.
+One step = one finest-level trace apply y = S x on a cold cache (the Infinity
+Cache is flushed before it) timed with HIP events, followed by one complete
+solve of S Lambda = b to ||b - S Lambda|| <= 1e-10 ||b|| from Lambda = 0
+(conjugate gradients preconditioned by one V(2,2) nested p/h multigrid cycle).
+Inputs are resident in HBM before the timed region.
+
+Prints one JSON line.  `value` is the trace apply throughput N(k) / t_apply.
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "trace-DoF/s of matrix-free HDG apply; GMG solve time to 1e-10 rel. residual"
+HBM_PEAK_GBS = 8000.0
+
+WORKLOADS = {
+    "lognormal_n256_k4": dict(n=256, k=4, sigma=1.0, seed=2),
+    "lognormal_n1024_k3": dict(n=1024, k=3, sigma=2.0, seed=3),
+    "poisson_sin_n16_k1": dict(n=16, k=1, sigma=None, seed=None),
+}
+
+
+def algorithmic_bytes(n, k):
+    """Bytes one apply must move: every nonzero block entry once (the summed
+    diagonal block of each face plus the blocks coupling it to the other interior
+    faces of its two elements), x read once, y written once, FP64."""
+    P = k + 1
+    nf = 2 * n * (n - 1)
+    m = np.full((n, n), 4)
+    m[0, :] -= 1
+    m[-1, :] -= 1
+    m[:, 0] -= 1
+    m[:, -1] -= 1
+    blocks = int((m * m).sum()) - nf
+    return blocks * P * P * 8 + 2 * nf * P * 8, 2 * blocks * P * P
+
+
+def cpu_baseline(sigma, seed, k, budget_s=12.0):
+    """The oracle's assembled-CSR apply (scipy, one thread) on a 64 x 64 sample of the
+    workload (same degree and coefficient law), repeated for about budget_s seconds."""
+    from oracle import hdg
+    from workloads import kappa_lognormal, normal_vector
+    n = 64
+    kap = kappa_lognormal(n, sigma, seed) if sigma else np.ones(n * n)
+    t0 = time.perf_counter()
+    S = hdg.Problem(n, k, kap).assemble()
+    t_setup = time.perf_counter() - t0
+    x = normal_vector(S.shape[0], 1)
+    reps, t0 = 0, time.perf_counter()
+    while time.perf_counter() - t0 < budget_s:
+        S @ x
+        reps += 1
+    dt = (time.perf_counter() - t0) / reps
+    return {"value": S.shape[0] / dt, "unit": "trace-DoF/s", "cores": 1, "kind": "oracle",
+            "sample": f"oracle CSR S@x (scipy, 1 thread), n=64 k={k} sample of the workload, "
+                      f"{reps} reps over {budget_s:.0f}s; oracle assembly of that sample {t_setup:.1f}s"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--workload", default="lognormal_n256_k4", choices=sorted(WORKLOADS))
+    ap.add_argument("--mode", default="pcg", choices=["pcg", "vcycle"])
+    ap.add_argument("--smoother", default="chain", choices=["chain", "face"])
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py: this build measures one GPU only; multi-GPU runs are not part of it "
+              "(the apply would shard by element rows with one halo exchange per apply).", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    import paper_1705_09907_amd as H
+    from workloads import kappa_lognormal, normal_vector
+
+    w = WORKLOADS[args.workload]
+    n, k = w["n"], w["k"]
+    kap = kappa_lognormal(n, w["sigma"], w["seed"]) if w["sigma"] else np.ones(n * n)
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    t0 = time.perf_counter()
+    S = H.Solver(n, k, kap, smoother=args.smoother)
+    torch.cuda.synchronize()
+    setup_s = time.perf_counter() - t0
+    N = S.num_dofs()
+    nq = S.nq
+    t0 = time.perf_counter()
+    b = S.assemble_rhs(np.ones((n * n, nq * nq)))
+    rhs_s = time.perf_counter() - t0
+    x = torch.tensor(normal_vector(N, 7), device=dev)
+    y = torch.empty_like(x)
+    lam = torch.zeros_like(x)
+    flush = torch.empty(1 << 27, dtype=torch.float64, device=dev)  # 1 GiB > Infinity Cache
+    stream = torch.cuda.current_stream()
+
+    def step(record):
+        flush.zero_()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        S.apply(k, x, y)
+        e1.record(stream)
+        lam.zero_()
+        s0, s1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        s0.record(stream)
+        _, it, rr, hist = S.solve(b, lam, rtol=1e-10, maxit=500, mode=args.mode)
+        s1.record(stream)
+        if record is not None:
+            record.append((e0, e1, s0, s1, it, rr, hist))
+
+    for _ in range(args.warmup):
+        step(None)
+    torch.cuda.synchronize()
+    rec = []
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        step(rec)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    apply_ms = np.array([r[0].elapsed_time(r[1]) for r in rec])
+    solve_ms = np.array([r[2].elapsed_time(r[3]) for r in rec])
+    iters = rec[-1][4]
+    relres = rec[-1][5]
+    hist = rec[-1][6]
+    rho = float((hist[-1] / hist[0]) ** (1.0 / max(len(hist) - 1, 1)))
+
+    # warm (back-to-back) applies, for reference
+    for _ in range(3):
+        S.apply(k, x, y)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    for _ in range(20):
+        S.apply(k, x, y)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    warm_ms = e0.elapsed_time(e1) / 20
+
+    t_apply = float(np.mean(apply_ms)) * 1e-3
+    byts, flops = algorithmic_bytes(n, k)
+    achieved = byts / t_apply / 1e9
+    out = {
+        "metric": METRIC, "value": N / t_apply, "unit": "trace-DoF/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": wall / args.steps * 1e3,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": args.workload, "n": n, "k": k, "tau": 1.0,
+                   "kappa": f"lognormal sigma={w['sigma']} seed={w['seed']}" if w["sigma"] else "1",
+                   "f": 1.0, "trace_dofs": N, "solver": f"{args.mode} + V(2,2), {args.smoother} Schwarz",
+                   "rtol": 1e-10},
+        "apply_us_cold": float(np.mean(apply_ms)) * 1e3,
+        "apply_us_warm": warm_ms * 1e3,
+        "solve_ms": float(np.median(solve_ms)), "solve_iters": iters, "solve_relres": relres,
+        "solve_rate": rho, "setup_s": setup_s, "rhs_s": rhs_s,
+        "roofline": {"bound": "hbm", "kernel": f"k_trace<P={k + 1}, APPLY>", "achieved": achieved,
+                     "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
+                     "traffic": None, "algorithmic_bytes": byts, "flops": flops},
+    }
+    S.close()
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(w["sigma"], w["seed"], k)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()
