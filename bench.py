@@ -76,6 +76,9 @@ def main():
     ap.add_argument("--mode", default="pcg", choices=["pcg", "vcycle"])
     ap.add_argument("--smoother", default="chain", choices=["chain", "face"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--warm", action="store_true", help="also time back-to-back (cache-warm) applies")
+    ap.add_argument("--calibrate-copy", action="store_true",
+                    help="run one 256 MiB device copy after the timed region (counter calibration)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py: this build measures one GPU only; multi-GPU runs are not part of it "
@@ -136,16 +139,22 @@ def main():
     hist = rec[-1][6]
     rho = float((hist[-1] / hist[0]) ** (1.0 / max(len(hist) - 1, 1)))
 
-    # warm (back-to-back) applies, for reference
-    for _ in range(3):
-        S.apply(k, x, y)
-    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    e0.record(stream)
-    for _ in range(20):
-        S.apply(k, x, y)
-    e1.record(stream)
-    torch.cuda.synchronize()
-    warm_ms = e0.elapsed_time(e1) / 20
+    warm_ms = None
+    if args.warm:  # back-to-back applies (blocks may stay in the Infinity Cache)
+        for _ in range(3):
+            S.apply(k, x, y)
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        for _ in range(20):
+            S.apply(k, x, y)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        warm_ms = e0.elapsed_time(e1) / 20
+    if args.calibrate_copy:
+        src = torch.ones(1 << 25, dtype=torch.float64, device=dev)
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
 
     t_apply = float(np.mean(apply_ms)) * 1e-3
     byts, flops = algorithmic_bytes(n, k)
@@ -160,7 +169,7 @@ def main():
                    "f": 1.0, "trace_dofs": N, "solver": f"{args.mode} + V(2,2), {args.smoother} Schwarz",
                    "rtol": 1e-10},
         "apply_us_cold": float(np.mean(apply_ms)) * 1e3,
-        "apply_us_warm": warm_ms * 1e3,
+        "apply_us_warm": None if warm_ms is None else warm_ms * 1e3,
         "solve_ms": float(np.median(solve_ms)), "solve_iters": iters, "solve_relres": relres,
         "solve_rate": rho, "setup_s": setup_s, "rhs_s": rhs_s,
         "roofline": {"bound": "hbm", "kernel": f"k_trace<P={k + 1}, APPLY>", "achieved": achieved,

@@ -23,7 +23,8 @@ struct PLevel {
   int64_t N = 0;
   double* slab = nullptr;
   double* dinv = nullptr;                                         // facet Schwarz
-  double *clmul = nullptr, *cdtinv = nullptr, *cupper = nullptr;  // chain Schwarz
+  double* chain = nullptr;                                        // chain Schwarz factors
+  int64_t cstride = 0;
   double* pmat = nullptr;                                         // P_p (p >= 1)
   double omega = 0.8;
   double *x = nullptr, *b = nullptr, *r = nullptr, *t = nullptr;
@@ -195,56 +196,95 @@ void build_face_data(hdg_ctx* h, PLevel& L, const Vec& blocks) {
     L.dinv = upload(h, dinv);
     return;
   }
-  // chain Schwarz: block-tridiagonal LU of every chain of faces (no pivoting;
-  // the chain matrices are SPD principal submatrices of S).
-  const int64_t nch = 2LL * n, m = n - 1, nv = (int64_t)n * (n - 1);
-  Vec lmul((size_t)m * P2 * nch, 0.0), dtinv((size_t)m * P2 * nch, 0.0), upper((size_t)m * P2 * nch, 0.0);
+  // chain Schwarz: block cyclic reduction factors of every chain of faces
+  // (the chain matrices are SPD principal submatrices of S, so every pivot
+  // block met by the reduction is SPD).
+  const int64_t nch = 2LL * n, nv = (int64_t)n * (n - 1);
+  const int m = n - 1;
+  std::vector<int> msz;
+  for (int ml = m;; ml = (ml + 1) / 2) {
+    msz.push_back(ml);
+    if (ml == 1) break;
+  }
+  int64_t nrec = 0;
+  for (int s : msz) nrec += s;
+  const int64_t R3 = 3LL * P2;
+  L.cstride = nrec * R3;
+  Vec fac((size_t)(nch * L.cstride), 0.0);
+  auto mul = [P](const double* X, const double* Y, double* Z) {  // Z = X Y
+    for (int a = 0; a < P; ++a)
+      for (int b = 0; b < P; ++b) {
+        double s = 0.0;
+        for (int q = 0; q < P; ++q) s += X[a * P + q] * Y[q * P + b];
+        Z[a * P + b] = s;
+      }
+  };
   hdg::parallel_for(nch, [&](int64_t c0, int64_t c1) {
-    Vec Dt(P2), Dprev_inv(P2), Lm(P2), Up(P2), Uprev(P2), tmp(P2);
+    Vec T(P2);
     for (int64_t c = c0; c < c1; ++c) {
       const bool vert = c < n;
       const int64_t base = vert ? c * (n - 1) : nv + (c - n);
       const int64_t stride = vert ? 1 : n;
-      const int sub = vert ? 1 : 3, sup = vert ? 4 : 6;   // slots coupling to previous / next in chain
-      for (int64_t i = 0; i < m; ++i) {
+      const int sub = vert ? 1 : 3, sup = vert ? 4 : 6;  // slots coupling to previous / next face
+      Vec A((size_t)m * P2, 0.0), D((size_t)m * P2), C((size_t)m * P2, 0.0);
+      for (int i = 0; i < m; ++i) {
         const int64_t f = base + stride * i;
         for (int e = 0; e < P2; ++e) {
-          Dt[e] = diag[(size_t)f * P2 + e];
-          Up[e] = (i + 1 < m) ? slab[tp_index(f, sup * P2 + e, NE)] : 0.0;
+          D[(size_t)i * P2 + e] = diag[(size_t)f * P2 + e];
+          if (i >= 1) A[(size_t)i * P2 + e] = slab[tp_index(f, sub * P2 + e, NE)];
+          if (i + 1 < m) C[(size_t)i * P2 + e] = slab[tp_index(f, sup * P2 + e, NE)];
         }
-        if (i > 0) {
-          // L_i = A_{i,i-1} Dt_{i-1}^{-1};  Dt_i = A_ii - L_i A_{i-1,i}
-          for (int a = 0; a < P; ++a)
-            for (int b2 = 0; b2 < P; ++b2) {
-              double s = 0.0;
-              for (int q = 0; q < P; ++q) s += slab[tp_index(f, sub * P2 + a * P + q, NE)] * Dprev_inv[q * P + b2];
-              Lm[a * P + b2] = s;
-            }
-          for (int a = 0; a < P; ++a)
-            for (int b2 = 0; b2 < P; ++b2) {
-              double s = 0.0;
-              for (int q = 0; q < P; ++q) s += Lm[a * P + q] * Uprev[q * P + b2];
-              Dt[a * P + b2] -= s;
-            }
-        } else {
-          std::fill(Lm.begin(), Lm.end(), 0.0);
+      }
+      double* rec = fac.data() + (size_t)c * L.cstride;
+      int64_t off = 0;
+      for (int ml : msz) {
+        if (ml == 1) {
+          Vec Di(D.begin(), D.begin() + P2);
+          if (!hdg::cholesky_inverse(P, Di)) throw std::runtime_error("chain pivot block not SPD");
+          std::copy(Di.begin(), Di.end(), rec + off * R3);
+          break;
         }
-        Vec Dinv(Dt);
-        if (!hdg::cholesky_inverse(P, Dinv)) throw std::runtime_error("chain pivot block not SPD");
-        for (int e = 0; e < P2; ++e) {
-          const size_t idx = ((size_t)i * P2 + e) * nch + c;
-          lmul[idx] = Lm[e];
-          dtinv[idx] = Dinv[e];
-          upper[idx] = Up[e];
+        Vec Dinv((size_t)ml * P2, 0.0);
+        for (int j = 1; j < ml; j += 2) {
+          Vec Di(D.begin() + (size_t)j * P2, D.begin() + (size_t)(j + 1) * P2);
+          if (!hdg::cholesky_inverse(P, Di)) throw std::runtime_error("chain pivot block not SPD");
+          std::copy(Di.begin(), Di.end(), Dinv.begin() + (size_t)j * P2);
+          double* r = rec + (off + j) * R3;
+          std::copy(Di.begin(), Di.end(), r);
+          std::copy(A.begin() + (size_t)j * P2, A.begin() + (size_t)(j + 1) * P2, r + P2);
+          std::copy(C.begin() + (size_t)j * P2, C.begin() + (size_t)(j + 1) * P2, r + 2 * P2);
         }
-        Dprev_inv = Dinv;
-        Uprev = Up;
+        const int mn = (ml + 1) / 2;
+        Vec An((size_t)mn * P2, 0.0), Dn((size_t)mn * P2), Cn((size_t)mn * P2, 0.0);
+        for (int j = 0; j < ml; j += 2) {
+          double* r = rec + (off + j) * R3;
+          double* Mm = r;
+          double* Mp = r + P2;
+          double* Dj = Dn.data() + (size_t)(j / 2) * P2;
+          std::copy(D.begin() + (size_t)j * P2, D.begin() + (size_t)(j + 1) * P2, Dj);
+          if (j >= 1) {
+            mul(A.data() + (size_t)j * P2, Dinv.data() + (size_t)(j - 1) * P2, Mm);
+            mul(Mm, C.data() + (size_t)(j - 1) * P2, T.data());
+            for (int e = 0; e < P2; ++e) Dj[e] -= T[e];
+            mul(Mm, A.data() + (size_t)(j - 1) * P2, T.data());
+            for (int e = 0; e < P2; ++e) An[(size_t)(j / 2) * P2 + e] = -T[e];
+          }
+          if (j + 1 < ml) {
+            mul(C.data() + (size_t)j * P2, Dinv.data() + (size_t)(j + 1) * P2, Mp);
+            mul(Mp, A.data() + (size_t)(j + 1) * P2, T.data());
+            for (int e = 0; e < P2; ++e) Dj[e] -= T[e];
+            mul(Mp, C.data() + (size_t)(j + 1) * P2, T.data());
+            for (int e = 0; e < P2; ++e) Cn[(size_t)(j / 2) * P2 + e] = -T[e];
+          }
+        }
+        A.swap(An);
+        D.swap(Dn);
+        C.swap(Cn);
+        off += ml;
       }
     }
   });
-  L.clmul = upload(h, lmul);
-  L.cdtinv = upload(h, dtinv);
-  L.cupper = upload(h, upper);
+  L.chain = upload(h, fac);
 }
 
 // Q1 stencil of P_J^T S0 P_J from the p = 0 element blocks (4 x 4).
@@ -390,13 +430,10 @@ void smooth(hdg_ctx* h, int p, const double* b, double* x, int nu, bool zero) {
       }
     } else {
       hdg::ChainArgs c{};
-      c.lmul = L.clmul;
-      c.dtinv = L.cdtinv;
-      c.upper = L.cupper;
+      c.factors = L.chain;
+      c.cstride = L.cstride;
       c.omega = L.omega;
       c.n = h->n;
-      c.nf = h->nf;
-      c.work = L.t;
       c.out = x;
       if (z) {
         c.r = b;
@@ -539,6 +576,8 @@ void validate_config(const hdg_config_t* c) {
   if (c->coarse_max < 1) throw ArgError("coarse_max must be >= 1");
   if (c->nq < 1 || c->nq > 32) throw ArgError("nq must be in [1, 32]");
   if ((int64_t)c->n * c->n > (int64_t)1 << 31) throw ArgError("n too large");
+  if (c->smoother == HDG_SMOOTH_CHAIN && (int64_t)(c->n - 1) * (c->k + 1) * 8 > 65536)
+    throw ArgError("chain smoother keeps one chain in LDS: needs (n-1)(k+1)*8 <= 65536 bytes; use the face smoother");
 }
 
 }  // namespace
@@ -885,8 +924,12 @@ hdg_status_t hdg_solve(hdg_handle_t h, const double* b, double* x, double rtol, 
       hipchk(hdg::launch_copy(h->vz, h->vd, N, h->stream), "copy");
       double rz = dot(h, h->vr, h->vz, N);
       while (rn > tol && it < maxit) {
-        apply(h, k, h->vd, h->vq);
-        const double dq = dot(h, h->vd, h->vq, N);
+        hdg::TraceArgs ta = targs(h, h->pl[k]);
+        ta.x = h->vd;
+        ta.y = h->vq;
+        ta.partial = h->partial;
+        hipchk(hdg::launch_trace(h->pl[k].P, hdg::TM_APPLY_DOT, ta, h->stream), "apply dot");
+        const double dq = reduce_scalar(h, hdg::trace_grid(h->ntiles));
         const double alpha = rz / dq;
         hipchk(hdg::launch_axpy(alpha, h->vd, x, N, h->stream), "axpy");
         hipchk(hdg::launch_axpy_norm(alpha, h->vq, h->vr, N, h->partial, h->stream), "axpy norm");

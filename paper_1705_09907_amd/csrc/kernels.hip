@@ -90,16 +90,18 @@ __global__ __launch_bounds__(kWG) void k_trace(TraceArgs a) {
 #pragma unroll
     for (int q = 0; q < NQ; ++q) {
       const dbl2 w = __builtin_nontemporal_load(sp + q * 64);
-      constexpr int dummy = 0;
-      (void)dummy;
       const int e0 = 2 * q, e1 = 2 * q + 1;
       acc[(e0 % P2) / P] += w.x * xv[e0 / P2][e0 % P];
       if (e1 < NE) acc[(e1 % P2) / P] += w.y * xv[e1 / P2][e1 % P];
     }
     if (valid) {
-      if constexpr (MODE == TM_APPLY) {
+      if constexpr (MODE == TM_APPLY || MODE == TM_APPLY_DOT) {
 #pragma unroll
         for (int r = 0; r < P; ++r) a.y[f * P + r] = acc[r];
+        if constexpr (MODE == TM_APPLY_DOT) {
+#pragma unroll
+          for (int r = 0; r < P; ++r) sq += xv[0][r] * acc[r];
+        }
       } else {
         double res[P];
 #pragma unroll
@@ -149,6 +151,7 @@ static hipError_t launch_trace_p(int mode, const TraceArgs& a, hipStream_t s) {
   const dim3 grid(trace_grid(a.ntiles)), block(kWG);
   switch (mode) {
     case TM_APPLY: hipLaunchKernelGGL((k_trace<P, TM_APPLY>), grid, block, 0, s, a); break;
+    case TM_APPLY_DOT: hipLaunchKernelGGL((k_trace<P, TM_APPLY_DOT>), grid, block, 0, s, a); break;
     case TM_RESID: hipLaunchKernelGGL((k_trace<P, TM_RESID>), grid, block, 0, s, a); break;
     case TM_FACE_SWEEP: hipLaunchKernelGGL((k_trace<P, TM_FACE_SWEEP>), grid, block, 0, s, a); break;
     case TM_RESID_RESTRICT:
@@ -276,76 +279,127 @@ hipError_t launch_p_prolong_add(int P, const double* pm, const double* ec, doubl
 }
 
 // ------------------------------------------------------------ chain Schwarz
-// One lane per chain (2n chains: vertical faces of element row c, then
-// horizontal faces of element column c - n).  Factors are stored
-// [position][P*P][chain] so that a wavefront reads contiguous memory at every
-// step of the block-tridiagonal forward / backward sweeps.
+// Exact solve with the block-tridiagonal matrix of every chain of faces (2n
+// chains: vertical faces of element row c, then horizontal faces of element
+// column c - n), by block cyclic reduction with factors precomputed at setup.
+// One workgroup per chain; the right-hand side lives in LDS and is reduced in
+// place: at level l the positions i = j 2^l with j even absorb their odd
+// neighbours, r_j -= M-_j r_{j-1} + M+_j r_{j+1}; after the single remaining
+// block is inverted, the odd positions are recovered top-down,
+// x_j = Dinv_j (r_j - A_j x_{j-1} - C_j x_{j+1}).  Every phase reads only
+// positions that the phase does not write, so a barrier between phases is
+// the only synchronisation.  Factor record of (level l, position j): 3 P^2
+// doubles at chain * cstride + (levoff[l] + j) * 3 P^2; even j: [M-, M+],
+// odd j: [Dinv, A, C]; the last level holds Dinv of its single block.
 template <int P>
-__global__ __launch_bounds__(64) void k_chain(ChainArgs a) {
+__global__ __launch_bounds__(256) void k_chain(ChainArgs a) {
   constexpr int P2 = P * P;
-  const int64_t nch = 2LL * a.n;
-  const int64_t c = (int64_t)blockIdx.x * 64 + threadIdx.x;
-  if (c >= nch) return;
+  extern __shared__ double R[];
+  const int64_t c = blockIdx.x;
   const int m = a.n - 1;
   const int64_t nv = (int64_t)a.n * (a.n - 1);
   const bool vert = c < a.n;
   const int64_t base = vert ? c * (a.n - 1) : nv + (c - a.n);
   const int64_t stride = vert ? 1 : a.n;
-  double y[P];
-#pragma unroll
-  for (int r = 0; r < P; ++r) y[r] = 0.0;
-  // forward: y_i = r_i - L_i y_{i-1}
-  for (int i = 0; i < m; ++i) {
-    const int64_t f = base + stride * i;
-    const double* L = a.lmul + ((int64_t)i * P2) * nch + c;
-    double yn[P];
-#pragma unroll
-    for (int r = 0; r < P; ++r) {
-      double s = a.r[f * P + r];
-#pragma unroll
-      for (int q = 0; q < P; ++q) s -= L[(r * P + q) * nch] * y[q];
-      yn[r] = s;
-    }
-#pragma unroll
-    for (int r = 0; r < P; ++r) { y[r] = yn[r]; a.work[f * P + r] = yn[r]; }
+  const double* F = a.factors + c * a.cstride;
+  for (int idx = threadIdx.x; idx < m * P; idx += blockDim.x) {
+    const int i = idx / P, r = idx - i * P;
+    R[idx] = a.r[(base + stride * i) * P + r];
   }
-  // backward: x_i = Dt_i^{-1} (y_i - U_i x_{i+1})
-  double xn[P];
+  __syncthreads();
+  int ml = m, lev = 0;
+  int64_t off = 0;  // record offset of the current level
+  while (ml > 1) {
+    for (int t = threadIdx.x; 2 * t < ml; t += blockDim.x) {
+      const int j = 2 * t;
+      const int i = j << lev;
+      const double* M = F + (off + j) * 3 * P2;
+      double v[P];
 #pragma unroll
-  for (int r = 0; r < P; ++r) xn[r] = 0.0;
-  for (int i = m - 1; i >= 0; --i) {
-    const int64_t f = base + stride * i;
-    const double* U = a.upper + ((int64_t)i * P2) * nch + c;
-    const double* Dt = a.dtinv + ((int64_t)i * P2) * nch + c;
-    double t[P];
+      for (int r = 0; r < P; ++r) v[r] = R[i * P + r];
+      if (j >= 1) {
+        const int il = (j - 1) << lev;
 #pragma unroll
-    for (int r = 0; r < P; ++r) {
-      double s = a.work[f * P + r];
+        for (int r = 0; r < P; ++r)
 #pragma unroll
-      for (int q = 0; q < P; ++q) s -= U[(r * P + q) * nch] * xn[q];
-      t[r] = s;
+          for (int q = 0; q < P; ++q) v[r] -= M[r * P + q] * R[il * P + q];
+      }
+      if (j + 1 < ml) {
+        const int ir = (j + 1) << lev;
+#pragma unroll
+        for (int r = 0; r < P; ++r)
+#pragma unroll
+          for (int q = 0; q < P; ++q) v[r] -= M[P2 + r * P + q] * R[ir * P + q];
+      }
+#pragma unroll
+      for (int r = 0; r < P; ++r) R[i * P + r] = v[r];
     }
-    double xi[P];
+    __syncthreads();
+    off += ml;
+    ml = (ml + 1) / 2;
+    ++lev;
+  }
+  if (threadIdx.x == 0) {
+    const double* Dv = F + off * 3 * P2;
+    double v[P];
 #pragma unroll
     for (int r = 0; r < P; ++r) {
       double s = 0.0;
 #pragma unroll
-      for (int q = 0; q < P; ++q) s += Dt[(r * P + q) * nch] * t[q];
-      xi[r] = s;
+      for (int q = 0; q < P; ++q) s += Dv[r * P + q] * R[q];
+      v[r] = s;
     }
 #pragma unroll
-    for (int r = 0; r < P; ++r) {
-      xn[r] = xi[r];
-      const double base_x = a.x ? a.x[f * P + r] : 0.0;
-      a.out[f * P + r] = base_x + a.omega * xi[r];
+    for (int r = 0; r < P; ++r) R[r] = v[r];
+  }
+  __syncthreads();
+  while (lev > 0) {
+    --lev;
+    ml = (m + (1 << lev) - 1) >> lev;   // size of level lev
+    off -= ml;
+    for (int t = threadIdx.x; 2 * t + 1 < ml; t += blockDim.x) {
+      const int j = 2 * t + 1;
+      const int i = j << lev;
+      const double* M = F + (off + j) * 3 * P2;
+      double u[P];
+#pragma unroll
+      for (int r = 0; r < P; ++r) u[r] = R[i * P + r];
+      const int il = (j - 1) << lev;
+#pragma unroll
+      for (int r = 0; r < P; ++r)
+#pragma unroll
+        for (int q = 0; q < P; ++q) u[r] -= M[P2 + r * P + q] * R[il * P + q];
+      if (j + 1 < ml) {
+        const int ir = (j + 1) << lev;
+#pragma unroll
+        for (int r = 0; r < P; ++r)
+#pragma unroll
+          for (int q = 0; q < P; ++q) u[r] -= M[2 * P2 + r * P + q] * R[ir * P + q];
+      }
+      double x[P];
+#pragma unroll
+      for (int r = 0; r < P; ++r) {
+        double s = 0.0;
+#pragma unroll
+        for (int q = 0; q < P; ++q) s += M[r * P + q] * u[q];
+        x[r] = s;
+      }
+#pragma unroll
+      for (int r = 0; r < P; ++r) R[i * P + r] = x[r];
     }
+    __syncthreads();
+  }
+  for (int idx = threadIdx.x; idx < m * P; idx += blockDim.x) {
+    const int i = idx / P, r = idx - i * P;
+    const int64_t g = (base + stride * i) * P + r;
+    a.out[g] = (a.x ? a.x[g] : 0.0) + a.omega * R[idx];
   }
 }
 
 hipError_t launch_chain_solve(int P, const ChainArgs& a, hipStream_t s) {
   const int64_t nch = 2LL * a.n;
-  const dim3 grid((unsigned)((nch + 63) / 64)), block(64);
-  HDG_DISPATCH_P(P, hipLaunchKernelGGL((k_chain<PP>), grid, block, 0, s, a));
+  const size_t lds = (size_t)(a.n - 1) * P * sizeof(double);
+  HDG_DISPATCH_P(P, hipLaunchKernelGGL((k_chain<PP>), dim3((unsigned)nch), dim3(256), lds, s, a));
   return hipGetLastError();
 }
 

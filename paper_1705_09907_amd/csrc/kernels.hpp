@@ -12,7 +12,8 @@ enum TraceMode : int {
   TM_APPLY = 0,          // y = S x
   TM_RESID = 1,          // y = b - S x
   TM_FACE_SWEEP = 2,     // y = x + omega Dinv (b - S x)        (facet Schwarz sweep)
-  TM_RESID_RESTRICT = 3  // y = P_p^T (b - S x)  (coarse vector, p - 1)
+  TM_RESID_RESTRICT = 3, // y = P_p^T (b - S x)  (coarse vector, p - 1)
+  TM_APPLY_DOT = 4       // y = S x and per-workgroup partial sums of x . y
 };
 
 struct TraceArgs {
@@ -21,7 +22,7 @@ struct TraceArgs {
   const double* b;       // RESID / SWEEP / RESID_RESTRICT
   const double* dinv;    // SWEEP: face-block inverses, tile-pair layout
   double* y;
-  double* partial;       // optional: per-workgroup sum of squares of (b - S x)
+  double* partial;       // optional: per-workgroup sum of squares of (b - S x), or of x . y
   const double* pmat;    // RESID_RESTRICT: P_p [(p+1) x p], row major (device)
   double omega;
   int n;
@@ -41,18 +42,17 @@ hipError_t launch_p_restrict(int P, const double* pmat, const double* rf, double
 hipError_t launch_p_prolong_add(int P, const double* pmat, const double* ec, double* xf, int64_t nf,
                                 hipStream_t s);
 
-// chain (line) Schwarz solve: z = omega M^{-1} r (+ x if x != nullptr), see chain.hip
+// chain Schwarz: out = x + omega M^{-1} r (x == nullptr: out = omega M^{-1} r);
+// M = block-tridiagonal matrix of each chain of faces, solved by block cyclic
+// reduction with the factors of chain_factor_layout (api.cpp).  out may alias x.
 struct ChainArgs {
-  const double* lmul;    // [face][P][P]   L_i (sub-diagonal multipliers), chain order
-  const double* dtinv;   // [face][P][P]   inverse of the eliminated diagonal block
-  const double* upper;   // [face][P][P]   super-diagonal block A_{i,i+1}
+  const double* factors;  // per chain: cstride doubles
+  int64_t cstride;
   const double* r;
-  const double* x;       // added to the result (nullable)
+  const double* x;
   double* out;
-  double* work;          // [N(p)] forward-sweep values
   double omega;
   int n;
-  int64_t nf;
 };
 hipError_t launch_chain_solve(int P, const ChainArgs& a, hipStream_t s);
 
