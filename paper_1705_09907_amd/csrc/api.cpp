@@ -206,10 +206,13 @@ void build_face_data(hdg_ctx* h, PLevel& L, const Vec& blocks) {
     msz.push_back(ml);
     if (ml == 1) break;
   }
-  int64_t nrec = 0;
-  for (int s : msz) nrec += s;
-  const int64_t R3 = 3LL * P2;
-  L.cstride = nrec * R3;
+  std::vector<int64_t> loff;  // per-level offset (doubles) of the factor records
+  int64_t tot = 0;
+  for (int s : msz) {
+    loff.push_back(tot);
+    tot += s == 1 ? (int64_t)P2 : (int64_t)2 * P2 * ((s + 1) / 2) + (int64_t)3 * P2 * (s / 2);
+  }
+  L.cstride = tot;
   Vec fac((size_t)(nch * L.cstride), 0.0);
   auto mul = [P](const double* X, const double* Y, double* Z) {  // Z = X Y
     for (int a = 0; a < P; ++a)
@@ -236,51 +239,63 @@ void build_face_data(hdg_ctx* h, PLevel& L, const Vec& blocks) {
         }
       }
       double* rec = fac.data() + (size_t)c * L.cstride;
-      int64_t off = 0;
-      for (int ml : msz) {
+      for (size_t lv = 0; lv < msz.size(); ++lv) {
+        const int ml = msz[lv];
+        double* lvl = rec + loff[lv];
         if (ml == 1) {
           Vec Di(D.begin(), D.begin() + P2);
           if (!hdg::cholesky_inverse(P, Di)) throw std::runtime_error("chain pivot block not SPD");
-          std::copy(Di.begin(), Di.end(), rec + off * R3);
+          std::copy(Di.begin(), Di.end(), lvl);
           break;
         }
+        const int ne = (ml + 1) / 2, no = ml / 2;
+        double* odd = lvl + (size_t)2 * P2 * ne;
         Vec Dinv((size_t)ml * P2, 0.0);
         for (int j = 1; j < ml; j += 2) {
           Vec Di(D.begin() + (size_t)j * P2, D.begin() + (size_t)(j + 1) * P2);
           if (!hdg::cholesky_inverse(P, Di)) throw std::runtime_error("chain pivot block not SPD");
           std::copy(Di.begin(), Di.end(), Dinv.begin() + (size_t)j * P2);
-          double* r = rec + (off + j) * R3;
-          std::copy(Di.begin(), Di.end(), r);
-          std::copy(A.begin() + (size_t)j * P2, A.begin() + (size_t)(j + 1) * P2, r + P2);
-          std::copy(C.begin() + (size_t)j * P2, C.begin() + (size_t)(j + 1) * P2, r + 2 * P2);
+          const int o = j / 2;
+          Vec W(P2), Z(P2);  // Dinv A, Dinv C
+          mul(Di.data(), A.data() + (size_t)j * P2, W.data());
+          mul(Di.data(), C.data() + (size_t)j * P2, Z.data());
+          for (int e = 0; e < P2; ++e) {
+            odd[(size_t)e * no + o] = Di[e];
+            odd[(size_t)(P2 + e) * no + o] = W[e];
+            odd[(size_t)(2 * P2 + e) * no + o] = Z[e];
+          }
         }
         const int mn = (ml + 1) / 2;
         Vec An((size_t)mn * P2, 0.0), Dn((size_t)mn * P2), Cn((size_t)mn * P2, 0.0);
+        Vec Mm(P2), Mp(P2);
         for (int j = 0; j < ml; j += 2) {
-          double* r = rec + (off + j) * R3;
-          double* Mm = r;
-          double* Mp = r + P2;
+          std::fill(Mm.begin(), Mm.end(), 0.0);
+          std::fill(Mp.begin(), Mp.end(), 0.0);
           double* Dj = Dn.data() + (size_t)(j / 2) * P2;
           std::copy(D.begin() + (size_t)j * P2, D.begin() + (size_t)(j + 1) * P2, Dj);
           if (j >= 1) {
-            mul(A.data() + (size_t)j * P2, Dinv.data() + (size_t)(j - 1) * P2, Mm);
-            mul(Mm, C.data() + (size_t)(j - 1) * P2, T.data());
+            mul(A.data() + (size_t)j * P2, Dinv.data() + (size_t)(j - 1) * P2, Mm.data());
+            mul(Mm.data(), C.data() + (size_t)(j - 1) * P2, T.data());
             for (int e = 0; e < P2; ++e) Dj[e] -= T[e];
-            mul(Mm, A.data() + (size_t)(j - 1) * P2, T.data());
+            mul(Mm.data(), A.data() + (size_t)(j - 1) * P2, T.data());
             for (int e = 0; e < P2; ++e) An[(size_t)(j / 2) * P2 + e] = -T[e];
           }
           if (j + 1 < ml) {
-            mul(C.data() + (size_t)j * P2, Dinv.data() + (size_t)(j + 1) * P2, Mp);
-            mul(Mp, A.data() + (size_t)(j + 1) * P2, T.data());
+            mul(C.data() + (size_t)j * P2, Dinv.data() + (size_t)(j + 1) * P2, Mp.data());
+            mul(Mp.data(), A.data() + (size_t)(j + 1) * P2, T.data());
             for (int e = 0; e < P2; ++e) Dj[e] -= T[e];
-            mul(Mp, C.data() + (size_t)(j + 1) * P2, T.data());
+            mul(Mp.data(), C.data() + (size_t)(j + 1) * P2, T.data());
             for (int e = 0; e < P2; ++e) Cn[(size_t)(j / 2) * P2 + e] = -T[e];
+          }
+          const int ev = j / 2;
+          for (int e = 0; e < P2; ++e) {
+            lvl[(size_t)e * ne + ev] = Mm[e];
+            lvl[(size_t)(P2 + e) * ne + ev] = Mp[e];
           }
         }
         A.swap(An);
         D.swap(Dn);
         C.swap(Cn);
-        off += ml;
       }
     }
   });
@@ -409,7 +424,7 @@ void residual(hdg_ctx* h, int p, const double* b, const double* x, double* r, bo
 
 double residual_norm(hdg_ctx* h, int p, const double* b, const double* x, double* r) {
   residual(h, p, b, x, r, true);
-  return std::sqrt(reduce_scalar(h, hdg::trace_grid(h->ntiles)));
+  return std::sqrt(reduce_scalar(h, hdg::trace_partials(h->ntiles)));
 }
 
 // nu sweeps of the level-p Schwarz smoother on x (in place); zero: x == 0 on entry
@@ -659,7 +674,7 @@ hdg_status_t hdg_create(const hdg_config_t* cfg, const double* kappa_host, void*
       if (p == 0) build_hlevels(h.get(), blocks);
     }
     const int64_t Nk = h->pl[h->k].N;
-    h->npartial = std::max(hdg::trace_grid(h->ntiles), 1024);
+    h->npartial = std::max(hdg::trace_partials(h->ntiles), 1024);
     h->partial = dalloc(h.get(), h->npartial);
     h->scal = dalloc(h.get(), 1);
     hipchk(hipHostMalloc((void**)&h->scal_h, sizeof(double), hipHostMallocDefault), "pinned");
@@ -929,7 +944,7 @@ hdg_status_t hdg_solve(hdg_handle_t h, const double* b, double* x, double rtol, 
         ta.y = h->vq;
         ta.partial = h->partial;
         hipchk(hdg::launch_trace(h->pl[k].P, hdg::TM_APPLY_DOT, ta, h->stream), "apply dot");
-        const double dq = reduce_scalar(h, hdg::trace_grid(h->ntiles));
+        const double dq = reduce_scalar(h, hdg::trace_partials(h->ntiles));
         const double alpha = rz / dq;
         hipchk(hdg::launch_axpy(alpha, h->vd, x, N, h->stream), "axpy");
         hipchk(hdg::launch_axpy_norm(alpha, h->vq, h->vr, N, h->partial, h->stream), "axpy norm");

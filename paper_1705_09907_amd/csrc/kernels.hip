@@ -6,9 +6,10 @@
 // a tile-interleaved layout so that every 16-byte load of a wavefront reads
 // 1 KiB of contiguous memory; the 7 (p+1) neighbour trace values are gathered
 // from x (L2 / MALL resident).  Each face writes only its own outputs: no
-// atomics, no barriers, no coloring.  Workgroups are remapped so that each of
-// the 8 XCDs walks a contiguous range of tiles (its L2 then holds the x values
-// its faces share).
+// atomics, no barriers, no coloring.  Consecutive workgroups take consecutive
+// tiles: the hardware deals them round-robin to the 8 XCDs, so all XCDs stream
+// neighbouring regions of the block array at any time (measured faster than
+// giving each XCD its own contiguous range, which favours x reuse in its L2).
 #include <hip/hip_runtime.h>
 
 #include "kernels.hpp"
@@ -54,11 +55,8 @@ __device__ __forceinline__ double block_sum(double v) {
   return s;
 }
 
-int trace_grid(int64_t ntiles) {
-  int64_t g = (ntiles + 3) / 4;
-  g = (g + 7) / 8 * 8;
-  return (int)g;
-}
+int trace_grid(int64_t ntiles) { return (int)((ntiles + 3) / 4); }
+int trace_partials(int64_t ntiles) { return 4 * trace_grid(ntiles); }
 
 template <int P, int MODE>
 __global__ __launch_bounds__(kWG) void k_trace(TraceArgs a) {
@@ -68,9 +66,7 @@ __global__ __launch_bounds__(kWG) void k_trace(TraceArgs a) {
   constexpr int NQD = (P2 + 1) / 2;
   const int lane = threadIdx.x & 63;
   const int wave = threadIdx.x >> 6;
-  const int per = gridDim.x >> 3;
-  const int lbid = (blockIdx.x & 7) * per + (blockIdx.x >> 3);  // XCD-contiguous ranges
-  const int64_t tile = (int64_t)lbid * (kWG / 64) + wave;
+  const int64_t tile = (int64_t)blockIdx.x * (kWG / 64) + wave;
   const int64_t nv = (int64_t)a.n * (a.n - 1);
   double sq = 0.0;
   if (tile < a.ntiles) {
@@ -140,9 +136,9 @@ __global__ __launch_bounds__(kWG) void k_trace(TraceArgs a) {
       }
     }
   }
-  if (a.partial != nullptr) {
-    const double s = block_sum(sq);
-    if (threadIdx.x == 0) a.partial[blockIdx.x] = s;
+  if (a.partial != nullptr) {  // per-wavefront partial, fixed shuffle tree, no barrier
+    for (int off = 32; off >= 1; off >>= 1) sq += __shfl_xor(sq, off, 64);
+    if (lane == 0) a.partial[(int64_t)blockIdx.x * (kWG / 64) + wave] = sq;
   }
 }
 
@@ -283,16 +279,19 @@ hipError_t launch_p_prolong_add(int P, const double* pm, const double* ec, doubl
 // chains: vertical faces of element row c, then horizontal faces of element
 // column c - n), by block cyclic reduction with factors precomputed at setup.
 // One workgroup per chain; the right-hand side lives in LDS and is reduced in
-// place: at level l the positions i = j 2^l with j even absorb their odd
-// neighbours, r_j -= M-_j r_{j-1} + M+_j r_{j+1}; after the single remaining
-// block is inverted, the odd positions are recovered top-down,
-// x_j = Dinv_j (r_j - A_j x_{j-1} - C_j x_{j+1}).  Every phase reads only
-// positions that the phase does not write, so a barrier between phases is
-// the only synchronisation.  Factor record of (level l, position j): 3 P^2
-// doubles at chain * cstride + (levoff[l] + j) * 3 P^2; even j: [M-, M+],
-// odd j: [Dinv, A, C]; the last level holds Dinv of its single block.
+// place.  Level l keeps the positions i = j 2^l with j even:
+//   forward   r_j <- r_j - M-_j r_{j-1} - M+_j r_{j+1}           (j even)
+//   last      x_0 = Dinv r_0
+//   backward  x_j = Dinv_j r_j - W_j x_{j-1} - Z_j x_{j+1}        (j odd)
+// with W = Dinv A, Z = Dinv C.  One thread per (position, row): it streams one
+// row of the position's blocks, so registers stay at a few times P for every
+// degree.  Factors of a level of size ml: the even records [M-, M+] as 2 P^2
+// arrays over the ne = ceil(ml/2) even positions, then the odd records
+// [Dinv, W, Z] as 3 P^2 arrays over the no = floor(ml/2) odd positions
+// (entry-major, so a wavefront reads consecutive addresses); the last level
+// stores Dinv of its single block.
 template <int P>
-__global__ __launch_bounds__(256) void k_chain(ChainArgs a) {
+__global__ __launch_bounds__(1024) void k_chain(ChainArgs a) {
   constexpr int P2 = P * P;
   extern __shared__ double R[];
   const int64_t c = blockIdx.x;
@@ -302,94 +301,110 @@ __global__ __launch_bounds__(256) void k_chain(ChainArgs a) {
   const int64_t base = vert ? c * (a.n - 1) : nv + (c - a.n);
   const int64_t stride = vert ? 1 : a.n;
   const double* F = a.factors + c * a.cstride;
-  for (int idx = threadIdx.x; idx < m * P; idx += blockDim.x) {
+  const int t = threadIdx.x;
+  const int nt = blockDim.x;
+  for (int idx = t; idx < m * P; idx += nt) {
     const int i = idx / P, r = idx - i * P;
     R[idx] = a.r[(base + stride * i) * P + r];
   }
-  __syncthreads();
   int ml = m, lev = 0;
-  int64_t off = 0;  // record offset of the current level
-  while (ml > 1) {
-    for (int t = threadIdx.x; 2 * t < ml; t += blockDim.x) {
-      const int j = 2 * t;
-      const int i = j << lev;
-      const double* M = F + (off + j) * 3 * P2;
-      double v[P];
+  int64_t off = 0;
+  // factor row of this thread's first item of the coming phase, loaded before the
+  // barrier that precedes the phase (factors do not depend on the data)
+  double pm[P], pp[P];
+  auto prefetch_fwd = [&](int mlv, int64_t offv) {
+    const int ne = (mlv + 1) >> 1;
+    if (mlv > 1 && t < ne * P) {
+      const int r = t / ne, tt = t - r * ne;
+      const double* E = F + offv;
 #pragma unroll
-      for (int r = 0; r < P; ++r) v[r] = R[i * P + r];
+      for (int q = 0; q < P; ++q) {
+        pm[q] = E[(int64_t)(r * P + q) * ne + tt];
+        pp[q] = E[(int64_t)(P2 + r * P + q) * ne + tt];
+      }
+    }
+  };
+  prefetch_fwd(ml, off);
+  __syncthreads();
+  while (ml > 1) {
+    const int ne = (ml + 1) >> 1;
+    const double* E = F + off;
+    for (int it = t; it < ne * P; it += nt) {
+      const int r = it / ne, tt = it - r * ne;
+      const int j = 2 * tt;
+      const int i = j << lev;
+      if (it != t) {
+#pragma unroll
+        for (int q = 0; q < P; ++q) {
+          pm[q] = E[(int64_t)(r * P + q) * ne + tt];
+          pp[q] = E[(int64_t)(P2 + r * P + q) * ne + tt];
+        }
+      }
+      double v = R[i * P + r];
       if (j >= 1) {
         const int il = (j - 1) << lev;
 #pragma unroll
-        for (int r = 0; r < P; ++r)
-#pragma unroll
-          for (int q = 0; q < P; ++q) v[r] -= M[r * P + q] * R[il * P + q];
+        for (int q = 0; q < P; ++q) v -= pm[q] * R[il * P + q];
       }
       if (j + 1 < ml) {
         const int ir = (j + 1) << lev;
 #pragma unroll
-        for (int r = 0; r < P; ++r)
-#pragma unroll
-          for (int q = 0; q < P; ++q) v[r] -= M[P2 + r * P + q] * R[ir * P + q];
+        for (int q = 0; q < P; ++q) v -= pp[q] * R[ir * P + q];
       }
-#pragma unroll
-      for (int r = 0; r < P; ++r) R[i * P + r] = v[r];
+      R[i * P + r] = v;
     }
-    __syncthreads();
-    off += ml;
-    ml = (ml + 1) / 2;
+    off += (int64_t)2 * P2 * ne + (int64_t)3 * P2 * (ml >> 1);
+    ml = ne;
     ++lev;
+    prefetch_fwd(ml, off);
+    __syncthreads();
   }
-  if (threadIdx.x == 0) {
-    const double* Dv = F + off * 3 * P2;
-    double v[P];
+  double xr = 0.0;
+  if (t < P) {
 #pragma unroll
-    for (int r = 0; r < P; ++r) {
-      double s = 0.0;
-#pragma unroll
-      for (int q = 0; q < P; ++q) s += Dv[r * P + q] * R[q];
-      v[r] = s;
-    }
-#pragma unroll
-    for (int r = 0; r < P; ++r) R[r] = v[r];
+    for (int q = 0; q < P; ++q) xr += F[off + t * P + q] * R[q];
   }
+  __syncthreads();
+  if (t < P) R[t] = xr;
   __syncthreads();
   while (lev > 0) {
     --lev;
-    ml = (m + (1 << lev) - 1) >> lev;   // size of level lev
-    off -= ml;
-    for (int t = threadIdx.x; 2 * t + 1 < ml; t += blockDim.x) {
-      const int j = 2 * t + 1;
+    ml = (m + (1 << lev) - 1) >> lev;
+    const int ne = (ml + 1) >> 1, no = ml >> 1;
+    int64_t lo = 0;  // offset of level lev: record sizes of the levels below it
+    for (int l = 0, s = m; l < lev; ++l, s = (s + 1) >> 1)
+      lo += (int64_t)2 * P2 * ((s + 1) >> 1) + (int64_t)3 * P2 * (s >> 1);
+    const double* O = F + lo + (int64_t)2 * P2 * ne;
+    // one pass computes every (position, row) value into registers; a thread
+    // handles at most ceil(no P / blockDim) of them, bounded below by kMaxItems
+    constexpr int kMaxItems = 8;
+    double res[kMaxItems];
+    int cnt = 0;
+    for (int it = t; it < no * P && cnt < kMaxItems; it += nt, ++cnt) {
+      const int r = it / no, tt = it - r * no;
+      const int j = 2 * tt + 1;
       const int i = j << lev;
-      const double* M = F + (off + j) * 3 * P2;
-      double u[P];
-#pragma unroll
-      for (int r = 0; r < P; ++r) u[r] = R[i * P + r];
       const int il = (j - 1) << lev;
+      double s = 0.0;
 #pragma unroll
-      for (int r = 0; r < P; ++r)
-#pragma unroll
-        for (int q = 0; q < P; ++q) u[r] -= M[P2 + r * P + q] * R[il * P + q];
+      for (int q = 0; q < P; ++q)
+        s += O[(int64_t)(r * P + q) * no + tt] * R[i * P + q] - O[(int64_t)(P2 + r * P + q) * no + tt] * R[il * P + q];
       if (j + 1 < ml) {
         const int ir = (j + 1) << lev;
 #pragma unroll
-        for (int r = 0; r < P; ++r)
-#pragma unroll
-          for (int q = 0; q < P; ++q) u[r] -= M[2 * P2 + r * P + q] * R[ir * P + q];
+        for (int q = 0; q < P; ++q) s -= O[(int64_t)(2 * P2 + r * P + q) * no + tt] * R[ir * P + q];
       }
-      double x[P];
-#pragma unroll
-      for (int r = 0; r < P; ++r) {
-        double s = 0.0;
-#pragma unroll
-        for (int q = 0; q < P; ++q) s += M[r * P + q] * u[q];
-        x[r] = s;
-      }
-#pragma unroll
-      for (int r = 0; r < P; ++r) R[i * P + r] = x[r];
+      res[cnt] = s;
+    }
+    __syncthreads();
+    cnt = 0;
+    for (int it = t; it < no * P && cnt < kMaxItems; it += nt, ++cnt) {
+      const int r = it / no, tt = it - r * no;
+      R[((2 * tt + 1) << lev) * P + r] = res[cnt];
     }
     __syncthreads();
   }
-  for (int idx = threadIdx.x; idx < m * P; idx += blockDim.x) {
+  for (int idx = t; idx < m * P; idx += nt) {
     const int i = idx / P, r = idx - i * P;
     const int64_t g = (base + stride * i) * P + r;
     a.out[g] = (a.x ? a.x[g] : 0.0) + a.omega * R[idx];
@@ -399,7 +414,12 @@ __global__ __launch_bounds__(256) void k_chain(ChainArgs a) {
 hipError_t launch_chain_solve(int P, const ChainArgs& a, hipStream_t s) {
   const int64_t nch = 2LL * a.n;
   const size_t lds = (size_t)(a.n - 1) * P * sizeof(double);
-  HDG_DISPATCH_P(P, hipLaunchKernelGGL((k_chain<PP>), dim3((unsigned)nch), dim3(256), lds, s, a));
+  // the back-substitution keeps at most 8 (position, row) items per thread
+  const int64_t items = (int64_t)((a.n - 1) / 2) * P;
+  int threads = 256;
+  while (threads < 1024 && items > (int64_t)threads * 8) threads *= 2;
+  if (items > (int64_t)threads * 8) return hipErrorInvalidValue;
+  HDG_DISPATCH_P(P, hipLaunchKernelGGL((k_chain<PP>), dim3((unsigned)nch), dim3(threads), lds, s, a));
   return hipGetLastError();
 }
 

@@ -22,7 +22,7 @@ struct TraceArgs {
   const double* b;       // RESID / SWEEP / RESID_RESTRICT
   const double* dinv;    // SWEEP: face-block inverses, tile-pair layout
   double* y;
-  double* partial;       // optional: per-workgroup sum of squares of (b - S x), or of x . y
+  double* partial;       // optional: per-wavefront sum of squares of (b - S x), or of x . y
   const double* pmat;    // RESID_RESTRICT: P_p [(p+1) x p], row major (device)
   double omega;
   int n;
@@ -30,7 +30,8 @@ struct TraceArgs {
   int64_t ntiles;        // ceil(nf / 64)
 };
 
-int trace_grid(int64_t ntiles);   // workgroups of a trace launch (multiple of 8)
+int trace_grid(int64_t ntiles);      // workgroups of a trace launch
+int trace_partials(int64_t ntiles);  // partial sums written when TraceArgs::partial is set (one per wavefront)
 hipError_t launch_trace(int P, int mode, const TraceArgs& a, hipStream_t s);
 
 // x = omega Dinv b (first facet sweep from a zero guess)
