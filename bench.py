@@ -8,6 +8,11 @@ solve of S Lambda = b to ||b - S Lambda|| <= 1e-10 ||b|| from Lambda = 0
 (conjugate gradients preconditioned by one V(2,2) nested p/h multigrid cycle).
 Inputs are resident in HBM before the timed region.
 
+With --precision f32 / bf16 the multigrid cycle runs in that precision (FP32
+vectors and accumulation, blocks FP32 or bfloat16) under the FP64 outer solver;
+the timed apply is then the reduced-precision one, and the plain FP64 solve of the
+same system is timed after the timed region for comparison.
+
 Prints one JSON line.  `value` is the trace apply throughput N(k) / t_apply.
 """
 import argparse
@@ -31,10 +36,15 @@ WORKLOADS = {
 }
 
 
-def algorithmic_bytes(n, k):
+MAT_BYTES = {"f64": 8, "f32": 4, "bf16": 4}  # the finest level keeps FP32 blocks in the bf16 cycle
+VEC_BYTES = {"f64": 8, "f32": 4, "bf16": 4}
+
+
+def algorithmic_bytes(n, k, prec="f64"):
     """Bytes one apply must move: every nonzero block entry once (the summed
     diagonal block of each face plus the blocks coupling it to the other interior
-    faces of its two elements), x read once, y written once, FP64."""
+    faces of its two elements), x read once, y written once, in the storage
+    precision of blocks and vectors."""
     P = k + 1
     nf = 2 * n * (n - 1)
     m = np.full((n, n), 4)
@@ -43,7 +53,7 @@ def algorithmic_bytes(n, k):
     m[:, 0] -= 1
     m[:, -1] -= 1
     blocks = int((m * m).sum()) - nf
-    return blocks * P * P * 8 + 2 * nf * P * 8, 2 * blocks * P * P
+    return blocks * P * P * MAT_BYTES[prec] + 2 * nf * P * VEC_BYTES[prec], 2 * blocks * P * P
 
 
 def cpu_baseline(sigma, seed, k, budget_s=12.0):
@@ -75,6 +85,8 @@ def main():
     ap.add_argument("--workload", default="lognormal_n256_k4", choices=sorted(WORKLOADS))
     ap.add_argument("--mode", default="pcg", choices=["pcg", "vcycle"])
     ap.add_argument("--smoother", default="chain", choices=["chain", "face"])
+    ap.add_argument("--precision", default="f64", choices=["f64", "f32", "bf16"],
+                    help="precision of the multigrid cycle and of the timed apply")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--warm", action="store_true", help="also time back-to-back (cache-warm) applies")
     ap.add_argument("--calibrate-copy", action="store_true",
@@ -95,7 +107,8 @@ def main():
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
     t0 = time.perf_counter()
-    S = H.Solver(n, k, kap, smoother=args.smoother)
+    lp = args.precision != "f64"
+    S = H.Solver(n, k, kap, smoother=args.smoother, precision=args.precision)
     torch.cuda.synchronize()
     setup_s = time.perf_counter() - t0
     N = S.num_dofs()
@@ -104,8 +117,11 @@ def main():
     b = S.assemble_rhs(np.ones((n * n, nq * nq)))
     rhs_s = time.perf_counter() - t0
     x = torch.tensor(normal_vector(N, 7), device=dev)
+    if lp:
+        x = x.float()
     y = torch.empty_like(x)
-    lam = torch.zeros_like(x)
+    lam = torch.zeros(N, dtype=torch.float64, device=dev)
+    apply = (lambda: S.apply_lp(k, x, y)) if lp else (lambda: S.apply(k, x, y))
     flush = torch.empty(1 << 27, dtype=torch.float64, device=dev)  # 1 GiB > Infinity Cache
     stream = torch.cuda.current_stream()
 
@@ -113,7 +129,7 @@ def main():
         flush.zero_()
         e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
         e0.record(stream)
-        S.apply(k, x, y)
+        apply()
         e1.record(stream)
         lam.zero_()
         s0, s1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
@@ -142,11 +158,11 @@ def main():
     warm_ms = None
     if args.warm:  # back-to-back applies (blocks may stay in the Infinity Cache)
         for _ in range(3):
-            S.apply(k, x, y)
+            apply()
         e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
         e0.record(stream)
         for _ in range(20):
-            S.apply(k, x, y)
+            apply()
         e1.record(stream)
         torch.cuda.synchronize()
         warm_ms = e0.elapsed_time(e1) / 20
@@ -156,27 +172,57 @@ def main():
         dst.copy_(src)
         torch.cuda.synchronize()
 
+    f64_ref = None
+    if lp:  # the plain FP64 path on the same system, same accuracy, after the timed region
+        S.close()
+        S64 = H.Solver(n, k, kap, smoother=args.smoother)
+        x64 = x.double()
+        y64 = torch.empty_like(x64)
+        at, st_ms = [], []
+        for rep in range(3):
+            flush.zero_()
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record(stream)
+            S64.apply(k, x64, y64)
+            e1.record(stream)
+            lam.zero_()
+            s0, s1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            s0.record(stream)
+            _, it64, rr64, _ = S64.solve(b, lam, rtol=1e-10, maxit=500, mode=args.mode)
+            s1.record(stream)
+            torch.cuda.synchronize()
+            if rep:
+                at.append(e0.elapsed_time(e1))
+                st_ms.append(s0.elapsed_time(s1))
+        f64_ref = {"apply_us_cold": float(np.mean(at)) * 1e3, "solve_ms": float(np.median(st_ms)),
+                   "solve_iters": it64, "solve_relres": rr64}
+        S64.close()
+
     t_apply = float(np.mean(apply_ms)) * 1e-3
-    byts, flops = algorithmic_bytes(n, k)
+    byts, flops = algorithmic_bytes(n, k, args.precision)
     achieved = byts / t_apply / 1e9
     out = {
         "metric": METRIC, "value": N / t_apply, "unit": "trace-DoF/s", "n_gpus": 1,
         "steps": args.steps, "warmup": args.warmup, "ms_per_step": wall / args.steps * 1e3,
-        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64",
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f64" if not lp else f"{args.precision} blocks, f32 vectors and accumulation; f64 outer solve",
         "data": "synthetic",
         "config": {"workload": args.workload, "n": n, "k": k, "tau": 1.0,
                    "kappa": f"lognormal sigma={w['sigma']} seed={w['seed']}" if w["sigma"] else "1",
-                   "f": 1.0, "trace_dofs": N, "solver": f"{args.mode} + V(2,2), {args.smoother} Schwarz",
+                   "f": 1.0, "trace_dofs": N,
+                   "solver": f"{args.mode} + V(2,2), {args.smoother} Schwarz, {args.precision} cycle",
                    "rtol": 1e-10},
         "apply_us_cold": float(np.mean(apply_ms)) * 1e3,
         "apply_us_warm": None if warm_ms is None else warm_ms * 1e3,
         "solve_ms": float(np.median(solve_ms)), "solve_iters": iters, "solve_relres": relres,
         "solve_rate": rho, "setup_s": setup_s, "rhs_s": rhs_s,
-        "roofline": {"bound": "hbm", "kernel": f"k_trace<P={k + 1}, APPLY>", "achieved": achieved,
+        "f64_reference": f64_ref,
+        "roofline": {"bound": "hbm", "kernel": f"k_trace<P={k + 1}, APPLY, {args.precision}>", "achieved": achieved,
                      "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
                      "traffic": None, "algorithmic_bytes": byts, "flops": flops},
     }
-    S.close()
+    if not lp:
+        S.close()
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(w["sigma"], w["seed"], k)
     print(json.dumps(out), flush=True)

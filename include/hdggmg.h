@@ -52,6 +52,18 @@ typedef enum {
 enum { HDG_SMOOTH_CHAIN = 0, HDG_SMOOTH_FACE = 1 };
 enum { HDG_COARSE_GALERKIN = 0, HDG_COARSE_REDISCRETIZE = 1 };
 enum { HDG_SOLVE_PCG = 0, HDG_SOLVE_VCYCLE = 1 };
+/* Precision of the multigrid cycle (the preconditioner).  The outer solver, its
+ * residuals and the finest-level operator it applies stay FP64 in every mode.
+ *   HDG_PREC_F64:  every level, vector and block in FP64 (the paper's setting).
+ *   HDG_PREC_F32:  cycle vectors, blocks, smoother factors and Q1 stencils FP32.
+ *   HDG_PREC_BF16: as F32, but on the coarse p-levels (p < k) the face blocks of
+ *                  the trace operator (and the facet inverses) are stored as
+ *                  bfloat16 (round to nearest even) and widened to FP32 in
+ *                  registers; arithmetic stays FP32.  The finest level keeps FP32
+ *                  blocks: its residuals of smooth corrections cancel below
+ *                  bfloat16 resolution and the preconditioner then fails.
+ * The coarsest Q1 inverse is FP64 in every mode. */
+enum { HDG_PREC_F64 = 0, HDG_PREC_F32 = 1, HDG_PREC_BF16 = 2 };
 
 #define HDG_MAX_DEGREE 8
 #define HDG_MAX_HLEVELS 24
@@ -75,7 +87,9 @@ typedef struct {
                                        <= 0: estimated with Lanczos at setup              */
   int32_t coarse_max;   /* coarsest Q1 level: first with <= coarse_max unknowns (default 2000) */
   int32_t nq;           /* Gauss-Legendre points per direction of f input (default k + 2) */
-  int32_t reserved[8];
+  int32_t precision;    /* HDG_PREC_F64 (default), HDG_PREC_F32 or HDG_PREC_BF16; reduced
+                           precision with the facet smoother needs every omega[p] > 0     */
+  int32_t reserved[7];
 } hdg_config_t;
 
 /* Defaults: tau 1, V(2,2), chain smoother, Galerkin p-levels, omega/lmax estimated,
@@ -133,15 +147,24 @@ hdg_status_t hdg_assemble_rhs(hdg_handle_t h, const double* f_qp_host, const dou
 
 /* y = S_p x, the assembly-free trace operator of Sec. 8 (Alg. algo_mv): every
  * interior face gathers the blocks of its two elements.  x, y: device [N(p)],
- * must not alias. */
+ * must not alias.  With a reduced-precision cycle only p = k is kept in FP64:
+ * p < k returns STATE. */
 hdg_status_t hdg_apply_trace_operator(hdg_handle_t h, int32_t p, const double* x, double* y);
 
+/* The same product in the cycle precision of a handle created with
+ * HDG_PREC_F32 or HDG_PREC_BF16: FP32 vectors, blocks in FP32 or bfloat16,
+ * FP32 accumulation.  x, y: device float [N(p)], must not alias.  Returns
+ * STATE for an FP64 handle. */
+hdg_status_t hdg_apply_trace_operator_lp(hdg_handle_t h, int32_t p, const float* x, float* y);
+
 /* r = b - S_p x; if norm2_host != NULL, *norm2_host = ||r||_2 (synchronizes;
- * deterministic reduction order).  r must not alias x. */
+ * deterministic reduction order).  r must not alias x.  Same level rule as
+ * hdg_apply_trace_operator. */
 hdg_status_t hdg_residual(hdg_handle_t h, int32_t p, const double* b, const double* x, double* r,
                           double* norm2_host);
 
-/* sweeps of the level-p Schwarz smoother x <- x + omega M^{-1} (b - S_p x) in place. */
+/* sweeps of the level-p Schwarz smoother x <- x + omega M^{-1} (b - S_p x) in place
+ * (in the cycle precision; b and x are FP64 in every mode). */
 hdg_status_t hdg_smooth(hdg_handle_t h, int32_t p, const double* b, double* x, int32_t sweeps);
 
 /* p-transfers (eqs. eq_mg_res / eq_mg_pro), face local, 1 <= p_fine <= k:
@@ -149,7 +172,8 @@ hdg_status_t hdg_smooth(hdg_handle_t h, int32_t p, const double* b, double* x, i
 hdg_status_t hdg_restrict(hdg_handle_t h, int32_t p_fine, const double* r_fine, double* r_coarse);
 hdg_status_t hdg_prolong(hdg_handle_t h, int32_t p_fine, const double* e_coarse, double* x_fine);
 
-/* One V(nu1, nu2) cycle for S_k x = b starting from x (in place). */
+/* One V(nu1, nu2) cycle for S_k x = b starting from x (in place), run in the
+ * cycle precision; b and x are FP64 in every mode. */
 hdg_status_t hdg_vcycle(hdg_handle_t h, const double* b, double* x);
 
 /* Solve S_k x = b to ||b - S x||_2 <= rtol ||b||_2, x in: initial guess, out:

@@ -18,6 +18,7 @@ HDG_MAX_HLEVELS = 24
 SMOOTHERS = {"chain": 0, "face": 1}
 COARSE = {"galerkin": 0, "rediscretize": 1}
 MODES = {"pcg": 0, "vcycle": 1}
+PRECISIONS = {"f64": 0, "f32": 1, "bf16": 2}
 STATUS = {0: "ok", -1: "invalid argument", -2: "out of memory", -3: "HIP error",
           -4: "not converged", -5: "non-finite value", -6: "invalid state"}
 
@@ -30,7 +31,7 @@ class Config(ctypes.Structure):
                 ("cheb_lo", ctypes.c_double), ("cheb_hi", ctypes.c_double),
                 ("cheb_lmax", ctypes.c_double * HDG_MAX_HLEVELS),
                 ("coarse_max", ctypes.c_int32), ("nq", ctypes.c_int32),
-                ("reserved", ctypes.c_int32 * 8)]
+                ("precision", ctypes.c_int32), ("reserved", ctypes.c_int32 * 7)]
 
 
 _P = ctypes.c_void_p
@@ -52,6 +53,7 @@ SIGNATURES = {
     "hdg_quadrature_nodes": [_I32, _PD],
     "hdg_assemble_rhs": [_P, _PD, _PD, _P],
     "hdg_apply_trace_operator": [_P, _I32, _P, _P],
+    "hdg_apply_trace_operator_lp": [_P, _I32, _P, _P],
     "hdg_residual": [_P, _I32, _P, _P, _P, _PD],
     "hdg_smooth": [_P, _I32, _P, _P, _I32],
     "hdg_restrict": [_P, _I32, _P, _P],
@@ -85,10 +87,11 @@ class HDGError(RuntimeError):
         self.status = status
 
 
-def _dptr(t, name, numel=None):
+def _dptr(t, name, numel=None, dtype="float64"):
     import torch
-    if not isinstance(t, torch.Tensor) or not t.is_cuda or t.dtype != torch.float64 or not t.is_contiguous():
-        raise TypeError(f"{name} must be a contiguous float64 CUDA tensor")
+    if (not isinstance(t, torch.Tensor) or not t.is_cuda or t.dtype != getattr(torch, dtype)
+            or not t.is_contiguous()):
+        raise TypeError(f"{name} must be a contiguous {dtype} CUDA tensor")
     if numel is not None and t.numel() != numel:
         raise ValueError(f"{name} has {t.numel()} entries, expected {numel}")
     return ctypes.c_void_p(t.data_ptr())
@@ -122,7 +125,8 @@ class Solver:
     """Handle over hdg_create: one n x n mesh, degree k, per-element kappa."""
 
     def __init__(self, n, k, kappa, tau=1.0, nu1=2, nu2=2, smoother="chain", coarse="galerkin",
-                 omega=None, cheb_lmax=None, cheb=(0.1, 1.1), coarse_max=2000, nq=None, stream=None):
+                 omega=None, cheb_lmax=None, cheb=(0.1, 1.1), coarse_max=2000, nq=None, stream=None,
+                 precision="f64"):
         import torch
         cfg = Config()
         lib.hdg_config_default(n, k, ctypes.byref(cfg))
@@ -139,7 +143,8 @@ class Solver:
         cfg.coarse_max = coarse_max
         if nq is not None:
             cfg.nq = nq
-        self.n, self.k, self.nq = n, k, cfg.nq
+        cfg.precision = PRECISIONS[precision]
+        self.n, self.k, self.nq, self.precision = n, k, cfg.nq, precision
         kap, kp = _host(kappa, "kappa", n * n)
         if stream is None:
             stream = torch.cuda.current_stream()
@@ -211,6 +216,15 @@ class Solver:
         N = self.num_dofs(p)
         y = self._empty(p) if y is None else y
         self._check(lib.hdg_apply_trace_operator(self._h, p, _dptr(x, "x", N), _dptr(y, "y", N)))
+        return y
+
+    def apply_lp(self, p, x, y=None):
+        """y = S_p x in the cycle precision (float32 tensors) of an f32 / bf16 handle."""
+        import torch
+        N = self.num_dofs(p)
+        y = torch.empty(N, dtype=torch.float32, device="cuda") if y is None else y
+        self._check(lib.hdg_apply_trace_operator_lp(self._h, p, _dptr(x, "x", N, "float32"),
+                                                    _dptr(y, "y", N, "float32")))
         return y
 
     def residual(self, p, b, x, r=None, norm=False):

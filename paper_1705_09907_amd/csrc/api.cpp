@@ -18,27 +18,34 @@ using hdg::Vec;
 
 namespace {
 
+// Device data of a p-level.  `slab`, `dinv` (matrix precision `mp`), `chain`,
+// `pmat` and the work vectors (vector precision) belong to the cycle; `slab64`
+// holds FP64 blocks where the FP64 operator is kept (every level in FP64 mode,
+// the finest level otherwise; it aliases `slab` in FP64 mode).
 struct PLevel {
   int p = 0, P = 1;
   int64_t N = 0;
-  double* slab = nullptr;
-  double* dinv = nullptr;                                         // facet Schwarz
-  double* chain = nullptr;                                        // chain Schwarz factors
+  hdg::Prec mp = hdg::Prec::F64;  // storage precision of slab / dinv in the cycle
+  void* slab = nullptr;
+  double* slab64 = nullptr;
+  void* dinv = nullptr;                                           // facet Schwarz
+  void* chain = nullptr;                                          // chain Schwarz factors
   int64_t cstride = 0;
-  double* pmat = nullptr;                                         // P_p (p >= 1)
+  void* pmat = nullptr;                                           // P_p (p >= 1)
+  double* pmat64 = nullptr;
   double omega = 0.8;
-  double *x = nullptr, *b = nullptr, *r = nullptr, *t = nullptr;
+  void *x = nullptr, *b = nullptr, *r = nullptr, *t = nullptr;
 };
 
 struct QLevel {
   int m = 0;
   int64_t Nv = 0;
   bool coarsest = false;
-  double* st = nullptr;
-  double* dinv = nullptr;
-  double* inv = nullptr;
+  void* st = nullptr;
+  void* dinv = nullptr;
+  double* inv = nullptr;   // coarsest level: FP64 dense inverse
   double lmax = 0.0;
-  double *x = nullptr, *b = nullptr, *r = nullptr, *d = nullptr, *t = nullptr;
+  void *x = nullptr, *b = nullptr, *r = nullptr, *d = nullptr, *t = nullptr;
 };
 
 }  // namespace
@@ -57,7 +64,9 @@ struct hdg_ctx {
   int npartial = 0;
   double* scal = nullptr;      // device scalar
   double* scal_h = nullptr;    // pinned host scalar
-  double *vr = nullptr, *vz = nullptr, *vd = nullptr, *vq = nullptr;  // solver vectors
+  double *vr = nullptr, *vz = nullptr, *vd = nullptr, *vq = nullptr;  // solver vectors (FP64)
+  void *cva = nullptr, *cvb = nullptr;  // cycle-precision copies of FP64 vectors (size N(k))
+  hdg::Prec prec = hdg::Prec::F64;      // precision of the multigrid cycle
   int nq = 0;
 };
 
@@ -74,22 +83,50 @@ inline void hipchk(hipError_t e, const char* what) {
   if (e != hipSuccess) throw HipError(std::string(what) + ": " + hipGetErrorString(e));
 }
 
-double* dalloc(hdg_ctx* h, int64_t n) {
+void* balloc(hdg_ctx* h, size_t bytes) {
   void* p = nullptr;
-  if (n <= 0) n = 1;
-  if (hipMalloc(&p, (size_t)n * sizeof(double)) != hipSuccess) {
+  if (bytes == 0) bytes = 16;
+  if (hipMalloc(&p, bytes) != hipSuccess) {
     (void)hipGetLastError();
     throw std::bad_alloc();
   }
   h->allocs.push_back(p);
-  return (double*)p;
+  return p;
 }
+double* dalloc(hdg_ctx* h, int64_t n) { return (double*)balloc(h, (size_t)std::max<int64_t>(n, 1) * 8); }
+void* valloc(hdg_ctx* h, int64_t n) { return balloc(h, (size_t)std::max<int64_t>(n, 1) * hdg::vec_bytes(h->prec)); }
 
 double* upload(hdg_ctx* h, const Vec& v) {
   double* d = dalloc(h, (int64_t)v.size());
   hipchk(hipMemcpy(d, v.data(), v.size() * sizeof(double), hipMemcpyHostToDevice), "upload");
   return d;
 }
+
+// bfloat16 of x: round to nearest even on the FP32 bits
+inline uint16_t to_bf16(double x) {
+  float f = (float)x;
+  uint32_t u;
+  std::memcpy(&u, &f, 4);
+  if ((u & 0x7f800000u) != 0x7f800000u) u += 0x7fffu + ((u >> 16) & 1u);
+  return (uint16_t)(u >> 16);
+}
+
+// Upload host FP64 data converted to `bytes_per` = 8 (FP64), 4 (FP32) or 2 (BF16).
+void* upload_as(hdg_ctx* h, const Vec& v, size_t bytes_per) {
+  if (bytes_per == 8) return upload(h, v);
+  void* d = balloc(h, v.size() * bytes_per);
+  if (bytes_per == 4) {
+    std::vector<float> t(v.size());
+    for (size_t i = 0; i < v.size(); ++i) t[i] = (float)v[i];
+    hipchk(hipMemcpy(d, t.data(), t.size() * 4, hipMemcpyHostToDevice), "upload f32");
+  } else {
+    std::vector<uint16_t> t(v.size());
+    for (size_t i = 0; i < v.size(); ++i) t[i] = to_bf16(v[i]);
+    hipchk(hipMemcpy(d, t.data(), t.size() * 2, hipMemcpyHostToDevice), "upload bf16");
+  }
+  return d;
+}
+void* upload_vec(hdg_ctx* h, const Vec& v) { return upload_as(h, v, hdg::vec_bytes(h->prec)); }
 
 template <typename F>
 hdg_status_t guarded(hdg_ctx* h, F&& body) {
@@ -110,11 +147,22 @@ hdg_status_t guarded(hdg_ctx* h, F&& body) {
   }
 }
 
-// Tile-pair layout (setup.hpp) of per-face data with NE entries per face.
-inline int64_t tp_index(int64_t f, int e, int NE) {
-  const int64_t NQ = (NE + 1) / 2;
-  const int64_t tile = f >> 6, lane = f & 63;
-  return ((tile * NQ + (e >> 1)) * 64 + lane) * 2 + (e & 1);
+// Interleaved device layout of per-face data with NE entries per face and V
+// entries per 16-byte load: entry e of face f at ((tile NQ + e/V) 64 + lane) V + e%V,
+// NQ = ceil(NE / V), tile = f / 64, lane = f % 64.  Packs canonical host data
+// fb[f NE + e] (FP64) into that layout and uploads it in the requested precision.
+void* pack_faces(hdg_ctx* h, const Vec& fb, int NE, hdg::Prec pr) {
+  const int V = hdg::mat_lanes16(pr);
+  const int64_t NQ = (NE + V - 1) / V;
+  Vec dev((size_t)(h->ntiles * NQ * 64 * V), 0.0);
+  hdg::parallel_for(h->nf, [&](int64_t f0, int64_t f1) {
+    for (int64_t f = f0; f < f1; ++f) {
+      const int64_t tile = f >> 6, lane = f & 63;
+      for (int e = 0; e < NE; ++e)
+        dev[(size_t)(((tile * NQ + e / V) * 64 + lane) * V + e % V)] = fb[(size_t)f * NE + e];
+    }
+  });
+  return upload_as(h, dev, hdg::mat_bytes(pr));
 }
 
 // ------------------------------------------------------- element blocks, host
@@ -154,11 +202,11 @@ inline double blk(const double* K, int P, int lr, int lc, int a, int c) {
 void build_face_data(hdg_ctx* h, PLevel& L, const Vec& blocks) {
   const int n = h->n, P = L.P, P2 = P * P, F4 = 4 * P, NE = 7 * P2;
   const int64_t nf = h->nf;
-  Vec slab((size_t)hdg::slab_doubles(n, P), 0.0);
+  Vec slab((size_t)nf * NE, 0.0);   // canonical: slab[f NE + e]
   const bool face = h->cfg.smoother == HDG_SMOOTH_FACE;
-  const int NQD = (P2 + 1) / 2;
-  Vec dinv(face ? (size_t)h->ntiles * NQD * 128 : 0, 0.0);
+  Vec dinv(face ? (size_t)nf * P2 : 0, 0.0);
   Vec diag(h->cfg.smoother == HDG_SMOOTH_CHAIN ? (size_t)nf * P2 : 0, 0.0);
+  auto tp_index = [NE](int64_t f, int e, int) { return (size_t)f * NE + e; };
   hdg::parallel_for(nf, [&](int64_t a0, int64_t a1) {
     Vec D(P2);
     for (int64_t f = a0; f < a1; ++f) {
@@ -185,15 +233,21 @@ void build_face_data(hdg_ctx* h, PLevel& L, const Vec& blocks) {
       if (face) {
         Vec Di(D);
         if (!hdg::cholesky_inverse(P, Di)) throw std::runtime_error("face block not SPD");
-        for (int e = 0; e < P2; ++e) dinv[tp_index(f, e, P2)] = Di[e];
+        for (int e = 0; e < P2; ++e) dinv[(size_t)f * P2 + e] = Di[e];
       } else {
         std::copy(D.begin(), D.end(), diag.begin() + (size_t)f * P2);
       }
     }
   });
-  L.slab = upload(h, slab);
+  // bfloat16 storage is used on the coarse p-levels only: the finest level's
+  // residual of a smooth correction cancels far below bfloat16 resolution
+  // (measured: the preconditioner diverges at lognormal sigma = 2), so it keeps FP32.
+  L.mp = (h->prec == hdg::Prec::BF16 && L.p == h->k) ? hdg::Prec::F32 : h->prec;
+  L.slab = pack_faces(h, slab, NE, L.mp);
+  if (h->prec == hdg::Prec::F64) L.slab64 = static_cast<double*>(L.slab);
+  else if (L.p == h->k) L.slab64 = static_cast<double*>(pack_faces(h, slab, NE, hdg::Prec::F64));
   if (face) {
-    L.dinv = upload(h, dinv);
+    L.dinv = pack_faces(h, dinv, P2, L.mp);
     return;
   }
   // chain Schwarz: block cyclic reduction factors of every chain of faces
@@ -299,7 +353,7 @@ void build_face_data(hdg_ctx* h, PLevel& L, const Vec& blocks) {
       }
     }
   });
-  L.chain = upload(h, fac);
+  L.chain = upload_vec(h, fac);
 }
 
 // Q1 stencil of P_J^T S0 P_J from the p = 0 element blocks (4 x 4).
@@ -359,17 +413,17 @@ void build_hlevels(hdg_ctx* h, const Vec& b0) {
         for (int64_t kk = A.ptr[r]; kk < A.ptr[r + 1]; ++kk) dense[(size_t)r * Q.Nv + A.col[kk]] = A.val[kk];
       if (!hdg::cholesky_inverse((int)Q.Nv, dense)) throw std::runtime_error("coarsest Q1 matrix not SPD");
       Q.inv = upload(h, dense);
-      Q.x = dalloc(h, Q.Nv);
-      Q.b = dalloc(h, Q.Nv);
+      Q.x = valloc(h, Q.Nv);
+      Q.b = valloc(h, Q.Nv);
       h->ql.push_back(Q);
       break;
     }
     Vec dinv(Q.Nv);
     for (int64_t v = 0; v < Q.Nv; ++v) dinv[v] = 1.0 / st[(size_t)4 * Q.Nv + v];
     Q.lmax = h->cfg.cheb_lmax[lev] > 0 ? h->cfg.cheb_lmax[lev] : hdg::lanczos_lmax(A, dinv, 30);
-    Q.st = upload(h, st);
-    Q.dinv = upload(h, dinv);
-    for (double** p : {&Q.x, &Q.b, &Q.r, &Q.d, &Q.t}) *p = dalloc(h, Q.Nv);
+    Q.st = upload_vec(h, st);
+    Q.dinv = upload_vec(h, dinv);
+    for (void** p : {&Q.x, &Q.b, &Q.r, &Q.d, &Q.t}) *p = valloc(h, Q.Nv);
     h->ql.push_back(Q);
     const hdg::Csr I = hdg::q1_bilinear(m);
     const hdg::Csr It = hdg::csr_transpose(I);
@@ -393,55 +447,64 @@ double dot(hdg_ctx* h, const double* a, const double* b, int64_t n) {
   return reduce_scalar(h, hdg::reduce_grid(n));
 }
 
-hdg::TraceArgs targs(hdg_ctx* h, const PLevel& L) {
+// Trace-kernel arguments of level L for FP64 (pr == F64) or the cycle precision:
+// the cycle uses the level's own blocks, FP64 in a reduced-precision cycle uses
+// the FP64 copy.  kprec() is the precision the kernel is launched with.
+hdg::TraceArgs targs(hdg_ctx* h, const PLevel& L, hdg::Prec pr) {
   hdg::TraceArgs a{};
-  a.slab = L.slab;
+  const bool cyc = pr != hdg::Prec::F64 || h->prec == hdg::Prec::F64;
+  a.slab = cyc ? L.slab : static_cast<const void*>(L.slab64);
   a.dinv = L.dinv;
-  a.pmat = L.pmat;
+  a.pmat = cyc ? L.pmat : static_cast<const void*>(L.pmat64);
   a.omega = L.omega;
   a.n = h->n;
   a.nf = h->nf;
   a.ntiles = h->ntiles;
+  if (!a.slab) throw std::logic_error("no FP64 operator at this level");
   return a;
 }
 
-void apply(hdg_ctx* h, int p, const double* x, double* y) {
-  hdg::TraceArgs a = targs(h, h->pl[p]);
+hdg::Prec kprec(const PLevel& L, hdg::Prec pr) { return pr == hdg::Prec::F64 ? pr : L.mp; }
+
+void apply(hdg_ctx* h, int p, const void* x, void* y, hdg::Prec pr) {
+  hdg::TraceArgs a = targs(h, h->pl[p], pr);
   a.x = x;
   a.y = y;
-  hipchk(hdg::launch_trace(h->pl[p].P, hdg::TM_APPLY, a, h->stream), "trace apply");
+  hipchk(hdg::launch_trace(kprec(h->pl[p], pr), h->pl[p].P, hdg::TM_APPLY, a, h->stream), "trace apply");
 }
 
 // r = b - S x, optionally the squared norm partials
-void residual(hdg_ctx* h, int p, const double* b, const double* x, double* r, bool norm) {
-  hdg::TraceArgs a = targs(h, h->pl[p]);
+void residual(hdg_ctx* h, int p, const void* b, const void* x, void* r, bool norm, hdg::Prec pr) {
+  hdg::TraceArgs a = targs(h, h->pl[p], pr);
   a.x = x;
   a.b = b;
   a.y = r;
   a.partial = norm ? h->partial : nullptr;
-  hipchk(hdg::launch_trace(h->pl[p].P, hdg::TM_RESID, a, h->stream), "trace residual");
+  hipchk(hdg::launch_trace(kprec(h->pl[p], pr), h->pl[p].P, hdg::TM_RESID, a, h->stream), "trace residual");
 }
 
 double residual_norm(hdg_ctx* h, int p, const double* b, const double* x, double* r) {
-  residual(h, p, b, x, r, true);
+  residual(h, p, b, x, r, true, hdg::Prec::F64);
   return std::sqrt(reduce_scalar(h, hdg::trace_partials(h->ntiles)));
 }
 
-// nu sweeps of the level-p Schwarz smoother on x (in place); zero: x == 0 on entry
-void smooth(hdg_ctx* h, int p, const double* b, double* x, int nu, bool zero) {
+// nu sweeps of the level-p Schwarz smoother on x (in place, cycle precision);
+// zero: x == 0 on entry
+void smooth(hdg_ctx* h, int p, const void* b, void* x, int nu, bool zero) {
   PLevel& L = h->pl[p];
+  const hdg::Prec pr = h->prec;
   for (int s = 0; s < nu; ++s) {
     const bool z = zero && s == 0;
     if (h->cfg.smoother == HDG_SMOOTH_FACE) {
       if (z) {
-        hipchk(hdg::launch_dinv_apply(L.P, L.dinv, b, L.omega, x, h->nf, h->stream), "dinv");
+        hipchk(hdg::launch_dinv_apply(L.mp, L.P, L.dinv, b, L.omega, x, h->nf, h->stream), "dinv");
       } else {
-        hdg::TraceArgs a = targs(h, L);
+        hdg::TraceArgs a = targs(h, L, pr);
         a.x = x;
         a.b = b;
         a.y = L.t;
-        hipchk(hdg::launch_trace(L.P, hdg::TM_FACE_SWEEP, a, h->stream), "face sweep");
-        hipchk(hdg::launch_copy(L.t, x, L.N, h->stream), "copy");
+        hipchk(hdg::launch_trace(L.mp, L.P, hdg::TM_FACE_SWEEP, a, h->stream), "face sweep");
+        hipchk(hdg::launch_copy(pr, L.t, x, L.N, h->stream), "copy");
       }
     } else {
       hdg::ChainArgs c{};
@@ -454,22 +517,22 @@ void smooth(hdg_ctx* h, int p, const double* b, double* x, int nu, bool zero) {
         c.r = b;
         c.x = nullptr;
       } else {
-        residual(h, p, b, x, L.r, false);
+        residual(h, p, b, x, L.r, false, pr);
         c.r = L.r;
         c.x = x;
       }
-      hipchk(hdg::launch_chain_solve(L.P, c, h->stream), "chain solve");
+      hipchk(hdg::launch_chain_solve(pr, L.P, c, h->stream), "chain solve");
     }
   }
 }
 
 // Chebyshev on Q1 level Q; result in Q.x.  zero: initial guess 0.
-void chebyshev(hdg_ctx* h, QLevel& Q, const double* b, int nu, bool zero) {
+void chebyshev(hdg_ctx* h, QLevel& Q, const void* b, int nu, bool zero) {
   const double a = h->cfg.cheb_lo * Q.lmax, c = h->cfg.cheb_hi * Q.lmax;
   const double theta = 0.5 * (c + a), delta = 0.5 * (c - a), sigma = theta / delta;
   double rho = 1.0 / sigma;
-  double* cur = Q.x;
-  double* nxt = Q.t;
+  void* cur = Q.x;
+  void* nxt = Q.t;
   for (int s = 0; s < nu; ++s) {
     double c1, c2;
     if (s == 0) {
@@ -481,77 +544,102 @@ void chebyshev(hdg_ctx* h, QLevel& Q, const double* b, int nu, bool zero) {
       c2 = 2.0 * rn / delta;
       rho = rn;
     }
-    const double* xin = (zero && s == 0) ? nullptr : cur;
-    hipchk(hdg::launch_q1_cheb(Q.st, Q.dinv, b, xin, Q.d, nxt, c1, c2, Q.m, h->stream), "chebyshev");
+    const void* xin = (zero && s == 0) ? nullptr : cur;
+    hipchk(hdg::launch_q1_cheb(h->prec, Q.st, Q.dinv, b, xin, Q.d, nxt, c1, c2, Q.m, h->stream), "chebyshev");
     std::swap(cur, nxt);
   }
-  if (cur != Q.x) hipchk(hdg::launch_copy(cur, Q.x, Q.Nv, h->stream), "copy");
+  if (cur != Q.x) hipchk(hdg::launch_copy(h->prec, cur, Q.x, Q.Nv, h->stream), "copy");
 }
 
 void qcycle(hdg_ctx* h, int l) {
   QLevel& Q = h->ql[l];
+  const hdg::Prec pr = h->prec;
   if (Q.coarsest) {
-    hipchk(hdg::launch_dense_gemv(Q.inv, Q.b, Q.x, (int)Q.Nv, h->stream), "coarse solve");
+    hipchk(hdg::launch_dense_gemv(pr, Q.inv, Q.b, Q.x, (int)Q.Nv, h->stream), "coarse solve");
     return;
   }
   chebyshev(h, Q, Q.b, h->cfg.nu1, true);
-  hipchk(hdg::launch_q1_resid(Q.st, Q.b, Q.x, Q.r, Q.m, h->stream), "q1 resid");
+  hipchk(hdg::launch_q1_resid(pr, Q.st, Q.b, Q.x, Q.r, Q.m, h->stream), "q1 resid");
   QLevel& C = h->ql[l + 1];
-  hipchk(hdg::launch_q1_restrict(Q.r, C.b, Q.m, h->stream), "q1 restrict");
+  hipchk(hdg::launch_q1_restrict(pr, Q.r, C.b, Q.m, h->stream), "q1 restrict");
   qcycle(h, l + 1);
-  hipchk(hdg::launch_q1_prolong_add(C.x, Q.x, Q.m, h->stream), "q1 prolong");
+  hipchk(hdg::launch_q1_prolong_add(pr, C.x, Q.x, Q.m, h->stream), "q1 prolong");
   chebyshev(h, Q, Q.b, h->cfg.nu2, false);
 }
 
-// V-cycle at p-level p for S_p x = b; zero: x == 0 on entry (its content is ignored)
-void pcycle(hdg_ctx* h, int p, const double* b, double* x, bool zero) {
+// V-cycle at p-level p for S_p x = b in the cycle precision; zero: x == 0 on
+// entry (its content is ignored)
+void pcycle(hdg_ctx* h, int p, const void* b, void* x, bool zero) {
   PLevel& L = h->pl[p];
+  const hdg::Prec pr = h->prec;
   smooth(h, p, b, x, h->cfg.nu1, zero);
   if (p >= 1) {
     PLevel& C = h->pl[p - 1];
-    hdg::TraceArgs a = targs(h, L);
+    hdg::TraceArgs a = targs(h, L, pr);
     a.x = x;
     a.b = b;
     a.y = C.b;
-    hipchk(hdg::launch_trace(L.P, hdg::TM_RESID_RESTRICT, a, h->stream), "resid restrict");
+    hipchk(hdg::launch_trace(L.mp, L.P, hdg::TM_RESID_RESTRICT, a, h->stream), "resid restrict");
     pcycle(h, p - 1, C.b, C.x, true);
-    hipchk(hdg::launch_p_prolong_add(L.P, L.pmat, C.x, x, h->nf, h->stream), "p prolong");
+    hipchk(hdg::launch_p_prolong_add(pr, L.P, L.pmat, C.x, x, h->nf, h->stream), "p prolong");
   } else {
-    residual(h, 0, b, x, L.r, false);
+    residual(h, 0, b, x, L.r, false, pr);
     QLevel& Q = h->ql[0];
-    hipchk(hdg::launch_pj_restrict(L.r, Q.b, h->n, h->stream), "pj restrict");
+    hipchk(hdg::launch_pj_restrict(pr, L.r, Q.b, h->n, h->stream), "pj restrict");
     qcycle(h, 0);
-    hipchk(hdg::launch_pj_prolong_add(Q.x, x, h->n, h->stream), "pj prolong");
+    hipchk(hdg::launch_pj_prolong_add(pr, Q.x, x, h->n, h->stream), "pj prolong");
   }
   smooth(h, p, b, x, h->cfg.nu2, false);
+}
+
+// FP64 vector <-> cycle-precision staging buffer (no-op copy-free in FP64 mode)
+const void* stage_in(hdg_ctx* h, const double* v, void* buf, int64_t n) {
+  if (h->prec == hdg::Prec::F64) return v;
+  hipchk(hdg::launch_to_f32(v, static_cast<float*>(buf), n, h->stream), "to f32");
+  return buf;
+}
+void stage_out(hdg_ctx* h, const void* buf, double* v, int64_t n) {
+  if (h->prec == hdg::Prec::F64) return;
+  hipchk(hdg::launch_to_f64(static_cast<const float*>(buf), v, n, h->stream), "to f64");
+}
+
+// One V-cycle preconditioner application z = B r at level k with FP64 vectors.
+void precondition(hdg_ctx* h, const double* r, double* z) {
+  const int64_t N = h->pl[h->k].N;
+  if (h->prec == hdg::Prec::F64) {
+    pcycle(h, h->k, r, z, true);
+    return;
+  }
+  pcycle(h, h->k, stage_in(h, r, h->cva, N), h->cvb, true);
+  stage_out(h, h->cvb, z, N);
 }
 
 // Largest eigenvalue of D^{-1} S_p (facet blocks) by Lanczos in the D inner product.
 double estimate_face_lmax(hdg_ctx* h, int p, int steps) {
   PLevel& L = h->pl[p];
   const int64_t N = L.N;
-  double *v = L.x, *z = L.b, *w = L.r, *vold = L.t;
+  double *v = (double*)L.x, *z = (double*)L.b, *w = (double*)L.r, *vold = (double*)L.t;
   Vec hv(N);
   for (int64_t i = 0; i < N; ++i) hv[i] = 1.0 + 0.25 * std::cos(0.37 * (double)i);
   hipchk(hipMemcpyAsync(v, hv.data(), N * sizeof(double), hipMemcpyHostToDevice, h->stream), "h2d");
   hipchk(hdg::launch_fill(0.0, vold, N, h->stream), "fill");
-  hipchk(hdg::launch_dinv_apply(L.P, L.dinv, v, 1.0, z, h->nf, h->stream), "dinv");
+  hipchk(hdg::launch_dinv_apply(hdg::Prec::F64, L.P, L.dinv, v, 1.0, z, h->nf, h->stream), "dinv");
   double beta = std::sqrt(dot(h, v, z, N));
   hipchk(hdg::launch_xpby(v, 1.0 / beta - 1.0, v, N, h->stream), "scale");  // v <- v / beta
   hipchk(hdg::launch_xpby(z, 1.0 / beta - 1.0, z, N, h->stream), "scale");
   std::vector<double> al, be;
   double bprev = 0.0;
   for (int s = 0; s < steps; ++s) {
-    apply(h, p, z, w);
+    apply(h, p, z, w, hdg::Prec::F64);
     const double alpha = dot(h, w, z, N);
     hipchk(hdg::launch_axpy(-alpha, v, w, N, h->stream), "axpy");
     hipchk(hdg::launch_axpy(-bprev, vold, w, N, h->stream), "axpy");
-    hipchk(hdg::launch_dinv_apply(L.P, L.dinv, w, 1.0, z, h->nf, h->stream), "dinv");
+    hipchk(hdg::launch_dinv_apply(hdg::Prec::F64, L.P, L.dinv, w, 1.0, z, h->nf, h->stream), "dinv");
     const double bn = std::sqrt(std::max(dot(h, w, z, N), 0.0));
     al.push_back(alpha);
     if (bn < 1e-14 * std::fabs(alpha)) break;
     be.push_back(bn);
-    hipchk(hdg::launch_copy(v, vold, N, h->stream), "copy");
+    hipchk(hdg::launch_copy(hdg::Prec::F64, v, vold, N, h->stream), "copy");
     hipchk(hdg::launch_fill(0.0, v, N, h->stream), "fill");
     hipchk(hdg::launch_axpy(1.0 / bn, w, v, N, h->stream), "axpy");
     hipchk(hdg::launch_xpby(z, 1.0 / bn - 1.0, z, N, h->stream), "scale");
@@ -591,8 +679,15 @@ void validate_config(const hdg_config_t* c) {
   if (c->coarse_max < 1) throw ArgError("coarse_max must be >= 1");
   if (c->nq < 1 || c->nq > 32) throw ArgError("nq must be in [1, 32]");
   if ((int64_t)c->n * c->n > (int64_t)1 << 31) throw ArgError("n too large");
-  if (c->smoother == HDG_SMOOTH_CHAIN && (int64_t)(c->n - 1) * (c->k + 1) * 8 > 65536)
-    throw ArgError("chain smoother keeps one chain in LDS: needs (n-1)(k+1)*8 <= 65536 bytes; use the face smoother");
+  if (c->precision != HDG_PREC_F64 && c->precision != HDG_PREC_F32 && c->precision != HDG_PREC_BF16)
+    throw ArgError("bad precision");
+  const int64_t vb = c->precision == HDG_PREC_F64 ? 8 : 4;
+  if (c->smoother == HDG_SMOOTH_CHAIN && (int64_t)(c->n - 1) * (c->k + 1) * vb > 65536)
+    throw ArgError("chain smoother keeps one chain in LDS: needs (n-1)(k+1) * (8 bytes FP64, 4 bytes "
+                   "otherwise) <= 65536; use the face smoother or a reduced precision");
+  if (c->smoother == HDG_SMOOTH_FACE && c->precision != HDG_PREC_F64)
+    for (int p = 0; p <= c->k; ++p)
+      if (!(c->omega[p] > 0)) throw ArgError("facet smoother in reduced precision needs omega[p] > 0 for every p");
 }
 
 }  // namespace
@@ -652,6 +747,8 @@ hdg_status_t hdg_create(const hdg_config_t* cfg, const double* kappa_host, void*
     h->k = cfg->k;
     h->nq = cfg->nq;
     h->stream = (hipStream_t)hip_stream;
+    h->prec = cfg->precision == HDG_PREC_F64 ? hdg::Prec::F64
+              : (cfg->precision == HDG_PREC_F32 ? hdg::Prec::F32 : hdg::Prec::BF16);
     const int64_t ne = (int64_t)h->n * h->n;
     h->kappa.assign(kappa_host, kappa_host + ne);
     for (double v : h->kappa)
@@ -668,9 +765,13 @@ hdg_status_t hdg_create(const hdg_config_t* cfg, const double* kappa_host, void*
       if (p == h->k || cfg->coarse == HDG_COARSE_REDISCRETIZE) blocks = blocks_finest(h.get(), p);
       else blocks = blocks_galerkin(h.get(), p + 1, blocks);
       build_face_data(h.get(), L, blocks);
-      if (p >= 1) L.pmat = upload(h.get(), hdg::p_prolongation(p));
+      if (p >= 1) {
+        const Vec Pp = hdg::p_prolongation(p);
+        L.pmat64 = upload(h.get(), Pp);
+        L.pmat = h->prec == hdg::Prec::F64 ? static_cast<void*>(L.pmat64) : upload_vec(h.get(), Pp);
+      }
       L.omega = cfg->omega[p] > 0 ? cfg->omega[p] : 0.8;
-      for (double** q : {&L.x, &L.b, &L.r, &L.t}) *q = dalloc(h.get(), L.N);
+      for (void** q : {&L.x, &L.b, &L.r, &L.t}) *q = valloc(h.get(), L.N);
       if (p == 0) build_hlevels(h.get(), blocks);
     }
     const int64_t Nk = h->pl[h->k].N;
@@ -682,6 +783,10 @@ hdg_status_t hdg_create(const hdg_config_t* cfg, const double* kappa_host, void*
     h->vz = dalloc(h.get(), Nk);
     h->vd = dalloc(h.get(), Nk);
     h->vq = dalloc(h.get(), Nk);
+    if (h->prec != hdg::Prec::F64) {
+      h->cva = valloc(h.get(), Nk);
+      h->cvb = valloc(h.get(), Nk);
+    }
     if (cfg->smoother == HDG_SMOOTH_FACE)
       for (int p = 0; p <= h->k; ++p)
         if (!(cfg->omega[p] > 0)) h->pl[p].omega = 4.0 / (3.0 * estimate_face_lmax(h.get(), p, 30));
@@ -841,10 +946,31 @@ hdg_status_t hdg_assemble_rhs(hdg_handle_t h, const double* f_qp_host, const dou
   });
 }
 
+namespace {
+hdg_status_t need_f64_level(hdg_handle_t h, int p) {
+  if (h->pl[p].slab64) return HDG_OK;
+  h->err = "reduced-precision handle keeps the FP64 operator at p = k only";
+  return HDG_ERR_STATE;
+}
+}  // namespace
+
 hdg_status_t hdg_apply_trace_operator(hdg_handle_t h, int32_t p, const double* x, double* y) {
   if (!h || !x || !y || p < 0 || p > h->k || x == y) return HDG_ERR_INVALID_ARG;
+  if (need_f64_level(h, p) != HDG_OK) return HDG_ERR_STATE;
   return guarded(h, [&]() -> hdg_status_t {
-    apply(h, p, x, y);
+    apply(h, p, x, y, hdg::Prec::F64);
+    return HDG_OK;
+  });
+}
+
+hdg_status_t hdg_apply_trace_operator_lp(hdg_handle_t h, int32_t p, const float* x, float* y) {
+  if (!h || !x || !y || p < 0 || p > h->k || (const void*)x == (const void*)y) return HDG_ERR_INVALID_ARG;
+  if (h->prec == hdg::Prec::F64) {
+    h->err = "handle was created with FP64 cycle precision";
+    return HDG_ERR_STATE;
+  }
+  return guarded(h, [&]() -> hdg_status_t {
+    apply(h, p, x, y, h->prec);
     return HDG_OK;
   });
 }
@@ -852,6 +978,7 @@ hdg_status_t hdg_apply_trace_operator(hdg_handle_t h, int32_t p, const double* x
 hdg_status_t hdg_residual(hdg_handle_t h, int32_t p, const double* b, const double* x, double* r,
                           double* norm2_host) {
   if (!h || !b || !x || !r || p < 0 || p > h->k || r == x) return HDG_ERR_INVALID_ARG;
+  if (need_f64_level(h, p) != HDG_OK) return HDG_ERR_STATE;
   return guarded(h, [&]() -> hdg_status_t {
     if (norm2_host) {
       const double v = residual_norm(h, p, b, x, r);
@@ -861,7 +988,7 @@ hdg_status_t hdg_residual(hdg_handle_t h, int32_t p, const double* b, const doub
         return HDG_ERR_NONFINITE;
       }
     } else {
-      residual(h, p, b, x, r, false);
+      residual(h, p, b, x, r, false, hdg::Prec::F64);
     }
     return HDG_OK;
   });
@@ -870,7 +997,14 @@ hdg_status_t hdg_residual(hdg_handle_t h, int32_t p, const double* b, const doub
 hdg_status_t hdg_smooth(hdg_handle_t h, int32_t p, const double* b, double* x, int32_t sweeps) {
   if (!h || !b || !x || p < 0 || p > h->k || sweeps < 0) return HDG_ERR_INVALID_ARG;
   return guarded(h, [&]() -> hdg_status_t {
-    smooth(h, p, b, x, sweeps, false);
+    const int64_t N = h->pl[p].N;
+    if (h->prec == hdg::Prec::F64) {
+      smooth(h, p, b, x, sweeps, false);
+    } else {
+      const void* bl = stage_in(h, b, h->cva, N);
+      smooth(h, p, bl, const_cast<void*>(stage_in(h, x, h->cvb, N)), sweeps, false);
+      stage_out(h, h->cvb, x, N);
+    }
     return HDG_OK;
   });
 }
@@ -878,7 +1012,8 @@ hdg_status_t hdg_smooth(hdg_handle_t h, int32_t p, const double* b, double* x, i
 hdg_status_t hdg_restrict(hdg_handle_t h, int32_t p_fine, const double* r_fine, double* r_coarse) {
   if (!h || !r_fine || !r_coarse || p_fine < 1 || p_fine > h->k) return HDG_ERR_INVALID_ARG;
   return guarded(h, [&]() -> hdg_status_t {
-    hipchk(hdg::launch_p_restrict(p_fine + 1, h->pl[p_fine].pmat, r_fine, r_coarse, h->nf, h->stream),
+    hipchk(hdg::launch_p_restrict(hdg::Prec::F64, p_fine + 1, h->pl[p_fine].pmat64, r_fine, r_coarse, h->nf,
+                                  h->stream),
            "restrict");
     return HDG_OK;
   });
@@ -887,7 +1022,8 @@ hdg_status_t hdg_restrict(hdg_handle_t h, int32_t p_fine, const double* r_fine, 
 hdg_status_t hdg_prolong(hdg_handle_t h, int32_t p_fine, const double* e_coarse, double* x_fine) {
   if (!h || !e_coarse || !x_fine || p_fine < 1 || p_fine > h->k) return HDG_ERR_INVALID_ARG;
   return guarded(h, [&]() -> hdg_status_t {
-    hipchk(hdg::launch_p_prolong_add(p_fine + 1, h->pl[p_fine].pmat, e_coarse, x_fine, h->nf, h->stream),
+    hipchk(hdg::launch_p_prolong_add(hdg::Prec::F64, p_fine + 1, h->pl[p_fine].pmat64, e_coarse, x_fine, h->nf,
+                                     h->stream),
            "prolong");
     return HDG_OK;
   });
@@ -896,7 +1032,14 @@ hdg_status_t hdg_prolong(hdg_handle_t h, int32_t p_fine, const double* e_coarse,
 hdg_status_t hdg_vcycle(hdg_handle_t h, const double* b, double* x) {
   if (!h || !b || !x || b == x) return HDG_ERR_INVALID_ARG;
   return guarded(h, [&]() -> hdg_status_t {
-    pcycle(h, h->k, b, x, false);
+    const int64_t N = h->pl[h->k].N;
+    if (h->prec == hdg::Prec::F64) {
+      pcycle(h, h->k, b, x, false);
+    } else {
+      const void* bl = stage_in(h, b, h->cva, N);
+      pcycle(h, h->k, bl, const_cast<void*>(stage_in(h, x, h->cvb, N)), false);
+      stage_out(h, h->cvb, x, N);
+    }
     return HDG_OK;
   });
 }
@@ -924,8 +1067,10 @@ hdg_status_t hdg_solve(hdg_handle_t h, const double* b, double* x, double rtol, 
     }
     const double tol = rtol * nb;
     if (mode == HDG_SOLVE_VCYCLE) {
+      // stationary iteration on the correction: x += B (b - S x), B one V-cycle
       while (rn > tol && it < maxit) {
-        pcycle(h, k, b, x, false);
+        precondition(h, h->vr, h->vz);
+        hipchk(hdg::launch_axpy(1.0, h->vz, x, N, h->stream), "axpy");
         rn = residual_norm(h, k, b, x, h->vr);
         ++it;
         if (history_host) history_host[it] = rn;
@@ -935,15 +1080,15 @@ hdg_status_t hdg_solve(hdg_handle_t h, const double* b, double* x, double rtol, 
         }
       }
     } else if (rn > tol && maxit > 0) {
-      pcycle(h, k, h->vr, h->vz, true);
-      hipchk(hdg::launch_copy(h->vz, h->vd, N, h->stream), "copy");
+      precondition(h, h->vr, h->vz);
+      hipchk(hdg::launch_copy(hdg::Prec::F64, h->vz, h->vd, N, h->stream), "copy");
       double rz = dot(h, h->vr, h->vz, N);
       while (rn > tol && it < maxit) {
-        hdg::TraceArgs ta = targs(h, h->pl[k]);
+        hdg::TraceArgs ta = targs(h, h->pl[k], hdg::Prec::F64);
         ta.x = h->vd;
         ta.y = h->vq;
         ta.partial = h->partial;
-        hipchk(hdg::launch_trace(h->pl[k].P, hdg::TM_APPLY_DOT, ta, h->stream), "apply dot");
+        hipchk(hdg::launch_trace(hdg::Prec::F64, h->pl[k].P, hdg::TM_APPLY_DOT, ta, h->stream), "apply dot");
         const double dq = reduce_scalar(h, hdg::trace_partials(h->ntiles));
         const double alpha = rz / dq;
         hipchk(hdg::launch_axpy(alpha, h->vd, x, N, h->stream), "axpy");
@@ -956,7 +1101,7 @@ hdg_status_t hdg_solve(hdg_handle_t h, const double* b, double* x, double rtol, 
           return finish(HDG_ERR_NONFINITE);
         }
         if (rn <= tol) break;
-        pcycle(h, k, h->vr, h->vz, true);
+        precondition(h, h->vr, h->vz);
         const double rz_new = dot(h, h->vr, h->vz, N);
         hipchk(hdg::launch_xpby(h->vz, rz_new / rz, h->vd, N, h->stream), "xpby");
         rz = rz_new;

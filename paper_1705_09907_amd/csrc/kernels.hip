@@ -10,15 +10,46 @@
 // tiles: the hardware deals them round-robin to the 8 XCDs, so all XCDs stream
 // neighbouring regions of the block array at any time (measured faster than
 // giving each XCD its own contiguous range, which favours x reuse in its L2).
+//
+// Every kernel is instantiated for FP64 blocks and vectors, FP32 blocks and
+// vectors, and BF16 blocks with FP32 vectors (FP32 accumulation).
 #include <hip/hip_runtime.h>
 
 #include "kernels.hpp"
 
 namespace hdg {
 
-typedef double dbl2 __attribute__((ext_vector_type(2)));
+typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
+typedef uint16_t bf16_t;  // bfloat16 storage: the high half of an FP32 word
 
 static constexpr int kWG = 256;
+
+// ---------------------------------------------------------------- storage
+// 16-byte load of V = 16 / sizeof(TM) consecutive matrix entries, widened to TV.
+template <typename TM, typename TV>
+struct Lanes16;
+template <>
+struct Lanes16<double, double> {
+  static constexpr int V = 2;
+  __device__ static void unpack(u32x4 r, double* w) { __builtin_memcpy(w, &r, 16); }
+};
+template <>
+struct Lanes16<float, float> {
+  static constexpr int V = 4;
+  __device__ static void unpack(u32x4 r, float* w) { __builtin_memcpy(w, &r, 16); }
+};
+template <>
+struct Lanes16<bf16_t, float> {
+  static constexpr int V = 8;
+  __device__ static void unpack(u32x4 r, float* w) {
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      const unsigned int u = r[i];
+      w[2 * i] = __uint_as_float(u << 16);
+      w[2 * i + 1] = __uint_as_float(u & 0xffff0000u);
+    }
+  }
+};
 
 // Face neighbours (App. numbering): g[0] = f, g[1..3] = other faces of the lo
 // element in local order, g[4..6] = other faces of the hi element; -1 = boundary.
@@ -58,12 +89,17 @@ __device__ __forceinline__ double block_sum(double v) {
 int trace_grid(int64_t ntiles) { return (int)((ntiles + 3) / 4); }
 int trace_partials(int64_t ntiles) { return 4 * trace_grid(ntiles); }
 
-template <int P, int MODE>
+template <int P, int MODE, typename TM, typename TV>
 __global__ __launch_bounds__(kWG) void k_trace(TraceArgs a) {
+  using L16 = Lanes16<TM, TV>;
+  constexpr int V = L16::V;
   constexpr int P2 = P * P;
   constexpr int NE = 7 * P2;
-  constexpr int NQ = (NE + 1) / 2;
-  constexpr int NQD = (P2 + 1) / 2;
+  constexpr int NQ = (NE + V - 1) / V;
+  constexpr int NQD = (P2 + V - 1) / V;
+  const TV* x = static_cast<const TV*>(a.x);
+  const TV* b = static_cast<const TV*>(a.b);
+  TV* y = static_cast<TV*>(a.y);
   const int lane = threadIdx.x & 63;
   const int wave = threadIdx.x >> 6;
   const int64_t tile = (int64_t)blockIdx.x * (kWG / 64) + wave;
@@ -74,62 +110,69 @@ __global__ __launch_bounds__(kWG) void k_trace(TraceArgs a) {
     const bool valid = f < a.nf;
     int64_t g[7];
     face_neighbours(a.n, nv, valid ? f : 0, g);
-    double xv[7][P];
+    TV xv[7][P];
 #pragma unroll
     for (int s = 0; s < 7; ++s)
 #pragma unroll
-      for (int c = 0; c < P; ++c) xv[s][c] = (valid && g[s] >= 0) ? a.x[g[s] * P + c] : 0.0;
-    double acc[P];
+      for (int c = 0; c < P; ++c) xv[s][c] = (valid && g[s] >= 0) ? x[g[s] * P + c] : TV(0);
+    TV acc[P];
 #pragma unroll
-    for (int r = 0; r < P; ++r) acc[r] = 0.0;
-    const dbl2* sp = reinterpret_cast<const dbl2*>(a.slab) + (tile * NQ) * 64 + lane;
+    for (int r = 0; r < P; ++r) acc[r] = TV(0);
+    const u32x4* sp = static_cast<const u32x4*>(a.slab) + (tile * NQ) * 64 + lane;
 #pragma unroll
     for (int q = 0; q < NQ; ++q) {
-      const dbl2 w = __builtin_nontemporal_load(sp + q * 64);
-      const int e0 = 2 * q, e1 = 2 * q + 1;
-      acc[(e0 % P2) / P] += w.x * xv[e0 / P2][e0 % P];
-      if (e1 < NE) acc[(e1 % P2) / P] += w.y * xv[e1 / P2][e1 % P];
+      TV w[V];
+      L16::unpack(__builtin_nontemporal_load(sp + q * 64), w);
+#pragma unroll
+      for (int u = 0; u < V; ++u) {
+        const int e = q * V + u;
+        if (e < NE) acc[(e % P2) / P] += w[u] * xv[e / P2][e % P];
+      }
     }
     if (valid) {
       if constexpr (MODE == TM_APPLY || MODE == TM_APPLY_DOT) {
 #pragma unroll
-        for (int r = 0; r < P; ++r) a.y[f * P + r] = acc[r];
+        for (int r = 0; r < P; ++r) y[f * P + r] = acc[r];
         if constexpr (MODE == TM_APPLY_DOT) {
 #pragma unroll
-          for (int r = 0; r < P; ++r) sq += xv[0][r] * acc[r];
+          for (int r = 0; r < P; ++r) sq += (double)xv[0][r] * (double)acc[r];
         }
       } else {
-        double res[P];
+        TV res[P];
 #pragma unroll
         for (int r = 0; r < P; ++r) {
-          res[r] = a.b[f * P + r] - acc[r];
-          sq += res[r] * res[r];
+          res[r] = b[f * P + r] - acc[r];
+          sq += (double)res[r] * (double)res[r];
         }
         if constexpr (MODE == TM_RESID) {
 #pragma unroll
-          for (int r = 0; r < P; ++r) a.y[f * P + r] = res[r];
+          for (int r = 0; r < P; ++r) y[f * P + r] = res[r];
         } else if constexpr (MODE == TM_FACE_SWEEP) {
-          const dbl2* dp = reinterpret_cast<const dbl2*>(a.dinv) + (tile * NQD) * 64 + lane;
-          double z[P];
+          const u32x4* dp = static_cast<const u32x4*>(a.dinv) + (tile * NQD) * 64 + lane;
+          TV z[P];
 #pragma unroll
-          for (int r = 0; r < P; ++r) z[r] = 0.0;
+          for (int r = 0; r < P; ++r) z[r] = TV(0);
 #pragma unroll
           for (int q = 0; q < NQD; ++q) {
-            const dbl2 w = dp[q * 64];
-            const int e0 = 2 * q, e1 = 2 * q + 1;
-            z[e0 / P] += w.x * res[e0 % P];
-            if (e1 < P2) z[e1 / P] += w.y * res[e1 % P];
+            TV w[V];
+            L16::unpack(dp[q * 64], w);
+#pragma unroll
+            for (int u = 0; u < V; ++u) {
+              const int e = q * V + u;
+              if (e < P2) z[e / P] += w[u] * res[e % P];
+            }
           }
 #pragma unroll
-          for (int r = 0; r < P; ++r) a.y[f * P + r] = xv[0][r] + a.omega * z[r];
+          for (int r = 0; r < P; ++r) y[f * P + r] = xv[0][r] + TV(a.omega) * z[r];
         } else {  // TM_RESID_RESTRICT, P >= 2: y[f (P-1) + c] = sum_r Pp[r][c] res[r]
           if constexpr (P >= 2) {
+            const TV* pm = static_cast<const TV*>(a.pmat);
 #pragma unroll
             for (int c = 0; c < P - 1; ++c) {
-              double s = 0.0;
+              TV s = TV(0);
 #pragma unroll
-              for (int r = 0; r < P; ++r) s += a.pmat[r * (P - 1) + c] * res[r];
-              a.y[f * (P - 1) + c] = s;
+              for (int r = 0; r < P; ++r) s += pm[r * (P - 1) + c] * res[r];
+              y[f * (P - 1) + c] = s;
             }
           }
         }
@@ -142,97 +185,32 @@ __global__ __launch_bounds__(kWG) void k_trace(TraceArgs a) {
   }
 }
 
-template <int P>
-static hipError_t launch_trace_p(int mode, const TraceArgs& a, hipStream_t s) {
+template <int P, typename TM, typename TV>
+static hipError_t launch_trace_t(int mode, const TraceArgs& a, hipStream_t s) {
   const dim3 grid(trace_grid(a.ntiles)), block(kWG);
   switch (mode) {
-    case TM_APPLY: hipLaunchKernelGGL((k_trace<P, TM_APPLY>), grid, block, 0, s, a); break;
-    case TM_APPLY_DOT: hipLaunchKernelGGL((k_trace<P, TM_APPLY_DOT>), grid, block, 0, s, a); break;
-    case TM_RESID: hipLaunchKernelGGL((k_trace<P, TM_RESID>), grid, block, 0, s, a); break;
-    case TM_FACE_SWEEP: hipLaunchKernelGGL((k_trace<P, TM_FACE_SWEEP>), grid, block, 0, s, a); break;
+    case TM_APPLY: hipLaunchKernelGGL((k_trace<P, TM_APPLY, TM, TV>), grid, block, 0, s, a); break;
+    case TM_APPLY_DOT: hipLaunchKernelGGL((k_trace<P, TM_APPLY_DOT, TM, TV>), grid, block, 0, s, a); break;
+    case TM_RESID: hipLaunchKernelGGL((k_trace<P, TM_RESID, TM, TV>), grid, block, 0, s, a); break;
+    case TM_FACE_SWEEP: hipLaunchKernelGGL((k_trace<P, TM_FACE_SWEEP, TM, TV>), grid, block, 0, s, a); break;
     case TM_RESID_RESTRICT:
       if (P < 2) return hipErrorInvalidValue;
-      hipLaunchKernelGGL((k_trace<P, TM_RESID_RESTRICT>), grid, block, 0, s, a);
+      hipLaunchKernelGGL((k_trace<P, TM_RESID_RESTRICT, TM, TV>), grid, block, 0, s, a);
       break;
     default: return hipErrorInvalidValue;
   }
   return hipGetLastError();
 }
 
-hipError_t launch_trace(int P, int mode, const TraceArgs& a, hipStream_t s) {
-  switch (P) {
-    case 1: return launch_trace_p<1>(mode, a, s);
-    case 2: return launch_trace_p<2>(mode, a, s);
-    case 3: return launch_trace_p<3>(mode, a, s);
-    case 4: return launch_trace_p<4>(mode, a, s);
-    case 5: return launch_trace_p<5>(mode, a, s);
-    case 6: return launch_trace_p<6>(mode, a, s);
-    case 7: return launch_trace_p<7>(mode, a, s);
-    case 8: return launch_trace_p<8>(mode, a, s);
-    case 9: return launch_trace_p<9>(mode, a, s);
-    default: return hipErrorInvalidValue;
-  }
-}
-
-// ------------------------------------------------------------ face-local ops
 template <int P>
-__global__ __launch_bounds__(kWG) void k_dinv_apply(const double* dinv, const double* b, double omega,
-                                                    double* x, int64_t nf) {
-  constexpr int P2 = P * P, NQD = (P2 + 1) / 2;
-  const int64_t f = (int64_t)blockIdx.x * kWG + threadIdx.x;
-  if (f >= nf) return;
-  const int64_t tile = f >> 6;
-  const int lane = (int)(f & 63);
-  double r[P], z[P];
-#pragma unroll
-  for (int c = 0; c < P; ++c) { r[c] = b[f * P + c]; z[c] = 0.0; }
-  const dbl2* dp = reinterpret_cast<const dbl2*>(dinv) + (tile * NQD) * 64 + lane;
-#pragma unroll
-  for (int q = 0; q < NQD; ++q) {
-    const dbl2 w = dp[q * 64];
-    const int e0 = 2 * q, e1 = 2 * q + 1;
-    z[e0 / P] += w.x * r[e0 % P];
-    if (e1 < P2) z[e1 / P] += w.y * r[e1 % P];
+static hipError_t launch_trace_p(Prec pr, int mode, const TraceArgs& a, hipStream_t s) {
+  switch (pr) {
+    case Prec::F64: return launch_trace_t<P, double, double>(mode, a, s);
+    case Prec::F32: return launch_trace_t<P, float, float>(mode, a, s);
+    case Prec::BF16: return launch_trace_t<P, bf16_t, float>(mode, a, s);
   }
-#pragma unroll
-  for (int c = 0; c < P; ++c) x[f * P + c] = omega * z[c];
+  return hipErrorInvalidValue;
 }
-
-template <int P>
-__global__ __launch_bounds__(kWG) void k_p_restrict(const double* pm, const double* rf, double* rc,
-                                                    int64_t nf) {
-  const int64_t f = (int64_t)blockIdx.x * kWG + threadIdx.x;
-  if (f >= nf) return;
-  double r[P];
-#pragma unroll
-  for (int a = 0; a < P; ++a) r[a] = rf[f * P + a];
-#pragma unroll
-  for (int c = 0; c < P - 1; ++c) {
-    double s = 0.0;
-#pragma unroll
-    for (int a = 0; a < P; ++a) s += pm[a * (P - 1) + c] * r[a];
-    rc[f * (P - 1) + c] = s;
-  }
-}
-
-template <int P>
-__global__ __launch_bounds__(kWG) void k_p_prolong_add(const double* pm, const double* ec, double* xf,
-                                                       int64_t nf) {
-  const int64_t f = (int64_t)blockIdx.x * kWG + threadIdx.x;
-  if (f >= nf) return;
-  double e[P - 1];
-#pragma unroll
-  for (int c = 0; c < P - 1; ++c) e[c] = ec[f * (P - 1) + c];
-#pragma unroll
-  for (int a = 0; a < P; ++a) {
-    double s = xf[f * P + a];
-#pragma unroll
-    for (int c = 0; c < P - 1; ++c) s += pm[a * (P - 1) + c] * e[c];
-    xf[f * P + a] = s;
-  }
-}
-
-static inline dim3 grid_for(int64_t n) { return dim3((unsigned)((n + kWG - 1) / kWG)); }
 
 #define HDG_DISPATCH_P(P, CALL)                       \
   switch (P) {                                        \
@@ -248,30 +226,119 @@ static inline dim3 grid_for(int64_t n) { return dim3((unsigned)((n + kWG - 1) / 
     default: return hipErrorInvalidValue;             \
   }
 
-hipError_t launch_dinv_apply(int P, const double* dinv, const double* b, double omega, double* x,
+hipError_t launch_trace(Prec pr, int P, int mode, const TraceArgs& a, hipStream_t s) {
+  HDG_DISPATCH_P(P, return launch_trace_p<PP>(pr, mode, a, s));
+  return hipErrorInvalidValue;
+}
+
+// ------------------------------------------------------------ face-local ops
+static inline dim3 grid_for(int64_t n) { return dim3((unsigned)((n + kWG - 1) / kWG)); }
+
+template <int P, typename TM, typename TV>
+__global__ __launch_bounds__(kWG) void k_dinv_apply(const void* dinv, const TV* b, double omega, TV* x,
+                                                    int64_t nf) {
+  using L16 = Lanes16<TM, TV>;
+  constexpr int V = L16::V, P2 = P * P, NQD = (P2 + V - 1) / V;
+  const int64_t f = (int64_t)blockIdx.x * kWG + threadIdx.x;
+  if (f >= nf) return;
+  const int64_t tile = f >> 6;
+  const int lane = (int)(f & 63);
+  TV r[P], z[P];
+#pragma unroll
+  for (int c = 0; c < P; ++c) { r[c] = b[f * P + c]; z[c] = TV(0); }
+  const u32x4* dp = static_cast<const u32x4*>(dinv) + (tile * NQD) * 64 + lane;
+#pragma unroll
+  for (int q = 0; q < NQD; ++q) {
+    TV w[V];
+    L16::unpack(dp[q * 64], w);
+#pragma unroll
+    for (int u = 0; u < V; ++u) {
+      const int e = q * V + u;
+      if (e < P2) z[e / P] += w[u] * r[e % P];
+    }
+  }
+#pragma unroll
+  for (int c = 0; c < P; ++c) x[f * P + c] = TV(omega) * z[c];
+}
+
+template <int P, typename T>
+__global__ __launch_bounds__(kWG) void k_p_restrict(const T* pm, const T* rf, T* rc, int64_t nf) {
+  const int64_t f = (int64_t)blockIdx.x * kWG + threadIdx.x;
+  if (f >= nf) return;
+  T r[P];
+#pragma unroll
+  for (int a = 0; a < P; ++a) r[a] = rf[f * P + a];
+#pragma unroll
+  for (int c = 0; c < P - 1; ++c) {
+    T s = T(0);
+#pragma unroll
+    for (int a = 0; a < P; ++a) s += pm[a * (P - 1) + c] * r[a];
+    rc[f * (P - 1) + c] = s;
+  }
+}
+
+template <int P, typename T>
+__global__ __launch_bounds__(kWG) void k_p_prolong_add(const T* pm, const T* ec, T* xf, int64_t nf) {
+  const int64_t f = (int64_t)blockIdx.x * kWG + threadIdx.x;
+  if (f >= nf) return;
+  T e[P - 1];
+#pragma unroll
+  for (int c = 0; c < P - 1; ++c) e[c] = ec[f * (P - 1) + c];
+#pragma unroll
+  for (int a = 0; a < P; ++a) {
+    T s = xf[f * P + a];
+#pragma unroll
+    for (int c = 0; c < P - 1; ++c) s += pm[a * (P - 1) + c] * e[c];
+    xf[f * P + a] = s;
+  }
+}
+
+hipError_t launch_dinv_apply(Prec pr, int P, const void* dinv, const void* b, double omega, void* x,
                              int64_t nf, hipStream_t s) {
   if (nf == 0) return hipSuccess;
-  HDG_DISPATCH_P(P, hipLaunchKernelGGL((k_dinv_apply<PP>), grid_for(nf), dim3(kWG), 0, s, dinv, b,
-                                       omega, x, nf));
+  switch (pr) {
+    case Prec::F64:
+      HDG_DISPATCH_P(P, hipLaunchKernelGGL((k_dinv_apply<PP, double, double>), grid_for(nf), dim3(kWG), 0, s,
+                                           dinv, (const double*)b, omega, (double*)x, nf));
+      break;
+    case Prec::F32:
+      HDG_DISPATCH_P(P, hipLaunchKernelGGL((k_dinv_apply<PP, float, float>), grid_for(nf), dim3(kWG), 0, s,
+                                           dinv, (const float*)b, omega, (float*)x, nf));
+      break;
+    case Prec::BF16:
+      HDG_DISPATCH_P(P, hipLaunchKernelGGL((k_dinv_apply<PP, bf16_t, float>), grid_for(nf), dim3(kWG), 0, s,
+                                           dinv, (const float*)b, omega, (float*)x, nf));
+      break;
+  }
   return hipGetLastError();
 }
 
-hipError_t launch_p_restrict(int P, const double* pm, const double* rf, double* rc, int64_t nf,
+template <typename T>
+static hipError_t p_restrict_t(int P, const void* pm, const void* rf, void* rc, int64_t nf, hipStream_t s) {
+  HDG_DISPATCH_P(P, if constexpr (PP >= 2) hipLaunchKernelGGL((k_p_restrict<PP, T>), grid_for(nf), dim3(kWG), 0,
+                                                               s, (const T*)pm, (const T*)rf, (T*)rc, nf));
+  return hipGetLastError();
+}
+template <typename T>
+static hipError_t p_prolong_t(int P, const void* pm, const void* ec, void* xf, int64_t nf, hipStream_t s) {
+  HDG_DISPATCH_P(P, if constexpr (PP >= 2) hipLaunchKernelGGL((k_p_prolong_add<PP, T>), grid_for(nf),
+                                                               dim3(kWG), 0, s, (const T*)pm, (const T*)ec,
+                                                               (T*)xf, nf));
+  return hipGetLastError();
+}
+
+hipError_t launch_p_restrict(Prec pr, int P, const void* pm, const void* rf, void* rc, int64_t nf,
                              hipStream_t s) {
   if (P < 2) return hipErrorInvalidValue;
   if (nf == 0) return hipSuccess;
-  HDG_DISPATCH_P(P, if constexpr (PP >= 2) hipLaunchKernelGGL((k_p_restrict<PP>), grid_for(nf),
-                                                               dim3(kWG), 0, s, pm, rf, rc, nf));
-  return hipGetLastError();
+  return pr == Prec::F64 ? p_restrict_t<double>(P, pm, rf, rc, nf, s) : p_restrict_t<float>(P, pm, rf, rc, nf, s);
 }
 
-hipError_t launch_p_prolong_add(int P, const double* pm, const double* ec, double* xf, int64_t nf,
+hipError_t launch_p_prolong_add(Prec pr, int P, const void* pm, const void* ec, void* xf, int64_t nf,
                                 hipStream_t s) {
   if (P < 2) return hipErrorInvalidValue;
   if (nf == 0) return hipSuccess;
-  HDG_DISPATCH_P(P, if constexpr (PP >= 2) hipLaunchKernelGGL((k_p_prolong_add<PP>), grid_for(nf),
-                                                               dim3(kWG), 0, s, pm, ec, xf, nf));
-  return hipGetLastError();
+  return pr == Prec::F64 ? p_prolong_t<double>(P, pm, ec, xf, nf, s) : p_prolong_t<float>(P, pm, ec, xf, nf, s);
 }
 
 // ------------------------------------------------------------ chain Schwarz
@@ -289,34 +356,37 @@ hipError_t launch_p_prolong_add(int P, const double* pm, const double* ec, doubl
 // arrays over the ne = ceil(ml/2) even positions, then the odd records
 // [Dinv, W, Z] as 3 P^2 arrays over the no = floor(ml/2) odd positions
 // (entry-major, so a wavefront reads consecutive addresses); the last level
-// stores Dinv of its single block.
-template <int P>
+// stores Dinv of its single block.  The factor row of a thread's first item of
+// the next forward phase is loaded before the barrier that precedes it.
+template <int P, typename T>
 __global__ __launch_bounds__(1024) void k_chain(ChainArgs a) {
   constexpr int P2 = P * P;
-  extern __shared__ double R[];
+  extern __shared__ unsigned char lds_raw[];
+  T* R = reinterpret_cast<T*>(lds_raw);
+  const T* rin = static_cast<const T*>(a.r);
+  const T* xin = static_cast<const T*>(a.x);
+  T* out = static_cast<T*>(a.out);
   const int64_t c = blockIdx.x;
   const int m = a.n - 1;
   const int64_t nv = (int64_t)a.n * (a.n - 1);
   const bool vert = c < a.n;
   const int64_t base = vert ? c * (a.n - 1) : nv + (c - a.n);
   const int64_t stride = vert ? 1 : a.n;
-  const double* F = a.factors + c * a.cstride;
+  const T* F = static_cast<const T*>(a.factors) + c * a.cstride;
   const int t = threadIdx.x;
   const int nt = blockDim.x;
   for (int idx = t; idx < m * P; idx += nt) {
     const int i = idx / P, r = idx - i * P;
-    R[idx] = a.r[(base + stride * i) * P + r];
+    R[idx] = rin[(base + stride * i) * P + r];
   }
   int ml = m, lev = 0;
   int64_t off = 0;
-  // factor row of this thread's first item of the coming phase, loaded before the
-  // barrier that precedes the phase (factors do not depend on the data)
-  double pm[P], pp[P];
+  T pm[P], pp[P];
   auto prefetch_fwd = [&](int mlv, int64_t offv) {
     const int ne = (mlv + 1) >> 1;
     if (mlv > 1 && t < ne * P) {
       const int r = t / ne, tt = t - r * ne;
-      const double* E = F + offv;
+      const T* E = F + offv;
 #pragma unroll
       for (int q = 0; q < P; ++q) {
         pm[q] = E[(int64_t)(r * P + q) * ne + tt];
@@ -328,7 +398,7 @@ __global__ __launch_bounds__(1024) void k_chain(ChainArgs a) {
   __syncthreads();
   while (ml > 1) {
     const int ne = (ml + 1) >> 1;
-    const double* E = F + off;
+    const T* E = F + off;
     for (int it = t; it < ne * P; it += nt) {
       const int r = it / ne, tt = it - r * ne;
       const int j = 2 * tt;
@@ -340,7 +410,7 @@ __global__ __launch_bounds__(1024) void k_chain(ChainArgs a) {
           pp[q] = E[(int64_t)(P2 + r * P + q) * ne + tt];
         }
       }
-      double v = R[i * P + r];
+      T v = R[i * P + r];
       if (j >= 1) {
         const int il = (j - 1) << lev;
 #pragma unroll
@@ -359,7 +429,7 @@ __global__ __launch_bounds__(1024) void k_chain(ChainArgs a) {
     prefetch_fwd(ml, off);
     __syncthreads();
   }
-  double xr = 0.0;
+  T xr = T(0);
   if (t < P) {
 #pragma unroll
     for (int q = 0; q < P; ++q) xr += F[off + t * P + q] * R[q];
@@ -374,18 +444,18 @@ __global__ __launch_bounds__(1024) void k_chain(ChainArgs a) {
     int64_t lo = 0;  // offset of level lev: record sizes of the levels below it
     for (int l = 0, s = m; l < lev; ++l, s = (s + 1) >> 1)
       lo += (int64_t)2 * P2 * ((s + 1) >> 1) + (int64_t)3 * P2 * (s >> 1);
-    const double* O = F + lo + (int64_t)2 * P2 * ne;
-    // one pass computes every (position, row) value into registers; a thread
-    // handles at most ceil(no P / blockDim) of them, bounded below by kMaxItems
+    const T* O = F + lo + (int64_t)2 * P2 * ne;
+    // each thread owns at most kMaxItems (position, row) items (the launcher
+    // sizes the workgroup for that): values first, then a barrier, then writes
     constexpr int kMaxItems = 8;
-    double res[kMaxItems];
+    T res[kMaxItems];
     int cnt = 0;
     for (int it = t; it < no * P && cnt < kMaxItems; it += nt, ++cnt) {
       const int r = it / no, tt = it - r * no;
       const int j = 2 * tt + 1;
       const int i = j << lev;
       const int il = (j - 1) << lev;
-      double s = 0.0;
+      T s = T(0);
 #pragma unroll
       for (int q = 0; q < P; ++q)
         s += O[(int64_t)(r * P + q) * no + tt] * R[i * P + q] - O[(int64_t)(P2 + r * P + q) * no + tt] * R[il * P + q];
@@ -407,26 +477,30 @@ __global__ __launch_bounds__(1024) void k_chain(ChainArgs a) {
   for (int idx = t; idx < m * P; idx += nt) {
     const int i = idx / P, r = idx - i * P;
     const int64_t g = (base + stride * i) * P + r;
-    a.out[g] = (a.x ? a.x[g] : 0.0) + a.omega * R[idx];
+    out[g] = (xin ? xin[g] : T(0)) + T(a.omega) * R[idx];
   }
 }
 
-hipError_t launch_chain_solve(int P, const ChainArgs& a, hipStream_t s) {
+hipError_t launch_chain_solve(Prec pr, int P, const ChainArgs& a, hipStream_t s) {
   const int64_t nch = 2LL * a.n;
-  const size_t lds = (size_t)(a.n - 1) * P * sizeof(double);
+  const size_t lds = (size_t)(a.n - 1) * P * vec_bytes(pr);
   // the back-substitution keeps at most 8 (position, row) items per thread
   const int64_t items = (int64_t)((a.n - 1) / 2) * P;
   int threads = 256;
   while (threads < 1024 && items > (int64_t)threads * 8) threads *= 2;
   if (items > (int64_t)threads * 8) return hipErrorInvalidValue;
-  HDG_DISPATCH_P(P, hipLaunchKernelGGL((k_chain<PP>), dim3((unsigned)nch), dim3(threads), lds, s, a));
+  if (pr == Prec::F64) {
+    HDG_DISPATCH_P(P, hipLaunchKernelGGL((k_chain<PP, double>), dim3((unsigned)nch), dim3(threads), lds, s, a));
+  } else {
+    HDG_DISPATCH_P(P, hipLaunchKernelGGL((k_chain<PP, float>), dim3((unsigned)nch), dim3(threads), lds, s, a));
+  }
   return hipGetLastError();
 }
 
 // ------------------------------------------------------------------ Q1 levels
-__device__ __forceinline__ double q1_apply(const double* st, const double* x, int m, int64_t Nv,
-                                           int i, int j, int64_t v) {
-  double s = 0.0;
+template <typename T>
+__device__ __forceinline__ T q1_apply(const T* st, const T* x, int m, int64_t Nv, int i, int j, int64_t v) {
+  T s = T(0);
 #pragma unroll
   for (int dj = -1; dj <= 1; ++dj)
 #pragma unroll
@@ -438,8 +512,8 @@ __device__ __forceinline__ double q1_apply(const double* st, const double* x, in
   return s;
 }
 
-__global__ __launch_bounds__(kWG) void k_q1_resid(const double* st, const double* b, const double* x,
-                                                  double* r, int m) {
+template <typename T>
+__global__ __launch_bounds__(kWG) void k_q1_resid(const T* st, const T* b, const T* x, T* r, int m) {
   const int64_t Nv = (int64_t)(m - 1) * (m - 1);
   const int64_t v = (int64_t)blockIdx.x * kWG + threadIdx.x;
   if (v >= Nv) return;
@@ -447,74 +521,78 @@ __global__ __launch_bounds__(kWG) void k_q1_resid(const double* st, const double
   r[v] = b[v] - q1_apply(st, x, m, Nv, i, j, v);
 }
 
-__global__ __launch_bounds__(kWG) void k_q1_cheb(const double* st, const double* dinv, const double* b,
-                                                 const double* x, double* d, double* xo, double c1,
-                                                 double c2, int m) {
+template <typename T>
+__global__ __launch_bounds__(kWG) void k_q1_cheb(const T* st, const T* dinv, const T* b, const T* x, T* d, T* xo,
+                                                 double c1, double c2, int m) {
   const int64_t Nv = (int64_t)(m - 1) * (m - 1);
   const int64_t v = (int64_t)blockIdx.x * kWG + threadIdx.x;
   if (v >= Nv) return;
   const int i = (int)(v % (m - 1)) + 1, j = (int)(v / (m - 1)) + 1;
-  const double ax = x ? q1_apply(st, x, m, Nv, i, j, v) : 0.0;
-  const double z = dinv[v] * (b[v] - ax);
-  const double dn = (c1 != 0.0 ? c1 * d[v] : 0.0) + c2 * z;
+  const T ax = x ? q1_apply(st, x, m, Nv, i, j, v) : T(0);
+  const T z = dinv[v] * (b[v] - ax);
+  const T dn = (c1 != 0.0 ? T(c1) * d[v] : T(0)) + T(c2) * z;
   d[v] = dn;
-  xo[v] = (x ? x[v] : 0.0) + dn;
+  xo[v] = (x ? x[v] : T(0)) + dn;
 }
 
 // full weighting: coarse vertex (I, J) gathers fine (2I + di, 2J + dj), weight w(di) w(dj)
-__global__ __launch_bounds__(kWG) void k_q1_restrict(const double* rf, double* rc, int mf) {
+template <typename T>
+__global__ __launch_bounds__(kWG) void k_q1_restrict(const T* rf, T* rc, int mf) {
   const int mc = mf / 2;
   const int64_t Nc = (int64_t)(mc - 1) * (mc - 1);
   const int64_t v = (int64_t)blockIdx.x * kWG + threadIdx.x;
   if (v >= Nc) return;
   const int I = (int)(v % (mc - 1)) + 1, J = (int)(v / (mc - 1)) + 1;
-  double s = 0.0;
+  T s = T(0);
 #pragma unroll
   for (int dj = -1; dj <= 1; ++dj)
 #pragma unroll
     for (int di = -1; di <= 1; ++di) {
-      const double w = (di == 0 ? 1.0 : 0.5) * (dj == 0 ? 1.0 : 0.5);
+      const T w = T((di == 0 ? 1.0 : 0.5) * (dj == 0 ? 1.0 : 0.5));
       const int fi = 2 * I + di, fj = 2 * J + dj;  // always interior of the fine mesh
       s += w * rf[(fi - 1) + (int64_t)(mf - 1) * (fj - 1)];
     }
   rc[v] = s;
 }
 
-__global__ __launch_bounds__(kWG) void k_q1_prolong_add(const double* ec, double* xf, int mf) {
+template <typename T>
+__global__ __launch_bounds__(kWG) void k_q1_prolong_add(const T* ec, T* xf, int mf) {
   const int mc = mf / 2;
   const int64_t Nf = (int64_t)(mf - 1) * (mf - 1);
   const int64_t v = (int64_t)blockIdx.x * kWG + threadIdx.x;
   if (v >= Nf) return;
   const int I = (int)(v % (mf - 1)) + 1, J = (int)(v / (mf - 1)) + 1;
   int xi[2], yi[2];
-  double wx[2], wy[2];
+  T wx[2], wy[2];
   int nx, ny;
-  if ((I & 1) == 0) { xi[0] = I / 2; wx[0] = 1.0; nx = 1; } else { xi[0] = I / 2; xi[1] = I / 2 + 1; wx[0] = wx[1] = 0.5; nx = 2; }
-  if ((J & 1) == 0) { yi[0] = J / 2; wy[0] = 1.0; ny = 1; } else { yi[0] = J / 2; yi[1] = J / 2 + 1; wy[0] = wy[1] = 0.5; ny = 2; }
-  double s = 0.0;
-  for (int b = 0; b < ny; ++b)
-    for (int a = 0; a < nx; ++a) {
-      const int ci = xi[a], cj = yi[b];
+  if ((I & 1) == 0) { xi[0] = I / 2; wx[0] = T(1); nx = 1; } else { xi[0] = I / 2; xi[1] = I / 2 + 1; wx[0] = wx[1] = T(0.5); nx = 2; }
+  if ((J & 1) == 0) { yi[0] = J / 2; wy[0] = T(1); ny = 1; } else { yi[0] = J / 2; yi[1] = J / 2 + 1; wy[0] = wy[1] = T(0.5); ny = 2; }
+  T s = T(0);
+  for (int bb = 0; bb < ny; ++bb)
+    for (int aa = 0; aa < nx; ++aa) {
+      const int ci = xi[aa], cj = yi[bb];
       if (ci >= 1 && cj >= 1 && ci <= mc - 1 && cj <= mc - 1)
-        s += wx[a] * wy[b] * ec[(ci - 1) + (int64_t)(mc - 1) * (cj - 1)];
+        s += wx[aa] * wy[bb] * ec[(ci - 1) + (int64_t)(mc - 1) * (cj - 1)];
     }
   xf[v] += s;
 }
 
 // P_J^T: vertex (i, j) gathers its four incident interior faces, weight 1/2
-__global__ __launch_bounds__(kWG) void k_pj_restrict(const double* rface, double* rv, int n) {
+template <typename T>
+__global__ __launch_bounds__(kWG) void k_pj_restrict(const T* rface, T* rv, int n) {
   const int64_t Nv = (int64_t)(n - 1) * (n - 1);
   const int64_t v = (int64_t)blockIdx.x * kWG + threadIdx.x;
   if (v >= Nv) return;
   const int i = (int)(v % (n - 1)) + 1, j = (int)(v / (n - 1)) + 1;
   const int64_t nv = (int64_t)n * (n - 1);
-  const double s = rface[(i - 1) + (int64_t)(n - 1) * j] + rface[(i - 1) + (int64_t)(n - 1) * (j - 1)] +
-                   rface[nv + i + (int64_t)n * (j - 1)] + rface[nv + (i - 1) + (int64_t)n * (j - 1)];
-  rv[v] = 0.5 * s;
+  const T s = rface[(i - 1) + (int64_t)(n - 1) * j] + rface[(i - 1) + (int64_t)(n - 1) * (j - 1)] +
+              rface[nv + i + (int64_t)n * (j - 1)] + rface[nv + (i - 1) + (int64_t)n * (j - 1)];
+  rv[v] = T(0.5) * s;
 }
 
 // P_J: face value += mean of its two end vertices (boundary vertices are 0)
-__global__ __launch_bounds__(kWG) void k_pj_prolong_add(const double* ev, double* xface, int n) {
+template <typename T>
+__global__ __launch_bounds__(kWG) void k_pj_prolong_add(const T* ev, T* xface, int n) {
   const int64_t nf = 2LL * n * (n - 1), nv = (int64_t)n * (n - 1);
   const int64_t f = (int64_t)blockIdx.x * kWG + threadIdx.x;
   if (f >= nf) return;
@@ -527,53 +605,64 @@ __global__ __launch_bounds__(kWG) void k_pj_prolong_add(const double* ev, double
     const int j = (int)(q / n) + 1, i = (int)(q % n);
     ai = i; aj = j; bi = i + 1; bj = j;
   }
-  double s = 0.0;
+  T s = T(0);
   if (ai >= 1 && aj >= 1 && ai <= n - 1 && aj <= n - 1) s += ev[(ai - 1) + (int64_t)(n - 1) * (aj - 1)];
   if (bi >= 1 && bj >= 1 && bi <= n - 1 && bj <= n - 1) s += ev[(bi - 1) + (int64_t)(n - 1) * (bj - 1)];
-  xface[f] += 0.5 * s;
+  xface[f] += T(0.5) * s;
 }
 
-// one wavefront per row, lanes stride the columns, fixed shuffle-tree sum
-__global__ __launch_bounds__(kWG) void k_dense_gemv(const double* A, const double* b, double* y, int m) {
+// one wavefront per row, lanes stride the columns, fixed shuffle-tree sum (FP64)
+template <typename T>
+__global__ __launch_bounds__(kWG) void k_dense_gemv(const double* A, const T* b, T* y, int m) {
   const int row = blockIdx.x * (kWG / 64) + (threadIdx.x >> 6);
   const int lane = threadIdx.x & 63;
   if (row >= m) return;
   double s = 0.0;
-  for (int c = lane; c < m; c += 64) s += A[(int64_t)row * m + c] * b[c];
+  for (int c = lane; c < m; c += 64) s += A[(int64_t)row * m + c] * (double)b[c];
   for (int off = 32; off >= 1; off >>= 1) s += __shfl_xor(s, off, 64);
-  if (lane == 0) y[row] = s;
+  if (lane == 0) y[row] = T(s);
 }
 
-hipError_t launch_q1_resid(const double* st, const double* b, const double* x, double* r, int m,
-                           hipStream_t s) {
-  hipLaunchKernelGGL(k_q1_resid, grid_for((int64_t)(m - 1) * (m - 1)), dim3(kWG), 0, s, st, b, x, r, m);
+#define HDG_DISPATCH_T(pr, CALL)                      \
+  if ((pr) == Prec::F64) { using TT = double; CALL; } \
+  else { using TT = float; CALL; }
+
+hipError_t launch_q1_resid(Prec pr, const void* st, const void* b, const void* x, void* r, int m, hipStream_t s) {
+  HDG_DISPATCH_T(pr, hipLaunchKernelGGL(k_q1_resid<TT>, grid_for((int64_t)(m - 1) * (m - 1)), dim3(kWG), 0, s,
+                                        (const TT*)st, (const TT*)b, (const TT*)x, (TT*)r, m));
   return hipGetLastError();
 }
-hipError_t launch_q1_cheb(const double* st, const double* dinv, const double* b, const double* x,
-                          double* d, double* xo, double c1, double c2, int m, hipStream_t s) {
-  hipLaunchKernelGGL(k_q1_cheb, grid_for((int64_t)(m - 1) * (m - 1)), dim3(kWG), 0, s, st, dinv, b, x,
-                     d, xo, c1, c2, m);
+hipError_t launch_q1_cheb(Prec pr, const void* st, const void* dinv, const void* b, const void* x, void* d,
+                          void* xo, double c1, double c2, int m, hipStream_t s) {
+  HDG_DISPATCH_T(pr, hipLaunchKernelGGL(k_q1_cheb<TT>, grid_for((int64_t)(m - 1) * (m - 1)), dim3(kWG), 0, s,
+                                        (const TT*)st, (const TT*)dinv, (const TT*)b, (const TT*)x, (TT*)d,
+                                        (TT*)xo, c1, c2, m));
   return hipGetLastError();
 }
-hipError_t launch_q1_restrict(const double* rf, double* rc, int mf, hipStream_t s) {
+hipError_t launch_q1_restrict(Prec pr, const void* rf, void* rc, int mf, hipStream_t s) {
   const int mc = mf / 2;
-  hipLaunchKernelGGL(k_q1_restrict, grid_for((int64_t)(mc - 1) * (mc - 1)), dim3(kWG), 0, s, rf, rc, mf);
+  HDG_DISPATCH_T(pr, hipLaunchKernelGGL(k_q1_restrict<TT>, grid_for((int64_t)(mc - 1) * (mc - 1)), dim3(kWG), 0,
+                                        s, (const TT*)rf, (TT*)rc, mf));
   return hipGetLastError();
 }
-hipError_t launch_q1_prolong_add(const double* ec, double* xf, int mf, hipStream_t s) {
-  hipLaunchKernelGGL(k_q1_prolong_add, grid_for((int64_t)(mf - 1) * (mf - 1)), dim3(kWG), 0, s, ec, xf, mf);
+hipError_t launch_q1_prolong_add(Prec pr, const void* ec, void* xf, int mf, hipStream_t s) {
+  HDG_DISPATCH_T(pr, hipLaunchKernelGGL(k_q1_prolong_add<TT>, grid_for((int64_t)(mf - 1) * (mf - 1)), dim3(kWG),
+                                        0, s, (const TT*)ec, (TT*)xf, mf));
   return hipGetLastError();
 }
-hipError_t launch_pj_restrict(const double* rface, double* rv, int n, hipStream_t s) {
-  hipLaunchKernelGGL(k_pj_restrict, grid_for((int64_t)(n - 1) * (n - 1)), dim3(kWG), 0, s, rface, rv, n);
+hipError_t launch_pj_restrict(Prec pr, const void* rface, void* rv, int n, hipStream_t s) {
+  HDG_DISPATCH_T(pr, hipLaunchKernelGGL(k_pj_restrict<TT>, grid_for((int64_t)(n - 1) * (n - 1)), dim3(kWG), 0, s,
+                                        (const TT*)rface, (TT*)rv, n));
   return hipGetLastError();
 }
-hipError_t launch_pj_prolong_add(const double* ev, double* xface, int n, hipStream_t s) {
-  hipLaunchKernelGGL(k_pj_prolong_add, grid_for(2LL * n * (n - 1)), dim3(kWG), 0, s, ev, xface, n);
+hipError_t launch_pj_prolong_add(Prec pr, const void* ev, void* xface, int n, hipStream_t s) {
+  HDG_DISPATCH_T(pr, hipLaunchKernelGGL(k_pj_prolong_add<TT>, grid_for(2LL * n * (n - 1)), dim3(kWG), 0, s,
+                                        (const TT*)ev, (TT*)xface, n));
   return hipGetLastError();
 }
-hipError_t launch_dense_gemv(const double* A, const double* b, double* y, int m, hipStream_t s) {
-  hipLaunchKernelGGL(k_dense_gemv, dim3((m + 3) / 4), dim3(kWG), 0, s, A, b, y, m);
+hipError_t launch_dense_gemv(Prec pr, const double* A, const void* b, void* y, int m, hipStream_t s) {
+  HDG_DISPATCH_T(pr, hipLaunchKernelGGL(k_dense_gemv<TT>, dim3((m + 3) / 4), dim3(kWG), 0, s, A, (const TT*)b,
+                                        (TT*)y, m));
   return hipGetLastError();
 }
 
@@ -620,7 +709,8 @@ __global__ __launch_bounds__(kWG) void k_axpy_norm(double alpha, const double* q
   const double t = block_sum(s);
   if (threadIdx.x == 0) partial[blockIdx.x] = t;
 }
-__global__ __launch_bounds__(kWG) void k_copy(const double* x, double* y, int64_t n) {
+template <typename T>
+__global__ __launch_bounds__(kWG) void k_copy(const T* x, T* y, int64_t n) {
   const int64_t i = (int64_t)blockIdx.x * kWG + threadIdx.x;
   if (i < n) y[i] = x[i];
 }
@@ -628,9 +718,16 @@ __global__ __launch_bounds__(kWG) void k_fill(double v, double* y, int64_t n) {
   const int64_t i = (int64_t)blockIdx.x * kWG + threadIdx.x;
   if (i < n) y[i] = v;
 }
+__global__ __launch_bounds__(kWG) void k_to_f32(const double* x, float* y, int64_t n) {
+  const int64_t i = (int64_t)blockIdx.x * kWG + threadIdx.x;
+  if (i < n) y[i] = (float)x[i];
+}
+__global__ __launch_bounds__(kWG) void k_to_f64(const float* x, double* y, int64_t n) {
+  const int64_t i = (int64_t)blockIdx.x * kWG + threadIdx.x;
+  if (i < n) y[i] = (double)x[i];
+}
 
-hipError_t launch_dot_partials(const double* a, const double* b, int64_t n, double* partial,
-                               hipStream_t s) {
+hipError_t launch_dot_partials(const double* a, const double* b, int64_t n, double* partial, hipStream_t s) {
   hipLaunchKernelGGL(k_dot_partials, dim3(reduce_grid(n)), dim3(kWG), 0, s, a, b, n, partial);
   return hipGetLastError();
 }
@@ -653,14 +750,24 @@ hipError_t launch_axpy_norm(double alpha, const double* q, double* r, int64_t n,
   hipLaunchKernelGGL(k_axpy_norm, dim3(reduce_grid(n)), dim3(kWG), 0, s, alpha, q, r, n, partial);
   return hipGetLastError();
 }
-hipError_t launch_copy(const double* x, double* y, int64_t n, hipStream_t s) {
+hipError_t launch_copy(Prec pr, const void* x, void* y, int64_t n, hipStream_t s) {
   if (n == 0) return hipSuccess;
-  hipLaunchKernelGGL(k_copy, grid_for(n), dim3(kWG), 0, s, x, y, n);
+  HDG_DISPATCH_T(pr, hipLaunchKernelGGL(k_copy<TT>, grid_for(n), dim3(kWG), 0, s, (const TT*)x, (TT*)y, n));
   return hipGetLastError();
 }
 hipError_t launch_fill(double v, double* y, int64_t n, hipStream_t s) {
   if (n == 0) return hipSuccess;
   hipLaunchKernelGGL(k_fill, grid_for(n), dim3(kWG), 0, s, v, y, n);
+  return hipGetLastError();
+}
+hipError_t launch_to_f32(const double* x, float* y, int64_t n, hipStream_t s) {
+  if (n == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_to_f32, grid_for(n), dim3(kWG), 0, s, x, y, n);
+  return hipGetLastError();
+}
+hipError_t launch_to_f64(const float* x, double* y, int64_t n, hipStream_t s) {
+  if (n == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_to_f64, grid_for(n), dim3(kWG), 0, s, x, y, n);
   return hipGetLastError();
 }
 

@@ -1,10 +1,20 @@
 // Launchers of the gfx950 kernels (defined in kernels.hip).  All pointers are
 // device pointers; every launch is asynchronous on `stream`.
+//
+// Precision: vectors are FP64 (Prec::F64) or FP32 (Prec::F32, Prec::BF16);
+// block matrices are stored in FP64, FP32 or BF16 respectively and accumulated
+// in the vector type.  Pointers to vectors and matrices are untyped here and
+// interpreted by the precision passed to each launcher.
 #pragma once
 #include <hip/hip_runtime.h>
 #include <cstdint>
 
 namespace hdg {
+
+enum class Prec : int { F64 = 0, F32 = 1, BF16 = 2 };
+inline size_t vec_bytes(Prec p) { return p == Prec::F64 ? 8 : 4; }      // vector element
+inline size_t mat_bytes(Prec p) { return p == Prec::F64 ? 8 : (p == Prec::F32 ? 4 : 2); }
+inline int mat_lanes16(Prec p) { return (int)(16 / mat_bytes(p)); }      // entries per 16-byte load
 
 // Operation fused into the face-owned gather y_f = sum of the two elements'
 // block rows of face f times x (Sec. 8, Alg. algo_mv).
@@ -13,17 +23,17 @@ enum TraceMode : int {
   TM_RESID = 1,          // y = b - S x
   TM_FACE_SWEEP = 2,     // y = x + omega Dinv (b - S x)        (facet Schwarz sweep)
   TM_RESID_RESTRICT = 3, // y = P_p^T (b - S x)  (coarse vector, p - 1)
-  TM_APPLY_DOT = 4       // y = S x and per-workgroup partial sums of x . y
+  TM_APPLY_DOT = 4       // y = S x and per-wavefront partial sums of x . y
 };
 
 struct TraceArgs {
-  const double* slab;    // face-major blocks (layout of setup.hpp)
-  const double* x;
-  const double* b;       // RESID / SWEEP / RESID_RESTRICT
-  const double* dinv;    // SWEEP: face-block inverses, tile-pair layout
-  double* y;
-  double* partial;       // optional: per-wavefront sum of squares of (b - S x), or of x . y
-  const double* pmat;    // RESID_RESTRICT: P_p [(p+1) x p], row major (device)
+  const void* slab;      // face-major blocks (layout of setup.hpp), matrix precision
+  const void* x;
+  const void* b;         // RESID / SWEEP / RESID_RESTRICT
+  const void* dinv;      // SWEEP: face-block inverses, same interleaved layout
+  void* y;
+  double* partial;       // optional: per-wavefront sum of squares of (b - S x), or of x . y (FP64)
+  const void* pmat;      // RESID_RESTRICT: P_p [(p+1) x p], row major, vector precision
   double omega;
   int n;
   int64_t nf;            // interior faces
@@ -31,58 +41,62 @@ struct TraceArgs {
 };
 
 int trace_grid(int64_t ntiles);      // workgroups of a trace launch
-int trace_partials(int64_t ntiles);  // partial sums written when TraceArgs::partial is set (one per wavefront)
-hipError_t launch_trace(int P, int mode, const TraceArgs& a, hipStream_t s);
+int trace_partials(int64_t ntiles);  // partial sums written when TraceArgs::partial is set
+hipError_t launch_trace(Prec pr, int P, int mode, const TraceArgs& a, hipStream_t s);
 
 // x = omega Dinv b (first facet sweep from a zero guess)
-hipError_t launch_dinv_apply(int P, const double* dinv, const double* b, double omega, double* x,
+hipError_t launch_dinv_apply(Prec pr, int P, const void* dinv, const void* b, double omega, void* x,
                              int64_t nf, hipStream_t s);
-// face-local p-transfers, P = p_fine + 1
-hipError_t launch_p_restrict(int P, const double* pmat, const double* rf, double* rc, int64_t nf,
+// face-local p-transfers, P = p_fine + 1, P_p in vector precision
+hipError_t launch_p_restrict(Prec pr, int P, const void* pmat, const void* rf, void* rc, int64_t nf,
                              hipStream_t s);
-hipError_t launch_p_prolong_add(int P, const double* pmat, const double* ec, double* xf, int64_t nf,
+hipError_t launch_p_prolong_add(Prec pr, int P, const void* pmat, const void* ec, void* xf, int64_t nf,
                                 hipStream_t s);
 
 // chain Schwarz: out = x + omega M^{-1} r (x == nullptr: out = omega M^{-1} r);
 // M = block-tridiagonal matrix of each chain of faces, solved by block cyclic
-// reduction with the factors of chain_factor_layout (api.cpp).  out may alias x.
+// reduction with the factors built in api.cpp (vector precision).  out may alias x.
 struct ChainArgs {
-  const double* factors;  // per chain: cstride doubles
+  const void* factors;  // per chain: cstride entries
   int64_t cstride;
-  const double* r;
-  const double* x;
-  double* out;
+  const void* r;
+  const void* x;
+  void* out;
   double omega;
   int n;
 };
-hipError_t launch_chain_solve(int P, const ChainArgs& a, hipStream_t s);
+hipError_t launch_chain_solve(Prec pr, int P, const ChainArgs& a, hipStream_t s);
 
-// Q1 levels: 9-point stencil st[9][Nv] on the interior vertices of an m x m mesh.
-hipError_t launch_q1_resid(const double* st, const double* b, const double* x, double* r, int m,
+// Q1 levels (vector precision): 9-point stencil st[9][Nv] on the interior
+// vertices of an m x m mesh.
+hipError_t launch_q1_resid(Prec pr, const void* st, const void* b, const void* x, void* r, int m,
                            hipStream_t s);
 // Chebyshev step: z = dinv (b - A x); d = c1 d + c2 z; xo = x + d  (x == nullptr: x = 0)
-hipError_t launch_q1_cheb(const double* st, const double* dinv, const double* b, const double* x,
-                          double* d, double* xo, double c1, double c2, int m, hipStream_t s);
-hipError_t launch_q1_restrict(const double* rf, double* rc, int m_fine, hipStream_t s);
-hipError_t launch_q1_prolong_add(const double* ec, double* xf, int m_fine, hipStream_t s);
+hipError_t launch_q1_cheb(Prec pr, const void* st, const void* dinv, const void* b, const void* x,
+                          void* d, void* xo, double c1, double c2, int m, hipStream_t s);
+hipError_t launch_q1_restrict(Prec pr, const void* rf, void* rc, int m_fine, hipStream_t s);
+hipError_t launch_q1_prolong_add(Prec pr, const void* ec, void* xf, int m_fine, hipStream_t s);
 // p = 0 faces <-> Q1 vertices of the same mesh
-hipError_t launch_pj_restrict(const double* rface, double* rv, int n, hipStream_t s);
-hipError_t launch_pj_prolong_add(const double* ev, double* xface, int n, hipStream_t s);
-// y = Ainv b, dense m x m row major
-hipError_t launch_dense_gemv(const double* Ainv, const double* b, double* y, int m, hipStream_t s);
+hipError_t launch_pj_restrict(Prec pr, const void* rface, void* rv, int n, hipStream_t s);
+hipError_t launch_pj_prolong_add(Prec pr, const void* ev, void* xface, int n, hipStream_t s);
+// y = Ainv b with an FP64 dense m x m inverse; b, y in vector precision
+hipError_t launch_dense_gemv(Prec pr, const double* Ainv, const void* b, void* y, int m, hipStream_t s);
 
-// deterministic reductions
+// deterministic reductions (FP64 vectors)
 int reduce_grid(int64_t n);
 hipError_t launch_dot_partials(const double* a, const double* b, int64_t n, double* partial,
                                hipStream_t s);
 hipError_t launch_sum_partials(const double* partial, int np, double* out, hipStream_t s);
-// vector updates
+// vector updates (FP64)
 hipError_t launch_axpy(double alpha, const double* x, double* y, int64_t n, hipStream_t s);   // y += a x
 hipError_t launch_xpby(const double* x, double beta, double* y, int64_t n, hipStream_t s);    // y = x + b y
 // r -= alpha q and per-workgroup sum of squares of the new r
 hipError_t launch_axpy_norm(double alpha, const double* q, double* r, int64_t n, double* partial,
                             hipStream_t s);
-hipError_t launch_copy(const double* x, double* y, int64_t n, hipStream_t s);
+// copies in vector precision, conversions between FP64 and FP32
+hipError_t launch_copy(Prec pr, const void* x, void* y, int64_t n, hipStream_t s);
 hipError_t launch_fill(double v, double* y, int64_t n, hipStream_t s);
+hipError_t launch_to_f32(const double* x, float* y, int64_t n, hipStream_t s);
+hipError_t launch_to_f64(const float* x, double* y, int64_t n, hipStream_t s);
 
 }  // namespace hdg

@@ -49,7 +49,7 @@ def test_quadrature_nodes_match_oracle():
 
 @pytest.mark.parametrize("field,value,code", [("n", 1, -1), ("k", 9, -1), ("k", -1, -1), ("tau", 0.0, -1),
                                               ("nu1", 0, -1), ("smoother", 7, -1), ("cheb_lo", 2.0, -1),
-                                              ("nq", 0, -1)])
+                                              ("nq", 0, -1), ("precision", 3, -1), ("precision", -1, -1)])
 def test_create_rejects_bad_config_before_any_device_call(field, value, code):
     cfg = H.Config()
     assert H.lib.hdg_config_default(8, 2, ctypes.byref(cfg)) == 0
@@ -58,6 +58,29 @@ def test_create_rejects_bad_config_before_any_device_call(field, value, code):
     h = ctypes.c_void_p()
     st = H.lib.hdg_create(ctypes.byref(cfg), kap.ctypes.data_as(H._PD), None, ctypes.byref(h))
     assert st == code and not h.value
+
+
+@pytest.mark.parametrize("prec", [1, 2])
+def test_reduced_precision_face_smoother_needs_omega(prec):
+    cfg = H.Config()
+    H.lib.hdg_config_default(8, 2, ctypes.byref(cfg))
+    cfg.smoother, cfg.precision = H.SMOOTHERS["face"], prec
+    kap = np.ones(64)
+    h = ctypes.c_void_p()
+    assert H.lib.hdg_create(ctypes.byref(cfg), kap.ctypes.data_as(H._PD), None, ctypes.byref(h)) == -1
+    assert not h.value
+
+
+def test_config_layout_matches_header():
+    """The Python mirror of hdg_config_t has the C layout (size and field offsets)."""
+    import re
+    src = open(__import__("os").path.join(__import__("os").path.dirname(__file__), "..", "include",
+                                          "hdggmg.h")).read()
+    body = src[src.index("typedef struct {"):src.index("} hdg_config_t;")]
+    names = re.findall(r"^\s*(?:int32_t|double)\s+([a-z_0-9]+(?:\s*,\s*[a-z_0-9]+)*)", body, re.M)
+    fields = [f.strip() for grp in names for f in grp.split(",")]
+    assert fields == [f[0] for f in H.Config._fields_]
+    assert ctypes.sizeof(H.Config) == 4 + 4 + 8 + 4 + 4 + 4 + 4 + 8 * 9 + 16 + 8 * 24 + 4 + 4 + 4 + 4 * 7
 
 
 @pytest.mark.parametrize("bad", [0.0, -1.0, np.nan, np.inf])
