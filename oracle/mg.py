@@ -43,6 +43,18 @@ nu1 = nu2), so it also serves as a preconditioner for conjugate gradients
 (Sec. 6, p-transfer paragraph).  Convergence monitor: the residual ratio of
 Sec. 7; stop at ||b - S x||_2 <= rtol ||b||_2.
 
+Krylov-accelerated coarse levels (not in the paper; an extension of its
+cycle): the K-cycle of Notay and Vassilevski (Numer. Linear Algebra Appl. 15,
+2008).  On the p-levels named in `inner`, the coarse-grid correction is not
+one recursive cycle but m steps of flexible conjugate gradients on that
+level's system, each step preconditioned by one cycle started at that level
+(itself possibly Krylov-accelerated further down).  Flexible CG is Notay's
+FCG(1) (SIAM J. Sci. Comput. 22, 2000): the new direction is A-orthogonalised
+against the previous one only, d = z - (z . q_prev / d_prev . q_prev) d_prev,
+and the step is alpha = d . r / d . q.  A cycle containing such levels is a
+nonlinear map, so the outer solver is FCG as well (mode 'fcg'); with a fixed
+symmetric cycle FCG reproduces preconditioned CG.
+
 Parity unpinned: the multigrid convergence factor itself.  The paper's
 figure (rho < 0.22) is for an FSAI smoother, so no printed value exists for
 these smoothers; tests check V-cycle and PCG solutions against the direct
@@ -245,8 +257,10 @@ class Hierarchy:
     """
 
     def __init__(self, n, k, kappa, tau=1.0, nu1=2, nu2=2, coarse='galerkin', smoother='chain',
-                 omega=None, lmax=None, cheb_lo=0.1, cheb_hi=1.1, coarse_max=2000, blocks_k=None):
+                 omega=None, lmax=None, cheb_lo=0.1, cheb_hi=1.1, coarse_max=2000, blocks_k=None,
+                 inner=None):
         self.n, self.k, self.nu1, self.nu2 = n, k, nu1, nu2
+        self.inner = dict(inner or {})   # p-level -> flexible-CG steps of its coarse correction
         self.cheb_lo, self.cheb_hi = cheb_lo, cheb_hi
         self.smoother = smoother
         if omega is None or np.isscalar(omega):
@@ -318,18 +332,44 @@ class Hierarchy:
         x = self.smooth(L, b, x, self.nu1)
         r = b - L.A @ x
         rc = L.Pmat.T @ r
-        ec = self.vcycle(rc, np.zeros(rc.shape[0]), lev + 1)
+        C = self.levels[lev + 1]
+        m = self.inner.get(C.p, 0) if C.kind == 'p' else 0
+        if m > 0:
+            ec = self.krylov_correction(lev + 1, rc, m)
+        else:
+            ec = self.vcycle(rc, np.zeros(rc.shape[0]), lev + 1)
         x = x + L.Pmat @ ec
         x = self.smooth(L, b, x, self.nu2)
         return x
+
+    def krylov_correction(self, lev, b, m):
+        """m steps of FCG(1) for A_lev e = b from e = 0, each preconditioned by one
+        cycle started at level lev (the K-cycle's coarse correction)."""
+        A = self.levels[lev].A
+        e = np.zeros_like(b)
+        r = b.copy()
+        d = q = dq = None
+        for step in range(m):
+            z = self.vcycle(r, np.zeros_like(r), lev)
+            d = z if d is None else z - ((z @ q) / dq) * d
+            q = A @ d
+            dq = d @ q
+            if not dq > 0.0:        # r == 0: nothing left to correct
+                break
+            alpha = (d @ r) / dq
+            e = e + alpha * d
+            r = r - alpha * q
+        return e
 
     def solve(self, b, x0=None, rtol=1e-10, maxit=200, mode='pcg'):
         """Solve S x = b to ||r||_2 <= rtol ||b||_2.
 
         mode 'vcycle': repeated V-cycles (the paper's stationary solver);
         mode 'pcg': conjugate gradients preconditioned by one V-cycle with zero
-        initial guess.  Returns x and the residual-norm history (entry 0 is the
-        initial residual; for 'pcg' the recursively updated residual)."""
+        initial guess; mode 'fcg': flexible CG, FCG(1), with the same
+        preconditioner (needed when the cycle has Krylov-accelerated levels).
+        Returns x and the residual-norm history (entry 0 is the initial
+        residual; for 'pcg' / 'fcg' the recursively updated residual)."""
         S = self.levels[0].A
         x = np.zeros(S.shape[0]) if x0 is None else np.array(x0, dtype=np.float64)
         nb = np.linalg.norm(b)
@@ -339,6 +379,18 @@ class Hierarchy:
             while hist[-1] > rtol * nb and len(hist) <= maxit:
                 x = self.vcycle(b, x)
                 hist.append(np.linalg.norm(b - S @ x))
+            return x, np.array(hist)
+        if mode == 'fcg':
+            d = q = dq = None
+            while hist[-1] > rtol * nb and len(hist) <= maxit:
+                z = self.vcycle(r, np.zeros_like(r))
+                d = z if d is None else z - ((z @ q) / dq) * d
+                q = S @ d
+                dq = d @ q
+                alpha = (d @ r) / dq
+                x = x + alpha * d
+                r = r - alpha * q
+                hist.append(np.linalg.norm(r))
             return x, np.array(hist)
         z = self.vcycle(r, np.zeros_like(r))
         d = z.copy()

@@ -4,7 +4,7 @@ import pytest
 import scipy.sparse as sp
 
 from oracle import hdg, mg, mesh as ms, quadrature as qd
-from workloads import kappa_lognormal, SinSin
+from workloads import kappa_lognormal, normal_vector, SinSin
 
 
 @pytest.mark.parametrize("p", range(1, 8))
@@ -150,3 +150,52 @@ def test_rediscretized_coarse_level_amplifies_rough_modes():
     G = (P.T @ S1 @ P).toarray()
     w = np.linalg.eigvals(np.linalg.solve(S0.toarray(), G)).real
     assert w.max() > 5.0       # coarse correction over-shoots some modes several-fold
+
+
+def test_krylov_correction_is_exact_after_dim_steps():
+    """K-cycle pin: with a fixed symmetric positive definite cycle below it, FCG(1)
+    is preconditioned CG, which ends at the exact solution after dim(level) steps.
+    So a Krylov-accelerated level with m = dim steps equals an exact coarse solve,
+    computed here with a sparse direct solver (no Krylov code involved)."""
+    import scipy.sparse.linalg as spla
+    n, k, p = 2, 2, 1
+    kap = kappa_lognormal(n, 1.0, 3)
+    N1 = ms.n_trace_dofs(n, p)
+    Hk = mg.Hierarchy(n, k, kap, inner={p: N1})
+    H = mg.Hierarchy(n, k, kap, omega=Hk.omega, lmax=Hk.lmax)
+    b = normal_vector(ms.n_trace_dofs(n, k), 4)
+    L, C = H.levels[0], H.levels[1]
+    assert C.kind == 'p' and C.p == p
+    x = H.smooth(L, b, np.zeros_like(b), H.nu1)
+    ec = spla.spsolve(C.A.tocsc(), L.Pmat.T @ (b - L.A @ x))
+    x = H.smooth(L, b, x + L.Pmat @ ec, H.nu2)
+    xk = Hk.vcycle(b, np.zeros_like(b))
+    assert np.abs(xk - x).max() <= 1e-9 * np.abs(x).max()
+
+
+def test_fcg_reduces_to_pcg_for_a_fixed_symmetric_cycle():
+    n, k = 16, 2
+    kap = kappa_lognormal(n, 1.0, 8)
+    pr = hdg.Problem(n, k, kap)
+    b = pr.rhs(np.ones((n * n, pr.ref.nq ** 2)))
+    H = mg.Hierarchy(n, k, kap)
+    x1, h1 = H.solve(b, mode='pcg', rtol=1e-10)
+    x2, h2 = H.solve(b, mode='fcg', rtol=1e-10)
+    m = min(len(h1), len(h2), 8)
+    assert np.allclose(h1[:m], h2[:m], rtol=1e-7, atol=0)
+    assert np.linalg.norm(x1 - x2) <= 1e-8 * np.linalg.norm(x1)
+
+
+@pytest.mark.parametrize("inner", [{0: 3}, {1: 2, 0: 2}])
+def test_kcycle_solution_matches_direct_in_fewer_iterations(inner):
+    n, k = 32, 3
+    kap = kappa_lognormal(n, 2.0, 9)
+    pr = hdg.Problem(n, k, kap)
+    b = pr.rhs(np.ones((n * n, pr.ref.nq ** 2)))
+    H = mg.Hierarchy(n, k, kap)
+    _, hv = H.solve(b, mode='pcg', rtol=1e-10)
+    Hk = mg.Hierarchy(n, k, kap, omega=H.omega, lmax=H.lmax, inner=inner)
+    x, hk = Hk.solve(b, mode='fcg', rtol=1e-10)
+    assert hk[-1] <= 1e-10 * np.linalg.norm(b)
+    assert np.linalg.norm(x - pr.solve_direct(b)) <= 1e-9 * np.linalg.norm(x)
+    assert len(hk) < len(hv)
