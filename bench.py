@@ -30,9 +30,9 @@ METRIC = "trace-DoF/s of matrix-free HDG apply; GMG solve time to 1e-10 rel. res
 HBM_PEAK_GBS = 8000.0
 
 WORKLOADS = {
-    "lognormal_n256_k4": dict(n=256, k=4, sigma=1.0, seed=2),
-    "lognormal_n1024_k3": dict(n=1024, k=3, sigma=2.0, seed=3),
-    "poisson_sin_n16_k1": dict(n=16, k=1, sigma=None, seed=None),
+    "lognormal_n256_k4": dict(n=256, k=4, sigma=1.0, seed=2, inner="1:2,0:2"),
+    "lognormal_n1024_k3": dict(n=1024, k=3, sigma=2.0, seed=3, inner="1:4,0:4"),
+    "poisson_sin_n16_k1": dict(n=16, k=1, sigma=None, seed=None, inner=""),
 }
 
 
@@ -83,7 +83,11 @@ def main():
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--workload", default="lognormal_n256_k4", choices=sorted(WORKLOADS))
-    ap.add_argument("--mode", default="pcg", choices=["pcg", "vcycle"])
+    ap.add_argument("--mode", default="auto", choices=["auto", "pcg", "vcycle", "fcg"],
+                    help="outer solver; auto = fcg with K-cycle levels, else pcg")
+    ap.add_argument("--inner", default="auto",
+                    help="K-cycle steps per p-level, e.g. '1:3,0:3'; 'auto' = the workload's tuned "
+                         "setting, '' = plain V-cycle")
     ap.add_argument("--smoother", default="chain", choices=["chain", "face"])
     ap.add_argument("--precision", default="f64", choices=["f64", "f32", "bf16"],
                     help="precision of the multigrid cycle and of the timed apply")
@@ -101,14 +105,18 @@ def main():
     import paper_1705_09907_amd as H
     from workloads import kappa_lognormal, normal_vector
 
-    w = WORKLOADS[args.workload]
     n, k = w["n"], w["k"]
     kap = kappa_lognormal(n, w["sigma"], w["seed"]) if w["sigma"] else np.ones(n * n)
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
     t0 = time.perf_counter()
     lp = args.precision != "f64"
-    S = H.Solver(n, k, kap, smoother=args.smoother, precision=args.precision)
+    w = WORKLOADS[args.workload]
+    spec = w["inner"] if args.inner == "auto" else args.inner
+    inner = {int(p): int(m) for p, m in (t.split(":") for t in spec.split(",") if t)}
+    if args.mode == "auto":
+        args.mode = "fcg" if inner else "pcg"
+    S = H.Solver(n, k, kap, smoother=args.smoother, precision=args.precision, inner=inner)
     torch.cuda.synchronize()
     setup_s = time.perf_counter() - t0
     N = S.num_dofs()
@@ -172,10 +180,30 @@ def main():
         dst.copy_(src)
         torch.cuda.synchronize()
 
+    def time_solve(solver, mode, reps=3):
+        ts, res = [], None
+        for rep in range(reps):
+            lam.zero_()
+            s0, s1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            s0.record(stream)
+            _, itr, rrr, _ = solver.solve(b, lam, rtol=1e-10, maxit=500, mode=mode)
+            s1.record(stream)
+            torch.cuda.synchronize()
+            if rep:
+                ts.append(s0.elapsed_time(s1))
+            res = (itr, rrr)
+        return {"solve_ms": float(np.median(ts)), "solve_iters": res[0], "solve_relres": res[1]}
+
+    plain_ref = None
+    if inner:  # the paper's plain V-cycle preconditioner (same precision), after the timed region
+        Sp = H.Solver(n, k, kap, smoother=args.smoother, precision=args.precision)
+        plain_ref = dict(time_solve(Sp, "pcg"), solver="pcg + V(2,2)")
+        Sp.close()
+
     f64_ref = None
     if lp:  # the plain FP64 path on the same system, same accuracy, after the timed region
         S.close()
-        S64 = H.Solver(n, k, kap, smoother=args.smoother)
+        S64 = H.Solver(n, k, kap, smoother=args.smoother, inner=inner)
         x64 = x.double()
         y64 = torch.empty_like(x64)
         at, st_ms = [], []
@@ -210,13 +238,14 @@ def main():
         "config": {"workload": args.workload, "n": n, "k": k, "tau": 1.0,
                    "kappa": f"lognormal sigma={w['sigma']} seed={w['seed']}" if w["sigma"] else "1",
                    "f": 1.0, "trace_dofs": N,
-                   "solver": f"{args.mode} + V(2,2), {args.smoother} Schwarz, {args.precision} cycle",
+                   "solver": f"{args.mode} + V(2,2), {args.smoother} Schwarz, {args.precision} cycle"
+                             + (f", K-cycle inner steps {inner}" if inner else ""),
                    "rtol": 1e-10},
         "apply_us_cold": float(np.mean(apply_ms)) * 1e3,
         "apply_us_warm": None if warm_ms is None else warm_ms * 1e3,
         "solve_ms": float(np.median(solve_ms)), "solve_iters": iters, "solve_relres": relres,
         "solve_rate": rho, "setup_s": setup_s, "rhs_s": rhs_s,
-        "f64_reference": f64_ref,
+        "f64_reference": f64_ref, "plain_vcycle_pcg_reference": plain_ref,
         "roofline": {"bound": "hbm", "kernel": f"k_trace<P={k + 1}, APPLY, {args.precision}>", "achieved": achieved,
                      "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
                      "traffic": None, "algorithmic_bytes": byts, "flops": flops},

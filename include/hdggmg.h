@@ -51,7 +51,7 @@ typedef enum {
 
 enum { HDG_SMOOTH_CHAIN = 0, HDG_SMOOTH_FACE = 1 };
 enum { HDG_COARSE_GALERKIN = 0, HDG_COARSE_REDISCRETIZE = 1 };
-enum { HDG_SOLVE_PCG = 0, HDG_SOLVE_VCYCLE = 1 };
+enum { HDG_SOLVE_PCG = 0, HDG_SOLVE_VCYCLE = 1, HDG_SOLVE_FCG = 2 };
 /* Precision of the multigrid cycle (the preconditioner).  The outer solver, its
  * residuals and the finest-level operator it applies stay FP64 in every mode.
  *   HDG_PREC_F64:  every level, vector and block in FP64 (the paper's setting).
@@ -89,7 +89,14 @@ typedef struct {
   int32_t nq;           /* Gauss-Legendre points per direction of f input (default k + 2) */
   int32_t precision;    /* HDG_PREC_F64 (default), HDG_PREC_F32 or HDG_PREC_BF16; reduced
                            precision with the facet smoother needs every omega[p] > 0     */
-  int32_t reserved[7];
+  int32_t inner_steps[HDG_MAX_DEGREE + 1]; /* K-cycle (Notay-Vassilevski): for p < k,
+                           inner_steps[p] = m > 0 replaces the level-p coarse correction
+                           of the cycle by m steps of flexible CG on S_p, each
+                           preconditioned by one cycle from level p (an extension of the
+                           paper's V-cycle; the cycle becomes nonlinear, so solve with
+                           HDG_SOLVE_FCG or HDG_SOLVE_VCYCLE).  0 (default): V-cycle.
+                           Range [0, 64]; must be 0 for p >= k.                          */
+  int32_t reserved[8];
 } hdg_config_t;
 
 /* Defaults: tau 1, V(2,2), chain smoother, Galerkin p-levels, omega/lmax estimated,
@@ -178,8 +185,10 @@ hdg_status_t hdg_vcycle(hdg_handle_t h, const double* b, double* x);
 
 /* Solve S_k x = b to ||b - S x||_2 <= rtol ||b||_2, x in: initial guess, out:
  * solution.  mode HDG_SOLVE_PCG (conjugate gradients preconditioned by one
- * V-cycle) or HDG_SOLVE_VCYCLE (repeated V-cycles, the paper's stationary
- * solver).  iters, relres: host outputs (nullable); history_host: nullable
+ * V-cycle), HDG_SOLVE_FCG (flexible CG, FCG(1), with the same preconditioner;
+ * required instead of PCG when inner_steps makes the cycle nonlinear -- PCG
+ * then returns INVALID_ARG) or HDG_SOLVE_VCYCLE (repeated cycles, the paper's
+ * stationary solver, applied as x += B (b - S x)).  iters, relres: host outputs (nullable); history_host: nullable
  * [maxit + 1] residual norms (entry 0 = initial).  Returns NOT_CONVERGED if
  * maxit is reached (outputs still valid), NONFINITE on NaN/Inf. */
 hdg_status_t hdg_solve(hdg_handle_t h, const double* b, double* x, double rtol, int32_t maxit,

@@ -17,7 +17,7 @@ HDG_MAX_DEGREE = 8
 HDG_MAX_HLEVELS = 24
 SMOOTHERS = {"chain": 0, "face": 1}
 COARSE = {"galerkin": 0, "rediscretize": 1}
-MODES = {"pcg": 0, "vcycle": 1}
+MODES = {"pcg": 0, "vcycle": 1, "fcg": 2}
 PRECISIONS = {"f64": 0, "f32": 1, "bf16": 2}
 STATUS = {0: "ok", -1: "invalid argument", -2: "out of memory", -3: "HIP error",
           -4: "not converged", -5: "non-finite value", -6: "invalid state"}
@@ -31,7 +31,8 @@ class Config(ctypes.Structure):
                 ("cheb_lo", ctypes.c_double), ("cheb_hi", ctypes.c_double),
                 ("cheb_lmax", ctypes.c_double * HDG_MAX_HLEVELS),
                 ("coarse_max", ctypes.c_int32), ("nq", ctypes.c_int32),
-                ("precision", ctypes.c_int32), ("reserved", ctypes.c_int32 * 7)]
+                ("precision", ctypes.c_int32), ("inner_steps", ctypes.c_int32 * (HDG_MAX_DEGREE + 1)),
+                ("reserved", ctypes.c_int32 * 8)]
 
 
 _P = ctypes.c_void_p
@@ -126,7 +127,7 @@ class Solver:
 
     def __init__(self, n, k, kappa, tau=1.0, nu1=2, nu2=2, smoother="chain", coarse="galerkin",
                  omega=None, cheb_lmax=None, cheb=(0.1, 1.1), coarse_max=2000, nq=None, stream=None,
-                 precision="f64"):
+                 precision="f64", inner=None):
         import torch
         cfg = Config()
         lib.hdg_config_default(n, k, ctypes.byref(cfg))
@@ -144,6 +145,8 @@ class Solver:
         if nq is not None:
             cfg.nq = nq
         cfg.precision = PRECISIONS[precision]
+        for p, m in (inner or {}).items():
+            cfg.inner_steps[p] = m
         self.n, self.k, self.nq, self.precision = n, k, cfg.nq, precision
         kap, kp = _host(kappa, "kappa", n * n)
         if stream is None:

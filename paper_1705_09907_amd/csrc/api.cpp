@@ -35,6 +35,8 @@ struct PLevel {
   double* pmat64 = nullptr;
   double omega = 0.8;
   void *x = nullptr, *b = nullptr, *r = nullptr, *t = nullptr;
+  int inner = 0;                                      // K-cycle: FCG steps of this level's correction
+  void *kz = nullptr, *kd = nullptr, *kq = nullptr;   // K-cycle work vectors
 };
 
 struct QLevel {
@@ -62,8 +64,8 @@ struct hdg_ctx {
   std::vector<void*> allocs;
   double* partial = nullptr;
   int npartial = 0;
-  double* scal = nullptr;      // device scalar
-  double* scal_h = nullptr;    // pinned host scalar
+  double* scal = nullptr;      // device scalars [4]
+  double* scal_h = nullptr;    // pinned host scalars [4]
   double *vr = nullptr, *vz = nullptr, *vd = nullptr, *vq = nullptr;  // solver vectors (FP64)
   void *cva = nullptr, *cvb = nullptr;  // cycle-precision copies of FP64 vectors (size N(k))
   hdg::Prec prec = hdg::Prec::F64;      // precision of the multigrid cycle
@@ -447,6 +449,24 @@ double dot(hdg_ctx* h, const double* a, const double* b, int64_t n) {
   return reduce_scalar(h, hdg::reduce_grid(n));
 }
 
+// Up to three dot products of vectors in precision pr, summed in FP64; one
+// synchronization.  pairs: {x0, y0, x1, y1, ...}
+void dots(hdg_ctx* h, hdg::Prec pr, int nd, std::initializer_list<const void*> pairs, int64_t n, double* out) {
+  hdg::DotArgs d{};
+  d.ndots = nd;
+  auto it = pairs.begin();
+  for (int j = 0; j < nd; ++j) {
+    d.x[j] = *it++;
+    d.y[j] = *it++;
+  }
+  const int np = hdg::reduce_grid(n);
+  hipchk(hdg::launch_dots(pr, d, n, h->partial, h->stream), "dots");
+  hipchk(hdg::launch_sum_partials_multi(h->partial, np, nd, h->scal, h->stream), "sum");
+  hipchk(hipMemcpyAsync(h->scal_h, h->scal, nd * sizeof(double), hipMemcpyDeviceToHost, h->stream), "d2h");
+  hipchk(hipStreamSynchronize(h->stream), "sync");
+  for (int j = 0; j < nd; ++j) out[j] = h->scal_h[j];
+}
+
 // Trace-kernel arguments of level L for FP64 (pr == F64) or the cycle precision:
 // the cycle uses the level's own blocks, FP64 in a reduced-precision cycle uses
 // the FP64 copy.  kprec() is the precision the kernel is launched with.
@@ -567,8 +587,11 @@ void qcycle(hdg_ctx* h, int l) {
   chebyshev(h, Q, Q.b, h->cfg.nu2, false);
 }
 
+void krylov_correction(hdg_ctx* h, int p, void* r, void* e, int m);
+
 // V-cycle at p-level p for S_p x = b in the cycle precision; zero: x == 0 on
-// entry (its content is ignored)
+// entry (its content is ignored).  A coarser p-level with inner > 0 takes its
+// correction from krylov_correction (K-cycle) instead of one recursive cycle.
 void pcycle(hdg_ctx* h, int p, const void* b, void* x, bool zero) {
   PLevel& L = h->pl[p];
   const hdg::Prec pr = h->prec;
@@ -580,7 +603,8 @@ void pcycle(hdg_ctx* h, int p, const void* b, void* x, bool zero) {
     a.b = b;
     a.y = C.b;
     hipchk(hdg::launch_trace(L.mp, L.P, hdg::TM_RESID_RESTRICT, a, h->stream), "resid restrict");
-    pcycle(h, p - 1, C.b, C.x, true);
+    if (C.inner > 0) krylov_correction(h, p - 1, C.b, C.x, C.inner);
+    else pcycle(h, p - 1, C.b, C.x, true);
     hipchk(hdg::launch_p_prolong_add(pr, L.P, L.pmat, C.x, x, h->nf, h->stream), "p prolong");
   } else {
     residual(h, 0, b, x, L.r, false, pr);
@@ -590,6 +614,43 @@ void pcycle(hdg_ctx* h, int p, const void* b, void* x, bool zero) {
     hipchk(hdg::launch_pj_prolong_add(pr, Q.x, x, h->n, h->stream), "pj prolong");
   }
   smooth(h, p, b, x, h->cfg.nu2, false);
+}
+
+// K-cycle coarse correction (Notay-Vassilevski): m steps of flexible CG, FCG(1),
+// for S_p e = r from e = 0, each preconditioned by one cycle started at level p.
+// r is overwritten (it becomes the running residual).  Direction update
+// d = z - (z . q / d . q) d_prev, step alpha = d . r / d . q with
+// d . r = z . r - beta d_prev . r (three dots, one synchronization).
+void krylov_correction(hdg_ctx* h, int p, void* r, void* e, int m) {
+  PLevel& L = h->pl[p];
+  const hdg::Prec pr = h->prec;
+  const int64_t N = L.N;
+  hipchk(hdg::launch_zero(pr, e, N, h->stream), "zero");
+  double dq = 0.0;
+  for (int step = 0; step < m; ++step) {
+    pcycle(h, p, r, L.kz, true);
+    double dr;
+    if (step == 0) {
+      hipchk(hdg::launch_copy(pr, L.kz, L.kd, N, h->stream), "copy");
+      dots(h, pr, 1, {L.kz, r}, N, &dr);
+    } else {
+      double v[3];
+      dots(h, pr, 3, {L.kz, L.kq, L.kz, r, L.kd, r}, N, v);
+      const double beta = v[0] / dq;
+      hipchk(hdg::launch_xpby(pr, L.kz, -beta, L.kd, N, h->stream), "xpby");
+      dr = v[1] - beta * v[2];
+    }
+    hdg::TraceArgs ta = targs(h, L, pr);
+    ta.x = L.kd;
+    ta.y = L.kq;
+    ta.partial = h->partial;
+    hipchk(hdg::launch_trace(L.mp, L.P, hdg::TM_APPLY_DOT, ta, h->stream), "apply dot");
+    dq = reduce_scalar(h, hdg::trace_partials(h->ntiles));
+    if (!(dq > 0.0) || !std::isfinite(dq)) break;  // r == 0: nothing left to correct
+    const double alpha = dr / dq;
+    hipchk(hdg::launch_axpy(pr, alpha, L.kd, e, N, h->stream), "axpy");
+    if (step + 1 < m) hipchk(hdg::launch_axpy(pr, -alpha, L.kq, r, N, h->stream), "axpy");
+  }
 }
 
 // FP64 vector <-> cycle-precision staging buffer (no-op copy-free in FP64 mode)
@@ -681,6 +742,10 @@ void validate_config(const hdg_config_t* c) {
   if ((int64_t)c->n * c->n > (int64_t)1 << 31) throw ArgError("n too large");
   if (c->precision != HDG_PREC_F64 && c->precision != HDG_PREC_F32 && c->precision != HDG_PREC_BF16)
     throw ArgError("bad precision");
+  for (int p = 0; p <= HDG_MAX_DEGREE; ++p) {
+    if (c->inner_steps[p] < 0 || c->inner_steps[p] > 64) throw ArgError("inner_steps must be in [0, 64]");
+    if (p >= c->k && c->inner_steps[p] != 0) throw ArgError("inner_steps[p] must be 0 for p >= k");
+  }
   const int64_t vb = c->precision == HDG_PREC_F64 ? 8 : 4;
   if (c->smoother == HDG_SMOOTH_CHAIN && (int64_t)(c->n - 1) * (c->k + 1) * vb > 65536)
     throw ArgError("chain smoother keeps one chain in LDS: needs (n-1)(k+1) * (8 bytes FP64, 4 bytes "
@@ -772,13 +837,16 @@ hdg_status_t hdg_create(const hdg_config_t* cfg, const double* kappa_host, void*
       }
       L.omega = cfg->omega[p] > 0 ? cfg->omega[p] : 0.8;
       for (void** q : {&L.x, &L.b, &L.r, &L.t}) *q = valloc(h.get(), L.N);
+      L.inner = cfg->inner_steps[p];
+      if (L.inner > 0)
+        for (void** q : {&L.kz, &L.kd, &L.kq}) *q = valloc(h.get(), L.N);
       if (p == 0) build_hlevels(h.get(), blocks);
     }
     const int64_t Nk = h->pl[h->k].N;
-    h->npartial = std::max(hdg::trace_partials(h->ntiles), 1024);
+    h->npartial = std::max(hdg::trace_partials(h->ntiles), 3 * 1024);
     h->partial = dalloc(h.get(), h->npartial);
-    h->scal = dalloc(h.get(), 1);
-    hipchk(hipHostMalloc((void**)&h->scal_h, sizeof(double), hipHostMallocDefault), "pinned");
+    h->scal = dalloc(h.get(), 4);
+    hipchk(hipHostMalloc((void**)&h->scal_h, 4 * sizeof(double), hipHostMallocDefault), "pinned");
     h->vr = dalloc(h.get(), Nk);
     h->vz = dalloc(h.get(), Nk);
     h->vd = dalloc(h.get(), Nk);
@@ -1047,8 +1115,14 @@ hdg_status_t hdg_vcycle(hdg_handle_t h, const double* b, double* x) {
 hdg_status_t hdg_solve(hdg_handle_t h, const double* b, double* x, double rtol, int32_t maxit,
                        int32_t mode, int32_t* iters, double* relres, double* history_host) {
   if (!h || !b || !x || b == x || maxit < 0 || !(rtol >= 0.0) ||
-      (mode != HDG_SOLVE_PCG && mode != HDG_SOLVE_VCYCLE))
+      (mode != HDG_SOLVE_PCG && mode != HDG_SOLVE_VCYCLE && mode != HDG_SOLVE_FCG))
     return HDG_ERR_INVALID_ARG;
+  if (mode == HDG_SOLVE_PCG)
+    for (const PLevel& L : h->pl)
+      if (L.inner > 0) {
+        h->err = "a cycle with Krylov-accelerated levels is nonlinear: use HDG_SOLVE_FCG or HDG_SOLVE_VCYCLE";
+        return HDG_ERR_INVALID_ARG;
+      }
   return guarded(h, [&]() -> hdg_status_t {
     const int k = h->k;
     const int64_t N = h->pl[k].N;
@@ -1080,9 +1154,14 @@ hdg_status_t hdg_solve(hdg_handle_t h, const double* b, double* x, double rtol, 
         }
       }
     } else if (rn > tol && maxit > 0) {
+      // conjugate gradients (PCG), or flexible CG, FCG(1) (Notay): the direction is
+      // A-orthogonalised against the previous one, d = z - (z . q / d . q) d, and
+      // alpha = d . r / d . q with d . r = z . r - beta d_prev . r
+      const bool flex = mode == HDG_SOLVE_FCG;
       precondition(h, h->vr, h->vz);
       hipchk(hdg::launch_copy(hdg::Prec::F64, h->vz, h->vd, N, h->stream), "copy");
       double rz = dot(h, h->vr, h->vz, N);
+      double dr = rz;
       while (rn > tol && it < maxit) {
         hdg::TraceArgs ta = targs(h, h->pl[k], hdg::Prec::F64);
         ta.x = h->vd;
@@ -1090,7 +1169,7 @@ hdg_status_t hdg_solve(hdg_handle_t h, const double* b, double* x, double rtol, 
         ta.partial = h->partial;
         hipchk(hdg::launch_trace(hdg::Prec::F64, h->pl[k].P, hdg::TM_APPLY_DOT, ta, h->stream), "apply dot");
         const double dq = reduce_scalar(h, hdg::trace_partials(h->ntiles));
-        const double alpha = rz / dq;
+        const double alpha = dr / dq;
         hipchk(hdg::launch_axpy(alpha, h->vd, x, N, h->stream), "axpy");
         hipchk(hdg::launch_axpy_norm(alpha, h->vq, h->vr, N, h->partial, h->stream), "axpy norm");
         rn = std::sqrt(reduce_scalar(h, hdg::reduce_grid(N)));
@@ -1102,9 +1181,18 @@ hdg_status_t hdg_solve(hdg_handle_t h, const double* b, double* x, double rtol, 
         }
         if (rn <= tol) break;
         precondition(h, h->vr, h->vz);
-        const double rz_new = dot(h, h->vr, h->vz, N);
-        hipchk(hdg::launch_xpby(h->vz, rz_new / rz, h->vd, N, h->stream), "xpby");
-        rz = rz_new;
+        if (flex) {
+          double v[3];
+          dots(h, hdg::Prec::F64, 3, {h->vz, h->vq, h->vz, h->vr, h->vd, h->vr}, N, v);
+          const double beta = v[0] / dq;
+          hipchk(hdg::launch_xpby(h->vz, -beta, h->vd, N, h->stream), "xpby");
+          dr = v[1] - beta * v[2];
+        } else {
+          const double rz_new = dot(h, h->vr, h->vz, N);
+          hipchk(hdg::launch_xpby(h->vz, rz_new / rz, h->vd, N, h->stream), "xpby");
+          rz = rz_new;
+          dr = rz;
+        }
       }
     }
     if (rn > tol) {

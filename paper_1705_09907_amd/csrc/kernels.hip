@@ -690,13 +690,43 @@ __global__ __launch_bounds__(kWG) void k_sum_partials(const double* partial, int
   if (threadIdx.x == 0) *out = t;
 }
 
-__global__ __launch_bounds__(kWG) void k_axpy(double alpha, const double* x, double* y, int64_t n) {
-  const int64_t i = (int64_t)blockIdx.x * kWG + threadIdx.x;
-  if (i < n) y[i] += alpha * x[i];
+// Up to three dot products x_j . y_j in one pass (FP64 accumulation), partials
+// of dot j at partial[j * gridDim.x + block].  Workgroup j of the summing
+// kernel adds the partials of dot j.
+template <typename T>
+__global__ __launch_bounds__(kWG) void k_dots_partials(DotArgs a, int64_t n, double* partial) {
+  double s[3] = {0.0, 0.0, 0.0};
+  for (int64_t i = (int64_t)blockIdx.x * kWG + threadIdx.x; i < n; i += (int64_t)gridDim.x * kWG)
+#pragma unroll
+    for (int j = 0; j < 3; ++j)
+      if (j < a.ndots) s[j] += (double)static_cast<const T*>(a.x[j])[i] * (double)static_cast<const T*>(a.y[j])[i];
+  for (int j = 0; j < a.ndots; ++j) {
+    const double t = block_sum(s[j]);
+    if (threadIdx.x == 0) partial[(int64_t)j * gridDim.x + blockIdx.x] = t;
+    __syncthreads();  // block_sum's shared slots are reused by the next dot
+  }
 }
-__global__ __launch_bounds__(kWG) void k_xpby(const double* x, double beta, double* y, int64_t n) {
+__global__ __launch_bounds__(kWG) void k_sum_partials_multi(const double* partial, int np, double* out) {
+  double s = 0.0;
+  for (int i = threadIdx.x; i < np; i += kWG) s += partial[(int64_t)blockIdx.x * np + i];
+  const double t = block_sum(s);
+  if (threadIdx.x == 0) out[blockIdx.x] = t;
+}
+
+template <typename T>
+__global__ __launch_bounds__(kWG) void k_axpy(double alpha, const T* x, T* y, int64_t n) {
   const int64_t i = (int64_t)blockIdx.x * kWG + threadIdx.x;
-  if (i < n) y[i] = x[i] + beta * y[i];
+  if (i < n) y[i] += T(alpha) * x[i];
+}
+template <typename T>
+__global__ __launch_bounds__(kWG) void k_xpby(const T* x, double beta, T* y, int64_t n) {
+  const int64_t i = (int64_t)blockIdx.x * kWG + threadIdx.x;
+  if (i < n) y[i] = x[i] + T(beta) * y[i];
+}
+template <typename T>
+__global__ __launch_bounds__(kWG) void k_fill_t(T v, T* y, int64_t n) {
+  const int64_t i = (int64_t)blockIdx.x * kWG + threadIdx.x;
+  if (i < n) y[i] = v;
 }
 __global__ __launch_bounds__(kWG) void k_axpy_norm(double alpha, const double* q, double* r, int64_t n,
                                                    double* partial) {
@@ -735,14 +765,35 @@ hipError_t launch_sum_partials(const double* partial, int np, double* out, hipSt
   hipLaunchKernelGGL(k_sum_partials, dim3(1), dim3(kWG), 0, s, partial, np, out);
   return hipGetLastError();
 }
-hipError_t launch_axpy(double alpha, const double* x, double* y, int64_t n, hipStream_t s) {
-  if (n == 0) return hipSuccess;
-  hipLaunchKernelGGL(k_axpy, grid_for(n), dim3(kWG), 0, s, alpha, x, y, n);
+hipError_t launch_dots(Prec pr, const DotArgs& a, int64_t n, double* partial, hipStream_t s) {
+  if (a.ndots < 1 || a.ndots > 3) return hipErrorInvalidValue;
+  HDG_DISPATCH_T(pr, hipLaunchKernelGGL(k_dots_partials<TT>, dim3(reduce_grid(n)), dim3(kWG), 0, s, a, n,
+                                        partial));
   return hipGetLastError();
 }
+hipError_t launch_sum_partials_multi(const double* partial, int np, int ndots, double* out, hipStream_t s) {
+  hipLaunchKernelGGL(k_sum_partials_multi, dim3(ndots), dim3(kWG), 0, s, partial, np, out);
+  return hipGetLastError();
+}
+hipError_t launch_axpy(double alpha, const double* x, double* y, int64_t n, hipStream_t s) {
+  return launch_axpy(Prec::F64, alpha, x, y, n, s);
+}
 hipError_t launch_xpby(const double* x, double beta, double* y, int64_t n, hipStream_t s) {
+  return launch_xpby(Prec::F64, x, beta, y, n, s);
+}
+hipError_t launch_axpy(Prec pr, double alpha, const void* x, void* y, int64_t n, hipStream_t s) {
   if (n == 0) return hipSuccess;
-  hipLaunchKernelGGL(k_xpby, grid_for(n), dim3(kWG), 0, s, x, beta, y, n);
+  HDG_DISPATCH_T(pr, hipLaunchKernelGGL(k_axpy<TT>, grid_for(n), dim3(kWG), 0, s, alpha, (const TT*)x, (TT*)y, n));
+  return hipGetLastError();
+}
+hipError_t launch_xpby(Prec pr, const void* x, double beta, void* y, int64_t n, hipStream_t s) {
+  if (n == 0) return hipSuccess;
+  HDG_DISPATCH_T(pr, hipLaunchKernelGGL(k_xpby<TT>, grid_for(n), dim3(kWG), 0, s, (const TT*)x, beta, (TT*)y, n));
+  return hipGetLastError();
+}
+hipError_t launch_zero(Prec pr, void* y, int64_t n, hipStream_t s) {
+  if (n == 0) return hipSuccess;
+  HDG_DISPATCH_T(pr, hipLaunchKernelGGL(k_fill_t<TT>, grid_for(n), dim3(kWG), 0, s, TT(0), (TT*)y, n));
   return hipGetLastError();
 }
 hipError_t launch_axpy_norm(double alpha, const double* q, double* r, int64_t n, double* partial,

@@ -87,9 +87,21 @@ int reduce_grid(int64_t n);
 hipError_t launch_dot_partials(const double* a, const double* b, int64_t n, double* partial,
                                hipStream_t s);
 hipError_t launch_sum_partials(const double* partial, int np, double* out, hipStream_t s);
-// vector updates (FP64)
+// up to three dot products x_j . y_j of vectors in precision pr, FP64 partials
+// (dot j at partial[j * reduce_grid(n) + i]); the multi-sum writes out[j]
+struct DotArgs {
+  const void* x[3];
+  const void* y[3];
+  int ndots;
+};
+hipError_t launch_dots(Prec pr, const DotArgs& a, int64_t n, double* partial, hipStream_t s);
+hipError_t launch_sum_partials_multi(const double* partial, int np, int ndots, double* out, hipStream_t s);
+// vector updates (FP64, or vector precision pr)
 hipError_t launch_axpy(double alpha, const double* x, double* y, int64_t n, hipStream_t s);   // y += a x
 hipError_t launch_xpby(const double* x, double beta, double* y, int64_t n, hipStream_t s);    // y = x + b y
+hipError_t launch_axpy(Prec pr, double alpha, const void* x, void* y, int64_t n, hipStream_t s);
+hipError_t launch_xpby(Prec pr, const void* x, double beta, void* y, int64_t n, hipStream_t s);
+hipError_t launch_zero(Prec pr, void* y, int64_t n, hipStream_t s);
 // r -= alpha q and per-workgroup sum of squares of the new r
 hipError_t launch_axpy_norm(double alpha, const double* q, double* r, int64_t n, double* partial,
                             hipStream_t s);

@@ -1,0 +1,116 @@
+"""GPU: Krylov-accelerated coarse levels (K-cycle) and the flexible CG solve,
+against the oracle's K-cycle and direct solve.
+
+Bars: one K-cycle from x = 0 equals the oracle's to 1e-10 relative (max norm);
+the first FCG residual norms agree with the oracle's to 1e-7 relative; solutions
+match the direct solve to 1e-9 relative with ||b - S x|| <= 1e-10 ||b||.
+"""
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+import paper_1705_09907_amd as H  # noqa: E402
+from oracle import hdg, mg  # noqa: E402
+from workloads import kappa_lognormal, normal_vector  # noqa: E402
+
+
+def dev(a):
+    return torch.tensor(np.asarray(a), dtype=torch.float64, device="cuda")
+
+
+def host(t):
+    torch.cuda.synchronize()
+    return t.detach().cpu().numpy()
+
+
+def _pair(n, k, sigma, inner, seed=12, precision="f64"):
+    kap = kappa_lognormal(n, sigma, seed)
+    Ho = mg.Hierarchy(n, k, kap, inner=inner)
+    lmax = [Ho.lmax[L.name] for L in Ho.levels if L.kind == 'q' and not L.coarsest]
+    S = H.Solver(n, k, kap, omega=Ho.omega, cheb_lmax=lmax, inner=inner, precision=precision)
+    return kap, Ho, S
+
+
+@pytest.mark.parametrize("n,k,sigma,inner", [(16, 2, 1.0, {0: 3}), (24, 3, 2.0, {1: 2, 0: 2}),
+                                             (32, 4, 1.0, {2: 2, 0: 4}), (8, 1, 1.0, {0: 1})])
+def test_kcycle_matches_oracle(n, k, sigma, inner):
+    print(f"case kcycle n={n} k={k} inner={inner}", flush=True)
+    kap, Ho, S = _pair(n, k, sigma, inner)
+    try:
+        b = normal_vector(S.num_dofs(), 40)
+        xg = host(S.vcycle(dev(b), torch.zeros(S.num_dofs(), dtype=torch.float64, device="cuda")))
+        xo = Ho.vcycle(b, np.zeros_like(b))
+        assert np.abs(xg - xo).max() <= 1e-10 * np.abs(xo).max()
+    finally:
+        S.close()
+
+
+def test_fcg_history_matches_oracle():
+    n, k, sigma, inner = 24, 3, 2.0, {1: 2, 0: 2}
+    kap, Ho, S = _pair(n, k, sigma, inner)
+    try:
+        pr = hdg.Problem(n, k, kap)
+        b = pr.rhs(np.ones((n * n, pr.ref.nq ** 2)))
+        _, ho = Ho.solve(b, mode='fcg', rtol=1e-10)
+        x, it, rr, hg = S.solve(dev(b), rtol=1e-10, maxit=200, mode="fcg")
+        m = min(len(ho), len(hg), 6)
+        assert np.allclose(hg[:m], ho[:m], rtol=1e-7, atol=0)
+        assert abs(len(hg) - len(ho)) <= 1
+    finally:
+        S.close()
+
+
+@pytest.mark.parametrize("precision", ["f64", "f32"])
+@pytest.mark.parametrize("n,k,sigma,inner", [(40, 3, 2.0, {1: 2, 0: 2}), (64, 2, 2.0, {0: 4}),
+                                             (32, 4, 1.0, {1: 3, 0: 3})])
+def test_fcg_kcycle_solve_matches_direct(precision, n, k, sigma, inner):
+    print(f"case fcg {precision} n={n} k={k} inner={inner}", flush=True)
+    kap = kappa_lognormal(n, sigma, 12)
+    pr = hdg.Problem(n, k, kap)
+    b = pr.rhs(np.ones((n * n, pr.ref.nq ** 2)))
+    xd = pr.solve_direct(b)
+    S = H.Solver(n, k, kap, inner=inner, precision=precision)
+    S0 = H.Solver(n, k, kap, precision=precision)
+    try:
+        x, it, rr, hist = S.solve(dev(b), rtol=1e-10, maxit=300, mode="fcg")
+        assert rr <= 1e-10 and hist[-1] <= 1e-10 * np.linalg.norm(b)
+        assert np.linalg.norm(host(x) - xd) <= 1e-9 * np.linalg.norm(xd)
+        _, it0, _, _ = S0.solve(dev(b), rtol=1e-10, maxit=300, mode="pcg")
+        assert it < it0, (it, it0)
+        # the stationary iteration with the same nonlinear cycle converges too
+        xv, itv, rrv, _ = S.solve(dev(b), rtol=1e-10, maxit=300, mode="vcycle")
+        assert rrv <= 1e-10 and np.linalg.norm(host(xv) - xd) <= 1e-9 * np.linalg.norm(xd)
+    finally:
+        S.close()
+        S0.close()
+
+
+def test_pcg_with_nonlinear_cycle_is_rejected():
+    n, k = 8, 2
+    S = H.Solver(n, k, np.ones(n * n), inner={0: 2})
+    try:
+        b = dev(normal_vector(S.num_dofs(), 1))
+        with pytest.raises(H.HDGError) as ei:
+            S.solve(b, mode="pcg")
+        assert ei.value.status == -1
+    finally:
+        S.close()
+
+
+@pytest.mark.parametrize("precision", ["f64", "f32"])
+def test_full_size_kcycle_solve(precision):
+    """1024 x 1024, k = 3, lognormal sigma = 2 (seed 3): FCG with Krylov-accelerated
+    p = 1 and p = 0 levels reaches 1e-10; the FP64 residual is recomputed."""
+    n, k = 1024, 3
+    print(f"case full-size kcycle {precision}", flush=True)
+    S = H.Solver(n, k, kappa_lognormal(n, 2.0, 3), inner={1: 3, 0: 3}, precision=precision)
+    try:
+        b = dev(normal_vector(S.num_dofs(), 31))
+        x, it, rr, hist = S.solve(b, rtol=1e-10, maxit=300, mode="fcg")
+        _, rn = S.residual(k, b, x, norm=True)
+        assert rr <= 1e-10 and rn <= 1.0001e-10 * float(torch.linalg.norm(b))
+        print(f"kcycle {precision} iterations {it}", flush=True)
+    finally:
+        S.close()

@@ -60,6 +60,17 @@ def test_create_rejects_bad_config_before_any_device_call(field, value, code):
     assert st == code and not h.value
 
 
+@pytest.mark.parametrize("p,m", [(2, 1), (0, -1), (0, 65), (5, 2)])
+def test_create_rejects_bad_inner_steps(p, m):
+    cfg = H.Config()
+    H.lib.hdg_config_default(8, 2, ctypes.byref(cfg))
+    cfg.inner_steps[p] = m
+    kap = np.ones(64)
+    h = ctypes.c_void_p()
+    assert H.lib.hdg_create(ctypes.byref(cfg), kap.ctypes.data_as(H._PD), None, ctypes.byref(h)) == -1
+    assert not h.value
+
+
 @pytest.mark.parametrize("prec", [1, 2])
 def test_reduced_precision_face_smoother_needs_omega(prec):
     cfg = H.Config()
@@ -80,7 +91,7 @@ def test_config_layout_matches_header():
     names = re.findall(r"^\s*(?:int32_t|double)\s+([a-z_0-9]+(?:\s*,\s*[a-z_0-9]+)*)", body, re.M)
     fields = [f.strip() for grp in names for f in grp.split(",")]
     assert fields == [f[0] for f in H.Config._fields_]
-    assert ctypes.sizeof(H.Config) == 4 + 4 + 8 + 4 + 4 + 4 + 4 + 8 * 9 + 16 + 8 * 24 + 4 + 4 + 4 + 4 * 7
+    assert ctypes.sizeof(H.Config) == 4 + 4 + 8 + 4 + 4 + 4 + 4 + 8 * 9 + 16 + 8 * 24 + 4 + 4 + 4 + 4 * 9 + 4 * 8
 
 
 @pytest.mark.parametrize("bad", [0.0, -1.0, np.nan, np.inf])
