@@ -105,17 +105,17 @@ def main():
     import paper_1705_09907_amd as H
     from workloads import kappa_lognormal, normal_vector
 
+    w = WORKLOADS[args.workload]
     n, k = w["n"], w["k"]
     kap = kappa_lognormal(n, w["sigma"], w["seed"]) if w["sigma"] else np.ones(n * n)
-    dev = torch.device("cuda:0")
-    torch.cuda.set_device(dev)
-    t0 = time.perf_counter()
     lp = args.precision != "f64"
-    w = WORKLOADS[args.workload]
     spec = w["inner"] if args.inner == "auto" else args.inner
     inner = {int(p): int(m) for p, m in (t.split(":") for t in spec.split(",") if t)}
     if args.mode == "auto":
         args.mode = "fcg" if inner else "pcg"
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    t0 = time.perf_counter()
     S = H.Solver(n, k, kap, smoother=args.smoother, precision=args.precision, inner=inner)
     torch.cuda.synchronize()
     setup_s = time.perf_counter() - t0

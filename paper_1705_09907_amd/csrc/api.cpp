@@ -35,6 +35,7 @@ struct PLevel {
   double* pmat64 = nullptr;
   double omega = 0.8;
   void *x = nullptr, *b = nullptr, *r = nullptr, *t = nullptr;
+  int chain_lds_level = 64;                           // chain factors of levels >= this are staged in LDS
   int inner = 0;                                      // K-cycle: FCG steps of this level's correction
   void *kz = nullptr, *kd = nullptr, *kq = nullptr;   // K-cycle work vectors
 };
@@ -356,6 +357,10 @@ void build_face_data(hdg_ctx* h, PLevel& L, const Vec& blocks) {
     }
   });
   L.chain = upload_vec(h, fac);
+  // stage the small levels' factors in LDS: at most 8 KiB, within 64 KiB in all
+  const size_t es = hdg::vec_bytes(h->prec);
+  const int64_t rhs_bytes = (int64_t)(n - 1) * P * (int64_t)es;
+  L.chain_lds_level = hdg::chain_lds_level(P, n, es, std::min<int64_t>(8192, 65536 - rhs_bytes));
 }
 
 // Q1 stencil of P_J^T S0 P_J from the p = 0 element blocks (4 x 4).
@@ -528,6 +533,8 @@ void smooth(hdg_ctx* h, int p, const void* b, void* x, int nu, bool zero) {
       }
     } else {
       hdg::ChainArgs c{};
+      c.lds_level = L.chain_lds_level;
+      c.remap = hdg::chain_remap(L.P);
       c.factors = L.chain;
       c.cstride = L.cstride;
       c.omega = L.omega;

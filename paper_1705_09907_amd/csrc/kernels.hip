@@ -350,23 +350,42 @@ hipError_t launch_p_prolong_add(Prec pr, int P, const void* pm, const void* ec, 
 //   forward   r_j <- r_j - M-_j r_{j-1} - M+_j r_{j+1}           (j even)
 //   last      x_0 = Dinv r_0
 //   backward  x_j = Dinv_j r_j - W_j x_{j-1} - Z_j x_{j+1}        (j odd)
-// with W = Dinv A, Z = Dinv C.  One thread per (position, row): it streams one
-// row of the position's blocks, so registers stay at a few times P for every
-// degree.  Factors of a level of size ml: the even records [M-, M+] as 2 P^2
-// arrays over the ne = ceil(ml/2) even positions, then the odd records
-// [Dinv, W, Z] as 3 P^2 arrays over the no = floor(ml/2) odd positions
-// (entry-major, so a wavefront reads consecutive addresses); the last level
-// stores Dinv of its single block.  The factor row of a thread's first item of
-// the next forward phase is loaded before the barrier that precedes it.
+// with W = Dinv A, Z = Dinv C.  Work item = (position, row): it streams one
+// row of the position's blocks.  Factors of a level of size ml: the even
+// records [M-, M+] as 2 P^2 arrays over the ne = ceil(ml/2) even positions,
+// then the odd records [Dinv, W, Z] as 3 P^2 arrays over the no = floor(ml/2)
+// odd positions (entry-major, so a wavefront reads consecutive addresses); the
+// last level stores Dinv of its single block.
+// The reduction has 2 log2(n) dependent phases, so the kernel is bound by the
+// latency of each phase's factor loads, not by bandwidth.  The factors of the
+// small levels l >= a.lds_level (a few KiB) are copied to LDS together with the
+// right-hand side, so only the first lds_level levels of each sweep wait on
+// HBM; there a thread issues the loads of a batch of KB items before using any
+// of them, and loads the first batch of the next level before the barrier that
+// ends the current one.
+template <int P>
+struct ChainBatch {  // items whose factor rows a thread keeps in flight
+  static constexpr int KB = P <= 1 ? 8 : (P <= 2 ? 4 : (P <= 4 ? 2 : 1));
+};
+static constexpr int kChainMaxRes = 8;  // backward items per thread (launcher bound)
+
 template <int P, typename T>
 __global__ __launch_bounds__(1024) void k_chain(ChainArgs a) {
   constexpr int P2 = P * P;
+  constexpr int KB = ChainBatch<P>::KB;
   extern __shared__ unsigned char lds_raw[];
   T* R = reinterpret_cast<T*>(lds_raw);
   const T* rin = static_cast<const T*>(a.r);
   const T* xin = static_cast<const T*>(a.x);
   T* out = static_cast<T*>(a.out);
-  const int64_t c = blockIdx.x;
+  // Neighbouring horizontal chains read neighbouring faces: the values of one
+  // position of 8 consecutive chains share cache lines.  Workgroups are dealt
+  // round-robin to the 8 XCDs, so chain c is given to workgroup
+  // (c mod (2n/8)) * 8 + c / (2n/8): consecutive chains then run on the same
+  // XCD at about the same time and share its L2.
+  const int64_t nch = 2LL * a.n;
+  const int64_t c = (a.remap && nch % 8 == 0) ? (int64_t)(blockIdx.x & 7) * (nch >> 3) + (blockIdx.x >> 3)
+                                                : (int64_t)blockIdx.x;
   const int m = a.n - 1;
   const int64_t nv = (int64_t)a.n * (a.n - 1);
   const bool vert = c < a.n;
@@ -375,120 +394,223 @@ __global__ __launch_bounds__(1024) void k_chain(ChainArgs a) {
   const T* F = static_cast<const T*>(a.factors) + c * a.cstride;
   const int t = threadIdx.x;
   const int nt = blockDim.x;
-  for (int idx = t; idx < m * P; idx += nt) {
-    const int i = idx / P, r = idx - i * P;
-    R[idx] = rin[(base + stride * i) * P + r];
-  }
-  int ml = m, lev = 0;
-  int64_t off = 0;
-  T pm[P], pp[P];
-  auto prefetch_fwd = [&](int mlv, int64_t offv) {
-    const int ne = (mlv + 1) >> 1;
-    if (mlv > 1 && t < ne * P) {
-      const int r = t / ne, tt = t - r * ne;
-      const T* E = F + offv;
+  auto level_offset = [&](int l) {
+    int64_t lo = 0;
+    for (int q = 0, s = m; q < l; ++q, s = (s + 1) >> 1)
+      lo += (int64_t)2 * P2 * ((s + 1) >> 1) + (int64_t)3 * P2 * (s >> 1);
+    return lo;
+  };
+  const int Ls = a.lds_level;
+  const int64_t tail_off = level_offset(Ls);
+  T* TL = R + m * P;  // LDS copy of the factors of levels >= Ls
+  // copies to LDS keep 8 loads per thread in flight (a load-store loop would
+  // wait for every load before the next one is issued)
+  constexpr int CB = 8;
+  for (int b0 = t; b0 < m * P; b0 += nt * CB) {
+    T v[CB];
 #pragma unroll
-      for (int q = 0; q < P; ++q) {
-        pm[q] = E[(int64_t)(r * P + q) * ne + tt];
-        pp[q] = E[(int64_t)(P2 + r * P + q) * ne + tt];
+    for (int u = 0; u < CB; ++u) {
+      const int idx = b0 + u * nt;
+      if (idx < m * P) {
+        const int i = idx / P, r = idx - i * P;
+        v[u] = rin[(base + stride * i) * P + r];
+      }
+    }
+#pragma unroll
+    for (int u = 0; u < CB; ++u)
+      if (b0 + u * nt < m * P) R[b0 + u * nt] = v[u];
+  }
+  const int64_t tail_len = a.cstride - tail_off;
+  for (int64_t b0 = t; b0 < tail_len; b0 += (int64_t)nt * CB) {
+    T v[CB];
+#pragma unroll
+    for (int u = 0; u < CB; ++u)
+      if (b0 + u * nt < tail_len) v[u] = F[tail_off + b0 + u * nt];
+#pragma unroll
+    for (int u = 0; u < CB; ++u)
+      if (b0 + u * nt < tail_len) TL[b0 + u * nt] = v[u];
+  }
+  __syncthreads();
+  auto lvl = [&](int l, int64_t off_l) -> const T* { return l >= Ls ? TL + (off_l - tail_off) : F + off_l; };
+  // ---- forward reduction
+  T pm[KB][P], pp[KB][P];
+  auto load_fwd = [&](const T* E, int ne, int c0) {
+#pragma unroll
+    for (int kk = 0; kk < KB; ++kk) {
+      const int it = c0 + kk * nt;
+      if (it < ne * P) {
+        const int r = it / ne, tt = it - r * ne;
+#pragma unroll
+        for (int q = 0; q < P; ++q) {
+          pm[kk][q] = E[(int64_t)(r * P + q) * ne + tt];
+          pp[kk][q] = E[(int64_t)(P2 + r * P + q) * ne + tt];
+        }
       }
     }
   };
-  prefetch_fwd(ml, off);
-  __syncthreads();
+  int ml = m, lev = 0;
+  int64_t off = 0;
+  if (ml > 1) load_fwd(lvl(0, 0), (ml + 1) >> 1, t);
   while (ml > 1) {
     const int ne = (ml + 1) >> 1;
-    const T* E = F + off;
-    for (int it = t; it < ne * P; it += nt) {
-      const int r = it / ne, tt = it - r * ne;
-      const int j = 2 * tt;
-      const int i = j << lev;
-      if (it != t) {
+    const T* E = lvl(lev, off);
+    for (int c0 = t; c0 < ne * P; c0 += nt * KB) {
+      if (c0 != t) load_fwd(E, ne, c0);
 #pragma unroll
-        for (int q = 0; q < P; ++q) {
-          pm[q] = E[(int64_t)(r * P + q) * ne + tt];
-          pp[q] = E[(int64_t)(P2 + r * P + q) * ne + tt];
+      for (int kk = 0; kk < KB; ++kk) {
+        const int it = c0 + kk * nt;
+        if (it < ne * P) {
+          const int r = it / ne, tt = it - r * ne;
+          const int j = 2 * tt;
+          const int i = j << lev;
+          T v = R[i * P + r];
+          if (j >= 1) {
+            const int il = (j - 1) << lev;
+#pragma unroll
+            for (int q = 0; q < P; ++q) v -= pm[kk][q] * R[il * P + q];
+          }
+          if (j + 1 < ml) {
+            const int ir = (j + 1) << lev;
+#pragma unroll
+            for (int q = 0; q < P; ++q) v -= pp[kk][q] * R[ir * P + q];
+          }
+          R[i * P + r] = v;
         }
       }
-      T v = R[i * P + r];
-      if (j >= 1) {
-        const int il = (j - 1) << lev;
-#pragma unroll
-        for (int q = 0; q < P; ++q) v -= pm[q] * R[il * P + q];
-      }
-      if (j + 1 < ml) {
-        const int ir = (j + 1) << lev;
-#pragma unroll
-        for (int q = 0; q < P; ++q) v -= pp[q] * R[ir * P + q];
-      }
-      R[i * P + r] = v;
     }
     off += (int64_t)2 * P2 * ne + (int64_t)3 * P2 * (ml >> 1);
     ml = ne;
     ++lev;
-    prefetch_fwd(ml, off);
+    if (ml > 1) load_fwd(lvl(lev, off), (ml + 1) >> 1, t);
     __syncthreads();
   }
   T xr = T(0);
   if (t < P) {
+    const T* D = lvl(lev, off);
 #pragma unroll
-    for (int q = 0; q < P; ++q) xr += F[off + t * P + q] * R[q];
+    for (int q = 0; q < P; ++q) xr += D[t * P + q] * R[q];
   }
   __syncthreads();
   if (t < P) R[t] = xr;
   __syncthreads();
+  // ---- back substitution: values of all items first, then a barrier, then writes
+  T od[KB][P], ow[KB][P], oz[KB][P];
+  auto load_bwd = [&](int l, int c0) {
+    const int mlv = (m + (1 << l) - 1) >> l;
+    const int ne = (mlv + 1) >> 1, no = mlv >> 1;
+    const T* O = lvl(l, level_offset(l)) + (int64_t)2 * P2 * ne;
+#pragma unroll
+    for (int kk = 0; kk < KB; ++kk) {
+      const int it = c0 + kk * nt;
+      if (it < no * P) {
+        const int r = it / no, tt = it - r * no;
+        const int j = 2 * tt + 1;
+#pragma unroll
+        for (int q = 0; q < P; ++q) {
+          od[kk][q] = O[(int64_t)(r * P + q) * no + tt];
+          ow[kk][q] = O[(int64_t)(P2 + r * P + q) * no + tt];
+          oz[kk][q] = (j + 1 < mlv) ? O[(int64_t)(2 * P2 + r * P + q) * no + tt] : T(0);
+        }
+      }
+    }
+  };
+  if (lev > 0) load_bwd(lev - 1, t);
   while (lev > 0) {
     --lev;
     ml = (m + (1 << lev) - 1) >> lev;
-    const int ne = (ml + 1) >> 1, no = ml >> 1;
-    int64_t lo = 0;  // offset of level lev: record sizes of the levels below it
-    for (int l = 0, s = m; l < lev; ++l, s = (s + 1) >> 1)
-      lo += (int64_t)2 * P2 * ((s + 1) >> 1) + (int64_t)3 * P2 * (s >> 1);
-    const T* O = F + lo + (int64_t)2 * P2 * ne;
-    // each thread owns at most kMaxItems (position, row) items (the launcher
-    // sizes the workgroup for that): values first, then a barrier, then writes
-    constexpr int kMaxItems = 8;
-    T res[kMaxItems];
+    const int no = ml >> 1;
+    T res[kChainMaxRes];
     int cnt = 0;
-    for (int it = t; it < no * P && cnt < kMaxItems; it += nt, ++cnt) {
-      const int r = it / no, tt = it - r * no;
-      const int j = 2 * tt + 1;
-      const int i = j << lev;
-      const int il = (j - 1) << lev;
-      T s = T(0);
+    for (int c0 = t; c0 < no * P; c0 += nt * KB) {
+      if (c0 != t) load_bwd(lev, c0);
 #pragma unroll
-      for (int q = 0; q < P; ++q)
-        s += O[(int64_t)(r * P + q) * no + tt] * R[i * P + q] - O[(int64_t)(P2 + r * P + q) * no + tt] * R[il * P + q];
-      if (j + 1 < ml) {
-        const int ir = (j + 1) << lev;
+      for (int kk = 0; kk < KB; ++kk) {
+        const int it = c0 + kk * nt;
+        if (it < no * P && cnt < kChainMaxRes) {
+          const int r = it / no, tt = it - r * no;
+          const int j = 2 * tt + 1;
+          const int i = j << lev;
+          const int il = (j - 1) << lev;
+          const int ir = (j + 1 < ml) ? ((j + 1) << lev) : il;  // oz = 0 when there is no right neighbour
+          T s = T(0);
 #pragma unroll
-        for (int q = 0; q < P; ++q) s -= O[(int64_t)(2 * P2 + r * P + q) * no + tt] * R[ir * P + q];
+          for (int q = 0; q < P; ++q) s += od[kk][q] * R[i * P + q] - ow[kk][q] * R[il * P + q] - oz[kk][q] * R[ir * P + q];
+          res[cnt++] = s;
+        }
       }
-      res[cnt] = s;
     }
+    if (lev > 0) load_bwd(lev - 1, t);
     __syncthreads();
     cnt = 0;
-    for (int it = t; it < no * P && cnt < kMaxItems; it += nt, ++cnt) {
+    for (int it = t; it < no * P && cnt < kChainMaxRes; it += nt, ++cnt) {
       const int r = it / no, tt = it - r * no;
       R[((2 * tt + 1) << lev) * P + r] = res[cnt];
     }
     __syncthreads();
   }
-  for (int idx = t; idx < m * P; idx += nt) {
-    const int i = idx / P, r = idx - i * P;
-    const int64_t g = (base + stride * i) * P + r;
-    out[g] = (xin ? xin[g] : T(0)) + T(a.omega) * R[idx];
+  for (int b0 = t; b0 < m * P; b0 += nt * CB) {
+    T v[CB];
+    int64_t g[CB];
+#pragma unroll
+    for (int u = 0; u < CB; ++u) {
+      const int idx = b0 + u * nt;
+      if (idx < m * P) {
+        const int i = idx / P, r = idx - i * P;
+        g[u] = (base + stride * i) * P + r;
+        v[u] = xin ? xin[g[u]] : T(0);
+      }
+    }
+#pragma unroll
+    for (int u = 0; u < CB; ++u)
+      if (b0 + u * nt < m * P) out[g[u]] = v[u] + T(a.omega) * R[b0 + u * nt];
   }
 }
 
+// Bytes of the factors of the levels >= l of one chain (element size es).
+static int64_t chain_tail_bytes(int P, int n, int l, size_t es) {
+  int64_t tot = 0;
+  int q = 0;
+  for (int s = n - 1;; s = (s + 1) >> 1, ++q) {
+    const int64_t rec = s == 1 ? (int64_t)P * P : (int64_t)2 * P * P * ((s + 1) >> 1) + (int64_t)3 * P * P * (s >> 1);
+    if (q >= l) tot += rec;
+    if (s == 1) break;
+  }
+  return tot * (int64_t)es;
+}
+
+int chain_lds_level(int P, int n, size_t es, int64_t budget) {
+  if (budget < 0) budget = 0;
+  int l = 0;
+  while (chain_tail_bytes(P, n, l, es) > budget) ++l;
+  return l;
+}
+
+size_t chain_lds_bytes(int P, int n, size_t es, int lds_level) {
+  return (size_t)(n - 1) * P * es + (size_t)chain_tail_bytes(P, n, lds_level, es);
+}
+
+// Workgroup size: measured best at n = 256 and 1024 is 128 threads for P <= 2 and
+// 256 for larger P (more threads per chain lengthen every phase), raised only as
+// far as the back substitution's kChainMaxRes items per thread require.
+int chain_threads(int P, int n) {
+  const int64_t bwd = (int64_t)((n - 1) / 2) * P;  // items of the first backward level
+  int64_t th = P <= 2 ? 128 : 256;
+  while (th < 1024 && bwd > th * kChainMaxRes) th += 64;
+  return (int)th;
+}
+
+// XCD-aware chain order pays where the strided right-hand side of horizontal
+// chains dominates (small P); measured neutral to slightly negative for P >= 4.
+int chain_remap(int P) { return P <= 3 ? 1 : 0; }
+
 hipError_t launch_chain_solve(Prec pr, int P, const ChainArgs& a, hipStream_t s) {
   const int64_t nch = 2LL * a.n;
-  const size_t lds = (size_t)(a.n - 1) * P * vec_bytes(pr);
-  // the back-substitution keeps at most 8 (position, row) items per thread
-  const int64_t items = (int64_t)((a.n - 1) / 2) * P;
-  int threads = 256;
-  while (threads < 1024 && items > (int64_t)threads * 8) threads *= 2;
-  if (items > (int64_t)threads * 8) return hipErrorInvalidValue;
+  const int threads = a.threads > 0 ? a.threads : chain_threads(P, a.n);
+  const size_t lds = chain_lds_bytes(P, a.n, vec_bytes(pr), a.lds_level);
+  if (lds > 65536) return hipErrorInvalidValue;
+  // the back substitution keeps at most kChainMaxRes (position, row) items per thread
+  if ((int64_t)((a.n - 1) / 2) * P > (int64_t)threads * kChainMaxRes || threads > 1024 || threads % 64)
+    return hipErrorInvalidValue;
   if (pr == Prec::F64) {
     HDG_DISPATCH_P(P, hipLaunchKernelGGL((k_chain<PP, double>), dim3((unsigned)nch), dim3(threads), lds, s, a));
   } else {

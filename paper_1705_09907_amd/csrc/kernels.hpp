@@ -64,7 +64,16 @@ struct ChainArgs {
   void* out;
   double omega;
   int n;
+  int threads;          // workgroup size; 0 = chain_threads(P, n)
+  int lds_level;        // factors of levels >= lds_level are staged in LDS (chain_lds_level)
+  int remap;            // 1: XCD-aware chain order (consecutive chains on one XCD)
 };
+int chain_threads(int P, int n);
+int chain_remap(int P);
+// first level whose factors (and all later ones) fit in `budget` bytes of LDS
+int chain_lds_level(int P, int n, size_t elem_bytes, int64_t budget);
+// dynamic LDS of a chain launch: right-hand side plus the staged factors
+size_t chain_lds_bytes(int P, int n, size_t elem_bytes, int lds_level);
 hipError_t launch_chain_solve(Prec pr, int P, const ChainArgs& a, hipStream_t s);
 
 // Q1 levels (vector precision): 9-point stencil st[9][Nv] on the interior
