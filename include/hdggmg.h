@@ -164,6 +164,15 @@ hdg_status_t hdg_apply_trace_operator(hdg_handle_t h, int32_t p, const double* x
  * STATE for an FP64 handle. */
 hdg_status_t hdg_apply_trace_operator_lp(hdg_handle_t h, int32_t p, const float* x, float* y);
 
+/* Measurement entry point: the same product as hdg_apply_trace_operator
+ * (precision HDG_PREC_F64, FP64 vectors) or hdg_apply_trace_operator_lp
+ * (precision = the handle's cycle precision, float vectors), launched with a
+ * pair of HIP events recorded at the kernel's own start and end.  Synchronizes
+ * and returns the kernel duration in microseconds (*kernel_us).  Errors as for
+ * the two calls it mirrors; INVALID_ARG for any other precision. */
+hdg_status_t hdg_apply_trace_operator_timed(hdg_handle_t h, int32_t p, int32_t precision, const void* x, void* y,
+                                            double* kernel_us);
+
 /* r = b - S_p x; if norm2_host != NULL, *norm2_host = ||r||_2 (synchronizes;
  * deterministic reduction order).  r must not alias x.  Same level rule as
  * hdg_apply_trace_operator. */

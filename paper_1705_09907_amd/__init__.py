@@ -55,6 +55,7 @@ SIGNATURES = {
     "hdg_assemble_rhs": [_P, _PD, _PD, _P],
     "hdg_apply_trace_operator": [_P, _I32, _P, _P],
     "hdg_apply_trace_operator_lp": [_P, _I32, _P, _P],
+    "hdg_apply_trace_operator_timed": [_P, _I32, _I32, _P, _P, _PD],
     "hdg_residual": [_P, _I32, _P, _P, _P, _PD],
     "hdg_smooth": [_P, _I32, _P, _P, _I32],
     "hdg_restrict": [_P, _I32, _P, _P],
@@ -229,6 +230,19 @@ class Solver:
         self._check(lib.hdg_apply_trace_operator_lp(self._h, p, _dptr(x, "x", N, "float32"),
                                                     _dptr(y, "y", N, "float32")))
         return y
+
+    def apply_timed(self, p, x, y):
+        """y = S_p x (float64 tensors: FP64 operator; float32: the cycle precision),
+        returning the kernel's own duration in microseconds (synchronizes)."""
+        import torch
+        N = self.num_dofs(p)
+        lp = x.dtype == torch.float32
+        dt = "float32" if lp else "float64"
+        us = ctypes.c_double()
+        self._check(lib.hdg_apply_trace_operator_timed(
+            self._h, p, PRECISIONS[self.precision] if lp else 0, _dptr(x, "x", N, dt), _dptr(y, "y", N, dt),
+            ctypes.byref(us)))
+        return us.value
 
     def residual(self, p, b, x, r=None, norm=False):
         N = self.num_dofs(p)

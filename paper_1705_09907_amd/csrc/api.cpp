@@ -69,6 +69,7 @@ struct hdg_ctx {
   double* scal_h = nullptr;    // pinned host scalars [4]
   double *vr = nullptr, *vz = nullptr, *vd = nullptr, *vq = nullptr;  // solver vectors (FP64)
   void *cva = nullptr, *cvb = nullptr;  // cycle-precision copies of FP64 vectors (size N(k))
+  hipEvent_t ev0 = nullptr, ev1 = nullptr;  // timed apply
   hdg::Prec prec = hdg::Prec::F64;      // precision of the multigrid cycle
   int nq = 0;
 };
@@ -881,6 +882,8 @@ hdg_status_t hdg_create(const hdg_config_t* cfg, const double* kappa_host, void*
 hdg_status_t hdg_destroy(hdg_handle_t h) {
   if (!h) return HDG_ERR_INVALID_ARG;
   (void)hipStreamSynchronize(h->stream);
+  if (h->ev0) (void)hipEventDestroy(h->ev0);
+  if (h->ev1) (void)hipEventDestroy(h->ev1);
   for (void* p : h->allocs) (void)hipFree(p);
   if (h->scal_h) (void)hipHostFree(h->scal_h);
   delete h;
@@ -1034,6 +1037,31 @@ hdg_status_t hdg_apply_trace_operator(hdg_handle_t h, int32_t p, const double* x
   if (need_f64_level(h, p) != HDG_OK) return HDG_ERR_STATE;
   return guarded(h, [&]() -> hdg_status_t {
     apply(h, p, x, y, hdg::Prec::F64);
+    return HDG_OK;
+  });
+}
+
+hdg_status_t hdg_apply_trace_operator_timed(hdg_handle_t h, int32_t p, int32_t precision, const void* x, void* y,
+                                            double* kernel_us) {
+  if (!h || !x || !y || !kernel_us || p < 0 || p > h->k || x == y) return HDG_ERR_INVALID_ARG;
+  if (precision != HDG_PREC_F64 && precision != (int32_t)h->prec) return HDG_ERR_INVALID_ARG;
+  if (precision == HDG_PREC_F64 && need_f64_level(h, p) != HDG_OK) return HDG_ERR_STATE;
+  return guarded(h, [&]() -> hdg_status_t {
+    if (!h->ev0) {
+      hipchk(hipEventCreate(&h->ev0), "event");
+      hipchk(hipEventCreate(&h->ev1), "event");
+    }
+    const hdg::Prec pr = precision == HDG_PREC_F64 ? hdg::Prec::F64 : h->prec;
+    hdg::TraceArgs a = targs(h, h->pl[p], pr);
+    a.x = x;
+    a.y = y;
+    a.ev_start = h->ev0;
+    a.ev_stop = h->ev1;
+    hipchk(hdg::launch_trace(kprec(h->pl[p], pr), h->pl[p].P, hdg::TM_APPLY, a, h->stream), "trace apply");
+    hipchk(hipEventSynchronize(h->ev1), "event sync");
+    float ms = 0.f;
+    hipchk(hipEventElapsedTime(&ms, h->ev0, h->ev1), "elapsed");
+    *kernel_us = 1e3 * (double)ms;
     return HDG_OK;
   });
 }

@@ -13,6 +13,7 @@
 //
 // Every kernel is instantiated for FP64 blocks and vectors, FP32 blocks and
 // vectors, and BF16 blocks with FP32 vectors (FP32 accumulation).
+#include <hip/hip_ext.h>
 #include <hip/hip_runtime.h>
 
 #include "kernels.hpp"
@@ -189,7 +190,13 @@ template <int P, typename TM, typename TV>
 static hipError_t launch_trace_t(int mode, const TraceArgs& a, hipStream_t s) {
   const dim3 grid(trace_grid(a.ntiles)), block(kWG);
   switch (mode) {
-    case TM_APPLY: hipLaunchKernelGGL((k_trace<P, TM_APPLY, TM, TV>), grid, block, 0, s, a); break;
+    case TM_APPLY:
+      if (a.ev_start)  // events recorded at the kernel's own start and end
+        hipExtLaunchKernelGGL((k_trace<P, TM_APPLY, TM, TV>), grid, block, 0, s, (hipEvent_t)a.ev_start,
+                              (hipEvent_t)a.ev_stop, 0, a);
+      else
+        hipLaunchKernelGGL((k_trace<P, TM_APPLY, TM, TV>), grid, block, 0, s, a);
+      break;
     case TM_APPLY_DOT: hipLaunchKernelGGL((k_trace<P, TM_APPLY_DOT, TM, TV>), grid, block, 0, s, a); break;
     case TM_RESID: hipLaunchKernelGGL((k_trace<P, TM_RESID, TM, TV>), grid, block, 0, s, a); break;
     case TM_FACE_SWEEP: hipLaunchKernelGGL((k_trace<P, TM_FACE_SWEEP, TM, TV>), grid, block, 0, s, a); break;

@@ -38,6 +38,8 @@ struct TraceArgs {
   int n;
   int64_t nf;            // interior faces
   int64_t ntiles;        // ceil(nf / 64)
+  void* ev_start;        // TM_APPLY: optional hipEvent_t pair recorded at the kernel's start / end
+  void* ev_stop;
 };
 
 int trace_grid(int64_t ntiles);      // workgroups of a trace launch

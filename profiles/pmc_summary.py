@@ -2,7 +2,9 @@
 
 usage: python profiles/pmc_summary.py <fetch_db> <write_db> <kernel-substring> [calib-substring]
 Prints, per matching kernel, the mean FETCH_SIZE and WRITE_SIZE per dispatch and,
-for the calibration kernel (a plain device copy of known size), the same figures.
+for the calibration kernel (a plain device copy of known size), the figures of its
+largest dispatch (the calibration copy; other dispatches of that kernel are small
+runtime copies).
 """
 import sqlite3
 import sys
@@ -28,8 +30,12 @@ def main():
         for name in sorted(set(f) | set(w)):
             if sub in name:
                 fv, wv = f.get(name, []), w.get(name, [])
-                fm = sum(fv) / len(fv) if fv else float("nan")
-                wm = sum(wv) / len(wv) if wv else float("nan")
+                if label == "calibration":
+                    fm = max(fv) if fv else float("nan")
+                    wm = max(wv) if wv else float("nan")
+                else:
+                    fm = sum(fv) / len(fv) if fv else float("nan")
+                    wm = sum(wv) / len(wv) if wv else float("nan")
                 print(f"{label}\t{name[:90]}\tdispatches={len(fv)}/{len(wv)}\t"
                       f"FETCH_KiB={fm:.1f}\tWRITE_KiB={wm:.1f}\tFETCH_MB={fm * 1024 / 1e6:.2f}\t"
                       f"WRITE_MB={wm * 1024 / 1e6:.2f}")
