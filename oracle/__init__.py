@@ -20,7 +20,10 @@ Modules
   hdg         local matrices, condensed blocks, global assembly, RHS, direct
               solve, reconstruction and L2 errors (Secs. 3 and 5).
   mg          p-transfers, h-transfers, Galerkin Q1 hierarchy, smoothers and
-              the V-cycle / solve driver (Secs. 6 and 7).
+              the V-cycle / solve driver (Secs. 6 and 7), K-cycle and flexible CG.
+  adjoint     misfit of the volume solution and its gradient with respect to
+              per-element log-coefficients by the adjoint method (an extension
+              built from eqs. shur0 / shur1; pinned by finite differences).
 
 Every function listed here is pinned by a ``-m "not gpu"`` test in
 ``tests/test_oracle_*.py`` against values the paper prints, closed forms,
