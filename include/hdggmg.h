@@ -203,6 +203,33 @@ hdg_status_t hdg_vcycle(hdg_handle_t h, const double* b, double* x);
 hdg_status_t hdg_solve(hdg_handle_t h, const double* b, double* x, double rtol, int32_t maxit,
                        int32_t mode, int32_t* iters, double* relres, double* history_host);
 
+/* ---- misfit gradient with respect to theta_K = log K_K (adjoint method) ----
+ * The paper solves forward problems only; these calls differentiate its
+ * discretisation.  With [Q; U]_K from the local solver (eq. shur0) and S
+ * Lambda = b (eq. shur1), L = 1/2 sum_K |U_K - U_obs,K|^2 over the (p+1)^2
+ * nodal values of each element's volume solution (volume node I = i + (k+1) j,
+ * Gauss-Lobatto nodes), and
+ *   dL/dtheta = per element  w_Q^T A_K Q_K,   Abb_K^T w = [0; r_K] + [C; -E] mu_K,
+ * where r = U - U_obs and mu solves the adjoint system S mu = c (c below;
+ * S is symmetric, so hdg_solve serves).  Element vectors: U, U_obs [n*n][(k+1)^2],
+ * Q [n*n][2 (k+1)^2] (x half then y half), grad [n*n]; device memory, FP64. */
+
+/* Step (iv) of Sec. 3 (eq. shur0): U (and Q if not NULL) from the interior
+ * traces lam and the source state (f and g_D) of the last hdg_assemble_rhs on
+ * this handle.  STATE if hdg_assemble_rhs was never called. */
+hdg_status_t hdg_reconstruct(hdg_handle_t h, const double* lam, double* U, double* Q);
+
+/* Adjoint right-hand side c = (dU/dLambda)^T (U - U_obs) = -sum_K R_K^T
+ * [C^T, E^T] Abb_K^{-T} [0; U_K - U_obs,K] (device [N(k)]), and, if misfit_host
+ * is not NULL, L = 1/2 |U - U_obs|^2 (synchronizes). */
+hdg_status_t hdg_misfit_adjoint_rhs(hdg_handle_t h, const double* U, const double* U_obs, double* c,
+                                    double* misfit_host);
+
+/* grad[K] = dL/dtheta_K from the forward traces lam, U = U(lam), the data and the
+ * adjoint solution mu of S mu = c.  STATE without a source state. */
+hdg_status_t hdg_misfit_gradient(hdg_handle_t h, const double* lam, const double* U, const double* U_obs,
+                                 const double* mu, double* grad);
+
 const char* hdg_last_error(hdg_handle_t h);
 const char* hdg_status_string(hdg_status_t s);
 

@@ -62,6 +62,9 @@ SIGNATURES = {
     "hdg_prolong": [_P, _I32, _P, _P],
     "hdg_vcycle": [_P, _P, _P],
     "hdg_solve": [_P, _P, _P, _D, _I32, _I32, _PI32, _PD, _PD],
+    "hdg_reconstruct": [_P, _P, _P, _P],
+    "hdg_misfit_adjoint_rhs": [_P, _P, _P, _P, _PD],
+    "hdg_misfit_gradient": [_P, _P, _P, _P, _P, _P],
     "hdg_last_error": [_P],
     "hdg_status_string": [_I32],
 }
@@ -272,6 +275,41 @@ class Solver:
         N = self.num_dofs()
         self._check(lib.hdg_vcycle(self._h, _dptr(b, "b", N), _dptr(x, "x", N)))
         return x
+
+    # ------------------------------------------------ misfit gradient (adjoint)
+    def _evec(self, t, name, per):
+        return _dptr(t, name, self.n * self.n * per)
+
+    def reconstruct(self, lam, U=None, Q=None, with_q=False):
+        """U (and Q) of every element from the traces lam and the last assembled source."""
+        import torch
+        P2 = (self.k + 1) ** 2
+        U = torch.empty(self.n * self.n * P2, dtype=torch.float64, device="cuda") if U is None else U
+        if with_q and Q is None:
+            Q = torch.empty(self.n * self.n * 2 * P2, dtype=torch.float64, device="cuda")
+        self._check(lib.hdg_reconstruct(self._h, _dptr(lam, "lam", self.num_dofs()), self._evec(U, "U", P2),
+                                        self._evec(Q, "Q", 2 * P2) if Q is not None else None))
+        return (U, Q) if with_q else U
+
+    def adjoint_rhs(self, U, U_obs, c=None):
+        """c = (dU/dLambda)^T (U - U_obs) and L = 1/2 |U - U_obs|^2."""
+        P2 = (self.k + 1) ** 2
+        c = self._empty(self.k) if c is None else c
+        L = ctypes.c_double()
+        self._check(lib.hdg_misfit_adjoint_rhs(self._h, self._evec(U, "U", P2), self._evec(U_obs, "U_obs", P2),
+                                               _dptr(c, "c", self.num_dofs()), ctypes.byref(L)))
+        return c, L.value
+
+    def misfit_gradient(self, lam, U, U_obs, mu, grad=None):
+        """dL/dtheta per element from the forward and adjoint traces."""
+        import torch
+        P2 = (self.k + 1) ** 2
+        N = self.num_dofs()
+        grad = torch.empty(self.n * self.n, dtype=torch.float64, device="cuda") if grad is None else grad
+        self._check(lib.hdg_misfit_gradient(self._h, _dptr(lam, "lam", N), self._evec(U, "U", P2),
+                                            self._evec(U_obs, "U_obs", P2), _dptr(mu, "mu", N),
+                                            self._evec(grad, "grad", 1)))
+        return grad
 
     def solve(self, b, x=None, rtol=1e-10, maxit=200, mode="pcg", raise_on_fail=True):
         import torch

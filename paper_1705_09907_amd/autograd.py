@@ -1,0 +1,53 @@
+"""Misfit of the HDG volume solution as a differentiable function of the
+per-element log-coefficients theta = log K (torch.autograd.Function).
+
+Forward: a library handle for K = exp(theta) (host setup of every level), the
+right-hand side, one multigrid solve S Lambda = b, reconstruction of U, and
+L = 1/2 |U - U_obs|^2.  Backward: the adjoint right-hand side, one solve
+S mu = c with the same operator and multigrid, and the element-local gradient
+kernel; every step runs in the library's HIP kernels.
+"""
+import numpy as np
+import torch
+
+from . import Solver
+
+
+class HDGMisfit(torch.autograd.Function):
+    """L(theta) for an n x n mesh at degree k.
+
+    theta: CPU or CUDA float64 tensor [n*n]; U_obs: CUDA float64 [n*n*(k+1)^2];
+    f_qp: host array [n*n, nq*nq] of source values (nq = k + 2 Gauss-Legendre
+    points per direction); gD_qp: host array [4n, nq] or None; solver_opts:
+    keyword arguments of Solver (smoother, inner, precision, ...) plus rtol,
+    mode and maxit of the two solves.
+    """
+
+    @staticmethod
+    def forward(ctx, theta, U_obs, n, k, f_qp, gD_qp=None, solver_opts=None):
+        opts = dict(solver_opts or {})
+        rtol = opts.pop("rtol", 1e-12)
+        mode = opts.pop("mode", "fcg" if opts.get("inner") else "pcg")
+        maxit = opts.pop("maxit", 500)
+        kappa = np.exp(theta.detach().double().cpu().numpy())
+        S = Solver(n, k, kappa, **opts)
+        b = S.assemble_rhs(f_qp, gD_qp)
+        lam, _, _, _ = S.solve(b, rtol=rtol, maxit=maxit, mode=mode)
+        U = S.reconstruct(lam)
+        c, L = S.adjoint_rhs(U, U_obs)
+        ctx.state = (S, lam, U, U_obs, c, rtol, maxit, mode)
+        return torch.tensor(L, dtype=torch.float64, device=theta.device)
+
+    @staticmethod
+    def backward(ctx, gL):
+        S, lam, U, U_obs, c, rtol, maxit, mode = ctx.state
+        mu, _, _, _ = S.solve(c, rtol=rtol, maxit=maxit, mode=mode)
+        g = S.misfit_gradient(lam, U, U_obs, mu)
+        S.close()
+        ctx.state = None
+        grad_theta = (gL.to(g.device) * g)
+        return grad_theta, None, None, None, None, None, None
+
+
+def misfit(theta, U_obs, n, k, f_qp, gD_qp=None, **solver_opts):
+    return HDGMisfit.apply(theta, U_obs, n, k, f_qp, gD_qp, solver_opts)

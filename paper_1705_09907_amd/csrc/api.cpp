@@ -70,6 +70,11 @@ struct hdg_ctx {
   double *vr = nullptr, *vz = nullptr, *vd = nullptr, *vq = nullptr;  // solver vectors (FP64)
   void *cva = nullptr, *cvb = nullptr;  // cycle-precision copies of FP64 vectors (size N(k))
   hipEvent_t ev0 = nullptr, ev1 = nullptr;  // timed apply
+  // misfit gradient: degree-k reference pack, coefficients, and the source state
+  // of the last hdg_assemble_rhs (load vectors, boundary traces)
+  double *ref_dev = nullptr, *kappa_dev = nullptr, *F_dev = nullptr, *lambd_dev = nullptr;
+  double *elem_t = nullptr, *elem_m = nullptr;
+  bool have_source = false;
   hdg::Prec prec = hdg::Prec::F64;      // precision of the multigrid cycle
   int nq = 0;
 };
@@ -866,6 +871,17 @@ hdg_status_t hdg_create(const hdg_config_t* cfg, const double* kappa_host, void*
     if (cfg->smoother == HDG_SMOOTH_FACE)
       for (int p = 0; p <= h->k; ++p)
         if (!(cfg->omega[p] > 0)) h->pl[p].omega = 4.0 / (3.0 * estimate_face_lmax(h.get(), p, 30));
+    {  // element-local reference data of degree k (misfit gradient)
+      hdg::RefDegree rd;
+      rd.build(h->k, 1.0 / h->n, cfg->tau);
+      const hdg::PencilRef pc = hdg::pencil_reference(rd);
+      Vec pack;
+      for (const Vec* v : std::initializer_list<const Vec*>{&pc.V, &pc.delta, &pc.mu, &rd.E, &rd.H, &rd.C, &rd.Bt,
+                                                            &rd.Mvinv})
+        pack.insert(pack.end(), v->begin(), v->end());
+      h->ref_dev = upload(h.get(), pack);
+      h->kappa_dev = upload(h.get(), h->kappa);
+    }
     hipchk(hipStreamSynchronize(h->stream), "setup sync");
     return HDG_OK;
   });
@@ -977,10 +993,11 @@ hdg_status_t hdg_assemble_rhs(hdg_handle_t h, const double* f_qp_host, const dou
       }
     }
     const int64_t ne = (int64_t)n * n;
-    Vec g((size_t)ne * F4);
+    Vec g((size_t)ne * F4), Fall((size_t)ne * P2);
     hdg::parallel_for(ne, [&](int64_t e0, int64_t e1) {
-      Vec F(P2), work((size_t)P2 * P2 + (size_t)P2 * F4), K((size_t)F4 * F4);
+      Vec work((size_t)P2 * P2 + (size_t)P2 * F4), K((size_t)F4 * F4);
       for (int64_t e = e0; e < e1; ++e) {
+        double* F = Fall.data() + (size_t)e * P2;
         const double* fq = f_qp_host + (size_t)e * nq * nq;
         for (int i2 = 0; i2 < P; ++i2)
           for (int i1 = 0; i1 < P; ++i1) {
@@ -991,7 +1008,7 @@ hdg_status_t hdg_assemble_rhs(hdg_handle_t h, const double* f_qp_host, const dou
             F[i1 + P * i2] = 0.25 * hh * hh * s;
           }
         double* ge = g.data() + (size_t)e * F4;
-        hdg::element_source(ref, h->kappa[e], F.data(), ge, work.data());
+        hdg::element_source(ref, h->kappa[e], F, ge, work.data());
         const int i = (int)(e % n), j = (int)(e / n);
         const bool touches = i == 0 || j == 0 || i == n - 1 || j == n - 1;
         if (touches && gD_qp_host) {
@@ -1019,7 +1036,17 @@ hdg_status_t hdg_assemble_rhs(hdg_handle_t h, const double* f_qp_host, const dou
       }
     });
     hipchk(hipMemcpyAsync(b, bh.data(), bh.size() * sizeof(double), hipMemcpyHostToDevice, h->stream), "h2d");
+    // source state for hdg_reconstruct / the misfit gradient
+    if (!h->F_dev) {
+      h->F_dev = dalloc(h, ne * P2);
+      h->lambd_dev = dalloc(h, 4LL * n * P);
+    }
+    hipchk(hipMemcpyAsync(h->F_dev, Fall.data(), Fall.size() * sizeof(double), hipMemcpyHostToDevice, h->stream),
+           "h2d");
+    hipchk(hipMemcpyAsync(h->lambd_dev, lam_bd.data(), lam_bd.size() * sizeof(double), hipMemcpyHostToDevice,
+                          h->stream), "h2d");
     hipchk(hipStreamSynchronize(h->stream), "sync");
+    h->have_source = true;
     return HDG_OK;
   });
 }
@@ -1143,6 +1170,79 @@ hdg_status_t hdg_vcycle(hdg_handle_t h, const double* b, double* x) {
       pcycle(h, h->k, bl, const_cast<void*>(stage_in(h, x, h->cvb, N)), false);
       stage_out(h, h->cvb, x, N);
     }
+    return HDG_OK;
+  });
+}
+
+namespace {
+hdg::ElemArgs elem_args(hdg_handle_t h) {
+  hdg::ElemArgs a{};
+  a.ref = h->ref_dev;
+  a.kappa = h->kappa_dev;
+  a.lam_bd = h->lambd_dev;
+  a.F = h->F_dev;
+  a.n = h->n;
+  return a;
+}
+hdg_status_t need_source(hdg_handle_t h) {
+  if (h->have_source) return HDG_OK;
+  h->err = "no source state: call hdg_assemble_rhs first";
+  return HDG_ERR_STATE;
+}
+}  // namespace
+
+hdg_status_t hdg_reconstruct(hdg_handle_t h, const double* lam, double* U, double* Q) {
+  if (!h || !lam || !U) return HDG_ERR_INVALID_ARG;
+  if (need_source(h) != HDG_OK) return HDG_ERR_STATE;
+  return guarded(h, [&]() -> hdg_status_t {
+    hdg::ElemArgs a = elem_args(h);
+    a.lam = lam;
+    a.Uout = U;
+    a.Qout = Q;
+    hipchk(hdg::launch_elem_reconstruct(h->k + 1, a, h->stream), "reconstruct");
+    return HDG_OK;
+  });
+}
+
+hdg_status_t hdg_misfit_adjoint_rhs(hdg_handle_t h, const double* U, const double* U_obs, double* c,
+                                    double* misfit_host) {
+  if (!h || !U || !U_obs || !c) return HDG_ERR_INVALID_ARG;
+  return guarded(h, [&]() -> hdg_status_t {
+    const int64_t ne = (int64_t)h->n * h->n;
+    const int P = h->k + 1;
+    if (!h->elem_t) {
+      h->elem_t = dalloc(h, ne * 4 * P);
+      h->elem_m = dalloc(h, ne);
+    }
+    hdg::ElemArgs a = elem_args(h);
+    a.U = U;
+    a.Uobs = U_obs;
+    a.tout = h->elem_t;
+    a.misfit = h->elem_m;
+    hipchk(hdg::launch_elem_adjoint(P, a, h->stream), "adjoint element");
+    hipchk(hdg::launch_face_gather(P, h->elem_t, c, h->n, h->stream), "face gather");
+    if (misfit_host) {
+      hipchk(hdg::launch_sum_partials(h->elem_m, (int)ne, h->scal, h->stream), "sum");
+      hipchk(hipMemcpyAsync(h->scal_h, h->scal, sizeof(double), hipMemcpyDeviceToHost, h->stream), "d2h");
+      hipchk(hipStreamSynchronize(h->stream), "sync");
+      *misfit_host = *h->scal_h;
+    }
+    return HDG_OK;
+  });
+}
+
+hdg_status_t hdg_misfit_gradient(hdg_handle_t h, const double* lam, const double* U, const double* U_obs,
+                                 const double* mu, double* grad) {
+  if (!h || !lam || !U || !U_obs || !mu || !grad) return HDG_ERR_INVALID_ARG;
+  if (need_source(h) != HDG_OK) return HDG_ERR_STATE;
+  return guarded(h, [&]() -> hdg_status_t {
+    hdg::ElemArgs a = elem_args(h);
+    a.lam = lam;
+    a.U = U;
+    a.Uobs = U_obs;
+    a.mu = mu;
+    a.grad = grad;
+    hipchk(hdg::launch_elem_gradient(h->k + 1, a, h->stream), "gradient");
     return HDG_OK;
   });
 }

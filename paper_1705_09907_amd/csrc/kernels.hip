@@ -796,6 +796,218 @@ hipError_t launch_dense_gemv(Prec pr, const double* A, const void* b, void* y, i
 }
 
 // ---------------------------------------------------------------- reductions
+// ----------------------------------------------------- element-local kernels
+// Misfit gradient with respect to theta_K = log K_K (adjoint method on eqs.
+// shur0 / shur1; A_K = exp(-theta_K) A0).  One 64-lane workgroup per element;
+// lanes take the rows of each small dense product, vectors live in LDS, the
+// reference matrices (a few KiB) stay in L1 / L2.
+template <int P>
+struct ElemRef {
+  static constexpr int P2 = P * P, F4 = 4 * P;
+  const double *V, *delta, *mu, *E, *H, *C, *Bt, *Mvinv;
+  __device__ explicit ElemRef(const double* r) {
+    V = r;
+    delta = V + P2 * P2;
+    mu = delta + P2;
+    E = mu + P2;
+    H = E + P2 * F4;
+    C = H + P2 * F4;
+    Bt = C + 2 * P2 * F4;
+    Mvinv = Bt + 2 * P2 * P2;
+  }
+};
+
+// the element's 4P trace values: interior faces from lam, boundary faces from
+// lam_bd (or 0 when lam_bd is null)
+template <int P>
+__device__ void elem_trace(const double* lam, const double* lam_bd, int n, int i, int j, double* out) {
+  const int64_t nv = (int64_t)n * (n - 1);
+  for (int idx = threadIdx.x; idx < 4 * P; idx += 64) {
+    const int lf = idx / P, c = idx - lf * P;
+    int64_t f = -1, nb = -1;
+    switch (lf) {
+      case 0: if (i >= 1) f = (i - 1) + (int64_t)(n - 1) * j; else nb = 3LL * n + j; break;
+      case 1: if (i <= n - 2) f = i + (int64_t)(n - 1) * j; else nb = (int64_t)n + j; break;
+      case 2: if (j >= 1) f = nv + i + (int64_t)n * (j - 1); else nb = i; break;
+      default: if (j <= n - 2) f = nv + i + (int64_t)n * j; else nb = 2LL * n + i; break;
+    }
+    out[idx] = f >= 0 ? lam[f * P + c] : (lam_bd ? lam_bd[nb * P + c] : 0.0);
+  }
+}
+
+// out = (D + K G)^{-1} in (both [P2] in LDS; tmp [P2] LDS scratch)
+template <int P>
+__device__ void elem_zsolve(const ElemRef<P>& R, double kap, const double* in, double* tmp, double* out) {
+  constexpr int P2 = P * P;
+  for (int q = threadIdx.x; q < P2; q += 64) {
+    double s = 0.0;
+    for (int I = 0; I < P2; ++I) s += R.V[I * P2 + q] * in[I];
+    tmp[q] = s / (R.delta[q] + kap * R.mu[q]);
+  }
+  __syncthreads();
+  for (int I = threadIdx.x; I < P2; I += 64) {
+    double s = 0.0;
+    for (int q = 0; q < P2; ++q) s += R.V[I * P2 + q] * tmp[q];
+    out[I] = s;
+  }
+  __syncthreads();
+}
+
+// out[I] = in0[I] - sum_c (E - K H)[I][c] lam[c]
+template <int P>
+__device__ void elem_rhs(const ElemRef<P>& R, double kap, const double* in0, const double* lam, double* out) {
+  constexpr int P2 = P * P, F4 = 4 * P;
+  for (int I = threadIdx.x; I < P2; I += 64) {
+    double s = in0[I];
+    for (int c = 0; c < F4; ++c) s -= (R.E[I * F4 + c] - kap * R.H[I * F4 + c]) * lam[c];
+    out[I] = s;
+  }
+  __syncthreads();
+}
+
+template <int P>
+__global__ __launch_bounds__(64) void k_elem_reconstruct(ElemArgs a) {
+  constexpr int P2 = P * P, F4 = 4 * P;
+  __shared__ double lam[F4], F[P2], t[P2], tmp[P2], U[P2], s[2 * P2];
+  const ElemRef<P> R(a.ref);
+  const int64_t e = blockIdx.x;
+  const int i = (int)(e % a.n), j = (int)(e / a.n);
+  const double kap = a.kappa[e];
+  elem_trace<P>(a.lam, a.lam_bd, a.n, i, j, lam);
+  for (int I = threadIdx.x; I < P2; I += 64) F[I] = a.F[e * P2 + I];
+  __syncthreads();
+  elem_rhs<P>(R, kap, F, lam, t);
+  elem_zsolve<P>(R, kap, t, tmp, U);
+  for (int I = threadIdx.x; I < P2; I += 64) a.Uout[e * P2 + I] = U[I];
+  if (a.Qout) {
+    for (int r = threadIdx.x; r < 2 * P2; r += 64) {
+      double v = 0.0;
+      for (int J = 0; J < P2; ++J) v += R.Bt[r * P2 + J] * U[J];
+      for (int c = 0; c < F4; ++c) v -= R.C[r * F4 + c] * lam[c];
+      s[r] = v;
+    }
+    __syncthreads();
+    for (int r = threadIdx.x; r < 2 * P2; r += 64) {
+      const int half = r / P2, I = r - half * P2;
+      double v = 0.0;
+      for (int J = 0; J < P2; ++J) v += R.Mvinv[I * P2 + J] * s[half * P2 + J];
+      a.Qout[e * 2 * P2 + r] = kap * v;
+    }
+  }
+}
+
+template <int P>
+__global__ __launch_bounds__(64) void k_elem_adjoint(ElemArgs a) {
+  constexpr int P2 = P * P, F4 = 4 * P;
+  __shared__ double r[P2], tmp[P2], z[P2];
+  const ElemRef<P> R(a.ref);
+  const int64_t e = blockIdx.x;
+  const double kap = a.kappa[e];
+  double sq = 0.0;
+  for (int I = threadIdx.x; I < P2; I += 64) {
+    const double v = a.U[e * P2 + I] - a.Uobs[e * P2 + I];
+    r[I] = v;
+    sq += v * v;
+  }
+  for (int off = 32; off >= 1; off >>= 1) sq += __shfl_xor(sq, off, 64);
+  if (threadIdx.x == 0) a.misfit[e] = 0.5 * sq;
+  __syncthreads();
+  elem_zsolve<P>(R, kap, r, tmp, z);
+  for (int c = threadIdx.x; c < F4; c += 64) {
+    double v = 0.0;
+    for (int I = 0; I < P2; ++I) v += (R.E[I * F4 + c] - kap * R.H[I * F4 + c]) * z[I];
+    a.tout[e * F4 + c] = -v;
+  }
+}
+
+template <int P>
+__global__ __launch_bounds__(64) void k_elem_gradient(ElemArgs a) {
+  constexpr int P2 = P * P, F4 = 4 * P;
+  __shared__ double lam[F4], mu[F4], r[P2], q1[P2], tmp[P2], w[P2], U[P2], s[2 * P2], v[2 * P2];
+  const ElemRef<P> R(a.ref);
+  const int64_t e = blockIdx.x;
+  const int i = (int)(e % a.n), j = (int)(e / a.n);
+  const double kap = a.kappa[e];
+  elem_trace<P>(a.lam, a.lam_bd, a.n, i, j, lam);
+  elem_trace<P>(a.mu, nullptr, a.n, i, j, mu);  // boundary traces are data: no adjoint there
+  for (int I = threadIdx.x; I < P2; I += 64) {
+    U[I] = a.U[e * P2 + I];
+    r[I] = U[I] - a.Uobs[e * P2 + I];
+  }
+  __syncthreads();
+  elem_rhs<P>(R, kap, r, mu, q1);
+  elem_zsolve<P>(R, kap, q1, tmp, w);
+  for (int row = threadIdx.x; row < 2 * P2; row += 64) {
+    double cv = 0.0, cs = 0.0;
+    for (int c = 0; c < F4; ++c) {
+      cv += R.C[row * F4 + c] * mu[c];
+      cs -= R.C[row * F4 + c] * lam[c];
+    }
+    for (int J = 0; J < P2; ++J) {
+      cv -= R.Bt[row * P2 + J] * w[J];
+      cs += R.Bt[row * P2 + J] * U[J];
+    }
+    v[row] = cv;
+    s[row] = cs;
+  }
+  __syncthreads();
+  double g = 0.0;
+  for (int row = threadIdx.x; row < 2 * P2; row += 64) {
+    const int half = row / P2, I = row - half * P2;
+    double m = 0.0;
+    for (int J = 0; J < P2; ++J) m += R.Mvinv[I * P2 + J] * s[half * P2 + J];
+    g += v[row] * m;
+  }
+  for (int off = 32; off >= 1; off >>= 1) g += __shfl_xor(g, off, 64);
+  if (threadIdx.x == 0) a.grad[e] = kap * g;
+}
+
+__global__ __launch_bounds__(kWG) void k_face_gather(const double* t, double* c, int n, int P) {
+  const int64_t nv = (int64_t)n * (n - 1), nf = 2 * nv;
+  const int64_t idx = (int64_t)blockIdx.x * kWG + threadIdx.x;
+  if (idx >= nf * P) return;
+  const int64_t f = idx / P;
+  const int a = (int)(idx - f * P);
+  int64_t lo, hi;
+  int llo, lhi;
+  if (f < nv) {
+    const int64_t j = f / (n - 1), i = f - j * (n - 1) + 1;
+    lo = (i - 1) + (int64_t)n * j;
+    hi = i + (int64_t)n * j;
+    llo = 1;
+    lhi = 0;
+  } else {
+    const int64_t g = f - nv, j = g / n + 1, i = g - (j - 1) * n;
+    lo = i + (int64_t)n * (j - 1);
+    hi = i + (int64_t)n * j;
+    llo = 3;
+    lhi = 2;
+  }
+  c[idx] = t[lo * 4 * P + llo * P + a] + t[hi * 4 * P + lhi * P + a];
+}
+
+hipError_t launch_elem_reconstruct(int P, const ElemArgs& a, hipStream_t s) {
+  HDG_DISPATCH_P(P, hipLaunchKernelGGL(k_elem_reconstruct<PP>, dim3((unsigned)((int64_t)a.n * a.n)), dim3(64), 0,
+                                       s, a));
+  return hipGetLastError();
+}
+hipError_t launch_elem_adjoint(int P, const ElemArgs& a, hipStream_t s) {
+  HDG_DISPATCH_P(P, hipLaunchKernelGGL(k_elem_adjoint<PP>, dim3((unsigned)((int64_t)a.n * a.n)), dim3(64), 0, s,
+                                       a));
+  return hipGetLastError();
+}
+hipError_t launch_elem_gradient(int P, const ElemArgs& a, hipStream_t s) {
+  HDG_DISPATCH_P(P, hipLaunchKernelGGL(k_elem_gradient<PP>, dim3((unsigned)((int64_t)a.n * a.n)), dim3(64), 0, s,
+                                       a));
+  return hipGetLastError();
+}
+hipError_t launch_face_gather(int P, const double* t, double* c, int n, hipStream_t s) {
+  const int64_t tot = 2LL * n * (n - 1) * P;
+  if (tot == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_face_gather, grid_for(tot), dim3(kWG), 0, s, t, c, n, P);
+  return hipGetLastError();
+}
+
 int reduce_grid(int64_t n) {
   int64_t g = (n + kWG * 4 - 1) / (kWG * 4);
   if (g > 1024) g = 1024;

@@ -93,6 +93,37 @@ hipError_t launch_pj_prolong_add(Prec pr, const void* ev, void* xface, int n, hi
 // y = Ainv b with an FP64 dense m x m inverse; b, y in vector precision
 hipError_t launch_dense_gemv(Prec pr, const double* Ainv, const void* b, void* y, int m, hipStream_t s);
 
+// Element-local kernels of the misfit gradient (FP64), one wavefront per element.
+// ref packs the degree-k reference data: V [P2][P2] (column i = eigenvector i of
+// the pencil (G, D + G)), delta [P2], mu [P2], E [P2][4P], H [P2][4P],
+// C [2 P2][4P], Bt [2 P2][P2], Mvinv [P2][P2]; so that for element coefficient K
+// (D + K G)^{-1} = V diag(1 / (delta + K mu)) V^T.
+struct ElemArgs {
+  const double* ref;
+  const double* kappa;    // [n n]
+  const double* lam;      // trace vector, interior faces
+  const double* lam_bd;   // [4 n][P] boundary traces (bottom, right, top, left)
+  const double* F;        // [n n][P2] load vectors
+  const double* U;        // [n n][P2]
+  const double* Uobs;     // [n n][P2]
+  const double* mu;       // adjoint trace vector, interior faces
+  double* Uout;           // reconstruct: U
+  double* Qout;           // reconstruct: Q [n n][2 P2] (nullable)
+  double* tout;           // adjoint: element trace contributions [n n][4P]
+  double* misfit;         // adjoint: 1/2 |U - Uobs|^2 per element [n n]
+  double* grad;           // gradient: dL/dtheta per element [n n]
+  int n;
+};
+// U = (D + K G)^{-1} (F - (E - K H) Lambda_K), Q = K A0^{-1} (B^T U - C Lambda_K)
+hipError_t launch_elem_reconstruct(int P, const ElemArgs& a, hipStream_t s);
+// t_K = -(E - K H)^T (D + K G)^{-1} (U_K - Uobs_K), misfit_K = 1/2 |U_K - Uobs_K|^2
+hipError_t launch_elem_adjoint(int P, const ElemArgs& a, hipStream_t s);
+// c_f = t_lo[f] + t_hi[f] on interior faces (face-owned gather of element rows)
+hipError_t launch_face_gather(int P, const double* t, double* c, int n, hipStream_t s);
+// grad_K = K (C mu_K - B^T w)^T A0^{-1} (B^T U_K - C Lambda_K),
+//          w = (D + K G)^{-1} (U_K - Uobs_K - (E - K H) mu_K)
+hipError_t launch_elem_gradient(int P, const ElemArgs& a, hipStream_t s);
+
 // deterministic reductions (FP64 vectors)
 int reduce_grid(int64_t n);
 hipError_t launch_dot_partials(const double* a, const double* b, int64_t n, double* partial,

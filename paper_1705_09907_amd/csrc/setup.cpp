@@ -194,7 +194,7 @@ void RefDegree::build(int p_, double h_, double tau_) {
       T[((size_t)2 * P2 + I) * P + m] = 0.5 * h * M1[i1 * P + m] * Lm[i2];
       T[((size_t)3 * P2 + I) * P + m] = 0.5 * h * M1[i1 * P + m] * Lp[i2];
     }
-  Vec C((size_t)2 * P2 * F4, 0.0);
+  C.assign((size_t)2 * P2 * F4, 0.0);
   E.assign((size_t)P2 * F4, 0.0);
   for (int lf = 0; lf < 4; ++lf)
     for (int I = 0; I < P2; ++I)
@@ -225,9 +225,10 @@ void RefDegree::build(int p_, double h_, double tau_) {
           s += B[(size_t)I * 2 * P2 + half * P2 + L] * A0inv_blk[(size_t)L * P2 + J];
         BA[(size_t)I * 2 * P2 + half * P2 + J] = s;
       }
-  Vec Bt((size_t)2 * P2 * P2);
+  Bt.assign((size_t)2 * P2 * P2, 0.0);
   for (int I = 0; I < P2; ++I)
     for (int J = 0; J < 2 * P2; ++J) Bt[(size_t)J * P2 + I] = B[(size_t)I * 2 * P2 + J];
+  Mvinv = A0inv_blk;
   G.assign((size_t)P2 * P2, 0.0);
   matmul(P2, 2 * P2, P2, BA.data(), Bt.data(), G.data());
   H.assign((size_t)P2 * F4, 0.0);
@@ -274,6 +275,84 @@ void element_source(const RefDegree& r, double kappa, const double* F, double* g
     for (int l = 0; l < P2; ++l) s += (kappa * r.H[l * F4 + a] - r.E[l * F4 + a]) * u[l];
     g[a] = s;
   }
+}
+
+// Cyclic Jacobi eigenvalue iteration for a symmetric N x N matrix (row major):
+// on return A is diagonal (the eigenvalues) and W holds the eigenvectors as
+// columns (Golub & Van Loan, Matrix Computations, Sec. 8.5).
+static void jacobi_eigen(int N, Vec& A, Vec& W) {
+  W.assign((size_t)N * N, 0.0);
+  for (int i = 0; i < N; ++i) W[(size_t)i * N + i] = 1.0;
+  for (int sweep = 0; sweep < 100; ++sweep) {
+    double off = 0.0, diag = 0.0;
+    for (int i = 0; i < N; ++i)
+      for (int j = 0; j < N; ++j) (i == j ? diag : off) += A[(size_t)i * N + j] * A[(size_t)i * N + j];
+    if (off <= 1e-30 * diag) return;
+    for (int p = 0; p < N - 1; ++p)
+      for (int q = p + 1; q < N; ++q) {
+        const double apq = A[(size_t)p * N + q];
+        if (apq == 0.0) continue;
+        const double app = A[(size_t)p * N + p], aqq = A[(size_t)q * N + q];
+        const double theta = (aqq - app) / (2.0 * apq);
+        const double t = (theta >= 0 ? 1.0 : -1.0) / (std::fabs(theta) + std::sqrt(theta * theta + 1.0));
+        const double c = 1.0 / std::sqrt(t * t + 1.0), s = t * c;
+        for (int k = 0; k < N; ++k) {  // A <- J^T A J
+          const double akp = A[(size_t)k * N + p], akq = A[(size_t)k * N + q];
+          A[(size_t)k * N + p] = c * akp - s * akq;
+          A[(size_t)k * N + q] = s * akp + c * akq;
+        }
+        for (int k = 0; k < N; ++k) {
+          const double apk = A[(size_t)p * N + k], aqk = A[(size_t)q * N + k];
+          A[(size_t)p * N + k] = c * apk - s * aqk;
+          A[(size_t)q * N + k] = s * apk + c * aqk;
+        }
+        for (int k = 0; k < N; ++k) {
+          const double wkp = W[(size_t)k * N + p], wkq = W[(size_t)k * N + q];
+          W[(size_t)k * N + p] = c * wkp - s * wkq;
+          W[(size_t)k * N + q] = s * wkp + c * wkq;
+        }
+      }
+  }
+  throw std::runtime_error("Jacobi eigenvalue iteration did not converge");
+}
+
+PencilRef pencil_reference(const RefDegree& r) {
+  const int N = r.P * r.P;
+  PencilRef out;
+  out.P2 = N;
+  Vec L((size_t)N * N);
+  for (int i = 0; i < N * N; ++i) L[i] = r.Dm[i] + r.G[i];
+  if (!cholesky(N, L.data())) throw std::runtime_error("D + G not SPD");
+  // Gh = L^{-1} G L^{-T}
+  Vec X(r.G);
+  forward_sub(N, L.data(), N, X.data());  // L^{-1} G
+  Vec Gh((size_t)N * N);
+  for (int i = 0; i < N; ++i)
+    for (int j = 0; j < N; ++j) Gh[(size_t)i * N + j] = X[(size_t)j * N + i];
+  forward_sub(N, L.data(), N, Gh.data());  // L^{-1} (L^{-1} G)^T
+  for (int i = 0; i < N; ++i)
+    for (int j = i + 1; j < N; ++j) {  // symmetrise the rounding
+      const double s = 0.5 * (Gh[(size_t)i * N + j] + Gh[(size_t)j * N + i]);
+      Gh[(size_t)i * N + j] = Gh[(size_t)j * N + i] = s;
+    }
+  Vec W;
+  jacobi_eigen(N, Gh, W);
+  out.V = W;
+  backward_sub(N, L.data(), N, out.V.data());  // V = L^{-T} W
+  out.delta.assign(N, 0.0);
+  out.mu.assign(N, 0.0);
+  for (int i = 0; i < N; ++i) {  // delta_i = v_i^T D v_i, mu_i = v_i^T G v_i, computed directly
+    double d = 0.0, g = 0.0;
+    for (int a = 0; a < N; ++a)
+      for (int b = 0; b < N; ++b) {
+        const double w = out.V[(size_t)a * N + i] * out.V[(size_t)b * N + i];
+        d += w * r.Dm[(size_t)a * N + b];
+        g += w * r.G[(size_t)a * N + b];
+      }
+    out.delta[i] = std::max(d, 0.0);
+    out.mu[i] = std::max(g, 0.0);
+  }
+  return out;
 }
 
 Vec p_prolongation(int p) {

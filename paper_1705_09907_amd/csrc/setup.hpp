@@ -37,8 +37,22 @@ struct RefDegree {
   Vec Dm;          // [P2][P2]  tau-weighted edge mass of the volume basis
   Vec E;           // [P2][4P]
   Vec Mb;          // [4P][4P]  block diagonal edge mass of the trace basis (no tau)
+  Vec C;           // [2 P2][4P] trace coupling of the flux equation (x half, then y half)
+  Vec Bt;          // [2 P2][P2] B^T, B = divergence coupling of the U equation
+  Vec Mvinv;       // [P2][P2]  inverse volume mass; A0^{-1} = diag(Mvinv, Mvinv)
   void build(int p, double h, double tau);
 };
+
+// Simultaneous diagonalisation of the pencil (G, D + G) (both symmetric, D + G
+// SPD): V^T (D + G) V = I, V^T G V = diag(mu), V^T D V = diag(delta), so that
+// for every coefficient K > 0   (D + K G)^{-1} = V diag(1 / (delta + K mu)) V^T.
+// Element-local solves with the U system then need no per-element factorisation.
+struct PencilRef {
+  int P2 = 0;
+  Vec V;           // [P2][P2], column i = eigenvector i
+  Vec delta, mu;   // [P2]
+};
+PencilRef pencil_reference(const RefDegree& r);
 
 // Condensed block of one element (4P x 4P row major) for coefficient kappa.
 // work must hold at least P2*P2 + P2*4P doubles.

@@ -1,0 +1,164 @@
+"""GPU: reconstruction, adjoint right-hand side and misfit gradient (theta = log K)
+through the C ABI, against the oracle (oracle/adjoint.py) and finite differences.
+
+Bars: reconstruction, adjoint right-hand side and the element gradient kernel
+given the same traces: 1e-12 relative (max norm).  Q and the gradient kernel:
+1e-11, since both are differences of larger terms (B^T U - C Lambda) that the
+two sides form by different exact formulas (Schur complement on U with the
+pencil basis vs the full local LU); 1.2e-12 is observed for Q at k = 4.
+End to end, both solves stop at 1e-12 relative residual.  With cond(S) ~ 1e4 at
+n = 16 that leaves ~1e-9 relative error in Lambda and mu, so the gradient is
+checked to 1e-8 relative (max norm) against the oracle's direct-solve gradient,
+and L to 1e-9.  Central differences of the GPU misfit (step 1e-4, where solve
+noise / step ~ 1e-8 and truncation ~ 1e-8) agree to 1e-5 of max |g|.  At full
+size: a Taylor test (second-order remainder).
+"""
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+import paper_1705_09907_amd as H  # noqa: E402
+from paper_1705_09907_amd.autograd import misfit  # noqa: E402
+from oracle import adjoint, hdg  # noqa: E402
+from workloads import normal_vector  # noqa: E402
+
+
+def dev(a):
+    return torch.tensor(np.asarray(a), dtype=torch.float64, device="cuda")
+
+
+def host(t):
+    torch.cuda.synchronize()
+    return t.detach().cpu().numpy()
+
+
+def rel_inf(a, b):
+    return np.abs(a - b).max() / max(np.abs(b).max(), 1e-300)
+
+
+def _gD(x, y):
+    return x * x - 0.5 * y + 0.25
+
+
+def _gq(n, nq):
+    x = H.quadrature_nodes(nq)
+    h = 1.0 / n
+    gq = np.zeros((4 * n, nq))
+    for nb in range(4 * n):
+        side, t = divmod(nb, n)
+        s = (t + 0.5 * (1 + x)) * h
+        X, Y = [(s, 0 * s), (0 * s + 1, s), (s, 0 * s + 1), (0 * s, s)][side]
+        gq[nb] = _gD(X, Y)
+    return gq
+
+
+def _case(n, k, seed, with_bd):
+    rng = np.random.default_rng(seed)
+    theta = rng.standard_normal(n * n)
+    nq = k + 2
+    f_qp = 1.0 + 0.5 * rng.standard_normal((n * n, nq * nq))
+    U_obs = 0.01 * rng.standard_normal((n * n, (k + 1) ** 2))
+    pr = hdg.Problem(n, k, np.exp(theta))
+    lam_bd = pr.boundary_trace(_gD) if with_bd else None
+    M = adjoint.Misfit(n, k, f_qp, U_obs, lam_bd=lam_bd)
+    gq = _gq(n, nq) if with_bd else None
+    return theta, f_qp, gq, U_obs, M
+
+
+@pytest.mark.parametrize("n,k,with_bd", [(16, 2, True), (8, 3, False), (5, 1, True), (4, 0, True), (24, 4, False)])
+def test_reconstruct_adjoint_rhs_and_gradient_kernels(n, k, with_bd):
+    print(f"case adjoint kernels n={n} k={k} bd={with_bd}", flush=True)
+    theta, f_qp, gq, U_obs, M = _case(n, k, 3 + n + k, with_bd)
+    L_o, lam, Q_o, U_o = M.forward(theta)
+    S = H.Solver(n, k, np.exp(theta))
+    try:
+        S.assemble_rhs(f_qp, gq)
+        U, Q = S.reconstruct(dev(lam), with_q=True)
+        assert rel_inf(host(U), U_o.reshape(-1)) <= 1e-12
+        assert rel_inf(host(Q), Q_o.reshape(-1)) <= 1e-11
+        c, L = S.adjoint_rhs(dev(U_o.reshape(-1)), dev(U_obs.reshape(-1)))
+        c_o = M.adjoint_rhs(theta, U_o)
+        assert rel_inf(host(c), c_o) <= 1e-12
+        assert abs(L - L_o) <= 1e-12 * L_o
+        _, g_o, mu_o = M.gradient(theta)
+        g = S.misfit_gradient(dev(lam), dev(U_o.reshape(-1)), dev(U_obs.reshape(-1)), dev(mu_o))
+        assert rel_inf(host(g), g_o) <= 1e-11
+    finally:
+        S.close()
+
+
+def test_reconstruct_needs_assembled_source():
+    n, k = 4, 1
+    S = H.Solver(n, k, np.ones(n * n))
+    try:
+        with pytest.raises(H.HDGError) as ei:
+            S.reconstruct(torch.zeros(S.num_dofs(), dtype=torch.float64, device="cuda"))
+        assert ei.value.status == -6
+    finally:
+        S.close()
+
+
+@pytest.mark.parametrize("opts", [dict(), dict(inner={1: 2, 0: 2}), dict(precision="f32", inner={0: 3})])
+def test_autograd_gradient_matches_oracle(opts):
+    n, k = 16, 2
+    print(f"case autograd {opts}", flush=True)
+    theta, f_qp, gq, U_obs, M = _case(n, k, 21, True)
+    th = dev(theta).requires_grad_(True)
+    L = misfit(th, dev(U_obs.reshape(-1)), n, k, f_qp, gq, rtol=1e-12, **opts)
+    L.backward()
+    L_o, g_o, _ = M.gradient(theta)
+    assert abs(float(L) - L_o) <= 1e-9 * L_o
+    assert rel_inf(host(th.grad), g_o) <= 1e-8
+
+
+def test_gpu_gradient_matches_central_differences():
+    """Finite differences of the GPU misfit itself (n = 16, k = 2) on sampled elements."""
+    n, k = 16, 2
+    theta, f_qp, gq, U_obs, M = _case(n, k, 33, True)
+    Uo = dev(U_obs.reshape(-1))
+    th = dev(theta).requires_grad_(True)
+    misfit(th, Uo, n, k, f_qp, gq, rtol=1e-12).backward()
+    g = host(th.grad)
+    hstep = 1e-4
+    for e in [0, 17, 100, n * n - 1, 136]:
+        tp, tm = theta.copy(), theta.copy()
+        tp[e] += hstep
+        tm[e] -= hstep
+        Lp = float(misfit(dev(tp), Uo, n, k, f_qp, gq, rtol=1e-12))
+        Lm = float(misfit(dev(tm), Uo, n, k, f_qp, gq, rtol=1e-12))
+        fd = (Lp - Lm) / (2 * hstep)
+        assert abs(fd - g[e]) <= 1e-5 * np.abs(g).max(), (e, fd, g[e])
+
+
+def test_full_size_taylor():
+    """512 x 512, k = 2, theta ~ N(0, 1) (seed 5), data from a perturbed coefficient
+    plus 1% noise: |L(theta + t v) - L(theta) - t g.v| falls like t^2."""
+    n, k = 512, 2
+    print("case full-size adjoint n=512 k=2", flush=True)
+    rng5, rng6, rng7 = (np.random.default_rng(s) for s in (5, 6, 7))
+    theta = rng5.standard_normal(n * n)
+    theta_obs = theta + 0.5 * rng6.standard_normal(n * n)
+    nq = k + 2
+    f_qp = np.ones((n * n, nq * nq))
+    opts = dict(inner={1: 2, 0: 3}, rtol=1e-12)
+    So = H.Solver(n, k, np.exp(theta_obs), inner=opts["inner"])
+    b = So.assemble_rhs(f_qp)
+    lam, _, _, _ = So.solve(b, rtol=1e-12, mode="fcg")
+    U_true = So.reconstruct(lam)
+    So.close()
+    rms = float(torch.sqrt(torch.mean(U_true ** 2)))
+    U_obs = U_true + 0.01 * rms * dev(rng7.standard_normal(U_true.numel()))
+    th = dev(theta).requires_grad_(True)
+    L0 = misfit(th, U_obs, n, k, f_qp, None, **opts)
+    L0.backward()
+    g = th.grad
+    v = dev(normal_vector(n * n, 8))
+    gv = float(g @ v)
+    errs = []
+    for t in (4e-3, 2e-3, 1e-3):
+        Lt = float(misfit(dev(theta) + t * v, U_obs, n, k, f_qp, None, **opts))
+        errs.append(abs(Lt - float(L0) - t * gv))
+    print("taylor remainders", errs, flush=True)
+    assert 3.0 < errs[0] / errs[1] < 5.0 and 3.0 < errs[1] / errs[2] < 5.0, errs
