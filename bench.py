@@ -16,6 +16,11 @@ vectors and accumulation, blocks FP32 or bfloat16) under the FP64 outer solver;
 the timed apply is then the reduced-precision one, and the plain FP64 solve of the
 same system is timed after the timed region for comparison.
 
+Workload adjoint_n512_k2 adds to every step one misfit gradient with respect to
+theta = log K (forward solve, reconstruction, adjoint right-hand side, adjoint
+solve, element gradient kernel), reported as gradient_ms; its data come from a
+perturbed coefficient plus 1% noise and are built before the timed region.
+
 Prints one JSON line.  `value` is the trace apply throughput N(k) / t_apply.
 """
 import argparse
@@ -36,6 +41,9 @@ WORKLOADS = {
     "lognormal_n256_k4": dict(n=256, k=4, sigma=1.0, seed=2, inner="1:2,0:2"),
     "lognormal_n1024_k3": dict(n=1024, k=3, sigma=2.0, seed=3, inner="1:4,0:4"),
     "poisson_sin_n16_k1": dict(n=16, k=1, sigma=None, seed=None, inner=""),
+    # misfit gradient: theta ~ N(0,1) (seed 5); data U(theta + 0.5 N(0,1) (seed 6)) plus
+    # 1% noise (seed 7); each step adds one gradient (forward + adjoint solve) to the solve
+    "adjoint_n512_k2": dict(n=512, k=2, sigma=1.0, seed=5, inner="1:2,0:3", adjoint=True),
 }
 
 
@@ -134,6 +142,18 @@ def main():
     lam = torch.zeros(N, dtype=torch.float64, device=dev)
     apply = (lambda: S.apply_lp(k, x, y)) if lp else (lambda: S.apply(k, x, y))
     flush = torch.empty(1 << 27, dtype=torch.float64, device=dev)  # 1 GiB > Infinity Cache
+    adj = None
+    if w.get("adjoint"):  # synthetic data for the misfit (before the timed region)
+        theta_obs = np.log(kap) + 0.5 * np.random.default_rng(6).standard_normal(n * n)
+        So = H.Solver(n, k, np.exp(theta_obs), smoother=args.smoother, inner=inner)
+        bo = So.assemble_rhs(np.ones((n * n, nq * nq)))
+        lo, _, _, _ = So.solve(bo, rtol=1e-10, maxit=500, mode=args.mode)
+        Ut = So.reconstruct(lo)
+        So.close()
+        rms = float(torch.sqrt(torch.mean(Ut ** 2)))
+        noise = torch.tensor(np.random.default_rng(7).standard_normal(Ut.numel()), device=dev)
+        adj = {"U_obs": Ut + 0.01 * rms * noise, "grad": torch.empty(n * n, dtype=torch.float64, device=dev)}
+        S.assemble_rhs(np.ones((n * n, nq * nq)))  # the handle's source state is this workload's f
     stream = torch.cuda.current_stream()
 
     def step(record):
@@ -146,8 +166,21 @@ def main():
         s0.record(stream)
         _, it, rr, hist = S.solve(b, lam, rtol=1e-10, maxit=500, mode=args.mode)
         s1.record(stream)
+        gms = None
+        if adj is not None:  # one misfit gradient: forward solve, reconstruction, adjoint solve
+            g0, g1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            g0.record(stream)
+            lam.zero_()
+            S.solve(b, lam, rtol=1e-10, maxit=500, mode=args.mode)
+            U = S.reconstruct(lam)
+            c, _ = S.adjoint_rhs(U, adj["U_obs"])
+            mu = torch.zeros_like(c)
+            S.solve(c, mu, rtol=1e-10, maxit=500, mode=args.mode)
+            S.misfit_gradient(lam, U, adj["U_obs"], mu, adj["grad"])
+            g1.record(stream)
+            gms = (g0, g1)
         if record is not None:
-            record.append((kus, None, s0, s1, it, rr, hist))
+            record.append((kus, gms, s0, s1, it, rr, hist))
 
     for _ in range(args.warmup):
         step(None)
@@ -159,6 +192,7 @@ def main():
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
     apply_ms = np.array([r[0] * 1e-3 for r in rec])
+    grad_ms = None if adj is None else float(np.median([r[1][0].elapsed_time(r[1][1]) for r in rec]))
     solve_ms = np.array([r[2].elapsed_time(r[3]) for r in rec])
     iters = rec[-1][4]
     relres = rec[-1][5]
@@ -247,6 +281,7 @@ def main():
         "apply_us_warm": None if warm_ms is None else warm_ms * 1e3,
         "solve_ms": float(np.median(solve_ms)), "solve_iters": iters, "solve_relres": relres,
         "solve_rate": rho, "setup_s": setup_s, "rhs_s": rhs_s,
+        "gradient_ms": grad_ms,
         "f64_reference": f64_ref, "plain_vcycle_pcg_reference": plain_ref,
         "roofline": {"bound": "hbm", "kernel": f"k_trace<P={k + 1}, APPLY, {args.precision}>", "achieved": achieved,
                      "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
