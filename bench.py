@@ -88,7 +88,42 @@ def cpu_baseline(sigma, seed, k, budget_s=12.0):
                       f"{reps} reps over {budget_s:.0f}s; oracle assembly of that sample {t_setup:.1f}s"}
 
 
+def pmc_summary(fetch_db, write_db, kernel, calib=None):
+    """Per-dispatch FETCH_SIZE / WRITE_SIZE (KiB) of the kernels whose name contains
+    `kernel`, averaged, from two rocprofv3 --pmc databases; for the calibration
+    kernel (a plain device copy of known size) the figures of its largest dispatch
+    (other dispatches of that kernel are small runtime copies)."""
+    import sqlite3
+    from collections import defaultdict
+
+    def per_kernel(db, counter):
+        out = defaultdict(list)
+        cur = sqlite3.connect(db).cursor()
+        for name, val in cur.execute("select kernel_name, value from counters_collection where counter_name=?",
+                                     (counter,)):
+            out[name].append(val)
+        return out
+
+    f, w = per_kernel(fetch_db, "FETCH_SIZE"), per_kernel(write_db, "WRITE_SIZE")
+    for label, sub in (("kernel", kernel), ("calibration", calib)):
+        if sub is None:
+            continue
+        for name in sorted(set(f) | set(w)):
+            if sub in name:
+                fv, wv = f.get(name, []), w.get(name, [])
+                agg = max if label == "calibration" else (lambda v: sum(v) / len(v))
+                fm = agg(fv) if fv else float("nan")
+                wm = agg(wv) if wv else float("nan")
+                print(f"{label}\t{name[:90]}\tdispatches={len(fv)}/{len(wv)}\t"
+                      f"FETCH_KiB={fm:.1f}\tWRITE_KiB={wm:.1f}\tFETCH_MB={fm * 1024 / 1e6:.2f}\t"
+                      f"WRITE_MB={wm * 1024 / 1e6:.2f}")
+
+
 def main():
+    if len(sys.argv) > 1 and sys.argv[1] == "--pmc-summary":
+        # bench.py --pmc-summary <fetch_db> <write_db> <kernel-substring> [calibration-substring]
+        pmc_summary(*sys.argv[2:6])
+        return
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=5)
