@@ -47,6 +47,11 @@ WORKLOADS = {
 }
 
 
+# HBM bytes per launch of the APPLY kernel, from FETCH_SIZE and WRITE_SIZE counter
+# passes scaled by a plain 256 MiB copy (x2.00 / x1.00), as recorded in
+# profiles/trace_apply_lognormal_n256_k4.md.  Reset to None whenever k_trace changes.
+MEASURED_TRAFFIC = {("lognormal_n256_k4", "f64"): 204.9e6}
+
 MAT_BYTES = {"f64": 8, "f32": 4, "bf16": 4}  # the finest level keeps FP32 blocks in the bf16 cycle
 VEC_BYTES = {"f64": 8, "f32": 4, "bf16": 4}
 
@@ -320,7 +325,8 @@ def main():
         "f64_reference": f64_ref, "plain_vcycle_pcg_reference": plain_ref,
         "roofline": {"bound": "hbm", "kernel": f"k_trace<P={k + 1}, APPLY, {args.precision}>", "achieved": achieved,
                      "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
-                     "traffic": None, "algorithmic_bytes": byts, "flops": flops},
+                     "traffic": MEASURED_TRAFFIC.get((args.workload, args.precision)),
+                     "algorithmic_bytes": byts, "flops": flops},
     }
     if not lp:
         S.close()
