@@ -44,6 +44,9 @@ WORKLOADS = {
     # misfit gradient: theta ~ N(0,1) (seed 5); data U(theta + 0.5 N(0,1) (seed 6)) plus
     # 1% noise (seed 7); each step adds one gradient (forward + adjoint solve) to the solve
     "adjoint_n512_k2": dict(n=512, k=2, sigma=1.0, seed=5, inner="1:2,0:3", adjoint=True),
+    # many right-hand sides: 64 vectors N(0,1) (seed 4), FP32 blocks; each step adds one
+    # cold apply Y = S X for all 64 at once (batch_us_cold, RHS-DoF/s)
+    "batch_n512_k5_r64": dict(n=512, k=5, sigma=1.0, seed=4, inner="1:2,0:2", nrhs=64, precision="f32"),
 }
 
 
@@ -159,6 +162,8 @@ def main():
     w = WORKLOADS[args.workload]
     n, k = w["n"], w["k"]
     kap = kappa_lognormal(n, w["sigma"], w["seed"]) if w["sigma"] else np.ones(n * n)
+    if w.get("precision") and args.precision == "f64":
+        args.precision = w["precision"]
     lp = args.precision != "f64"
     spec = w["inner"] if args.inner == "auto" else args.inner
     inner = {int(p): int(m) for p, m in (t.split(":") for t in spec.split(",") if t)}
@@ -182,6 +187,12 @@ def main():
     lam = torch.zeros(N, dtype=torch.float64, device=dev)
     apply = (lambda: S.apply_lp(k, x, y)) if lp else (lambda: S.apply(k, x, y))
     flush = torch.empty(1 << 27, dtype=torch.float64, device=dev)  # 1 GiB > Infinity Cache
+    batch = None
+    if w.get("nrhs"):  # many right-hand sides at once (cycle precision)
+        gen = torch.Generator(device=dev).manual_seed(4)
+        X = torch.randn(N, w["nrhs"], device=dev, generator=gen,
+                        dtype=torch.float32 if lp else torch.float64)
+        batch = {"X": X, "Y": torch.empty_like(X)}
     adj = None
     if w.get("adjoint"):  # synthetic data for the misfit (before the timed region)
         theta_obs = np.log(kap) + 0.5 * np.random.default_rng(6).standard_normal(n * n)
@@ -206,6 +217,14 @@ def main():
         s0.record(stream)
         _, it, rr, hist = S.solve(b, lam, rtol=1e-10, maxit=500, mode=args.mode)
         s1.record(stream)
+        bev = None
+        if batch is not None:  # cold apply of all right-hand sides at once
+            flush.zero_()
+            b0, b1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            b0.record(stream)
+            S.apply_multi(k, batch["X"], batch["Y"])
+            b1.record(stream)
+            bev = (b0, b1)
         gms = None
         if adj is not None:  # one misfit gradient: forward solve, reconstruction, adjoint solve
             g0, g1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
@@ -220,7 +239,7 @@ def main():
             g1.record(stream)
             gms = (g0, g1)
         if record is not None:
-            record.append((kus, gms, s0, s1, it, rr, hist))
+            record.append((kus, gms, s0, s1, it, rr, hist, bev))
 
     for _ in range(args.warmup):
         step(None)
@@ -233,6 +252,18 @@ def main():
     wall = time.perf_counter() - t0
     apply_ms = np.array([r[0] * 1e-3 for r in rec])
     grad_ms = None if adj is None else float(np.median([r[1][0].elapsed_time(r[1][1]) for r in rec]))
+    batch_out = None
+    if batch is not None:
+        bus = float(np.mean([r[7][0].elapsed_time(r[7][1]) for r in rec])) * 1e3
+        R_ = w["nrhs"]
+        _, fl1 = algorithmic_bytes(n, k)          # 2 x (block entries)
+        entries = fl1 // 2
+        # every block entry once, X and Y once, in the cycle precision
+        bb = entries * MAT_BYTES[args.precision] + 2 * N * R_ * VEC_BYTES[args.precision]
+        batch_out = {"nrhs": R_, "batch_us_cold": bus, "rhs_dof_per_s": R_ * N / (bus * 1e-6),
+                     "algorithmic_bytes": bb, "achieved_GBs": bb / (bus * 1e-6) / 1e9,
+                     "frac_hbm": bb / (bus * 1e-6) / 1e9 / HBM_PEAK_GBS,
+                     "flops": fl1 * R_, "timing": "HIP events on the stream, after a cache flush"}
     solve_ms = np.array([r[2].elapsed_time(r[3]) for r in rec])
     iters = rec[-1][4]
     relres = rec[-1][5]
@@ -321,7 +352,7 @@ def main():
         "apply_us_warm": None if warm_ms is None else warm_ms * 1e3,
         "solve_ms": float(np.median(solve_ms)), "solve_iters": iters, "solve_relres": relres,
         "solve_rate": rho, "setup_s": setup_s, "rhs_s": rhs_s,
-        "gradient_ms": grad_ms,
+        "gradient_ms": grad_ms, "batch": batch_out,
         "f64_reference": f64_ref, "plain_vcycle_pcg_reference": plain_ref,
         "roofline": {"bound": "hbm", "kernel": f"k_trace<P={k + 1}, APPLY, {args.precision}>", "achieved": achieved,
                      "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,

@@ -164,6 +164,15 @@ hdg_status_t hdg_apply_trace_operator(hdg_handle_t h, int32_t p, const double* x
  * STATE for an FP64 handle. */
 hdg_status_t hdg_apply_trace_operator_lp(hdg_handle_t h, int32_t p, const float* x, float* y);
 
+/* Y = S_p X for nrhs right-hand sides at once (1 <= nrhs <= 4096): X, Y are
+ * device arrays [N(p)][nrhs], the right-hand sides of one trace DoF contiguous.
+ * precision HDG_PREC_F64: double arrays and the FP64 operator (same level rule
+ * as hdg_apply_trace_operator); the cycle precision of the handle: float arrays
+ * and that precision's blocks.  The blocks are read once per call, whatever
+ * nrhs.  X and Y must not alias. */
+hdg_status_t hdg_apply_trace_operator_multi(hdg_handle_t h, int32_t p, int32_t precision, int32_t nrhs,
+                                            const void* X, void* Y);
+
 /* Measurement entry point: the same product as hdg_apply_trace_operator
  * (precision HDG_PREC_F64, FP64 vectors) or hdg_apply_trace_operator_lp
  * (precision = the handle's cycle precision, float vectors), launched with a

@@ -56,6 +56,7 @@ SIGNATURES = {
     "hdg_apply_trace_operator": [_P, _I32, _P, _P],
     "hdg_apply_trace_operator_lp": [_P, _I32, _P, _P],
     "hdg_apply_trace_operator_timed": [_P, _I32, _I32, _P, _P, _PD],
+    "hdg_apply_trace_operator_multi": [_P, _I32, _I32, _I32, _P, _P],
     "hdg_residual": [_P, _I32, _P, _P, _P, _PD],
     "hdg_smooth": [_P, _I32, _P, _P, _I32],
     "hdg_restrict": [_P, _I32, _P, _P],
@@ -246,6 +247,21 @@ class Solver:
             self._h, p, PRECISIONS[self.precision] if lp else 0, _dptr(x, "x", N, dt), _dptr(y, "y", N, dt),
             ctypes.byref(us)))
         return us.value
+
+    def apply_multi(self, p, X, Y=None):
+        """Y = S_p X for X [N(p), nrhs] (float64: FP64 operator; float32: the cycle precision)."""
+        import torch
+        N = self.num_dofs(p)
+        if X.dim() != 2 or X.shape[0] != N:
+            raise ValueError(f"X must be [{N}, nrhs]")
+        lp = X.dtype == torch.float32
+        dt = "float32" if lp else "float64"
+        Y = torch.empty_like(X) if Y is None else Y
+        R = X.shape[1]
+        self._check(lib.hdg_apply_trace_operator_multi(
+            self._h, p, PRECISIONS[self.precision] if lp else 0, R, _dptr(X, "X", N * R, dt),
+            _dptr(Y, "Y", N * R, dt)))
+        return Y
 
     def residual(self, p, b, x, r=None, norm=False):
         N = self.num_dofs(p)

@@ -1093,6 +1093,28 @@ hdg_status_t hdg_apply_trace_operator_timed(hdg_handle_t h, int32_t p, int32_t p
   });
 }
 
+hdg_status_t hdg_apply_trace_operator_multi(hdg_handle_t h, int32_t p, int32_t precision, int32_t nrhs,
+                                            const void* X, void* Y) {
+  if (!h || !X || !Y || p < 0 || p > h->k || X == Y || nrhs < 1 || nrhs > 4096) return HDG_ERR_INVALID_ARG;
+  if (precision != HDG_PREC_F64 && precision != (int32_t)h->prec) return HDG_ERR_INVALID_ARG;
+  if (precision == HDG_PREC_F64 && need_f64_level(h, p) != HDG_OK) return HDG_ERR_STATE;
+  return guarded(h, [&]() -> hdg_status_t {
+    const hdg::Prec pr = precision == HDG_PREC_F64 ? hdg::Prec::F64 : h->prec;
+    const PLevel& L = h->pl[p];
+    hdg::MultiArgs a{};
+    a.slab = pr == hdg::Prec::F64 && h->prec != hdg::Prec::F64 ? static_cast<const void*>(L.slab64) : L.slab;
+    a.X = X;
+    a.Y = Y;
+    a.nrhs = nrhs;
+    a.n = h->n;
+    a.nf = h->nf;
+    a.ntiles = h->ntiles;
+    a.remap = 1;
+    hipchk(hdg::launch_trace_multi(kprec(L, pr), L.P, a, h->stream), "trace apply multi");
+    return HDG_OK;
+  });
+}
+
 hdg_status_t hdg_apply_trace_operator_lp(hdg_handle_t h, int32_t p, const float* x, float* y) {
   if (!h || !x || !y || p < 0 || p > h->k || (const void*)x == (const void*)y) return HDG_ERR_INVALID_ARG;
   if (h->prec == hdg::Prec::F64) {

@@ -219,6 +219,85 @@ static hipError_t launch_trace_p(Prec pr, int mode, const TraceArgs& a, hipStrea
   return hipErrorInvalidValue;
 }
 
+// ------------------------------------------------- many right-hand sides
+// One workgroup per group of FW consecutive faces (FW divides 64, so a group
+// lies in one tile): the group's 7 P^2 blocks are read once from the
+// interleaved slab (runs of FW 16-byte words) into LDS, then threads take
+// (face, right-hand side) pairs; with 64 or more right-hand sides a wavefront
+// works on one face with its lanes over right-hand sides, so every x gather and
+// y store is a contiguous 64-lane access and the block entries are LDS
+// broadcasts.  LDS holds each block transposed with its columns padded to PQ
+// (a multiple of 16 bytes), so the P entries that multiply one gathered x value
+// come in a few 16-byte LDS reads.
+template <int P, typename TV>
+struct MultiGroup {
+  static constexpr int FW = P <= 6 ? 16 : 8;
+  static constexpr int PQ = sizeof(TV) == 8 ? (P + 1) / 2 * 2 : (P + 3) / 4 * 4;
+};
+
+template <int P, typename TM, typename TV>
+__global__ __launch_bounds__(256) void k_trace_multi(MultiArgs a) {
+  using L16 = Lanes16<TM, TV>;
+  constexpr int V = L16::V;
+  constexpr int P2 = P * P;
+  constexpr int NE = 7 * P2;
+  constexpr int NQ = (NE + V - 1) / V;
+  constexpr int FW = MultiGroup<P, TV>::FW;
+  constexpr int PQ = MultiGroup<P, TV>::PQ;
+  __shared__ __align__(16) TV blk[FW][7 * P * PQ];
+  // a.remap: workgroups are dealt round-robin to the 8 XCDs; giving XCD x the
+  // contiguous range of groups [x G/8, (x+1) G/8) lets its L2 serve the x rows
+  // that neighbouring groups share
+  const int64_t G = (a.nf + FW - 1) / FW;
+  int64_t grp = blockIdx.x;
+  if (a.remap && G % 8 == 0) grp = (int64_t)(blockIdx.x & 7) * (G >> 3) + (blockIdx.x >> 3);
+  const int64_t f0 = grp * FW;
+  const int64_t tile = f0 >> 6;
+  const int l0 = (int)(f0 & 63);
+  const u32x4* sp = static_cast<const u32x4*>(a.slab) + tile * NQ * 64 + l0;
+  for (int i = threadIdx.x; i < NQ * FW; i += blockDim.x) {
+    const int q = i / FW, fl = i - q * FW;
+    TV w[V];
+    L16::unpack(__builtin_nontemporal_load(sp + q * 64 + fl), w);
+#pragma unroll
+    for (int u = 0; u < V; ++u) {
+      const int e = q * V + u;  // slot s, row r, column c  ->  blk[s][c][r]
+      if (e < NE) {
+        const int s = e / P2, rc = e - s * P2, r = rc / P, c = rc - r * P;
+        blk[fl][(s * P + c) * PQ + r] = w[u];
+      }
+    }
+  }
+  __syncthreads();
+  const TV* X = static_cast<const TV*>(a.X);
+  TV* Y = static_cast<TV*>(a.Y);
+  const int R = a.nrhs;
+  const int64_t nv = (int64_t)a.n * (a.n - 1);
+  for (int pair = threadIdx.x; pair < FW * R; pair += blockDim.x) {
+    const int fl = pair / R, r = pair - fl * R;
+    const int64_t f = f0 + fl;
+    if (f >= a.nf) continue;
+    int64_t g[7];
+    face_neighbours(a.n, nv, f, g);
+    TV acc[P];
+#pragma unroll
+    for (int q = 0; q < P; ++q) acc[q] = TV(0);
+#pragma unroll
+    for (int s = 0; s < 7; ++s) {
+      if (g[s] < 0) continue;
+#pragma unroll
+      for (int c = 0; c < P; ++c) {
+        const TV xv = X[(g[s] * P + c) * R + r];
+        const TV* col = &blk[fl][(s * P + c) * PQ];
+#pragma unroll
+        for (int q = 0; q < P; ++q) acc[q] += col[q] * xv;
+      }
+    }
+#pragma unroll
+    for (int q = 0; q < P; ++q) Y[(f * P + q) * R + r] = acc[q];
+  }
+}
+
 #define HDG_DISPATCH_P(P, CALL)                       \
   switch (P) {                                        \
     case 1: { constexpr int PP = 1; CALL; } break;    \
@@ -232,6 +311,26 @@ static hipError_t launch_trace_p(Prec pr, int mode, const TraceArgs& a, hipStrea
     case 9: { constexpr int PP = 9; CALL; } break;    \
     default: return hipErrorInvalidValue;             \
   }
+
+template <int P>
+static hipError_t launch_trace_multi_p(Prec pr, const MultiArgs& a, hipStream_t s) {
+  constexpr int FW = MultiGroup<P, double>::FW;
+  const dim3 grid((unsigned)((a.nf + FW - 1) / FW));
+  const int64_t pairs = (int64_t)FW * a.nrhs;
+  const dim3 block((unsigned)(pairs >= 256 ? 256 : (pairs + 63) / 64 * 64));
+  switch (pr) {
+    case Prec::F64: hipLaunchKernelGGL((k_trace_multi<P, double, double>), grid, block, 0, s, a); break;
+    case Prec::F32: hipLaunchKernelGGL((k_trace_multi<P, float, float>), grid, block, 0, s, a); break;
+    case Prec::BF16: hipLaunchKernelGGL((k_trace_multi<P, bf16_t, float>), grid, block, 0, s, a); break;
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_trace_multi(Prec pr, int P, const MultiArgs& a, hipStream_t s) {
+  if (a.nrhs < 1) return hipErrorInvalidValue;
+  if (a.nf == 0) return hipSuccess;
+  HDG_DISPATCH_P(P, return launch_trace_multi_p<PP>(pr, a, s));
+}
 
 hipError_t launch_trace(Prec pr, int P, int mode, const TraceArgs& a, hipStream_t s) {
   HDG_DISPATCH_P(P, return launch_trace_p<PP>(pr, mode, a, s));

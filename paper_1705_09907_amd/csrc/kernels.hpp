@@ -46,6 +46,20 @@ int trace_grid(int64_t ntiles);      // workgroups of a trace launch
 int trace_partials(int64_t ntiles);  // partial sums written when TraceArgs::partial is set
 hipError_t launch_trace(Prec pr, int P, int mode, const TraceArgs& a, hipStream_t s);
 
+// Y = S X for nrhs right-hand sides at once; X, Y [nf P][nrhs] (right-hand
+// sides contiguous), vector precision.  The blocks of a group of faces are read
+// once into LDS and applied to every right-hand side.
+struct MultiArgs {
+  const void* slab;
+  const void* X;
+  void* Y;
+  int nrhs;
+  int n;
+  int64_t nf, ntiles;
+  int remap;   // XCD-contiguous group order
+};
+hipError_t launch_trace_multi(Prec pr, int P, const MultiArgs& a, hipStream_t s);
+
 // x = omega Dinv b (first facet sweep from a zero guess)
 hipError_t launch_dinv_apply(Prec pr, int P, const void* dinv, const void* b, double omega, void* x,
                              int64_t nf, hipStream_t s);
