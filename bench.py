@@ -127,6 +127,68 @@ def pmc_summary(fetch_db, write_db, kernel, calib=None):
                       f"WRITE_MB={wm * 1024 / 1e6:.2f}")
 
 
+def uneven_batch(args):
+    """32 meshes n_i = 64 + 32 (i mod 11), k_i = 2 + (i mod 3), K lognormal sigma = 1
+    (seed 40 + i): one cold apply of all meshes in one launch, against 32 cold
+    applies launched back to back.  Prints one JSON line."""
+    import torch
+    import paper_1705_09907_amd as H
+    from workloads import kappa_lognormal, normal_vector
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    spec = [(64 + 32 * (i % 11), 2 + (i % 3)) for i in range(32)]
+    t0 = time.perf_counter()
+    solvers = [H.Solver(n, k, kappa_lognormal(n, 1.0, 40 + i)) for i, (n, k) in enumerate(spec)]
+    setup_s = time.perf_counter() - t0
+    xs = [torch.tensor(normal_vector(s.num_dofs(), 7 + i), device=dev) for i, s in enumerate(solvers)]
+    ys = [torch.empty_like(x) for x in xs]
+    flush = torch.empty(1 << 27, dtype=torch.float64, device=dev)
+    stream = torch.cuda.current_stream()
+    Ntot = sum(s.num_dofs() for s in solvers)
+    byts = sum(algorithmic_bytes(n, k)[0] for n, k in spec)
+
+    def timed(fn):
+        flush.zero_()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        fn()
+        e1.record(stream)
+        torch.cuda.synchronize()
+        return e0.elapsed_time(e1) * 1e3
+
+    def one_launch():
+        H.apply_batch(solvers, xs, ys)
+
+    def separate():
+        for s, x, y in zip(solvers, xs, ys):
+            s.apply(s.k, x, y)
+
+    for _ in range(args.warmup):
+        timed(one_launch)
+        timed(separate)
+    wall0 = time.perf_counter()
+    t_one = [timed(one_launch) for _ in range(args.steps)]
+    t_sep = [timed(separate) for _ in range(args.steps)]
+    wall = time.perf_counter() - wall0
+    t1 = float(np.mean(t_one))
+    achieved = byts / (t1 * 1e-6) / 1e9
+    out = {"metric": METRIC, "value": Ntot / (t1 * 1e-6), "unit": "trace-DoF/s", "n_gpus": 1,
+           "steps": args.steps, "warmup": args.warmup, "ms_per_step": wall / args.steps * 1e3,
+           "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64",
+           "data": "synthetic",
+           "config": {"workload": "uneven32", "meshes": len(spec), "n": [n for n, _ in spec],
+                      "k": [k for _, k in spec], "kappa": "lognormal sigma=1 seeds 40..71",
+                      "trace_dofs": Ntot},
+           "apply_us_one_launch": t1, "apply_us_separate": float(np.mean(t_sep)), "setup_s": setup_s,
+           "roofline": {"bound": "hbm", "kernel": "k_trace_batch<5>", "achieved": achieved,
+                        "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                        "algorithmic_bytes": byts,
+                        "timing": "HIP events on the stream around the call, after a cache flush"}}
+    for s in solvers:
+        s.close()
+    print(json.dumps(out), flush=True)
+
+
 def main():
     if len(sys.argv) > 1 and sys.argv[1] == "--pmc-summary":
         # bench.py --pmc-summary <fetch_db> <write_db> <kernel-substring> [calibration-substring]
@@ -136,7 +198,7 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--workload", default="lognormal_n256_k4", choices=sorted(WORKLOADS))
+    ap.add_argument("--workload", default="lognormal_n256_k4", choices=sorted(WORKLOADS) + ["uneven32"])
     ap.add_argument("--mode", default="auto", choices=["auto", "pcg", "vcycle", "fcg"],
                     help="outer solver; auto = fcg with K-cycle levels, else pcg")
     ap.add_argument("--inner", default="auto",
@@ -154,6 +216,9 @@ def main():
         print("bench.py: this build measures one GPU only; multi-GPU runs are not part of it "
               "(the apply would shard by element rows with one halo exchange per apply).", file=sys.stderr)
         sys.exit(2)
+    if args.workload == "uneven32":
+        uneven_batch(args)
+        return
 
     import torch
     import paper_1705_09907_amd as H

@@ -173,6 +173,16 @@ hdg_status_t hdg_apply_trace_operator_lp(hdg_handle_t h, int32_t p, const float*
 hdg_status_t hdg_apply_trace_operator_multi(hdg_handle_t h, int32_t p, int32_t precision, int32_t nrhs,
                                             const void* X, void* Y);
 
+/* y_i = S x_i for count meshes of any sizes and degrees in ONE kernel launch
+ * (FP64 operators, level p[i] of handles[i]; same level rule as
+ * hdg_apply_trace_operator).  handles, p, X, Y: host arrays of count entries;
+ * X[i], Y[i]: device [N_i(p[i])] vectors, not aliased.  A fixed grid walks the
+ * (mesh, 64-face tile) items with a static stride; each y_i is bit-identical to
+ * the single-mesh apply.  Runs on the stream of handles[0] (inputs of every mesh
+ * must be ready there) and synchronizes that stream before returning. */
+hdg_status_t hdg_apply_trace_operator_batch(int32_t count, const hdg_handle_t* handles, const int32_t* p,
+                                            const double* const* X, double* const* Y);
+
 /* Measurement entry point: the same product as hdg_apply_trace_operator
  * (precision HDG_PREC_F64, FP64 vectors) or hdg_apply_trace_operator_lp
  * (precision = the handle's cycle precision, float vectors), launched with a

@@ -70,6 +70,9 @@ struct hdg_ctx {
   double *vr = nullptr, *vz = nullptr, *vd = nullptr, *vq = nullptr;  // solver vectors (FP64)
   void *cva = nullptr, *cvb = nullptr;  // cycle-precision copies of FP64 vectors (size N(k))
   hipEvent_t ev0 = nullptr, ev1 = nullptr;  // timed apply
+  hdg::BatchMesh* batch_dev = nullptr;      // descriptor table of hdg_apply_trace_operator_batch
+  int batch_cap = 0;
+  std::vector<hdg::BatchMesh> batch_host;
   // misfit gradient: degree-k reference pack, coefficients, and the source state
   // of the last hdg_assemble_rhs (load vectors, boundary traces)
   double *ref_dev = nullptr, *kappa_dev = nullptr, *F_dev = nullptr, *lambd_dev = nullptr;
@@ -1111,6 +1114,50 @@ hdg_status_t hdg_apply_trace_operator_multi(hdg_handle_t h, int32_t p, int32_t p
     a.ntiles = h->ntiles;
     a.remap = 1;
     hipchk(hdg::launch_trace_multi(kprec(L, pr), L.P, a, h->stream), "trace apply multi");
+    return HDG_OK;
+  });
+}
+
+hdg_status_t hdg_apply_trace_operator_batch(int32_t count, const hdg_handle_t* handles, const int32_t* p,
+                                            const double* const* X, double* const* Y) {
+  if (count < 1 || !handles || !p || !X || !Y) return HDG_ERR_INVALID_ARG;
+  for (int i = 0; i < count; ++i) {
+    hdg_handle_t h = handles[i];
+    if (!h || p[i] < 0 || p[i] > h->k || !X[i] || !Y[i] || (const void*)X[i] == (const void*)Y[i])
+      return HDG_ERR_INVALID_ARG;
+    if (need_f64_level(h, p[i]) != HDG_OK) return HDG_ERR_STATE;
+  }
+  hdg_handle_t h0 = handles[0];
+  return guarded(h0, [&]() -> hdg_status_t {
+    h0->batch_host.resize(count);
+    int64_t tot = 0;
+    int pmax = 1;
+    for (int i = 0; i < count; ++i) {
+      const hdg_handle_t h = handles[i];
+      const PLevel& L = h->pl[p[i]];
+      hdg::BatchMesh& M = h0->batch_host[i];
+      M.slab = L.slab64;
+      M.x = X[i];
+      M.y = Y[i];
+      M.nf = h->nf;
+      M.ntiles = h->ntiles;
+      M.tile0 = tot;
+      M.n = h->n;
+      M.P = L.P;
+      pmax = std::max(pmax, L.P);
+      tot += h->ntiles;
+    }
+    if (h0->batch_cap < count) {
+      h0->batch_dev = static_cast<hdg::BatchMesh*>(balloc(h0, sizeof(hdg::BatchMesh) * (size_t)count));
+      h0->batch_cap = count;
+    }
+    hipchk(hipMemcpyAsync(h0->batch_dev, h0->batch_host.data(), sizeof(hdg::BatchMesh) * (size_t)count,
+                          hipMemcpyHostToDevice, h0->stream), "h2d");
+    // a fixed grid: 8 workgroups per compute unit, or fewer for small batches
+    const int64_t need = (tot + 3) / 4;
+    const int grid = (int)std::max<int64_t>(1, std::min<int64_t>(need, 256 * 8));
+    hipchk(hdg::launch_trace_batch(h0->batch_dev, count, tot, grid, pmax, h0->stream), "trace apply batch");
+    hipchk(hipStreamSynchronize(h0->stream), "sync");  // the descriptor table is reused by the next call
     return HDG_OK;
   });
 }

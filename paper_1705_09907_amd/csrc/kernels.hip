@@ -186,6 +186,93 @@ __global__ __launch_bounds__(kWG) void k_trace(TraceArgs a) {
   }
 }
 
+// ------------------------------------------------ many meshes in one launch
+// y = S x on one 64-face tile of one mesh, by one wavefront: the APPLY path of
+// k_trace with the same loads and the same order of operations.
+template <int P>
+__device__ __forceinline__ void apply_tile_f64(const BatchMesh& M, int64_t tile, int lane) {
+  using L16 = Lanes16<double, double>;
+  constexpr int V = L16::V;
+  constexpr int P2 = P * P;
+  constexpr int NE = 7 * P2;
+  constexpr int NQ = (NE + V - 1) / V;
+  const double* x = static_cast<const double*>(M.x);
+  double* y = static_cast<double*>(M.y);
+  const int64_t nv = (int64_t)M.n * (M.n - 1);
+  const int64_t f = tile * 64 + lane;
+  const bool valid = f < M.nf;
+  int64_t g[7];
+  face_neighbours(M.n, nv, valid ? f : 0, g);
+  double xv[7][P];
+#pragma unroll
+  for (int s = 0; s < 7; ++s)
+#pragma unroll
+    for (int c = 0; c < P; ++c) xv[s][c] = (valid && g[s] >= 0) ? x[g[s] * P + c] : 0.0;
+  double acc[P];
+#pragma unroll
+  for (int r = 0; r < P; ++r) acc[r] = 0.0;
+  const u32x4* sp = static_cast<const u32x4*>(M.slab) + (tile * NQ) * 64 + lane;
+#pragma unroll
+  for (int q = 0; q < NQ; ++q) {
+    double w[V];
+    L16::unpack(__builtin_nontemporal_load(sp + q * 64), w);
+#pragma unroll
+    for (int u = 0; u < V; ++u) {
+      const int e = q * V + u;
+      if (e < NE) acc[(e % P2) / P] += w[u] * xv[e / P2][e % P];
+    }
+  }
+  if (valid) {
+#pragma unroll
+    for (int r = 0; r < P; ++r) y[f * P + r] = acc[r];
+  }
+}
+
+// A fixed grid of workgroups walks the list of (mesh, tile) items with a static
+// stride (deterministic); wavefront w of workgroup b takes items 4 b + w,
+// 4 b + w + 4 G, ...  Meshes are found by a scan of the tile offsets.  PMAX is
+// the largest P compiled in: registers are sized for it, so the launcher takes
+// the smallest instance that covers the batch (P <= 5: about half the registers
+// of P <= 9).
+template <int PMAX>
+__global__ __launch_bounds__(kWG) void k_trace_batch(const BatchMesh* meshes, int nmesh, int64_t total) {
+  const int lane = threadIdx.x & 63;
+  const int64_t nwaves = (int64_t)gridDim.x * (kWG / 64);
+  for (int64_t item = (int64_t)blockIdx.x * (kWG / 64) + (threadIdx.x >> 6); item < total; item += nwaves) {
+    int m = 0;
+    while (m + 1 < nmesh && meshes[m + 1].tile0 <= item) ++m;
+    const BatchMesh& M = meshes[m];
+    const int64_t tile = item - M.tile0;
+    switch (M.P) {
+      case 1: apply_tile_f64<1>(M, tile, lane); break;
+      case 2: apply_tile_f64<2>(M, tile, lane); break;
+      case 3: apply_tile_f64<3>(M, tile, lane); break;
+      case 4: apply_tile_f64<4>(M, tile, lane); break;
+      case 5: apply_tile_f64<5>(M, tile, lane); break;
+      default:
+        if constexpr (PMAX > 5) {
+          switch (M.P) {
+            case 6: apply_tile_f64<6>(M, tile, lane); break;
+            case 7: apply_tile_f64<7>(M, tile, lane); break;
+            case 8: apply_tile_f64<8>(M, tile, lane); break;
+            default: apply_tile_f64<9>(M, tile, lane); break;
+          }
+        }
+        break;
+    }
+  }
+}
+
+hipError_t launch_trace_batch(const BatchMesh* meshes_dev, int nmesh, int64_t total_tiles, int grid, int pmax,
+                              hipStream_t s) {
+  if (total_tiles == 0) return hipSuccess;
+  if (pmax <= 5)
+    hipLaunchKernelGGL(k_trace_batch<5>, dim3((unsigned)grid), dim3(kWG), 0, s, meshes_dev, nmesh, total_tiles);
+  else
+    hipLaunchKernelGGL(k_trace_batch<9>, dim3((unsigned)grid), dim3(kWG), 0, s, meshes_dev, nmesh, total_tiles);
+  return hipGetLastError();
+}
+
 template <int P, typename TM, typename TV>
 static hipError_t launch_trace_t(int mode, const TraceArgs& a, hipStream_t s) {
   const dim3 grid(trace_grid(a.ntiles)), block(kWG);

@@ -60,6 +60,19 @@ struct MultiArgs {
 };
 hipError_t launch_trace_multi(Prec pr, int P, const MultiArgs& a, hipStream_t s);
 
+// y_m = S_m x_m for many meshes (FP64) in one launch: a fixed grid walks the
+// (mesh, tile) items; tile0 = first item of the mesh (prefix sum of ntiles).
+struct BatchMesh {
+  const void* slab;
+  const void* x;
+  void* y;
+  int64_t nf, ntiles, tile0;
+  int n, P;
+};
+// pmax: the largest P in the batch (selects the register budget)
+hipError_t launch_trace_batch(const BatchMesh* meshes_dev, int nmesh, int64_t total_tiles, int grid, int pmax,
+                              hipStream_t s);
+
 // x = omega Dinv b (first facet sweep from a zero guess)
 hipError_t launch_dinv_apply(Prec pr, int P, const void* dinv, const void* b, double omega, void* x,
                              int64_t nf, hipStream_t s);

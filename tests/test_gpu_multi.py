@@ -122,3 +122,38 @@ def test_full_size_batch_sampled():
             assert np.all(np.abs(Yh[f * P:(f + 1) * P] - exact) <= lim), f
     finally:
         S.close()
+
+
+@pytest.mark.parametrize("meshes", [
+    [(16, 2), (24, 3), (7, 1), (40, 4), (2, 2), (33, 0)],          # P <= 5 instance
+    [(12, 6), (9, 2), (20, 8), (5, 4)],                             # P <= 9 instance
+])
+def test_batch_of_meshes_one_launch_bitwise(meshes):
+    """Many meshes of different sizes and degrees in one launch: every mesh's
+    result is bit-identical to its own apply, and matches the oracle."""
+    print(f"case batch {meshes}", flush=True)
+    solvers, xs, refs = [], [], []
+    try:
+        for i, (n, k) in enumerate(meshes):
+            kap = kappa_lognormal(n, 1.0, 40 + i)
+            S = H.Solver(n, k, kap)
+            x = dev(np.random.default_rng(i).standard_normal(S.num_dofs()))
+            solvers.append(S)
+            xs.append(x)
+            refs.append(host(S.apply(k, x)))
+        ys = H.apply_batch(solvers, xs)
+        for (n, k), y, r, x, i in zip(meshes, ys, refs, xs, range(len(meshes))):
+            assert np.array_equal(host(y), r), (n, k)
+        # coarse levels too
+        lv = [max(0, s.k - 1) for s in solvers]
+        ys = H.apply_batch(solvers, [torch.ones(s.num_dofs(l), dtype=torch.float64, device="cuda")
+                                     for s, l in zip(solvers, lv)], levels=lv)
+        for s, l, y in zip(solvers, lv, ys):
+            one = torch.ones(s.num_dofs(l), dtype=torch.float64, device="cuda")
+            assert np.array_equal(host(y), host(s.apply(l, one)))
+        n, k = meshes[0]
+        Ho = mg.Hierarchy(n, k, kappa_lognormal(n, 1.0, 40), smoother="face", omega=0.7)
+        assert rel_inf(host(H.apply_batch(solvers[:1], xs[:1])[0]), Ho.levels[0].A @ host(xs[0])) <= 1e-12
+    finally:
+        for s in solvers:
+            s.close()
