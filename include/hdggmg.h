@@ -96,7 +96,11 @@ typedef struct {
                            paper's V-cycle; the cycle becomes nonlinear, so solve with
                            HDG_SOLVE_FCG or HDG_SOLVE_VCYCLE).  0 (default): V-cycle.
                            Range [0, 64]; must be 0 for p >= k.                          */
-  int32_t reserved[8];
+  int32_t graph;        /* 1: the solver's preconditioner (the whole cycle, Krylov-accelerated
+                           levels included) is captured once as a HIP graph on a library
+                           stream and replayed on the handle's stream; 0 (default): eager
+                           launches.  Same kernels in the same order either way.         */
+  int32_t reserved[7];
 } hdg_config_t;
 
 /* Defaults: tau 1, V(2,2), chain smoother, Galerkin p-levels, omega/lmax estimated,

@@ -32,7 +32,7 @@ class Config(ctypes.Structure):
                 ("cheb_lmax", ctypes.c_double * HDG_MAX_HLEVELS),
                 ("coarse_max", ctypes.c_int32), ("nq", ctypes.c_int32),
                 ("precision", ctypes.c_int32), ("inner_steps", ctypes.c_int32 * (HDG_MAX_DEGREE + 1)),
-                ("reserved", ctypes.c_int32 * 8)]
+                ("graph", ctypes.c_int32), ("reserved", ctypes.c_int32 * 7)]
 
 
 _P = ctypes.c_void_p
@@ -149,7 +149,7 @@ class Solver:
 
     def __init__(self, n, k, kappa, tau=1.0, nu1=2, nu2=2, smoother="chain", coarse="galerkin",
                  omega=None, cheb_lmax=None, cheb=(0.1, 1.1), coarse_max=2000, nq=None, stream=None,
-                 precision="f64", inner=None):
+                 precision="f64", inner=None, graph=False):
         import torch
         cfg = Config()
         lib.hdg_config_default(n, k, ctypes.byref(cfg))
@@ -169,6 +169,7 @@ class Solver:
         cfg.precision = PRECISIONS[precision]
         for p, m in (inner or {}).items():
             cfg.inner_steps[p] = m
+        cfg.graph = 1 if graph else 0
         self.n, self.k, self.nq, self.precision = n, k, cfg.nq, precision
         kap, kp = _host(kappa, "kappa", n * n)
         if stream is None:

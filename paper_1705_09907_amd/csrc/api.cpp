@@ -70,6 +70,10 @@ struct hdg_ctx {
   double *vr = nullptr, *vz = nullptr, *vd = nullptr, *vq = nullptr;  // solver vectors (FP64)
   void *cva = nullptr, *cvb = nullptr;  // cycle-precision copies of FP64 vectors (size N(k))
   hipEvent_t ev0 = nullptr, ev1 = nullptr;  // timed apply
+  double* dsc = nullptr;                    // device scalars of the K-cycle (8 per p-level)
+  hipStream_t cap_stream = nullptr;         // capture of the preconditioner as a HIP graph
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t graph_exec = nullptr;
   hdg::BatchMesh* batch_dev = nullptr;      // descriptor table of hdg_apply_trace_operator_batch
   int batch_cap = 0;
   std::vector<hdg::BatchMesh> batch_host;
@@ -636,36 +640,47 @@ void pcycle(hdg_ctx* h, int p, const void* b, void* x, bool zero) {
 // for S_p e = r from e = 0, each preconditioned by one cycle started at level p.
 // r is overwritten (it becomes the running residual).  Direction update
 // d = z - (z . q / d . q) d_prev, step alpha = d . r / d . q with
-// d . r = z . r - beta d_prev . r (three dots, one synchronization).
+// d . r = z . r - beta d_prev . r.  The scalars stay on the device (slots
+// sc[0..4] of this level): no host round trip, so the cycle can be captured
+// in a graph.  A vanishing residual gives d . q = 0; every ratio with a
+// non-positive denominator is taken as 0, which leaves e unchanged from then on.
+void device_dots(hdg_ctx* h, hdg::Prec pr, int nd, std::initializer_list<const void*> pairs, int64_t n,
+                 double* out_dev) {
+  hdg::DotArgs d{};
+  d.ndots = nd;
+  auto it = pairs.begin();
+  for (int j = 0; j < nd; ++j) {
+    d.x[j] = *it++;
+    d.y[j] = *it++;
+  }
+  hipchk(hdg::launch_dots(pr, d, n, h->partial, h->stream), "dots");
+  hipchk(hdg::launch_sum_partials_multi(h->partial, hdg::reduce_grid(n), nd, out_dev, h->stream), "sum");
+}
+
 void krylov_correction(hdg_ctx* h, int p, void* r, void* e, int m) {
   PLevel& L = h->pl[p];
   const hdg::Prec pr = h->prec;
   const int64_t N = L.N;
+  double* sc = h->dsc + 8 * p;  // 0: d.r  1: d.q  2: z.q  3: z.r  4: d_prev.r
   hipchk(hdg::launch_zero(pr, e, N, h->stream), "zero");
-  double dq = 0.0;
   for (int step = 0; step < m; ++step) {
     pcycle(h, p, r, L.kz, true);
-    double dr;
     if (step == 0) {
       hipchk(hdg::launch_copy(pr, L.kz, L.kd, N, h->stream), "copy");
-      dots(h, pr, 1, {L.kz, r}, N, &dr);
+      device_dots(h, pr, 1, {L.kz, r}, N, sc);
     } else {
-      double v[3];
-      dots(h, pr, 3, {L.kz, L.kq, L.kz, r, L.kd, r}, N, v);
-      const double beta = v[0] / dq;
-      hipchk(hdg::launch_xpby(pr, L.kz, -beta, L.kd, N, h->stream), "xpby");
-      dr = v[1] - beta * v[2];
+      device_dots(h, pr, 3, {L.kz, L.kq, L.kz, r, L.kd, r}, N, sc + 2);
+      hipchk(hdg::launch_fcg_scalars(sc, h->stream), "fcg scalars");
+      hipchk(hdg::launch_xpby_dev(pr, L.kz, sc, 2, 1, -1.0, L.kd, N, h->stream), "xpby");
     }
     hdg::TraceArgs ta = targs(h, L, pr);
     ta.x = L.kd;
     ta.y = L.kq;
     ta.partial = h->partial;
     hipchk(hdg::launch_trace(L.mp, L.P, hdg::TM_APPLY_DOT, ta, h->stream), "apply dot");
-    dq = reduce_scalar(h, hdg::trace_partials(h->ntiles));
-    if (!(dq > 0.0) || !std::isfinite(dq)) break;  // r == 0: nothing left to correct
-    const double alpha = dr / dq;
-    hipchk(hdg::launch_axpy(pr, alpha, L.kd, e, N, h->stream), "axpy");
-    if (step + 1 < m) hipchk(hdg::launch_axpy(pr, -alpha, L.kq, r, N, h->stream), "axpy");
+    hipchk(hdg::launch_sum_partials(h->partial, hdg::trace_partials(h->ntiles), sc + 1, h->stream), "sum");
+    hipchk(hdg::launch_axpy_dev(pr, sc, 0, 1, 1.0, L.kd, e, N, h->stream), "axpy");
+    if (step + 1 < m) hipchk(hdg::launch_axpy_dev(pr, sc, 0, 1, -1.0, L.kq, r, N, h->stream), "axpy");
   }
 }
 
@@ -681,7 +696,7 @@ void stage_out(hdg_ctx* h, const void* buf, double* v, int64_t n) {
 }
 
 // One V-cycle preconditioner application z = B r at level k with FP64 vectors.
-void precondition(hdg_ctx* h, const double* r, double* z) {
+void precondition_body(hdg_ctx* h, const double* r, double* z) {
   const int64_t N = h->pl[h->k].N;
   if (h->prec == hdg::Prec::F64) {
     pcycle(h, h->k, r, z, true);
@@ -689,6 +704,37 @@ void precondition(hdg_ctx* h, const double* r, double* z) {
   }
   pcycle(h, h->k, stage_in(h, r, h->cva, N), h->cvb, true);
   stage_out(h, h->cvb, z, N);
+}
+
+// The solver's z = B r (r = vr, z = vz).  With cfg.graph the whole cycle,
+// Krylov-accelerated levels included, is captured once on a library stream as a
+// HIP graph and replayed on the handle's stream: hundreds of launches become one.
+// Everything the cycle touches is owned by the handle and fixed, and it makes no
+// host round trip, allocation or memset.
+void precondition(hdg_ctx* h) {
+  if (!h->cfg.graph) {
+    precondition_body(h, h->vr, h->vz);
+    return;
+  }
+  if (!h->graph_exec) {
+    if (!h->cap_stream) hipchk(hipStreamCreateWithFlags(&h->cap_stream, hipStreamNonBlocking), "stream");
+    hipStream_t user = h->stream;
+    h->stream = h->cap_stream;
+    hipchk(hipStreamBeginCapture(h->cap_stream, hipStreamCaptureModeThreadLocal), "begin capture");
+    try {
+      precondition_body(h, h->vr, h->vz);
+    } catch (...) {
+      hipGraph_t g = nullptr;
+      (void)hipStreamEndCapture(h->cap_stream, &g);
+      if (g) (void)hipGraphDestroy(g);
+      h->stream = user;
+      throw;
+    }
+    h->stream = user;
+    hipchk(hipStreamEndCapture(h->cap_stream, &h->graph), "end capture");
+    hipchk(hipGraphInstantiate(&h->graph_exec, h->graph, nullptr, nullptr, 0), "instantiate");
+  }
+  hipchk(hipGraphLaunch(h->graph_exec, h->stream), "graph launch");
 }
 
 // Largest eigenvalue of D^{-1} S_p (facet blocks) by Lanczos in the D inner product.
@@ -758,6 +804,7 @@ void validate_config(const hdg_config_t* c) {
   if ((int64_t)c->n * c->n > (int64_t)1 << 31) throw ArgError("n too large");
   if (c->precision != HDG_PREC_F64 && c->precision != HDG_PREC_F32 && c->precision != HDG_PREC_BF16)
     throw ArgError("bad precision");
+  if (c->graph != 0 && c->graph != 1) throw ArgError("graph must be 0 or 1");
   for (int p = 0; p <= HDG_MAX_DEGREE; ++p) {
     if (c->inner_steps[p] < 0 || c->inner_steps[p] > 64) throw ArgError("inner_steps must be in [0, 64]");
     if (p >= c->k && c->inner_steps[p] != 0) throw ArgError("inner_steps[p] must be 0 for p >= k");
@@ -867,6 +914,7 @@ hdg_status_t hdg_create(const hdg_config_t* cfg, const double* kappa_host, void*
     h->vz = dalloc(h.get(), Nk);
     h->vd = dalloc(h.get(), Nk);
     h->vq = dalloc(h.get(), Nk);
+    h->dsc = dalloc(h.get(), 8LL * (h->k + 1));
     if (h->prec != hdg::Prec::F64) {
       h->cva = valloc(h.get(), Nk);
       h->cvb = valloc(h.get(), Nk);
@@ -901,6 +949,9 @@ hdg_status_t hdg_create(const hdg_config_t* cfg, const double* kappa_host, void*
 hdg_status_t hdg_destroy(hdg_handle_t h) {
   if (!h) return HDG_ERR_INVALID_ARG;
   (void)hipStreamSynchronize(h->stream);
+  if (h->graph_exec) (void)hipGraphExecDestroy(h->graph_exec);
+  if (h->graph) (void)hipGraphDestroy(h->graph);
+  if (h->cap_stream) (void)hipStreamDestroy(h->cap_stream);
   if (h->ev0) (void)hipEventDestroy(h->ev0);
   if (h->ev1) (void)hipEventDestroy(h->ev1);
   for (void* p : h->allocs) (void)hipFree(p);
@@ -1347,7 +1398,7 @@ hdg_status_t hdg_solve(hdg_handle_t h, const double* b, double* x, double rtol, 
     if (mode == HDG_SOLVE_VCYCLE) {
       // stationary iteration on the correction: x += B (b - S x), B one V-cycle
       while (rn > tol && it < maxit) {
-        precondition(h, h->vr, h->vz);
+        precondition(h);
         hipchk(hdg::launch_axpy(1.0, h->vz, x, N, h->stream), "axpy");
         rn = residual_norm(h, k, b, x, h->vr);
         ++it;
@@ -1362,7 +1413,7 @@ hdg_status_t hdg_solve(hdg_handle_t h, const double* b, double* x, double rtol, 
       // A-orthogonalised against the previous one, d = z - (z . q / d . q) d, and
       // alpha = d . r / d . q with d . r = z . r - beta d_prev . r
       const bool flex = mode == HDG_SOLVE_FCG;
-      precondition(h, h->vr, h->vz);
+      precondition(h);
       hipchk(hdg::launch_copy(hdg::Prec::F64, h->vz, h->vd, N, h->stream), "copy");
       double rz = dot(h, h->vr, h->vz, N);
       double dr = rz;
@@ -1384,7 +1435,7 @@ hdg_status_t hdg_solve(hdg_handle_t h, const double* b, double* x, double rtol, 
           return finish(HDG_ERR_NONFINITE);
         }
         if (rn <= tol) break;
-        precondition(h, h->vr, h->vz);
+        precondition(h);
         if (flex) {
           double v[3];
           dots(h, hdg::Prec::F64, 3, {h->vz, h->vq, h->vz, h->vr, h->vd, h->vr}, N, v);

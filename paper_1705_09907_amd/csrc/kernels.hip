@@ -1318,6 +1318,44 @@ hipError_t launch_xpby(Prec pr, const void* x, double beta, void* y, int64_t n, 
   HDG_DISPATCH_T(pr, hipLaunchKernelGGL(k_xpby<TT>, grid_for(n), dim3(kWG), 0, s, (const TT*)x, beta, (TT*)y, n));
   return hipGetLastError();
 }
+__device__ __forceinline__ double ratio_or_zero(double a, double b) {
+  const double r = a / b;
+  return (b > 0.0 && isfinite(r)) ? r : 0.0;
+}
+template <typename T>
+__global__ __launch_bounds__(kWG) void k_axpy_dev(const double* sc, int num, int den, double sign, const T* x,
+                                                  T* y, int64_t n) {
+  const int64_t i = (int64_t)blockIdx.x * kWG + threadIdx.x;
+  if (i < n) y[i] += T(sign * ratio_or_zero(sc[num], sc[den])) * x[i];
+}
+template <typename T>
+__global__ __launch_bounds__(kWG) void k_xpby_dev(const T* x, const double* sc, int num, int den, double sign,
+                                                  T* y, int64_t n) {
+  const int64_t i = (int64_t)blockIdx.x * kWG + threadIdx.x;
+  if (i < n) y[i] = x[i] + T(sign * ratio_or_zero(sc[num], sc[den])) * y[i];
+}
+__global__ void k_fcg_scalars(double* sc) {
+  if (threadIdx.x == 0) sc[0] = sc[3] - ratio_or_zero(sc[2], sc[1]) * sc[4];
+}
+hipError_t launch_axpy_dev(Prec pr, const double* sc, int num, int den, double sign, const void* x, void* y,
+                           int64_t n, hipStream_t s) {
+  if (n == 0) return hipSuccess;
+  HDG_DISPATCH_T(pr, hipLaunchKernelGGL(k_axpy_dev<TT>, grid_for(n), dim3(kWG), 0, s, sc, num, den, sign,
+                                        (const TT*)x, (TT*)y, n));
+  return hipGetLastError();
+}
+hipError_t launch_xpby_dev(Prec pr, const void* x, const double* sc, int num, int den, double sign, void* y,
+                           int64_t n, hipStream_t s) {
+  if (n == 0) return hipSuccess;
+  HDG_DISPATCH_T(pr, hipLaunchKernelGGL(k_xpby_dev<TT>, grid_for(n), dim3(kWG), 0, s, (const TT*)x, sc, num, den,
+                                        sign, (TT*)y, n));
+  return hipGetLastError();
+}
+hipError_t launch_fcg_scalars(double* sc, hipStream_t s) {
+  hipLaunchKernelGGL(k_fcg_scalars, dim3(1), dim3(64), 0, s, sc);
+  return hipGetLastError();
+}
+
 hipError_t launch_zero(Prec pr, void* y, int64_t n, hipStream_t s) {
   if (n == 0) return hipSuccess;
   HDG_DISPATCH_T(pr, hipLaunchKernelGGL(k_fill_t<TT>, grid_for(n), dim3(kWG), 0, s, TT(0), (TT*)y, n));

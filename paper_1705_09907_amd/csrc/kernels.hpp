@@ -171,6 +171,15 @@ hipError_t launch_xpby(const double* x, double beta, double* y, int64_t n, hipSt
 hipError_t launch_axpy(Prec pr, double alpha, const void* x, void* y, int64_t n, hipStream_t s);
 hipError_t launch_xpby(Prec pr, const void* x, double beta, void* y, int64_t n, hipStream_t s);
 hipError_t launch_zero(Prec pr, void* y, int64_t n, hipStream_t s);
+// Updates whose coefficient is a ratio of device scalars, c = sign sc[num] / sc[den]
+// (c = 0 when sc[den] is not > 0 or the ratio is not finite): no host round trip.
+hipError_t launch_axpy_dev(Prec pr, const double* sc, int num, int den, double sign, const void* x, void* y,
+                           int64_t n, hipStream_t s);                                          // y += c x
+hipError_t launch_xpby_dev(Prec pr, const void* x, const double* sc, int num, int den, double sign, void* y,
+                           int64_t n, hipStream_t s);                                          // y = x + c y
+// Flexible-CG direction scalars on the device: with sc[1] = d.q, sc[2] = z.q,
+// sc[3] = z.r, sc[4] = d.r:  sc[0] = sc[3] - (sc[2] / sc[1]) sc[4]  (the new d.r)
+hipError_t launch_fcg_scalars(double* sc, hipStream_t s);
 // r -= alpha q and per-workgroup sum of squares of the new r
 hipError_t launch_axpy_norm(double alpha, const double* q, double* r, int64_t n, double* partial,
                             hipStream_t s);
