@@ -237,7 +237,7 @@ def main():
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
     t0 = time.perf_counter()
-    S = H.Solver(n, k, kap, smoother=args.smoother, precision=args.precision, inner=inner)
+    S = H.Solver(n, k, kap, smoother=args.smoother, precision=args.precision, inner=inner, autotune=True)
     torch.cuda.synchronize()
     setup_s = time.perf_counter() - t0
     N = S.num_dofs()
@@ -375,7 +375,7 @@ def main():
     f64_ref = None
     if lp:  # the plain FP64 path on the same system, same accuracy, after the timed region
         S.close()
-        S64 = H.Solver(n, k, kap, smoother=args.smoother, inner=inner)
+        S64 = H.Solver(n, k, kap, smoother=args.smoother, inner=inner, autotune=True)
         x64 = x.double()
         y64 = torch.empty_like(x64)
         at, st_ms = [], []

@@ -100,7 +100,11 @@ typedef struct {
                            levels included) is captured once as a HIP graph on a library
                            stream and replayed on the handle's stream; 0 (default): eager
                            launches.  Same kernels in the same order either way.         */
-  int32_t reserved[7];
+  int32_t autotune;     /* 1: at setup, time the chain Schwarz launch shapes (workgroup size,
+                           XCD-aware chain order, LDS staging depth) of every level and keep
+                           the fastest; 0 (default): measured fixed defaults.  Results are
+                           identical either way (same operations in the same order).     */
+  int32_t reserved[6];
 } hdg_config_t;
 
 /* Defaults: tau 1, V(2,2), chain smoother, Galerkin p-levels, omega/lmax estimated,
@@ -129,6 +133,11 @@ hdg_status_t hdg_hlevel_mesh(hdg_handle_t h, int32_t level, int32_t* m);
 /* Damping and lambda_max actually used (after estimation). */
 hdg_status_t hdg_get_params(hdg_handle_t h, double* omega_out /*[k+1]*/,
                             double* lmax_out /*[num_hlevels]*/);
+
+/* The chain Schwarz launch shape in use at level p (after autotuning, if any):
+ * workgroup size, XCD-aware chain order (0/1), first cyclic-reduction level whose
+ * factors are staged in LDS.  Each output pointer may be NULL. */
+hdg_status_t hdg_get_chain_shape(hdg_handle_t h, int32_t p, int32_t* threads, int32_t* remap, int32_t* lds_level);
 
 /* Copy the condensed block of element e at level p (4(p+1) x 4(p+1), row major,
  * local faces left, right, bottom, top) to host memory: Sec. 3, eqs. shur0

@@ -32,7 +32,7 @@ class Config(ctypes.Structure):
                 ("cheb_lmax", ctypes.c_double * HDG_MAX_HLEVELS),
                 ("coarse_max", ctypes.c_int32), ("nq", ctypes.c_int32),
                 ("precision", ctypes.c_int32), ("inner_steps", ctypes.c_int32 * (HDG_MAX_DEGREE + 1)),
-                ("graph", ctypes.c_int32), ("reserved", ctypes.c_int32 * 7)]
+                ("graph", ctypes.c_int32), ("autotune", ctypes.c_int32), ("reserved", ctypes.c_int32 * 6)]
 
 
 _P = ctypes.c_void_p
@@ -49,6 +49,7 @@ SIGNATURES = {
     "hdg_num_hlevels": [_P, _PI32],
     "hdg_hlevel_mesh": [_P, _I32, _PI32],
     "hdg_get_params": [_P, _PD, _PD],
+    "hdg_get_chain_shape": [_P, _I32, _PI32, _PI32, _PI32],
     "hdg_get_element_block": [_P, _I32, _I64, _PD],
     "hdg_element_block_host": [_I32, _I32, _I32, _D, _D, _I32, _PD],
     "hdg_quadrature_nodes": [_I32, _PD],
@@ -149,7 +150,7 @@ class Solver:
 
     def __init__(self, n, k, kappa, tau=1.0, nu1=2, nu2=2, smoother="chain", coarse="galerkin",
                  omega=None, cheb_lmax=None, cheb=(0.1, 1.1), coarse_max=2000, nq=None, stream=None,
-                 precision="f64", inner=None, graph=False):
+                 precision="f64", inner=None, graph=False, autotune=False):
         import torch
         cfg = Config()
         lib.hdg_config_default(n, k, ctypes.byref(cfg))
@@ -170,6 +171,7 @@ class Solver:
         for p, m in (inner or {}).items():
             cfg.inner_steps[p] = m
         cfg.graph = 1 if graph else 0
+        cfg.autotune = 1 if autotune else 0
         self.n, self.k, self.nq, self.precision = n, k, cfg.nq, precision
         kap, kp = _host(kappa, "kappa", n * n)
         if stream is None:
@@ -218,6 +220,12 @@ class Solver:
         lm = np.zeros(self.num_hlevels())
         self._check(lib.hdg_get_params(self._h, om.ctypes.data_as(_PD), lm.ctypes.data_as(_PD)))
         return om, lm
+
+    def chain_shape(self, p):
+        """(workgroup size, XCD-aware order, LDS staging level) of the chain solve at level p."""
+        t, r, l = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int32()
+        self._check(lib.hdg_get_chain_shape(self._h, p, ctypes.byref(t), ctypes.byref(r), ctypes.byref(l)))
+        return t.value, r.value, l.value
 
     def element_block(self, p, e):
         out = np.zeros((4 * (p + 1), 4 * (p + 1)))

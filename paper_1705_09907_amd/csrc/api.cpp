@@ -36,6 +36,8 @@ struct PLevel {
   double omega = 0.8;
   void *x = nullptr, *b = nullptr, *r = nullptr, *t = nullptr;
   int chain_lds_level = 64;                           // chain factors of levels >= this are staged in LDS
+  int chain_threads = 0;                              // chain launch shape (0: chain_threads default)
+  int chain_remap = -1;                               // -1: chain_remap default
   int inner = 0;                                      // K-cycle: FCG steps of this level's correction
   void *kz = nullptr, *kd = nullptr, *kq = nullptr;   // K-cycle work vectors
 };
@@ -547,7 +549,8 @@ void smooth(hdg_ctx* h, int p, const void* b, void* x, int nu, bool zero) {
     } else {
       hdg::ChainArgs c{};
       c.lds_level = L.chain_lds_level;
-      c.remap = hdg::chain_remap(L.P);
+      c.threads = L.chain_threads;
+      c.remap = L.chain_remap >= 0 ? L.chain_remap : hdg::chain_remap(L.P);
       c.factors = L.chain;
       c.cstride = L.cstride;
       c.omega = L.omega;
@@ -790,6 +793,69 @@ double estimate_face_lmax(hdg_ctx* h, int p, int steps) {
   return hi;
 }
 
+// Autotuner of the chain Schwarz launch shape of level p: workgroup size,
+// XCD-aware chain order and LDS staging depth.  Every candidate solves each chain
+// with the same operations in the same order, so the choice changes the time
+// only, never the result.  Each candidate is timed (best of 3, after one warm-up
+// launch) on the level's scratch vectors; the fastest is kept.
+void tune_chain(hdg_ctx* h, int p) {
+  PLevel& L = h->pl[p];
+  const hdg::Prec pr = h->prec;
+  hipchk(hdg::launch_zero(pr, L.r, L.N, h->stream), "zero");
+  const size_t es = hdg::vec_bytes(pr);
+  const int64_t rhs_bytes = (int64_t)(h->n - 1) * L.P * (int64_t)es;
+  const int lds_default = L.chain_lds_level;
+  const int lds_staged = hdg::chain_lds_level(L.P, h->n, es, std::min<int64_t>(24576, 65536 - rhs_bytes));
+  hipEvent_t e0, e1;
+  hipchk(hipEventCreate(&e0), "event");
+  hipchk(hipEventCreate(&e1), "event");
+  float best = 1e30f;
+  int bt = 0, br = -1, bl = lds_default;
+  const int64_t bwd = (int64_t)((h->n - 1) / 2) * L.P;
+  for (int th : {64, 128, 256, 512, 1024}) {
+    if (bwd > (int64_t)th * 8) continue;
+    for (int rm : {0, 1})
+      for (int ll : {lds_default, lds_staged, 64}) {
+        hdg::ChainArgs c{};
+        c.factors = L.chain;
+        c.cstride = L.cstride;
+        c.omega = L.omega;
+        c.n = h->n;
+        c.r = L.r;
+        c.x = nullptr;
+        c.out = L.t;
+        c.threads = th;
+        c.remap = rm;
+        c.lds_level = ll;
+        if (hdg::launch_chain_solve(pr, L.P, c, h->stream) != hipSuccess) {
+          (void)hipGetLastError();
+          continue;
+        }
+        float t = 1e30f;
+        for (int rep = 0; rep < 3; ++rep) {
+          hipchk(hipEventRecord(e0, h->stream), "event");
+          hipchk(hdg::launch_chain_solve(pr, L.P, c, h->stream), "chain tune");
+          hipchk(hipEventRecord(e1, h->stream), "event");
+          hipchk(hipEventSynchronize(e1), "event sync");
+          float ms = 0.f;
+          hipchk(hipEventElapsedTime(&ms, e0, e1), "elapsed");
+          t = std::min(t, ms);
+        }
+        if (t < best) {
+          best = t;
+          bt = th;
+          br = rm;
+          bl = ll;
+        }
+      }
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  L.chain_threads = bt;
+  L.chain_remap = br;
+  L.chain_lds_level = bl;
+}
+
 void validate_config(const hdg_config_t* c) {
   if (!c) throw ArgError("cfg is NULL");
   if (c->n < 2) throw ArgError("n must be >= 2");
@@ -805,6 +871,7 @@ void validate_config(const hdg_config_t* c) {
   if (c->precision != HDG_PREC_F64 && c->precision != HDG_PREC_F32 && c->precision != HDG_PREC_BF16)
     throw ArgError("bad precision");
   if (c->graph != 0 && c->graph != 1) throw ArgError("graph must be 0 or 1");
+  if (c->autotune != 0 && c->autotune != 1) throw ArgError("autotune must be 0 or 1");
   for (int p = 0; p <= HDG_MAX_DEGREE; ++p) {
     if (c->inner_steps[p] < 0 || c->inner_steps[p] > 64) throw ArgError("inner_steps must be in [0, 64]");
     if (p >= c->k && c->inner_steps[p] != 0) throw ArgError("inner_steps[p] must be 0 for p >= k");
@@ -915,6 +982,8 @@ hdg_status_t hdg_create(const hdg_config_t* cfg, const double* kappa_host, void*
     h->vd = dalloc(h.get(), Nk);
     h->vq = dalloc(h.get(), Nk);
     h->dsc = dalloc(h.get(), 8LL * (h->k + 1));
+    if (cfg->autotune && cfg->smoother == HDG_SMOOTH_CHAIN)
+      for (int p = 0; p <= h->k; ++p) tune_chain(h.get(), p);
     if (h->prec != hdg::Prec::F64) {
       h->cva = valloc(h.get(), Nk);
       h->cvb = valloc(h.get(), Nk);
@@ -984,6 +1053,15 @@ hdg_status_t hdg_get_params(hdg_handle_t h, double* omega_out, double* lmax_out)
     for (int p = 0; p <= h->k; ++p) omega_out[p] = h->pl[p].omega;
   if (lmax_out)
     for (size_t l = 0; l < h->ql.size(); ++l) lmax_out[l] = h->ql[l].lmax;
+  return HDG_OK;
+}
+
+hdg_status_t hdg_get_chain_shape(hdg_handle_t h, int32_t p, int32_t* threads, int32_t* remap, int32_t* lds_level) {
+  if (!h || p < 0 || p > h->k) return HDG_ERR_INVALID_ARG;
+  const PLevel& L = h->pl[p];
+  if (threads) *threads = L.chain_threads > 0 ? L.chain_threads : hdg::chain_threads(L.P, h->n);
+  if (remap) *remap = L.chain_remap >= 0 ? L.chain_remap : hdg::chain_remap(L.P);
+  if (lds_level) *lds_level = L.chain_lds_level;
   return HDG_OK;
 }
 

@@ -49,3 +49,26 @@ def test_graph_replays_equal_eager(n, k, sigma, opts, mode):
     finally:
         Se.close()
         Sg.close()
+
+
+@pytest.mark.parametrize("n,k,prec", [(64, 3, "f64"), (40, 4, "f32"), (2, 1, "f64")])
+def test_autotuned_chain_shapes_give_identical_results(n, k, prec):
+    """The autotuner only picks launch shapes: the solve is bit-identical to the
+    default shapes, and every picked shape is a valid one."""
+    print(f"case autotune n={n} k={k} {prec}", flush=True)
+    kap = kappa_lognormal(n, 1.0, 5)
+    pr = hdg.Problem(n, k, kap)
+    b = torch.tensor(pr.rhs(np.ones((n * n, pr.ref.nq ** 2))), device="cuda")
+    S0 = H.Solver(n, k, kap, precision=prec, inner={0: 2} if k >= 1 else None)
+    S1 = H.Solver(n, k, kap, precision=prec, inner={0: 2} if k >= 1 else None, autotune=True)
+    try:
+        for p in range(k + 1):
+            th, rm, ll = S1.chain_shape(p)
+            assert th % 64 == 0 and 64 <= th <= 1024 and rm in (0, 1) and ll >= 0
+            assert ((n - 1) // 2) * (p + 1) <= th * 8
+        x0, it0, _, _ = S0.solve(b, rtol=1e-10, mode="fcg")
+        x1, it1, _, _ = S1.solve(b, rtol=1e-10, mode="fcg")
+        assert it0 == it1 and np.array_equal(host(x0), host(x1))
+    finally:
+        S0.close()
+        S1.close()

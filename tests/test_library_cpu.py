@@ -50,7 +50,7 @@ def test_quadrature_nodes_match_oracle():
 @pytest.mark.parametrize("field,value,code", [("n", 1, -1), ("k", 9, -1), ("k", -1, -1), ("tau", 0.0, -1),
                                               ("nu1", 0, -1), ("smoother", 7, -1), ("cheb_lo", 2.0, -1),
                                               ("nq", 0, -1), ("precision", 3, -1), ("precision", -1, -1),
-                                              ("graph", 2, -1)])
+                                              ("graph", 2, -1), ("autotune", -1, -1)])
 def test_create_rejects_bad_config_before_any_device_call(field, value, code):
     cfg = H.Config()
     assert H.lib.hdg_config_default(8, 2, ctypes.byref(cfg)) == 0
@@ -92,7 +92,7 @@ def test_config_layout_matches_header():
     names = re.findall(r"^\s*(?:int32_t|double)\s+([a-z_0-9]+(?:\s*,\s*[a-z_0-9]+)*)", body, re.M)
     fields = [f.strip() for grp in names for f in grp.split(",")]
     assert fields == [f[0] for f in H.Config._fields_]
-    assert ctypes.sizeof(H.Config) == 4 + 4 + 8 + 4 + 4 + 4 + 4 + 8 * 9 + 16 + 8 * 24 + 4 + 4 + 4 + 4 * 9 + 4 + 4 * 7
+    assert ctypes.sizeof(H.Config) == 4 + 4 + 8 + 4 + 4 + 4 + 4 + 8 * 9 + 16 + 8 * 24 + 4 + 4 + 4 + 4 * 9 + 4 + 4 + 4 * 6
 
 
 @pytest.mark.parametrize("bad", [0.0, -1.0, np.nan, np.inf])
