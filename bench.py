@@ -398,6 +398,22 @@ def main():
                    "solve_iters": it64, "solve_relres": rr64}
         S64.close()
 
+    # context: a STREAM-style triad a = b + s c on this GPU (torch's elementwise
+    # kernel, 3 x 256 MiB FP64), the reachable-bandwidth figure the paper compares with
+    tb = torch.rand(1 << 25, dtype=torch.float64, device=dev)
+    tc = torch.rand_like(tb)
+    ta = torch.empty_like(tb)
+    for _ in range(3):
+        torch.add(tb, tc, alpha=1.5, out=ta)
+    t0e, t1e = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    t0e.record(stream)
+    for _ in range(10):
+        torch.add(tb, tc, alpha=1.5, out=ta)
+    t1e.record(stream)
+    torch.cuda.synchronize()
+    triad_gbs = 3 * tb.numel() * 8 / (t0e.elapsed_time(t1e) / 10 * 1e-3) / 1e9
+    del ta, tb, tc
+
     t_apply = float(np.mean(apply_ms)) * 1e-3
     byts, flops = algorithmic_bytes(n, k, args.precision)
     achieved = byts / t_apply / 1e9
@@ -422,6 +438,7 @@ def main():
         "roofline": {"bound": "hbm", "kernel": f"k_trace<P={k + 1}, APPLY, {args.precision}>", "achieved": achieved,
                      "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
                      "traffic": MEASURED_TRAFFIC.get((args.workload, args.precision)),
+                     "stream_triad_GBs": triad_gbs, "frac_of_triad": achieved / triad_gbs,
                      "algorithmic_bytes": byts, "flops": flops},
     }
     if not lp:
