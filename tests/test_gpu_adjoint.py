@@ -109,7 +109,7 @@ def test_autograd_gradient_matches_oracle(opts):
     L = misfit(th, dev(U_obs.reshape(-1)), n, k, f_qp, gq, rtol=1e-12, **opts)
     L.backward()
     L_o, g_o, _ = M.gradient(theta)
-    assert abs(float(L) - L_o) <= 1e-9 * L_o
+    assert abs(float(L.detach()) - L_o) <= 1e-9 * L_o
     assert rel_inf(host(th.grad), g_o) <= 1e-8
 
 
@@ -159,6 +159,6 @@ def test_full_size_taylor():
     errs = []
     for t in (4e-3, 2e-3, 1e-3):
         Lt = float(misfit(dev(theta) + t * v, U_obs, n, k, f_qp, None, **opts))
-        errs.append(abs(Lt - float(L0) - t * gv))
+        errs.append(abs(Lt - float(L0.detach()) - t * gv))
     print("taylor remainders", errs, flush=True)
     assert 3.0 < errs[0] / errs[1] < 5.0 and 3.0 < errs[1] / errs[2] < 5.0, errs
