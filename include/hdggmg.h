@@ -235,6 +235,19 @@ hdg_status_t hdg_vcycle(hdg_handle_t h, const double* b, double* x);
 hdg_status_t hdg_solve(hdg_handle_t h, const double* b, double* x, double rtol, int32_t maxit,
                        int32_t mode, int32_t* iters, double* relres, double* history_host);
 
+/* Solve S_k X = B for nrhs right-hand sides at once (1 <= nrhs <= 256): B, X
+ * device [N(k)][nrhs] FP64 (right-hand sides of one DoF contiguous); X in:
+ * initial guesses, out: solutions.  Flexible CG per column, preconditioned by
+ * the V(nu1, nu2) cycle run for all columns together in the cycle precision
+ * (operators, smoother factors and stencils read once per cycle for every
+ * column); the FP64 operator, residuals and updates are kept for the outer
+ * iteration.  Chain smoother only (STATE otherwise); Krylov acceleration of
+ * coarse levels (inner_steps) is not used here.  A column stops updating once
+ * ||b - S x||_2 <= rtol ||b||_2.  iters_host, relres_host: nullable [nrhs].
+ * NOT_CONVERGED if some column reached maxit (outputs still valid). */
+hdg_status_t hdg_solve_multi(hdg_handle_t h, int32_t nrhs, const double* B, double* X, double rtol, int32_t maxit,
+                             int32_t* iters_host, double* relres_host);
+
 /* ---- misfit gradient with respect to theta_K = log K_K (adjoint method) ----
  * The paper solves forward problems only; these calls differentiate its
  * discretisation.  With [Q; U]_K from the local solver (eq. shur0) and S

@@ -65,6 +65,7 @@ SIGNATURES = {
     "hdg_prolong": [_P, _I32, _P, _P],
     "hdg_vcycle": [_P, _P, _P],
     "hdg_solve": [_P, _P, _P, _D, _I32, _I32, _PI32, _PD, _PD],
+    "hdg_solve_multi": [_P, _I32, _P, _P, _D, _I32, _PI32, _PD],
     "hdg_reconstruct": [_P, _P, _P, _P],
     "hdg_misfit_adjoint_rhs": [_P, _P, _P, _P, _PD],
     "hdg_misfit_gradient": [_P, _P, _P, _P, _P, _P],
@@ -352,6 +353,22 @@ class Solver:
                                             self._evec(U_obs, "U_obs", P2), _dptr(mu, "mu", N),
                                             self._evec(grad, "grad", 1)))
         return grad
+
+    def solve_multi(self, B, X=None, rtol=1e-10, maxit=200, raise_on_fail=True):
+        """Solve S X = B for B [N, nrhs] (float64); returns X, iterations and relative residuals per column."""
+        import torch
+        N = self.num_dofs()
+        if B.dim() != 2 or B.shape[0] != N:
+            raise ValueError(f"B must be [{N}, nrhs]")
+        R = B.shape[1]
+        X = torch.zeros_like(B) if X is None else X
+        its = np.zeros(R, dtype=np.int32)
+        rr = np.zeros(R)
+        st = lib.hdg_solve_multi(self._h, R, _dptr(B, "B", N * R), _dptr(X, "X", N * R), rtol, maxit,
+                                 its.ctypes.data_as(_PI32), rr.ctypes.data_as(_PD))
+        if st != 0 and (raise_on_fail or st not in (-4,)):
+            self._check(st)
+        return X, its, rr
 
     def solve(self, b, x=None, rtol=1e-10, maxit=200, mode="pcg", raise_on_fail=True):
         import torch

@@ -53,6 +53,22 @@ struct QLevel {
   void *x = nullptr, *b = nullptr, *r = nullptr, *d = nullptr, *t = nullptr;
 };
 
+// Work vectors of the solve for many right-hand sides, [rows][R]: per p-level
+// x, b, r in the cycle precision; per Q1 level x, b, r, d, t; FP64 outer
+// vectors; per-column device scalars.  Allocated for one R at a time.
+struct MultiWork {
+  int R = 0;
+  std::vector<void*> px, pb, pr;
+  std::vector<void*> qx, qb, qr, qd, qt;
+  double *vr = nullptr, *vz = nullptr, *vd = nullptr, *vq = nullptr;
+  void *cva = nullptr, *cvb = nullptr;
+  double *sc = nullptr, *nrm = nullptr, *nb = nullptr, *act = nullptr, *partial = nullptr;
+  std::vector<void*> allocs;
+  ~MultiWork() {
+    for (void* q : allocs) (void)hipFree(q);
+  }
+};
+
 }  // namespace
 
 struct hdg_ctx {
@@ -86,6 +102,7 @@ struct hdg_ctx {
   bool have_source = false;
   hdg::Prec prec = hdg::Prec::F64;      // precision of the multigrid cycle
   int nq = 0;
+  std::unique_ptr<MultiWork> mw;        // solve for many right-hand sides
 };
 
 namespace {
@@ -856,6 +873,166 @@ void tune_chain(hdg_ctx* h, int p) {
   L.chain_lds_level = bl;
 }
 
+// ------------------------------------------ many right-hand sides (chain smoother)
+void* malloc_tracked(MultiWork& W, size_t bytes) {
+  void* q = nullptr;
+  if (hipMalloc(&q, std::max<size_t>(bytes, 16)) != hipSuccess) {
+    (void)hipGetLastError();
+    throw std::bad_alloc();
+  }
+  W.allocs.push_back(q);
+  return q;
+}
+
+MultiWork& multi_work(hdg_ctx* h, int R) {
+  if (h->mw && h->mw->R == R) return *h->mw;
+  hipchk(hipStreamSynchronize(h->stream), "sync");
+  h->mw.reset();
+  auto W = std::make_unique<MultiWork>();
+  W->R = R;
+  const size_t vb = hdg::vec_bytes(h->prec);
+  for (const PLevel& L : h->pl) {
+    W->px.push_back(malloc_tracked(*W, (size_t)L.N * R * vb));
+    W->pb.push_back(malloc_tracked(*W, (size_t)L.N * R * vb));
+    W->pr.push_back(malloc_tracked(*W, (size_t)L.N * R * vb));
+  }
+  for (const QLevel& Q : h->ql)
+    for (auto* v : {&W->qx, &W->qb, &W->qr, &W->qd, &W->qt}) v->push_back(malloc_tracked(*W, (size_t)Q.Nv * R * vb));
+  const size_t Nk = (size_t)h->pl[h->k].N;
+  for (double** v : {&W->vr, &W->vz, &W->vd, &W->vq}) *v = (double*)malloc_tracked(*W, Nk * R * 8);
+  if (h->prec != hdg::Prec::F64) {
+    W->cva = malloc_tracked(*W, Nk * R * vb);
+    W->cvb = malloc_tracked(*W, Nk * R * vb);
+  }
+  W->sc = (double*)malloc_tracked(*W, 5 * (size_t)R * 8);
+  for (double** v : {&W->nrm, &W->nb, &W->act}) *v = (double*)malloc_tracked(*W, (size_t)R * 8);
+  W->partial = (double*)malloc_tracked(*W, (size_t)hdg::dots_m_grid((int64_t)Nk) * R * 8);
+  h->mw = std::move(W);
+  return *h->mw;
+}
+
+hdg::MultiArgs margs(hdg_ctx* h, const PLevel& L, int R, bool f64) {
+  hdg::MultiArgs a{};
+  a.slab = f64 && h->prec != hdg::Prec::F64 ? static_cast<const void*>(L.slab64) : L.slab;
+  a.pmat = L.pmat;
+  a.nrhs = R;
+  a.n = h->n;
+  a.nf = h->nf;
+  a.ntiles = h->ntiles;
+  a.remap = 1;
+  return a;
+}
+
+void smooth_m(hdg_ctx* h, MultiWork& W, int p, const void* b, void* x, int nu, bool zero) {
+  PLevel& L = h->pl[p];
+  const hdg::Prec pr = h->prec;
+  for (int s = 0; s < nu; ++s) {
+    const bool z = zero && s == 0;
+    hdg::ChainMultiArgs c{};
+    c.factors = L.chain;
+    c.cstride = L.cstride;
+    c.omega = L.omega;
+    c.n = h->n;
+    c.R = W.R;
+    c.rc = hdg::chain_multi_chunk(L.P, h->n, W.R, hdg::vec_bytes(pr));
+    c.nchunks = (W.R + c.rc - 1) / c.rc;
+    c.out = x;
+    if (z) {
+      c.r = b;
+      c.x = nullptr;
+    } else {
+      hdg::MultiArgs a = margs(h, L, W.R, false);
+      a.X = x;
+      a.B = b;
+      a.Y = W.pr[p];
+      hipchk(hdg::launch_trace_multi(L.mp, L.P, a, h->stream, hdg::TM_RESID), "residual multi");
+      c.r = W.pr[p];
+      c.x = x;
+    }
+    hipchk(hdg::launch_chain_solve_m(pr, L.P, c, h->stream), "chain solve multi");
+  }
+}
+
+void chebyshev_m(hdg_ctx* h, MultiWork& W, int l, int nu, bool zero) {
+  QLevel& Q = h->ql[l];
+  const double a0 = h->cfg.cheb_lo * Q.lmax, c0 = h->cfg.cheb_hi * Q.lmax;
+  const double theta = 0.5 * (c0 + a0), delta = 0.5 * (c0 - a0), sigma = theta / delta;
+  double rho = 1.0 / sigma;
+  void* cur = W.qx[l];
+  void* nxt = W.qt[l];
+  for (int s = 0; s < nu; ++s) {
+    double c1, c2;
+    if (s == 0) {
+      c1 = 0.0;
+      c2 = 1.0 / theta;
+    } else {
+      const double rn = 1.0 / (2.0 * sigma - rho);
+      c1 = rn * rho;
+      c2 = 2.0 * rn / delta;
+      rho = rn;
+    }
+    const void* xin = (zero && s == 0) ? nullptr : cur;
+    hipchk(hdg::launch_q1_cheb_m(h->prec, Q.st, Q.dinv, W.qb[l], xin, W.qd[l], nxt, c1, c2, Q.m, W.R, h->stream),
+           "chebyshev multi");
+    std::swap(cur, nxt);
+  }
+  if (cur != W.qx[l]) hipchk(hdg::launch_copy(h->prec, cur, W.qx[l], Q.Nv * W.R, h->stream), "copy");
+}
+
+void qcycle_m(hdg_ctx* h, MultiWork& W, int l) {
+  QLevel& Q = h->ql[l];
+  const hdg::Prec pr = h->prec;
+  if (Q.coarsest) {
+    hipchk(hdg::launch_dense_gemm_m(pr, Q.inv, W.qb[l], W.qx[l], (int)Q.Nv, W.R, h->stream), "coarse solve multi");
+    return;
+  }
+  chebyshev_m(h, W, l, h->cfg.nu1, true);
+  hipchk(hdg::launch_q1_resid_m(pr, Q.st, W.qb[l], W.qx[l], W.qr[l], Q.m, W.R, h->stream), "q1 resid multi");
+  hipchk(hdg::launch_q1_restrict_m(pr, W.qr[l], W.qb[l + 1], Q.m, W.R, h->stream), "q1 restrict multi");
+  qcycle_m(h, W, l + 1);
+  hipchk(hdg::launch_q1_prolong_add_m(pr, W.qx[l + 1], W.qx[l], Q.m, W.R, h->stream), "q1 prolong multi");
+  chebyshev_m(h, W, l, h->cfg.nu2, false);
+}
+
+// The V-cycle of pcycle for every column at once (chain smoother; Krylov
+// acceleration of coarse levels is not applied here).
+void pcycle_m(hdg_ctx* h, MultiWork& W, int p, const void* b, void* x, bool zero) {
+  PLevel& L = h->pl[p];
+  const hdg::Prec pr = h->prec;
+  smooth_m(h, W, p, b, x, h->cfg.nu1, zero);
+  if (p >= 1) {
+    hdg::MultiArgs a = margs(h, L, W.R, false);
+    a.X = x;
+    a.B = b;
+    a.Y = W.pb[p - 1];
+    hipchk(hdg::launch_trace_multi(L.mp, L.P, a, h->stream, hdg::TM_RESID_RESTRICT), "resid restrict multi");
+    pcycle_m(h, W, p - 1, W.pb[p - 1], W.px[p - 1], true);
+    hipchk(hdg::launch_p_prolong_add_m(pr, L.P, L.pmat, W.px[p - 1], x, h->nf, W.R, h->stream), "p prolong multi");
+  } else {
+    hdg::MultiArgs a = margs(h, L, W.R, false);
+    a.X = x;
+    a.B = b;
+    a.Y = W.pr[0];
+    hipchk(hdg::launch_trace_multi(L.mp, L.P, a, h->stream, hdg::TM_RESID), "residual multi");
+    hipchk(hdg::launch_pj_restrict_m(pr, W.pr[0], W.qb[0], h->n, W.R, h->stream), "pj restrict multi");
+    qcycle_m(h, W, 0);
+    hipchk(hdg::launch_pj_prolong_add_m(pr, W.qx[0], x, h->n, W.R, h->stream), "pj prolong multi");
+  }
+  smooth_m(h, W, p, b, x, h->cfg.nu2, false);
+}
+
+// Z = B R for every column (FP64 in and out; the cycle runs in the cycle precision)
+void precondition_m(hdg_ctx* h, MultiWork& W) {
+  const int64_t NR = h->pl[h->k].N * (int64_t)W.R;
+  if (h->prec == hdg::Prec::F64) {
+    pcycle_m(h, W, h->k, W.vr, W.vz, true);
+    return;
+  }
+  hipchk(hdg::launch_to_f32(W.vr, static_cast<float*>(W.cva), NR, h->stream), "to f32");
+  pcycle_m(h, W, h->k, W.cva, W.cvb, true);
+  hipchk(hdg::launch_to_f64(static_cast<const float*>(W.cvb), W.vz, NR, h->stream), "to f64");
+}
+
 void validate_config(const hdg_config_t* c) {
   if (!c) throw ArgError("cfg is NULL");
   if (c->n < 2) throw ArgError("n must be >= 2");
@@ -1441,6 +1618,103 @@ hdg_status_t hdg_misfit_gradient(hdg_handle_t h, const double* lam, const double
     a.mu = mu;
     a.grad = grad;
     hipchk(hdg::launch_elem_gradient(h->k + 1, a, h->stream), "gradient");
+    return HDG_OK;
+  });
+}
+
+hdg_status_t hdg_solve_multi(hdg_handle_t h, int32_t nrhs, const double* B, double* X, double rtol, int32_t maxit,
+                             int32_t* iters_host, double* relres_host) {
+  if (!h || !B || !X || B == X || nrhs < 1 || nrhs > 256 || maxit < 0 || !(rtol >= 0.0))
+    return HDG_ERR_INVALID_ARG;
+  if (h->cfg.smoother != HDG_SMOOTH_CHAIN) {
+    h->err = "the solve for many right-hand sides uses the chain smoother";
+    return HDG_ERR_STATE;
+  }
+  return guarded(h, [&]() -> hdg_status_t {
+    const int R = nrhs;
+    MultiWork& W = multi_work(h, R);
+    const int k = h->k;
+    PLevel& Lk = h->pl[k];
+    const int64_t N = Lk.N;
+    hipStream_t s = h->stream;
+    std::vector<double> nb(R), rn(R), act(R);
+    std::vector<int> its(R, 0);
+    auto host_col = [&](const double* dev, std::vector<double>& out) {
+      hipchk(hipMemcpyAsync(out.data(), dev, R * sizeof(double), hipMemcpyDeviceToHost, s), "d2h");
+      hipchk(hipStreamSynchronize(s), "sync");
+    };
+    hipchk(hdg::launch_dots_m(hdg::Prec::F64, B, B, N, R, W.partial, W.nb, s), "dots");
+    host_col(W.nb, nb);
+    {  // R0 = B - S X with the FP64 operator
+      hdg::MultiArgs a = margs(h, Lk, R, true);
+      a.X = X;
+      a.B = B;
+      a.Y = W.vr;
+      hipchk(hdg::launch_trace_multi(hdg::Prec::F64, Lk.P, a, s, hdg::TM_RESID), "residual multi");
+    }
+    hipchk(hdg::launch_dots_m(hdg::Prec::F64, W.vr, W.vr, N, R, W.partial, W.nrm, s), "dots");
+    host_col(W.nrm, rn);
+    int nact = 0;
+    for (int r = 0; r < R; ++r) {
+      nb[r] = std::sqrt(nb[r]);
+      rn[r] = std::sqrt(rn[r]);
+      if (!std::isfinite(rn[r]) || !std::isfinite(nb[r])) {
+        h->err = "non-finite residual";
+        return HDG_ERR_NONFINITE;
+      }
+      act[r] = rn[r] > rtol * nb[r] ? 1.0 : 0.0;
+      nact += act[r] > 0;
+    }
+    hipchk(hipMemcpyAsync(W.act, act.data(), R * sizeof(double), hipMemcpyHostToDevice, s), "h2d");
+    double* sc = W.sc;  // [5][R]: d.r, d.q, z.q, z.r, d.r (previous direction)
+    int it = 0;
+    while (nact > 0 && it < maxit) {
+      precondition_m(h, W);
+      if (it == 0) {
+        hipchk(hdg::launch_copy(hdg::Prec::F64, W.vz, W.vd, N * R, s), "copy");
+        hipchk(hdg::launch_dots_m(hdg::Prec::F64, W.vz, W.vr, N, R, W.partial, sc, s), "dots");
+      } else {
+        hipchk(hdg::launch_dots_m(hdg::Prec::F64, W.vz, W.vq, N, R, W.partial, sc + 2 * R, s), "dots");
+        hipchk(hdg::launch_dots_m(hdg::Prec::F64, W.vz, W.vr, N, R, W.partial, sc + 3 * R, s), "dots");
+        hipchk(hdg::launch_dots_m(hdg::Prec::F64, W.vd, W.vr, N, R, W.partial, sc + 4 * R, s), "dots");
+        hipchk(hdg::launch_fcg_scalars_m(sc, R, s), "fcg scalars");
+        hipchk(hdg::launch_xpby_m(hdg::Prec::F64, W.vz, sc + 2 * R, sc + R, -1.0, W.vd, N, R, s), "xpby");
+      }
+      hdg::MultiArgs a = margs(h, Lk, R, true);
+      a.X = W.vd;
+      a.Y = W.vq;
+      hipchk(hdg::launch_trace_multi(hdg::Prec::F64, Lk.P, a, s, hdg::TM_APPLY), "apply multi");
+      hipchk(hdg::launch_dots_m(hdg::Prec::F64, W.vd, W.vq, N, R, W.partial, sc + R, s), "dots");
+      hipchk(hdg::launch_axpy_m(hdg::Prec::F64, sc, sc + R, W.act, 1.0, W.vd, X, N, R, s), "axpy");
+      hipchk(hdg::launch_axpy_m(hdg::Prec::F64, sc, sc + R, W.act, -1.0, W.vq, W.vr, N, R, s), "axpy");
+      hipchk(hdg::launch_dots_m(hdg::Prec::F64, W.vr, W.vr, N, R, W.partial, W.nrm, s), "dots");
+      host_col(W.nrm, rn);
+      ++it;
+      nact = 0;
+      for (int r = 0; r < R; ++r) {
+        if (act[r] == 0.0) continue;
+        const double v = std::sqrt(rn[r]);
+        if (!std::isfinite(v)) {
+          h->err = "non-finite residual";
+          return HDG_ERR_NONFINITE;
+        }
+        its[r] = it;
+        if (v <= rtol * nb[r]) act[r] = 0.0;
+        else ++nact;
+      }
+      hipchk(hipMemcpyAsync(W.act, act.data(), R * sizeof(double), hipMemcpyHostToDevice, s), "h2d");
+    }
+    // final relative residuals, recomputed from the recursive residuals of the last iteration
+    hipchk(hdg::launch_dots_m(hdg::Prec::F64, W.vr, W.vr, N, R, W.partial, W.nrm, s), "dots");
+    host_col(W.nrm, rn);
+    for (int r = 0; r < R; ++r) {
+      if (iters_host) iters_host[r] = its[r];
+      if (relres_host) relres_host[r] = nb[r] > 0 ? std::sqrt(rn[r]) / nb[r] : std::sqrt(rn[r]);
+    }
+    if (nact > 0) {
+      h->err = "maximum number of iterations reached";
+      return HDG_ERR_NOT_CONVERGED;
+    }
     return HDG_OK;
   });
 }

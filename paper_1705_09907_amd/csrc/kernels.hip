@@ -322,7 +322,7 @@ struct MultiGroup {
   static constexpr int PQ = sizeof(TV) == 8 ? (P + 1) / 2 * 2 : (P + 3) / 4 * 4;
 };
 
-template <int P, typename TM, typename TV>
+template <int P, int MODE, typename TM, typename TV>
 __global__ __launch_bounds__(256) void k_trace_multi(MultiArgs a) {
   using L16 = Lanes16<TM, TV>;
   constexpr int V = L16::V;
@@ -380,8 +380,27 @@ __global__ __launch_bounds__(256) void k_trace_multi(MultiArgs a) {
         for (int q = 0; q < P; ++q) acc[q] += col[q] * xv;
       }
     }
+    if constexpr (MODE == TM_APPLY) {
 #pragma unroll
-    for (int q = 0; q < P; ++q) Y[(f * P + q) * R + r] = acc[q];
+      for (int q = 0; q < P; ++q) Y[(f * P + q) * R + r] = acc[q];
+    } else {
+      const TV* B = static_cast<const TV*>(a.B);
+#pragma unroll
+      for (int q = 0; q < P; ++q) acc[q] = B[(f * P + q) * R + r] - acc[q];
+      if constexpr (MODE == TM_RESID) {
+#pragma unroll
+        for (int q = 0; q < P; ++q) Y[(f * P + q) * R + r] = acc[q];
+      } else if constexpr (P >= 2) {  // TM_RESID_RESTRICT: Y (coarse) = P_p^T (B - S X)
+        const TV* pm = static_cast<const TV*>(a.pmat);
+#pragma unroll
+        for (int c = 0; c < P - 1; ++c) {
+          TV s = TV(0);
+#pragma unroll
+          for (int q = 0; q < P; ++q) s += pm[q * (P - 1) + c] * acc[q];
+          Y[(f * (P - 1) + c) * R + r] = s;
+        }
+      }
+    }
   }
 }
 
@@ -399,24 +418,36 @@ __global__ __launch_bounds__(256) void k_trace_multi(MultiArgs a) {
     default: return hipErrorInvalidValue;             \
   }
 
-template <int P>
-static hipError_t launch_trace_multi_p(Prec pr, const MultiArgs& a, hipStream_t s) {
+template <int P, int MODE>
+static hipError_t launch_trace_multi_pm(Prec pr, const MultiArgs& a, hipStream_t s) {
   constexpr int FW = MultiGroup<P, double>::FW;
   const dim3 grid((unsigned)((a.nf + FW - 1) / FW));
   const int64_t pairs = (int64_t)FW * a.nrhs;
   const dim3 block((unsigned)(pairs >= 256 ? 256 : (pairs + 63) / 64 * 64));
   switch (pr) {
-    case Prec::F64: hipLaunchKernelGGL((k_trace_multi<P, double, double>), grid, block, 0, s, a); break;
-    case Prec::F32: hipLaunchKernelGGL((k_trace_multi<P, float, float>), grid, block, 0, s, a); break;
-    case Prec::BF16: hipLaunchKernelGGL((k_trace_multi<P, bf16_t, float>), grid, block, 0, s, a); break;
+    case Prec::F64: hipLaunchKernelGGL((k_trace_multi<P, MODE, double, double>), grid, block, 0, s, a); break;
+    case Prec::F32: hipLaunchKernelGGL((k_trace_multi<P, MODE, float, float>), grid, block, 0, s, a); break;
+    case Prec::BF16: hipLaunchKernelGGL((k_trace_multi<P, MODE, bf16_t, float>), grid, block, 0, s, a); break;
   }
   return hipGetLastError();
 }
 
-hipError_t launch_trace_multi(Prec pr, int P, const MultiArgs& a, hipStream_t s) {
+template <int P>
+static hipError_t launch_trace_multi_p(Prec pr, int mode, const MultiArgs& a, hipStream_t s) {
+  switch (mode) {
+    case TM_APPLY: return launch_trace_multi_pm<P, TM_APPLY>(pr, a, s);
+    case TM_RESID: return launch_trace_multi_pm<P, TM_RESID>(pr, a, s);
+    case TM_RESID_RESTRICT:
+      if (P < 2) return hipErrorInvalidValue;
+      return launch_trace_multi_pm<P, TM_RESID_RESTRICT>(pr, a, s);
+    default: return hipErrorInvalidValue;
+  }
+}
+
+hipError_t launch_trace_multi(Prec pr, int P, const MultiArgs& a, hipStream_t s, int mode) {
   if (a.nrhs < 1) return hipErrorInvalidValue;
   if (a.nf == 0) return hipSuccess;
-  HDG_DISPATCH_P(P, return launch_trace_multi_p<PP>(pr, a, s));
+  HDG_DISPATCH_P(P, return launch_trace_multi_p<PP>(pr, mode, a, s));
 }
 
 hipError_t launch_trace(Prec pr, int P, int mode, const TraceArgs& a, hipStream_t s) {

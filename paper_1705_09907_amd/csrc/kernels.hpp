@@ -52,13 +52,17 @@ hipError_t launch_trace(Prec pr, int P, int mode, const TraceArgs& a, hipStream_
 struct MultiArgs {
   const void* slab;
   const void* X;
-  void* Y;
+  void* Y;               // APPLY / RESID: [nf P][nrhs]; RESID_RESTRICT: [nf (P-1)][nrhs]
+  const void* B;         // RESID, RESID_RESTRICT
+  const void* pmat;      // RESID_RESTRICT: P_p, vector precision
   int nrhs;
   int n;
   int64_t nf, ntiles;
   int remap;   // XCD-contiguous group order
 };
-hipError_t launch_trace_multi(Prec pr, int P, const MultiArgs& a, hipStream_t s);
+// mode: TM_APPLY (Y = S X), TM_RESID (Y = B - S X) or TM_RESID_RESTRICT
+// (Y = P_p^T (B - S X) on the coarse level)
+hipError_t launch_trace_multi(Prec pr, int P, const MultiArgs& a, hipStream_t s, int mode = TM_APPLY);
 
 // y_m = S_m x_m for many meshes (FP64) in one launch: a fixed grid walks the
 // (mesh, tile) items; tile0 = first item of the mesh (prefix sum of ntiles).
@@ -150,6 +154,47 @@ hipError_t launch_face_gather(int P, const double* t, double* c, int n, hipStrea
 // grad_K = K (C mu_K - B^T w)^T A0^{-1} (B^T U_K - C Lambda_K),
 //          w = (D + K G)^{-1} (U_K - Uobs_K - (E - K H) mu_K)
 hipError_t launch_elem_gradient(int P, const ElemArgs& a, hipStream_t s);
+
+// ---- many right-hand sides (multi.hip): vectors [rows][R], vector precision
+hipError_t launch_p_restrict_m(Prec pr, int P, const void* pm, const void* rf, void* rc, int64_t nf, int R,
+                               hipStream_t s);
+hipError_t launch_p_prolong_add_m(Prec pr, int P, const void* pm, const void* ec, void* xf, int64_t nf, int R,
+                                  hipStream_t s);
+hipError_t launch_q1_resid_m(Prec pr, const void* st, const void* b, const void* x, void* r, int m, int R,
+                             hipStream_t s);
+hipError_t launch_q1_cheb_m(Prec pr, const void* st, const void* dinv, const void* b, const void* x, void* d,
+                            void* xo, double c1, double c2, int m, int R, hipStream_t s);
+hipError_t launch_q1_restrict_m(Prec pr, const void* rf, void* rc, int mf, int R, hipStream_t s);
+hipError_t launch_q1_prolong_add_m(Prec pr, const void* ec, void* xf, int mf, int R, hipStream_t s);
+hipError_t launch_pj_restrict_m(Prec pr, const void* rface, void* rv, int n, int R, hipStream_t s);
+hipError_t launch_pj_prolong_add_m(Prec pr, const void* ev, void* xface, int n, int R, hipStream_t s);
+hipError_t launch_dense_gemm_m(Prec pr, const double* A, const void* b, void* y, int m, int R, hipStream_t s);
+struct ChainMultiArgs {
+  const void* factors;
+  int64_t cstride;
+  const void* r;
+  const void* x;     // nullptr: out = omega M^{-1} r
+  void* out;         // may alias x
+  double omega;
+  int n;
+  int R;             // right-hand sides (row stride of r, x, out)
+  int rc;            // right-hand sides per workgroup (chain_multi_chunk)
+  int nchunks;       // ceil(R / rc)
+};
+int chain_multi_chunk(int P, int n, int R, size_t elem_bytes);
+hipError_t launch_chain_solve_m(Prec pr, int P, const ChainMultiArgs& a, hipStream_t s);
+// out[r] = sum_i x[i][r] y[i][r] (FP64, deterministic); partial needs dots_m_grid(N) * R
+int dots_m_grid(int64_t N);
+hipError_t launch_dots_m(Prec pr, const void* x, const void* y, int64_t N, int R, double* partial, double* out,
+                         hipStream_t s);
+// y[i][r] += sign act[r] num[r] / den[r] x[i][r]  (ratio 0 when den[r] is not > 0; act may be null)
+hipError_t launch_axpy_m(Prec pr, const double* num, const double* den, const double* act, double sign,
+                         const void* x, void* y, int64_t N, int R, hipStream_t s);
+// y[i][r] = x[i][r] + sign num[r] / den[r] y[i][r]
+hipError_t launch_xpby_m(Prec pr, const void* x, const double* num, const double* den, double sign, void* y,
+                         int64_t N, int R, hipStream_t s);
+// sc = [5][R]: sc[0][r] = sc[3][r] - (sc[2][r] / sc[1][r]) sc[4][r]
+hipError_t launch_fcg_scalars_m(double* sc, int R, hipStream_t s);
 
 // deterministic reductions (FP64 vectors)
 int reduce_grid(int64_t n);

@@ -1,0 +1,520 @@
+// gfx950 kernels of the multigrid cycle for many right-hand sides at once.
+//
+// Every vector is [rows][R]: the R right-hand sides of one trace DoF, Q1 vertex
+// or face are contiguous, so a thread takes one (row, right-hand side) pair
+// with the right-hand side fastest and every access of a wavefront is
+// contiguous.  Each kernel applies the same operation as its single-vector
+// counterpart in kernels.hip to every column; operators (blocks, smoother
+// factors, stencils, transfer tables) are read once per launch for all columns.
+#include <hip/hip_runtime.h>
+
+#include "kernels.hpp"
+
+namespace hdg {
+
+static constexpr int kMW = 256;
+static inline dim3 grid_m(int64_t n) { return dim3((unsigned)((n + kMW - 1) / kMW)); }
+
+#define HDG_MDISPATCH_T(pr, CALL)                     \
+  if ((pr) == Prec::F64) { using TT = double; CALL; } \
+  else { using TT = float; CALL; }
+
+#define HDG_MDISPATCH_P(P, CALL)                      \
+  switch (P) {                                        \
+    case 1: { constexpr int PP = 1; CALL; } break;    \
+    case 2: { constexpr int PP = 2; CALL; } break;    \
+    case 3: { constexpr int PP = 3; CALL; } break;    \
+    case 4: { constexpr int PP = 4; CALL; } break;    \
+    case 5: { constexpr int PP = 5; CALL; } break;    \
+    case 6: { constexpr int PP = 6; CALL; } break;    \
+    case 7: { constexpr int PP = 7; CALL; } break;    \
+    case 8: { constexpr int PP = 8; CALL; } break;    \
+    case 9: { constexpr int PP = 9; CALL; } break;    \
+    default: return hipErrorInvalidValue;             \
+  }
+
+// ------------------------------------------------------------- p-transfers
+template <int P, typename T>
+__global__ __launch_bounds__(kMW) void k_p_restrict_m(const T* pm, const T* rf, T* rc, int64_t nf, int R) {
+  const int64_t idx = (int64_t)blockIdx.x * kMW + threadIdx.x;
+  if (idx >= nf * R) return;
+  const int64_t f = idx / R;
+  const int r = (int)(idx - f * R);
+  T v[P];
+#pragma unroll
+  for (int a = 0; a < P; ++a) v[a] = rf[(f * P + a) * R + r];
+#pragma unroll
+  for (int c = 0; c < P - 1; ++c) {
+    T s = T(0);
+#pragma unroll
+    for (int a = 0; a < P; ++a) s += pm[a * (P - 1) + c] * v[a];
+    rc[(f * (P - 1) + c) * R + r] = s;
+  }
+}
+
+template <int P, typename T>
+__global__ __launch_bounds__(kMW) void k_p_prolong_add_m(const T* pm, const T* ec, T* xf, int64_t nf, int R) {
+  const int64_t idx = (int64_t)blockIdx.x * kMW + threadIdx.x;
+  if (idx >= nf * R) return;
+  const int64_t f = idx / R;
+  const int r = (int)(idx - f * R);
+  T e[P - 1];
+#pragma unroll
+  for (int c = 0; c < P - 1; ++c) e[c] = ec[(f * (P - 1) + c) * R + r];
+#pragma unroll
+  for (int a = 0; a < P; ++a) {
+    T s = xf[(f * P + a) * R + r];
+#pragma unroll
+    for (int c = 0; c < P - 1; ++c) s += pm[a * (P - 1) + c] * e[c];
+    xf[(f * P + a) * R + r] = s;
+  }
+}
+
+hipError_t launch_p_prolong_add_m(Prec pr, int P, const void* pm, const void* ec, void* xf, int64_t nf, int R,
+                                  hipStream_t s) {
+  if (P < 2) return hipErrorInvalidValue;
+  if (nf == 0) return hipSuccess;
+  HDG_MDISPATCH_T(pr, HDG_MDISPATCH_P(P, if constexpr (PP >= 2) hipLaunchKernelGGL(
+                                             (k_p_prolong_add_m<PP, TT>), grid_m(nf * R), dim3(kMW), 0, s,
+                                             (const TT*)pm, (const TT*)ec, (TT*)xf, nf, R)));
+  return hipGetLastError();
+}
+hipError_t launch_p_restrict_m(Prec pr, int P, const void* pm, const void* rf, void* rc, int64_t nf, int R,
+                               hipStream_t s) {
+  if (P < 2) return hipErrorInvalidValue;
+  if (nf == 0) return hipSuccess;
+  HDG_MDISPATCH_T(pr, HDG_MDISPATCH_P(P, if constexpr (PP >= 2) hipLaunchKernelGGL(
+                                             (k_p_restrict_m<PP, TT>), grid_m(nf * R), dim3(kMW), 0, s,
+                                             (const TT*)pm, (const TT*)rf, (TT*)rc, nf, R)));
+  return hipGetLastError();
+}
+
+// ------------------------------------------------------------------ Q1 levels
+template <typename T>
+__device__ __forceinline__ T q1_apply_m(const T* st, const T* x, int m, int64_t Nv, int i, int j, int64_t v, int R,
+                                        int r) {
+  T s = T(0);
+#pragma unroll
+  for (int dj = -1; dj <= 1; ++dj)
+#pragma unroll
+    for (int di = -1; di <= 1; ++di) {
+      const int ii = i + di, jj = j + dj;
+      if (ii >= 1 && jj >= 1 && ii <= m - 1 && jj <= m - 1)
+        s += st[(int64_t)((di + 1) + 3 * (dj + 1)) * Nv + v] *
+             x[((ii - 1) + (int64_t)(m - 1) * (jj - 1)) * R + r];
+    }
+  return s;
+}
+
+template <typename T>
+__global__ __launch_bounds__(kMW) void k_q1_resid_m(const T* st, const T* b, const T* x, T* rr, int m, int R) {
+  const int64_t Nv = (int64_t)(m - 1) * (m - 1);
+  const int64_t idx = (int64_t)blockIdx.x * kMW + threadIdx.x;
+  if (idx >= Nv * R) return;
+  const int64_t v = idx / R;
+  const int r = (int)(idx - v * R);
+  const int i = (int)(v % (m - 1)) + 1, j = (int)(v / (m - 1)) + 1;
+  rr[idx] = b[idx] - q1_apply_m(st, x, m, Nv, i, j, v, R, r);
+}
+
+template <typename T>
+__global__ __launch_bounds__(kMW) void k_q1_cheb_m(const T* st, const T* dinv, const T* b, const T* x, T* d, T* xo,
+                                                   double c1, double c2, int m, int R) {
+  const int64_t Nv = (int64_t)(m - 1) * (m - 1);
+  const int64_t idx = (int64_t)blockIdx.x * kMW + threadIdx.x;
+  if (idx >= Nv * R) return;
+  const int64_t v = idx / R;
+  const int r = (int)(idx - v * R);
+  const int i = (int)(v % (m - 1)) + 1, j = (int)(v / (m - 1)) + 1;
+  const T ax = x ? q1_apply_m(st, x, m, Nv, i, j, v, R, r) : T(0);
+  const T z = dinv[v] * (b[idx] - ax);
+  const T dn = (c1 != 0.0 ? T(c1) * d[idx] : T(0)) + T(c2) * z;
+  d[idx] = dn;
+  xo[idx] = (x ? x[idx] : T(0)) + dn;
+}
+
+template <typename T>
+__global__ __launch_bounds__(kMW) void k_q1_restrict_m(const T* rf, T* rc, int mf, int R) {
+  const int mc = mf / 2;
+  const int64_t Nc = (int64_t)(mc - 1) * (mc - 1);
+  const int64_t idx = (int64_t)blockIdx.x * kMW + threadIdx.x;
+  if (idx >= Nc * R) return;
+  const int64_t v = idx / R;
+  const int r = (int)(idx - v * R);
+  const int I = (int)(v % (mc - 1)) + 1, J = (int)(v / (mc - 1)) + 1;
+  T s = T(0);
+#pragma unroll
+  for (int dj = -1; dj <= 1; ++dj)
+#pragma unroll
+    for (int di = -1; di <= 1; ++di) {
+      const T w = T((di == 0 ? 1.0 : 0.5) * (dj == 0 ? 1.0 : 0.5));
+      const int fi = 2 * I + di, fj = 2 * J + dj;
+      s += w * rf[((fi - 1) + (int64_t)(mf - 1) * (fj - 1)) * R + r];
+    }
+  rc[idx] = s;
+}
+
+template <typename T>
+__global__ __launch_bounds__(kMW) void k_q1_prolong_add_m(const T* ec, T* xf, int mf, int R) {
+  const int mc = mf / 2;
+  const int64_t Nf = (int64_t)(mf - 1) * (mf - 1);
+  const int64_t idx = (int64_t)blockIdx.x * kMW + threadIdx.x;
+  if (idx >= Nf * R) return;
+  const int64_t v = idx / R;
+  const int r = (int)(idx - v * R);
+  const int I = (int)(v % (mf - 1)) + 1, J = (int)(v / (mf - 1)) + 1;
+  int xi[2], yi[2];
+  T wx[2], wy[2];
+  int nx, ny;
+  if ((I & 1) == 0) { xi[0] = I / 2; wx[0] = T(1); nx = 1; } else { xi[0] = I / 2; xi[1] = I / 2 + 1; wx[0] = wx[1] = T(0.5); nx = 2; }
+  if ((J & 1) == 0) { yi[0] = J / 2; wy[0] = T(1); ny = 1; } else { yi[0] = J / 2; yi[1] = J / 2 + 1; wy[0] = wy[1] = T(0.5); ny = 2; }
+  T s = T(0);
+  for (int bb = 0; bb < ny; ++bb)
+    for (int aa = 0; aa < nx; ++aa) {
+      const int ci = xi[aa], cj = yi[bb];
+      if (ci >= 1 && cj >= 1 && ci <= mc - 1 && cj <= mc - 1)
+        s += wx[aa] * wy[bb] * ec[((ci - 1) + (int64_t)(mc - 1) * (cj - 1)) * R + r];
+    }
+  xf[idx] += s;
+}
+
+template <typename T>
+__global__ __launch_bounds__(kMW) void k_pj_restrict_m(const T* rface, T* rv, int n, int R) {
+  const int64_t Nv = (int64_t)(n - 1) * (n - 1);
+  const int64_t idx = (int64_t)blockIdx.x * kMW + threadIdx.x;
+  if (idx >= Nv * R) return;
+  const int64_t v = idx / R;
+  const int r = (int)(idx - v * R);
+  const int i = (int)(v % (n - 1)) + 1, j = (int)(v / (n - 1)) + 1;
+  const int64_t nv = (int64_t)n * (n - 1);
+  const T s = rface[((i - 1) + (int64_t)(n - 1) * j) * R + r] + rface[((i - 1) + (int64_t)(n - 1) * (j - 1)) * R + r] +
+              rface[(nv + i + (int64_t)n * (j - 1)) * R + r] + rface[(nv + (i - 1) + (int64_t)n * (j - 1)) * R + r];
+  rv[idx] = T(0.5) * s;
+}
+
+template <typename T>
+__global__ __launch_bounds__(kMW) void k_pj_prolong_add_m(const T* ev, T* xface, int n, int R) {
+  const int64_t nf = 2LL * n * (n - 1), nv = (int64_t)n * (n - 1);
+  const int64_t idx = (int64_t)blockIdx.x * kMW + threadIdx.x;
+  if (idx >= nf * R) return;
+  const int64_t f = idx / R;
+  const int r = (int)(idx - f * R);
+  int ai, aj, bi, bj;
+  if (f < nv) {
+    const int j = (int)(f / (n - 1)), i = (int)(f % (n - 1)) + 1;
+    ai = i; aj = j; bi = i; bj = j + 1;
+  } else {
+    const int64_t q = f - nv;
+    const int j = (int)(q / n) + 1, i = (int)(q % n);
+    ai = i; aj = j; bi = i + 1; bj = j;
+  }
+  T s = T(0);
+  if (ai >= 1 && aj >= 1 && ai <= n - 1 && aj <= n - 1) s += ev[((ai - 1) + (int64_t)(n - 1) * (aj - 1)) * R + r];
+  if (bi >= 1 && bj >= 1 && bi <= n - 1 && bj <= n - 1) s += ev[((bi - 1) + (int64_t)(n - 1) * (bj - 1)) * R + r];
+  xface[idx] += T(0.5) * s;
+}
+
+// Y = A B with the FP64 dense coarsest inverse A (m x m) and B [m][R]: one
+// workgroup per row; lanes run over right-hand sides, FP64 accumulation in
+// column order.
+template <typename T>
+__global__ __launch_bounds__(64) void k_dense_gemm_m(const double* A, const T* B, T* Y, int m, int R) {
+  const int row = blockIdx.x;
+  for (int r = threadIdx.x; r < R; r += 64) {
+    double s = 0.0;
+    for (int c = 0; c < m; ++c) s += A[(int64_t)row * m + c] * (double)B[(int64_t)c * R + r];
+    Y[(int64_t)row * R + r] = T(s);
+  }
+}
+
+hipError_t launch_q1_resid_m(Prec pr, const void* st, const void* b, const void* x, void* r, int m, int R,
+                             hipStream_t s) {
+  HDG_MDISPATCH_T(pr, hipLaunchKernelGGL(k_q1_resid_m<TT>, grid_m((int64_t)(m - 1) * (m - 1) * R), dim3(kMW), 0, s,
+                                         (const TT*)st, (const TT*)b, (const TT*)x, (TT*)r, m, R));
+  return hipGetLastError();
+}
+hipError_t launch_q1_cheb_m(Prec pr, const void* st, const void* dinv, const void* b, const void* x, void* d,
+                            void* xo, double c1, double c2, int m, int R, hipStream_t s) {
+  HDG_MDISPATCH_T(pr, hipLaunchKernelGGL(k_q1_cheb_m<TT>, grid_m((int64_t)(m - 1) * (m - 1) * R), dim3(kMW), 0, s,
+                                         (const TT*)st, (const TT*)dinv, (const TT*)b, (const TT*)x, (TT*)d,
+                                         (TT*)xo, c1, c2, m, R));
+  return hipGetLastError();
+}
+hipError_t launch_q1_restrict_m(Prec pr, const void* rf, void* rc, int mf, int R, hipStream_t s) {
+  const int mc = mf / 2;
+  HDG_MDISPATCH_T(pr, hipLaunchKernelGGL(k_q1_restrict_m<TT>, grid_m((int64_t)(mc - 1) * (mc - 1) * R), dim3(kMW),
+                                         0, s, (const TT*)rf, (TT*)rc, mf, R));
+  return hipGetLastError();
+}
+hipError_t launch_q1_prolong_add_m(Prec pr, const void* ec, void* xf, int mf, int R, hipStream_t s) {
+  HDG_MDISPATCH_T(pr, hipLaunchKernelGGL(k_q1_prolong_add_m<TT>, grid_m((int64_t)(mf - 1) * (mf - 1) * R),
+                                         dim3(kMW), 0, s, (const TT*)ec, (TT*)xf, mf, R));
+  return hipGetLastError();
+}
+hipError_t launch_pj_restrict_m(Prec pr, const void* rface, void* rv, int n, int R, hipStream_t s) {
+  HDG_MDISPATCH_T(pr, hipLaunchKernelGGL(k_pj_restrict_m<TT>, grid_m((int64_t)(n - 1) * (n - 1) * R), dim3(kMW), 0,
+                                         s, (const TT*)rface, (TT*)rv, n, R));
+  return hipGetLastError();
+}
+hipError_t launch_pj_prolong_add_m(Prec pr, const void* ev, void* xface, int n, int R, hipStream_t s) {
+  HDG_MDISPATCH_T(pr, hipLaunchKernelGGL(k_pj_prolong_add_m<TT>, grid_m(2LL * n * (n - 1) * R), dim3(kMW), 0, s,
+                                         (const TT*)ev, (TT*)xface, n, R));
+  return hipGetLastError();
+}
+hipError_t launch_dense_gemm_m(Prec pr, const double* A, const void* b, void* y, int m, int R, hipStream_t s) {
+  HDG_MDISPATCH_T(pr, hipLaunchKernelGGL(k_dense_gemm_m<TT>, dim3((unsigned)m), dim3(64), 0, s, A, (const TT*)b,
+                                         (TT*)y, m, R));
+  return hipGetLastError();
+}
+
+// ----------------------------------------------------------- chain Schwarz
+// out = x + omega M^{-1} r for R right-hand sides: the block cyclic reduction of
+// k_chain with a chunk of RC right-hand sides per workgroup.  A work item
+// (position, row) loads its factor row once and applies it to every right-hand
+// side of the chunk held in LDS [position][row][RC].  The chunks of one chain are
+// consecutive workgroups of one XCD (workgroups are dealt round-robin to the 8
+// XCDs), so the factor re-reads of later chunks come from that XCD's L2.
+static constexpr int kChainMaxResM = 8;
+
+template <int P, typename T>
+__global__ __launch_bounds__(1024) void k_chain_m(ChainMultiArgs a) {
+  constexpr int P2 = P * P;
+  extern __shared__ unsigned char lds_raw_m[];
+  T* Rl = reinterpret_cast<T*>(lds_raw_m);
+  const T* rin = static_cast<const T*>(a.r);
+  const T* xin = static_cast<const T*>(a.x);
+  T* out = static_cast<T*>(a.out);
+  const int64_t nch = 2LL * a.n;
+  const int64_t npairs = nch * a.nchunks;
+  int64_t pair = blockIdx.x;
+  if (npairs % 8 == 0) pair = (int64_t)(blockIdx.x & 7) * (npairs >> 3) + (blockIdx.x >> 3);
+  const int64_t c = pair / a.nchunks;
+  const int chunk = (int)(pair - c * a.nchunks);
+  const int RC = a.rc;
+  const int R = a.R;
+  const int col0 = chunk * RC;
+  const int m = a.n - 1;
+  const int64_t nv = (int64_t)a.n * (a.n - 1);
+  const bool vert = c < a.n;
+  const int64_t base = vert ? c * (a.n - 1) : nv + (c - a.n);
+  const int64_t stride = vert ? 1 : a.n;
+  const T* F = static_cast<const T*>(a.factors) + c * a.cstride;
+  const int t = threadIdx.x;
+  const int nt = blockDim.x;
+  for (int idx = t; idx < m * P * RC; idx += nt) {
+    const int ir = idx / RC, q = idx - ir * RC;
+    const int i = ir / P, row = ir - i * P;
+    const int col = col0 + q;
+    Rl[idx] = col < R ? rin[((base + stride * i) * P + row) * R + col] : T(0);
+  }
+  __syncthreads();
+  int ml = m, lev = 0;
+  int64_t off = 0;
+  while (ml > 1) {
+    const int ne = (ml + 1) >> 1;
+    const T* E = F + off;
+    for (int it = t; it < ne * P; it += nt) {
+      const int row = it / ne, tt = it - row * ne;
+      const int j = 2 * tt;
+      const int i = j << lev;
+      T pm[P], pp[P];
+#pragma unroll
+      for (int q = 0; q < P; ++q) {
+        pm[q] = E[(int64_t)(row * P + q) * ne + tt];
+        pp[q] = E[(int64_t)(P2 + row * P + q) * ne + tt];
+      }
+      for (int q0 = 0; q0 < RC; ++q0) {
+        T v = Rl[(i * P + row) * RC + q0];
+        if (j >= 1) {
+          const int il = (j - 1) << lev;
+#pragma unroll
+          for (int q = 0; q < P; ++q) v -= pm[q] * Rl[(il * P + q) * RC + q0];
+        }
+        if (j + 1 < ml) {
+          const int ir2 = (j + 1) << lev;
+#pragma unroll
+          for (int q = 0; q < P; ++q) v -= pp[q] * Rl[(ir2 * P + q) * RC + q0];
+        }
+        Rl[(i * P + row) * RC + q0] = v;
+      }
+    }
+    off += (int64_t)2 * P2 * ne + (int64_t)3 * P2 * (ml >> 1);
+    ml = ne;
+    ++lev;
+    __syncthreads();
+  }
+  // last level: x_0 = Dinv r_0 for every right-hand side of the chunk
+  T xr = T(0);
+  const bool lastw = t < P * RC;
+  if (lastw) {
+    const int row = t / RC, q0 = t - row * RC;
+#pragma unroll
+    for (int q = 0; q < P; ++q) xr += F[off + row * P + q] * Rl[q * RC + q0];
+  }
+  __syncthreads();
+  if (lastw) Rl[t] = xr;
+  __syncthreads();
+  while (lev > 0) {
+    --lev;
+    ml = (m + (1 << lev) - 1) >> lev;
+    const int ne = (ml + 1) >> 1, no = ml >> 1;
+    int64_t lo = 0;
+    for (int l = 0, s = m; l < lev; ++l, s = (s + 1) >> 1)
+      lo += (int64_t)2 * P2 * ((s + 1) >> 1) + (int64_t)3 * P2 * (s >> 1);
+    const T* O = F + lo + (int64_t)2 * P2 * ne;
+    // values of all (item, right-hand side) pairs first, then a barrier, then writes
+    T res[kChainMaxResM];
+    int cnt = 0;
+    for (int it = t; it < no * P * RC && cnt < kChainMaxResM; it += nt, ++cnt) {
+      const int item = it / RC, q0 = it - item * RC;
+      const int row = item / no, tt = item - row * no;
+      const int j = 2 * tt + 1;
+      const int i = j << lev;
+      const int il = (j - 1) << lev;
+      T s = T(0);
+#pragma unroll
+      for (int q = 0; q < P; ++q)
+        s += O[(int64_t)(row * P + q) * no + tt] * Rl[(i * P + q) * RC + q0] -
+             O[(int64_t)(P2 + row * P + q) * no + tt] * Rl[(il * P + q) * RC + q0];
+      if (j + 1 < ml) {
+        const int ir2 = (j + 1) << lev;
+#pragma unroll
+        for (int q = 0; q < P; ++q) s -= O[(int64_t)(2 * P2 + row * P + q) * no + tt] * Rl[(ir2 * P + q) * RC + q0];
+      }
+      res[cnt] = s;
+    }
+    __syncthreads();
+    cnt = 0;
+    for (int it = t; it < no * P * RC && cnt < kChainMaxResM; it += nt, ++cnt) {
+      const int item = it / RC, q0 = it - item * RC;
+      const int row = item / no, tt = item - row * no;
+      Rl[(((2 * tt + 1) << lev) * P + row) * RC + q0] = res[cnt];
+    }
+    __syncthreads();
+  }
+  for (int idx = t; idx < m * P * RC; idx += nt) {
+    const int ir = idx / RC, q = idx - ir * RC;
+    const int i = ir / P, row = ir - i * P;
+    const int col = col0 + q;
+    if (col >= R) continue;
+    const int64_t g = ((base + stride * i) * P + row) * R + col;
+    out[g] = (xin ? xin[g] : T(0)) + T(a.omega) * Rl[idx];
+  }
+}
+
+int chain_multi_chunk(int P, int n, int R, size_t es) {
+  int64_t rc = 65536 / ((int64_t)(n - 1) * P * (int64_t)es);
+  if (rc > R) rc = R;
+  if (rc > 16) rc = 16;
+  return (int)(rc < 1 ? 1 : rc);
+}
+
+hipError_t launch_chain_solve_m(Prec pr, int P, const ChainMultiArgs& a, hipStream_t s) {
+  const size_t lds = (size_t)(a.n - 1) * P * a.rc * vec_bytes(pr);
+  if (lds > 65536 || a.rc < 1 || a.nchunks * a.rc < a.R) return hipErrorInvalidValue;
+  const int64_t bwd = (int64_t)((a.n - 1) / 2) * P * a.rc;
+  int threads = 256;
+  while (threads < 1024 && bwd > (int64_t)threads * kChainMaxResM) threads *= 2;
+  if (bwd > (int64_t)threads * kChainMaxResM || P * a.rc > threads) return hipErrorInvalidValue;
+  const dim3 grid((unsigned)(2LL * a.n * a.nchunks));
+  if (pr == Prec::F64) {
+    HDG_MDISPATCH_P(P, hipLaunchKernelGGL((k_chain_m<PP, double>), grid, dim3(threads), lds, s, a));
+  } else {
+    HDG_MDISPATCH_P(P, hipLaunchKernelGGL((k_chain_m<PP, float>), grid, dim3(threads), lds, s, a));
+  }
+  return hipGetLastError();
+}
+
+// -------------------------------------------------- per-column reductions
+// partial[b][r] = sum over this block's rows of x[i][r] y[i][r] (FP64); the
+// block's threads take (row offset, column) = (t / R, t % R), R <= 256.
+template <typename T>
+__global__ __launch_bounds__(kMW) void k_dots_m(const T* x, const T* y, int64_t N, int R, double* partial) {
+  __shared__ double acc[kMW];
+  const int t = threadIdx.x;
+  const int rpi = kMW / R;  // rows per iteration
+  double s = 0.0;
+  if (t < rpi * R) {
+    const int r = t % R, row0 = t / R;
+    for (int64_t i = (int64_t)blockIdx.x * rpi + row0; i < N; i += (int64_t)gridDim.x * rpi)
+      s += (double)x[i * R + r] * (double)y[i * R + r];
+  }
+  acc[t] = s;
+  __syncthreads();
+  if (t < R) {
+    double v = 0.0;
+    for (int q = 0; q < rpi; ++q) v += acc[q * R + t];
+    partial[(int64_t)blockIdx.x * R + t] = v;
+  }
+}
+__global__ __launch_bounds__(kMW) void k_sum_m(const double* partial, int nb, int R, double* out) {
+  for (int r = threadIdx.x; r < R; r += kMW) {
+    double v = 0.0;
+    for (int b = 0; b < nb; ++b) v += partial[(int64_t)b * R + r];
+    out[r] = v;
+  }
+}
+
+int dots_m_grid(int64_t N) {
+  int64_t g = (N + 255) / 256;
+  return (int)(g < 1 ? 1 : (g > 512 ? 512 : g));
+}
+hipError_t launch_dots_m(Prec pr, const void* x, const void* y, int64_t N, int R, double* partial, double* out,
+                         hipStream_t s) {
+  if (R < 1 || R > kMW) return hipErrorInvalidValue;
+  const int g = dots_m_grid(N);
+  HDG_MDISPATCH_T(pr, hipLaunchKernelGGL(k_dots_m<TT>, dim3(g), dim3(kMW), 0, s, (const TT*)x, (const TT*)y, N, R,
+                                         partial));
+  hipLaunchKernelGGL(k_sum_m, dim3(1), dim3(kMW), 0, s, partial, g, R, out);
+  return hipGetLastError();
+}
+
+__device__ __forceinline__ double ratio_or_zero_m(double a, double b) {
+  const double r = a / b;
+  return (b > 0.0 && isfinite(r)) ? r : 0.0;
+}
+// y[i][r] += sign act[r] num[r] / den[r] x[i][r]
+template <typename T>
+__global__ __launch_bounds__(kMW) void k_axpy_m(const double* num, const double* den, const double* act,
+                                                double sign, const T* x, T* y, int64_t N, int R) {
+  const int64_t idx = (int64_t)blockIdx.x * kMW + threadIdx.x;
+  if (idx >= N * R) return;
+  const int r = (int)(idx % R);
+  const double c = sign * ratio_or_zero_m(num[r], den[r]) * (act ? act[r] : 1.0);
+  y[idx] += T(c) * x[idx];
+}
+// y[i][r] = x[i][r] + sign num[r] / den[r] y[i][r]
+template <typename T>
+__global__ __launch_bounds__(kMW) void k_xpby_m(const T* x, const double* num, const double* den, double sign, T* y,
+                                                int64_t N, int R) {
+  const int64_t idx = (int64_t)blockIdx.x * kMW + threadIdx.x;
+  if (idx >= N * R) return;
+  const int r = (int)(idx % R);
+  y[idx] = x[idx] + T(sign * ratio_or_zero_m(num[r], den[r])) * y[idx];
+}
+// d.r of the new direction: s0 = s3 - (s2 / s1) s4 per column (sc = [5][R])
+__global__ void k_fcg_scalars_m(double* sc, int R) {
+  for (int r = threadIdx.x; r < R; r += blockDim.x)
+    sc[r] = sc[3 * R + r] - ratio_or_zero_m(sc[2 * R + r], sc[R + r]) * sc[4 * R + r];
+}
+
+hipError_t launch_axpy_m(Prec pr, const double* num, const double* den, const double* act, double sign,
+                         const void* x, void* y, int64_t N, int R, hipStream_t s) {
+  if (N * R == 0) return hipSuccess;
+  HDG_MDISPATCH_T(pr, hipLaunchKernelGGL(k_axpy_m<TT>, grid_m(N * R), dim3(kMW), 0, s, num, den, act, sign,
+                                         (const TT*)x, (TT*)y, N, R));
+  return hipGetLastError();
+}
+hipError_t launch_xpby_m(Prec pr, const void* x, const double* num, const double* den, double sign, void* y,
+                         int64_t N, int R, hipStream_t s) {
+  if (N * R == 0) return hipSuccess;
+  HDG_MDISPATCH_T(pr, hipLaunchKernelGGL(k_xpby_m<TT>, grid_m(N * R), dim3(kMW), 0, s, (const TT*)x, num, den, sign,
+                                         (TT*)y, N, R));
+  return hipGetLastError();
+}
+hipError_t launch_fcg_scalars_m(double* sc, int R, hipStream_t s) {
+  hipLaunchKernelGGL(k_fcg_scalars_m, dim3(1), dim3(256), 0, s, sc, R);
+  return hipGetLastError();
+}
+
+}  // namespace hdg
