@@ -63,6 +63,7 @@ struct MultiWork {
   double *vr = nullptr, *vz = nullptr, *vd = nullptr, *vq = nullptr;
   void *cva = nullptr, *cvb = nullptr;
   double *sc = nullptr, *nrm = nullptr, *nb = nullptr, *act = nullptr, *partial = nullptr;
+  std::vector<int> rc;   // chain solve: columns per workgroup, per p-level (autotuned)
   std::vector<void*> allocs;
   ~MultiWork() {
     for (void* q : allocs) (void)hipFree(q);
@@ -907,6 +908,53 @@ MultiWork& multi_work(hdg_ctx* h, int R) {
   W->sc = (double*)malloc_tracked(*W, 5 * (size_t)R * 8);
   for (double** v : {&W->nrm, &W->nb, &W->act}) *v = (double*)malloc_tracked(*W, (size_t)R * 8);
   W->partial = (double*)malloc_tracked(*W, (size_t)hdg::dots_m_grid((int64_t)Nk) * R * 8);
+  // columns per workgroup of the chain solve: time the powers of two up to the
+  // LDS limit on the level's scratch vectors (best of 2 after a warm-up) and keep
+  // the fastest; the chunking does not change any column's arithmetic
+  const size_t vbytes = hdg::vec_bytes(h->prec);
+  hipEvent_t e0, e1;
+  hipchk(hipEventCreate(&e0), "event");
+  hipchk(hipEventCreate(&e1), "event");
+  for (const PLevel& L : h->pl) {
+    const int rmax = hdg::chain_multi_chunk(L.P, h->n, R, vbytes);
+    int best_rc = rmax;
+    float best = 1e30f;
+    hipchk(hdg::launch_zero(h->prec, W->pr[L.p], L.N * R, h->stream), "zero");
+    for (int rc = 1; rc <= rmax; rc *= 2) {
+      hdg::ChainMultiArgs c{};
+      c.factors = L.chain;
+      c.cstride = L.cstride;
+      c.omega = L.omega;
+      c.n = h->n;
+      c.R = R;
+      c.rc = rc;
+      c.nchunks = (R + rc - 1) / rc;
+      c.r = W->pr[L.p];
+      c.x = nullptr;
+      c.out = W->px[L.p];
+      if (h->cfg.smoother != HDG_SMOOTH_CHAIN || hdg::launch_chain_solve_m(h->prec, L.P, c, h->stream) != hipSuccess) {
+        (void)hipGetLastError();
+        continue;
+      }
+      float t = 1e30f;
+      for (int rep = 0; rep < 2; ++rep) {
+        hipchk(hipEventRecord(e0, h->stream), "event");
+        hipchk(hdg::launch_chain_solve_m(h->prec, L.P, c, h->stream), "chain tune");
+        hipchk(hipEventRecord(e1, h->stream), "event");
+        hipchk(hipEventSynchronize(e1), "event sync");
+        float ms = 0.f;
+        hipchk(hipEventElapsedTime(&ms, e0, e1), "elapsed");
+        t = std::min(t, ms);
+      }
+      if (t < best) {
+        best = t;
+        best_rc = rc;
+      }
+    }
+    W->rc.push_back(best_rc);
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
   h->mw = std::move(W);
   return *h->mw;
 }
@@ -934,7 +982,7 @@ void smooth_m(hdg_ctx* h, MultiWork& W, int p, const void* b, void* x, int nu, b
     c.omega = L.omega;
     c.n = h->n;
     c.R = W.R;
-    c.rc = hdg::chain_multi_chunk(L.P, h->n, W.R, hdg::vec_bytes(pr));
+    c.rc = W.rc[p];
     c.nchunks = (W.R + c.rc - 1) / c.rc;
     c.out = x;
     if (z) {

@@ -180,6 +180,7 @@ struct ChainMultiArgs {
   int R;             // right-hand sides (row stride of r, x, out)
   int rc;            // right-hand sides per workgroup (chain_multi_chunk)
   int nchunks;       // ceil(R / rc)
+  int threads;       // workgroup size (0: smallest of 256, 512, 1024 that fits the items)
 };
 int chain_multi_chunk(int P, int n, int R, size_t elem_bytes);
 hipError_t launch_chain_solve_m(Prec pr, int P, const ChainMultiArgs& a, hipStream_t s);

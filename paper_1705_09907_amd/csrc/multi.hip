@@ -413,7 +413,7 @@ hipError_t launch_chain_solve_m(Prec pr, int P, const ChainMultiArgs& a, hipStre
   const size_t lds = (size_t)(a.n - 1) * P * a.rc * vec_bytes(pr);
   if (lds > 65536 || a.rc < 1 || a.nchunks * a.rc < a.R) return hipErrorInvalidValue;
   const int64_t bwd = (int64_t)((a.n - 1) / 2) * P * a.rc;
-  int threads = 256;
+  int threads = a.threads > 0 ? a.threads : 256;
   while (threads < 1024 && bwd > (int64_t)threads * kChainMaxResM) threads *= 2;
   if (bwd > (int64_t)threads * kChainMaxResM || P * a.rc > threads) return hipErrorInvalidValue;
   const dim3 grid((unsigned)(2LL * a.n * a.nchunks));
