@@ -15,7 +15,8 @@ from oracle import hdg, mg, mesh as ms, quadrature as qd  # noqa: E402
 from workloads import (SinSin, PolyProblem, kappa_lognormal, kappa_const,  # noqa: E402
                        normal_vector)
 
-CASES = [(2, 1, None), (16, 1, None), (24, 3, 1.0), (40, 4, 1.0), (64, 2, 2.0), (16, 0, 1.0)]
+CASES = [(2, 1, None), (16, 1, None), (24, 3, 1.0), (40, 4, 1.0), (64, 2, 2.0), (16, 0, 1.0),
+         (11, 6, 1.0), (9, 8, 1.0)]   # the highest degrees: P = 7 and P = 9
 
 
 def _kappa(n, sigma, seed=12):
@@ -124,7 +125,8 @@ def test_p_transfers(k):
         S.close()
 
 
-@pytest.mark.parametrize("n,k,sigma", [(16, 1, None), (24, 3, 1.0), (64, 2, 2.0), (16, 0, 1.0), (2, 1, None)])
+@pytest.mark.parametrize("n,k,sigma", [(16, 1, None), (24, 3, 1.0), (64, 2, 2.0), (16, 0, 1.0), (2, 1, None),
+                                       (10, 7, 1.0)])
 @pytest.mark.parametrize("smoother", ["face", "chain"])
 def test_vcycle_iterates(n, k, sigma, smoother):
     print(f"case vcycle {smoother} n={n} k={k}", flush=True)
