@@ -811,6 +811,21 @@ double estimate_face_lmax(hdg_ctx* h, int p, int steps) {
   return hi;
 }
 
+// A pair of timing events, destroyed on every exit path.
+struct EventPair {
+  hipEvent_t a = nullptr, b = nullptr;
+  EventPair() {
+    hipchk(hipEventCreate(&a), "event");
+    hipchk(hipEventCreate(&b), "event");
+  }
+  ~EventPair() {
+    if (a) (void)hipEventDestroy(a);
+    if (b) (void)hipEventDestroy(b);
+  }
+  EventPair(const EventPair&) = delete;
+  EventPair& operator=(const EventPair&) = delete;
+};
+
 // Autotuner of the chain Schwarz launch shape of level p: workgroup size,
 // XCD-aware chain order and LDS staging depth.  Every candidate solves each chain
 // with the same operations in the same order, so the choice changes the time
@@ -824,9 +839,8 @@ void tune_chain(hdg_ctx* h, int p) {
   const int64_t rhs_bytes = (int64_t)(h->n - 1) * L.P * (int64_t)es;
   const int lds_default = L.chain_lds_level;
   const int lds_staged = hdg::chain_lds_level(L.P, h->n, es, std::min<int64_t>(24576, 65536 - rhs_bytes));
-  hipEvent_t e0, e1;
-  hipchk(hipEventCreate(&e0), "event");
-  hipchk(hipEventCreate(&e1), "event");
+  EventPair ev;
+  hipEvent_t e0 = ev.a, e1 = ev.b;
   float best = 1e30f;
   int bt = 0, br = -1, bl = lds_default;
   const int64_t bwd = (int64_t)((h->n - 1) / 2) * L.P;
@@ -867,8 +881,6 @@ void tune_chain(hdg_ctx* h, int p) {
         }
       }
   }
-  (void)hipEventDestroy(e0);
-  (void)hipEventDestroy(e1);
   L.chain_threads = bt;
   L.chain_remap = br;
   L.chain_lds_level = bl;
@@ -912,9 +924,8 @@ MultiWork& multi_work(hdg_ctx* h, int R) {
   // LDS limit on the level's scratch vectors (best of 2 after a warm-up) and keep
   // the fastest; the chunking does not change any column's arithmetic
   const size_t vbytes = hdg::vec_bytes(h->prec);
-  hipEvent_t e0, e1;
-  hipchk(hipEventCreate(&e0), "event");
-  hipchk(hipEventCreate(&e1), "event");
+  EventPair ev;
+  hipEvent_t e0 = ev.a, e1 = ev.b;
   for (const PLevel& L : h->pl) {
     const int rmax = hdg::chain_multi_chunk(L.P, h->n, R, vbytes);
     int best_rc = rmax;
@@ -953,8 +964,6 @@ MultiWork& multi_work(hdg_ctx* h, int R) {
     }
     W->rc.push_back(best_rc);
   }
-  (void)hipEventDestroy(e0);
-  (void)hipEventDestroy(e1);
   h->mw = std::move(W);
   return *h->mw;
 }
