@@ -288,7 +288,10 @@ void build_face_data(hdg_ctx* h, PLevel& L, const Vec& blocks) {
   }
   // chain Schwarz: block cyclic reduction factors of every chain of faces
   // (the chain matrices are SPD principal submatrices of S, so every pivot
-  // block met by the reduction is SPD).
+  // block met by the reduction is SPD).  Only the odd positions' records
+  // [Dinv, W = Dinv A, Z = Dinv C] are stored: by the symmetry of every reduced
+  // matrix (A_j = C_{j-1}^T), the even positions' multipliers are
+  // M-_j = A_j Dinv_{j-1} = Z_{j-1}^T and M+_j = C_j Dinv_{j+1} = W_{j+1}^T.
   const int64_t nch = 2LL * n, nv = (int64_t)n * (n - 1);
   const int m = n - 1;
   std::vector<int> msz;
@@ -300,7 +303,7 @@ void build_face_data(hdg_ctx* h, PLevel& L, const Vec& blocks) {
   int64_t tot = 0;
   for (int s : msz) {
     loff.push_back(tot);
-    tot += s == 1 ? (int64_t)P2 : (int64_t)2 * P2 * ((s + 1) / 2) + (int64_t)3 * P2 * (s / 2);
+    tot += s == 1 ? (int64_t)P2 : (int64_t)3 * P2 * (s / 2);
   }
   L.cstride = tot;
   Vec fac((size_t)(nch * L.cstride), 0.0);
@@ -338,8 +341,8 @@ void build_face_data(hdg_ctx* h, PLevel& L, const Vec& blocks) {
           std::copy(Di.begin(), Di.end(), lvl);
           break;
         }
-        const int ne = (ml + 1) / 2, no = ml / 2;
-        double* odd = lvl + (size_t)2 * P2 * ne;
+        const int no = ml / 2;
+        double* odd = lvl;
         Vec Dinv((size_t)ml * P2, 0.0);
         for (int j = 1; j < ml; j += 2) {
           Vec Di(D.begin() + (size_t)j * P2, D.begin() + (size_t)(j + 1) * P2);
@@ -376,11 +379,6 @@ void build_face_data(hdg_ctx* h, PLevel& L, const Vec& blocks) {
             for (int e = 0; e < P2; ++e) Dj[e] -= T[e];
             mul(Mp.data(), C.data() + (size_t)(j + 1) * P2, T.data());
             for (int e = 0; e < P2; ++e) Cn[(size_t)(j / 2) * P2 + e] = -T[e];
-          }
-          const int ev = j / 2;
-          for (int e = 0; e < P2; ++e) {
-            lvl[(size_t)e * ne + ev] = Mm[e];
-            lvl[(size_t)(P2 + e) * ne + ev] = Mp[e];
           }
         }
         A.swap(An);

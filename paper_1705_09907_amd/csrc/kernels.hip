@@ -574,12 +574,20 @@ hipError_t launch_p_prolong_add(Prec pr, int P, const void* pm, const void* ec, 
 //   forward   r_j <- r_j - M-_j r_{j-1} - M+_j r_{j+1}           (j even)
 //   last      x_0 = Dinv r_0
 //   backward  x_j = Dinv_j r_j - W_j x_{j-1} - Z_j x_{j+1}        (j odd)
-// with W = Dinv A, Z = Dinv C.  Work item = (position, row): it streams one
-// row of the position's blocks.  Factors of a level of size ml: the even
-// records [M-, M+] as 2 P^2 arrays over the ne = ceil(ml/2) even positions,
-// then the odd records [Dinv, W, Z] as 3 P^2 arrays over the no = floor(ml/2)
-// odd positions (entry-major, so a wavefront reads consecutive addresses); the
-// last level stores Dinv of its single block.
+// with W = Dinv A, Z = Dinv C.  Every reduced matrix is symmetric, so the
+// even positions' multipliers need no storage of their own: M-_j = Z_{j-1}^T
+// and M+_j = W_{j+1}^T.  Work item = (position, row): it streams one row of
+// its blocks (a column of W or Z for the forward reduction).  Factors of a
+// level of size ml: the odd records [Dinv, W, Z] as 3 P^2 arrays over the
+// no = floor(ml/2) odd positions (entry-major, so a wavefront reads
+// consecutive addresses); the last level stores Dinv of its single block.
+// The right-hand side in LDS is ordered by level too: a position whose odd
+// index at level l is o (position (2o+1) 2^l) sits in level l's array
+// [row][o] of floor(ml_l/2) columns, at word P (m - ml_l) + o + row floor(ml_l/2)
+// (the arrays of the levels before l hold m - ml_l positions); position 0
+// takes the last P words.  Every phase then reads and writes its operands at
+// unit stride across a wavefront, where the position-major order had lanes
+// 2^(l+1) P words apart and serialised the LDS banks.
 // The reduction has 2 log2(n) dependent phases, so the kernel is bound by the
 // latency of each phase's factor loads, not by bandwidth.  The factors of the
 // small levels l >= a.lds_level (a few KiB) are copied to LDS together with the
@@ -618,10 +626,22 @@ __global__ __launch_bounds__(1024) void k_chain(ChainArgs a) {
   const T* F = static_cast<const T*>(a.factors) + c * a.cstride;
   const int t = threadIdx.x;
   const int nt = blockDim.x;
+  // LDS word of row 0 of position pos of level l, and the row stride
+  auto slot = [m](int l, int pos, int& rs) -> int {
+    if (pos == 0) {
+      rs = 1;
+      return P * (m - 1);
+    }
+    const int z = __builtin_ctz((unsigned)pos);
+    const int lv = l + z;
+    const int mlv = (m + (1 << lv) - 1) >> lv;
+    rs = mlv >> 1;
+    return P * (m - mlv) + (pos >> (z + 1));
+  };
   auto level_offset = [&](int l) {
     int64_t lo = 0;
     for (int q = 0, s = m; q < l; ++q, s = (s + 1) >> 1)
-      lo += (int64_t)2 * P2 * ((s + 1) >> 1) + (int64_t)3 * P2 * (s >> 1);
+      lo += (int64_t)3 * P2 * (s >> 1);
     return lo;
   };
   const int Ls = a.lds_level;
@@ -641,8 +661,15 @@ __global__ __launch_bounds__(1024) void k_chain(ChainArgs a) {
       }
     }
 #pragma unroll
-    for (int u = 0; u < CB; ++u)
-      if (b0 + u * nt < m * P) R[b0 + u * nt] = v[u];
+    for (int u = 0; u < CB; ++u) {
+      const int idx = b0 + u * nt;
+      if (idx < m * P) {
+        const int i = idx / P, r = idx - i * P;
+        int rs;
+        const int w = slot(0, i, rs);
+        R[w + r * rs] = v[u];
+      }
+    }
   }
   const int64_t tail_len = a.cstride - tail_off;
   for (int64_t b0 = t; b0 < tail_len; b0 += (int64_t)nt * CB) {
@@ -658,7 +685,10 @@ __global__ __launch_bounds__(1024) void k_chain(ChainArgs a) {
   auto lvl = [&](int l, int64_t off_l) -> const T* { return l >= Ls ? TL + (off_l - tail_off) : F + off_l; };
   // ---- forward reduction
   T pm[KB][P], pp[KB][P];
-  auto load_fwd = [&](const T* E, int ne, int c0) {
+  // row r of M-_j and M+_j of even position j = 2 tt: column r of Z at odd
+  // index tt - 1 and of W at odd index tt
+  auto load_fwd = [&](const T* O, int ml_, int c0) {
+    const int ne = (ml_ + 1) >> 1, no = ml_ >> 1;
 #pragma unroll
     for (int kk = 0; kk < KB; ++kk) {
       const int it = c0 + kk * nt;
@@ -666,63 +696,65 @@ __global__ __launch_bounds__(1024) void k_chain(ChainArgs a) {
         const int r = it / ne, tt = it - r * ne;
 #pragma unroll
         for (int q = 0; q < P; ++q) {
-          pm[kk][q] = E[(int64_t)(r * P + q) * ne + tt];
-          pp[kk][q] = E[(int64_t)(P2 + r * P + q) * ne + tt];
+          pm[kk][q] = tt >= 1 ? O[(int64_t)(2 * P2 + q * P + r) * no + tt - 1] : T(0);
+          pp[kk][q] = tt < no ? O[(int64_t)(P2 + q * P + r) * no + tt] : T(0);
         }
       }
     }
   };
   int ml = m, lev = 0;
   int64_t off = 0;
-  if (ml > 1) load_fwd(lvl(0, 0), (ml + 1) >> 1, t);
+  if (ml > 1) load_fwd(lvl(0, 0), ml, t);
   while (ml > 1) {
     const int ne = (ml + 1) >> 1;
     const T* E = lvl(lev, off);
     for (int c0 = t; c0 < ne * P; c0 += nt * KB) {
-      if (c0 != t) load_fwd(E, ne, c0);
+      if (c0 != t) load_fwd(E, ml, c0);
 #pragma unroll
       for (int kk = 0; kk < KB; ++kk) {
         const int it = c0 + kk * nt;
         if (it < ne * P) {
           const int r = it / ne, tt = it - r * ne;
           const int j = 2 * tt;
-          const int i = j << lev;
-          T v = R[i * P + r];
+          const int no = ml >> 1;
+          const int ob = P * (m - ml);  // level lev's odd positions: [row][o]
+          int rs;
+          const int w = slot(lev + 1, tt, rs) + r * rs;
+          T v = R[w];
           if (j >= 1) {
-            const int il = (j - 1) << lev;
 #pragma unroll
-            for (int q = 0; q < P; ++q) v -= pm[kk][q] * R[il * P + q];
+            for (int q = 0; q < P; ++q) v -= pm[kk][q] * R[ob + q * no + tt - 1];
           }
           if (j + 1 < ml) {
-            const int ir = (j + 1) << lev;
 #pragma unroll
-            for (int q = 0; q < P; ++q) v -= pp[kk][q] * R[ir * P + q];
+            for (int q = 0; q < P; ++q) v -= pp[kk][q] * R[ob + q * no + tt];
           }
-          R[i * P + r] = v;
+          R[w] = v;
         }
       }
     }
-    off += (int64_t)2 * P2 * ne + (int64_t)3 * P2 * (ml >> 1);
+    off += (int64_t)3 * P2 * (ml >> 1);
     ml = ne;
     ++lev;
-    if (ml > 1) load_fwd(lvl(lev, off), (ml + 1) >> 1, t);
+    if (ml > 1) load_fwd(lvl(lev, off), ml, t);
     __syncthreads();
   }
   T xr = T(0);
+  const int top = P * (m - 1);
   if (t < P) {
     const T* D = lvl(lev, off);
 #pragma unroll
-    for (int q = 0; q < P; ++q) xr += D[t * P + q] * R[q];
+    for (int q = 0; q < P; ++q) xr += D[t * P + q] * R[top + q];
   }
   __syncthreads();
-  if (t < P) R[t] = xr;
+  if (t < P) R[top + t] = xr;
   __syncthreads();
   // ---- back substitution: values of all items first, then a barrier, then writes
   T od[KB][P], ow[KB][P], oz[KB][P];
   auto load_bwd = [&](int l, int c0) {
     const int mlv = (m + (1 << l) - 1) >> l;
-    const int ne = (mlv + 1) >> 1, no = mlv >> 1;
-    const T* O = lvl(l, level_offset(l)) + (int64_t)2 * P2 * ne;
+    const int no = mlv >> 1;
+    const T* O = lvl(l, level_offset(l));
 #pragma unroll
     for (int kk = 0; kk < KB; ++kk) {
       const int it = c0 + kk * nt;
@@ -753,12 +785,15 @@ __global__ __launch_bounds__(1024) void k_chain(ChainArgs a) {
         if (it < no * P && cnt < kChainMaxRes) {
           const int r = it / no, tt = it - r * no;
           const int j = 2 * tt + 1;
-          const int i = j << lev;
-          const int il = (j - 1) << lev;
-          const int ir = (j + 1 < ml) ? ((j + 1) << lev) : il;  // oz = 0 when there is no right neighbour
+          const int ob = P * (m - ml) + tt;  // own right-hand side, row stride no
+          int rl, rr;
+          const int wl = slot(lev + 1, tt, rl);
+          // oz = 0 when there is no right neighbour: reuse the left one
+          const int wr = (j + 1 < ml) ? slot(lev + 1, tt + 1, rr) : (rr = rl, wl);
           T s = T(0);
 #pragma unroll
-          for (int q = 0; q < P; ++q) s += od[kk][q] * R[i * P + q] - ow[kk][q] * R[il * P + q] - oz[kk][q] * R[ir * P + q];
+          for (int q = 0; q < P; ++q)
+            s += od[kk][q] * R[ob + q * no] - ow[kk][q] * R[wl + q * rl] - oz[kk][q] * R[wr + q * rr];
           res[cnt++] = s;
         }
       }
@@ -768,7 +803,7 @@ __global__ __launch_bounds__(1024) void k_chain(ChainArgs a) {
     cnt = 0;
     for (int it = t; it < no * P && cnt < kChainMaxRes; it += nt, ++cnt) {
       const int r = it / no, tt = it - r * no;
-      R[((2 * tt + 1) << lev) * P + r] = res[cnt];
+      R[P * (m - ml) + tt + r * no] = res[cnt];
     }
     __syncthreads();
   }
@@ -785,8 +820,15 @@ __global__ __launch_bounds__(1024) void k_chain(ChainArgs a) {
       }
     }
 #pragma unroll
-    for (int u = 0; u < CB; ++u)
-      if (b0 + u * nt < m * P) out[g[u]] = v[u] + T(a.omega) * R[b0 + u * nt];
+    for (int u = 0; u < CB; ++u) {
+      const int idx = b0 + u * nt;
+      if (idx < m * P) {
+        const int i = idx / P, r = idx - i * P;
+        int rs;
+        const int w = slot(0, i, rs);
+        out[g[u]] = v[u] + T(a.omega) * R[w + r * rs];
+      }
+    }
   }
 }
 
@@ -795,7 +837,7 @@ static int64_t chain_tail_bytes(int P, int n, int l, size_t es) {
   int64_t tot = 0;
   int q = 0;
   for (int s = n - 1;; s = (s + 1) >> 1, ++q) {
-    const int64_t rec = s == 1 ? (int64_t)P * P : (int64_t)2 * P * P * ((s + 1) >> 1) + (int64_t)3 * P * P * (s >> 1);
+    const int64_t rec = s == 1 ? (int64_t)P * P : (int64_t)3 * P * P * (s >> 1);
     if (q >= l) tot += rec;
     if (s == 1) break;
   }

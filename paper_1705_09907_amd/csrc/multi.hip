@@ -311,17 +311,18 @@ __global__ __launch_bounds__(1024) void k_chain_m(ChainMultiArgs a) {
   int ml = m, lev = 0;
   int64_t off = 0;
   while (ml > 1) {
-    const int ne = (ml + 1) >> 1;
-    const T* E = F + off;
+    const int ne = (ml + 1) >> 1, no = ml >> 1;
+    const T* O = F + off;
     for (int it = t; it < ne * P; it += nt) {
       const int row = it / ne, tt = it - row * ne;
       const int j = 2 * tt;
       const int i = j << lev;
+      // M-_j = Z_{j-1}^T, M+_j = W_{j+1}^T (odd indices tt - 1 and tt)
       T pm[P], pp[P];
 #pragma unroll
       for (int q = 0; q < P; ++q) {
-        pm[q] = E[(int64_t)(row * P + q) * ne + tt];
-        pp[q] = E[(int64_t)(P2 + row * P + q) * ne + tt];
+        pm[q] = tt >= 1 ? O[(int64_t)(2 * P2 + q * P + row) * no + tt - 1] : T(0);
+        pp[q] = tt < no ? O[(int64_t)(P2 + q * P + row) * no + tt] : T(0);
       }
       for (int q0 = 0; q0 < RC; ++q0) {
         T v = Rl[(i * P + row) * RC + q0];
@@ -338,7 +339,7 @@ __global__ __launch_bounds__(1024) void k_chain_m(ChainMultiArgs a) {
         Rl[(i * P + row) * RC + q0] = v;
       }
     }
-    off += (int64_t)2 * P2 * ne + (int64_t)3 * P2 * (ml >> 1);
+    off += (int64_t)3 * P2 * no;
     ml = ne;
     ++lev;
     __syncthreads();
@@ -357,11 +358,10 @@ __global__ __launch_bounds__(1024) void k_chain_m(ChainMultiArgs a) {
   while (lev > 0) {
     --lev;
     ml = (m + (1 << lev) - 1) >> lev;
-    const int ne = (ml + 1) >> 1, no = ml >> 1;
+    const int no = ml >> 1;
     int64_t lo = 0;
-    for (int l = 0, s = m; l < lev; ++l, s = (s + 1) >> 1)
-      lo += (int64_t)2 * P2 * ((s + 1) >> 1) + (int64_t)3 * P2 * (s >> 1);
-    const T* O = F + lo + (int64_t)2 * P2 * ne;
+    for (int l = 0, s = m; l < lev; ++l, s = (s + 1) >> 1) lo += (int64_t)3 * P2 * (s >> 1);
+    const T* O = F + lo;
     // values of all (item, right-hand side) pairs first, then a barrier, then writes
     T res[kChainMaxResM];
     int cnt = 0;
