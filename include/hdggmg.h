@@ -76,7 +76,9 @@ typedef struct {
   int32_t nu1, nu2;     /* pre/post smoothing steps per level (Sec. 7 uses 2, 2)           */
   int32_t smoother;     /* HDG_SMOOTH_CHAIN: additive Schwarz with one subdomain per chain
                            of faces (vertical faces of an element row / horizontal faces
-                           of an element column); HDG_SMOOTH_FACE: one subdomain per facet
+                           of an element column), solved in LDS: needs
+                           ((n-1)(k+1) + (k+1)^2) * (8 bytes FP64, 4 otherwise) <= 65536;
+                           HDG_SMOOTH_FACE: one subdomain per facet
                            (Sec. 6, additive Schwarz relaxation, zero overlap)           */
   int32_t coarse;       /* p-level coarse operators: HDG_COARSE_GALERKIN (element-wise
                            P^T K P) or HDG_COARSE_REDISCRETIZE (degree-p HDG, Sec. 6)     */
@@ -231,7 +233,14 @@ hdg_status_t hdg_vcycle(hdg_handle_t h, const double* b, double* x);
  * then returns INVALID_ARG) or HDG_SOLVE_VCYCLE (repeated cycles, the paper's
  * stationary solver, applied as x += B (b - S x)).  iters, relres: host outputs (nullable); history_host: nullable
  * [maxit + 1] residual norms (entry 0 = initial).  Returns NOT_CONVERGED if
- * maxit is reached (outputs still valid), NONFINITE on NaN/Inf. */
+ * maxit is reached (outputs still valid), NONFINITE on NaN/Inf.
+ * Residual norms: entry 0 and every VCYCLE entry is ||b - S x|| computed from
+ * x; PCG and FCG use the recursively updated residual r <- r - alpha S d (the
+ * usual Krylov stopping test), which drifts from b - S x by rounding.  The
+ * computed b - S x cannot fall below about eps || |S| |x| ||_2 (rounding of
+ * S x itself); with high coefficient contrast and a smooth right-hand side that
+ * floor can exceed rtol ||b|| while the recursive norm goes below it.
+ * hdg_residual gives the true residual of the returned x. */
 hdg_status_t hdg_solve(hdg_handle_t h, const double* b, double* x, double rtol, int32_t maxit,
                        int32_t mode, int32_t* iters, double* relres, double* history_host);
 
@@ -243,7 +252,8 @@ hdg_status_t hdg_solve(hdg_handle_t h, const double* b, double* x, double rtol, 
  * column); the FP64 operator, residuals and updates are kept for the outer
  * iteration.  Chain smoother only (STATE otherwise); Krylov acceleration of
  * coarse levels (inner_steps) is not used here.  A column stops updating once
- * ||b - S x||_2 <= rtol ||b||_2.  iters_host, relres_host: nullable [nrhs].
+ * its recursively updated residual norm is <= rtol ||b||_2 (see hdg_solve).
+ * iters_host, relres_host: nullable [nrhs].
  * NOT_CONVERGED if some column reached maxit (outputs still valid). */
 hdg_status_t hdg_solve_multi(hdg_handle_t h, int32_t nrhs, const double* B, double* X, double rtol, int32_t maxit,
                              int32_t* iters_host, double* relres_host);

@@ -841,9 +841,8 @@ void tune_chain(hdg_ctx* h, int p) {
   hipEvent_t e0 = ev.a, e1 = ev.b;
   float best = 1e30f;
   int bt = 0, br = -1, bl = lds_default;
-  const int64_t bwd = (int64_t)((h->n - 1) / 2) * L.P;
   for (int th : {64, 128, 256, 512, 1024}) {
-    if (bwd > (int64_t)th * 8) continue;
+    if (th > hdg::chain_max_threads(L.P)) continue;
     for (int rm : {0, 1})
       for (int ll : {lds_default, lds_staged, 64}) {
         hdg::ChainArgs c{};
@@ -1109,9 +1108,9 @@ void validate_config(const hdg_config_t* c) {
     if (p >= c->k && c->inner_steps[p] != 0) throw ArgError("inner_steps[p] must be 0 for p >= k");
   }
   const int64_t vb = c->precision == HDG_PREC_F64 ? 8 : 4;
-  if (c->smoother == HDG_SMOOTH_CHAIN && (int64_t)(c->n - 1) * (c->k + 1) * vb > 65536)
-    throw ArgError("chain smoother keeps one chain in LDS: needs (n-1)(k+1) * (8 bytes FP64, 4 bytes "
-                   "otherwise) <= 65536; use the face smoother or a reduced precision");
+  if (c->smoother == HDG_SMOOTH_CHAIN && ((int64_t)(c->n - 1) * (c->k + 1) + (int64_t)(c->k + 1) * (c->k + 1)) * vb > 65536)
+    throw ArgError("chain smoother keeps one chain and one block in LDS: needs ((n-1)(k+1) + (k+1)^2) * "
+                   "(8 bytes FP64, 4 bytes otherwise) <= 65536; use the face smoother or a reduced precision");
   if (c->smoother == HDG_SMOOTH_FACE && c->precision != HDG_PREC_F64)
     for (int p = 0; p <= c->k; ++p)
       if (!(c->omega[p] > 0)) throw ArgError("facet smoother in reduced precision needs omega[p] > 0 for every p");

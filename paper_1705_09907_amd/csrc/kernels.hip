@@ -588,23 +588,47 @@ hipError_t launch_p_prolong_add(Prec pr, int P, const void* pm, const void* ec, 
 // takes the last P words.  Every phase then reads and writes its operands at
 // unit stride across a wavefront, where the position-major order had lanes
 // 2^(l+1) P words apart and serialised the LDS banks.
-// The reduction has 2 log2(n) dependent phases, so the kernel is bound by the
-// latency of each phase's factor loads, not by bandwidth.  The factors of the
-// small levels l >= a.lds_level (a few KiB) are copied to LDS together with the
-// right-hand side, so only the first lds_level levels of each sweep wait on
-// HBM; there a thread issues the loads of a batch of KB items before using any
-// of them, and loads the first batch of the next level before the barrier that
-// ends the current one.
+// The reduction has 2 log2(n) dependent phases.  Work item = (position, block
+// of RB rows): a thread loads the item's factor rows once, reads the position's
+// neighbours from LDS once and updates RB rows, so the index arithmetic of an
+// item is shared by its P RB multiply-adds.  The factors of the small levels
+// l >= a.lds_level (a few KiB) are copied to LDS together with the right-hand
+// side, so only the first lds_level levels of each sweep wait on HBM; there a
+// thread issues the loads of a batch of KB positions before using any of them,
+// and loads the first batch of the next level before the barrier that ends the
+// current one.
 template <int P>
-struct ChainBatch {  // items whose factor rows a thread keeps in flight
-  static constexpr int KB = P <= 1 ? 8 : (P <= 2 ? 4 : (P <= 4 ? 2 : 1));
+struct ChainShape {
+  // Rows per item (RBF forward, RBB backward) and positions whose loads are in
+  // flight together (KBF, KBB): a batch holds KBF RBF 2P forward or KBB RBB 3P
+  // backward factor entries, at most 32 and 27 doubles.
+  static constexpr int RBF = P <= 4 ? P : (P <= 5 ? 3 : (P <= 8 ? 2 : 1));
+  static constexpr int RBB = P <= 3 ? P : (P <= 4 ? 2 : 1);
+  static constexpr int NRBF = (P + RBF - 1) / RBF;
+  static constexpr int NRBB = (P + RBB - 1) / RBB;
+  static constexpr int KBF = P <= 1 ? 8 : (P <= 2 ? 4 : 1);
+  static constexpr int KBB = P <= 1 ? 8 : (P <= 2 ? 2 : 1);
+  // positions per thread in the back substitution, whose results wait in
+  // registers for the barrier: the launcher keeps floor((n-1)/2) <= threads MAXPOS
+  static constexpr int MAXPOS = P <= 1 ? 8 : (P <= 3 ? 4 : 2);
+  static constexpr int MAXT = P <= 4 ? 1024 : 512;  // workgroup size bound (registers)
 };
-static constexpr int kChainMaxRes = 8;  // backward items per thread (launcher bound)
+
+// Workgroup barrier that orders LDS accesses only: global loads issued before it
+// (the prefetched factors of the next level) stay in flight across it, where
+// __syncthreads() would wait for them.  For kernels whose waves never read
+// global memory written by another wave of the workgroup.
+__device__ __forceinline__ void lds_barrier() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup", "local");
+  __builtin_amdgcn_s_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
+}
 
 template <int P, typename T>
-__global__ __launch_bounds__(1024) void k_chain(ChainArgs a) {
+__global__ __launch_bounds__(ChainShape<P>::MAXT) void k_chain(ChainArgs a) {
   constexpr int P2 = P * P;
-  constexpr int KB = ChainBatch<P>::KB;
+  using CS = ChainShape<P>;
+  constexpr int MAXPOS = CS::MAXPOS;
   extern __shared__ unsigned char lds_raw[];
   T* R = reinterpret_cast<T*>(lds_raw);
   const T* rin = static_cast<const T*>(a.r);
@@ -644,33 +668,37 @@ __global__ __launch_bounds__(1024) void k_chain(ChainArgs a) {
       lo += (int64_t)3 * P2 * (s >> 1);
     return lo;
   };
-  const int Ls = a.lds_level;
+  int Lf = 0;  // index of the last level (a single block)
+  for (int s = m; s > 1; s = (s + 1) >> 1) ++Lf;
+  const int Ls = a.lds_level < Lf ? a.lds_level : Lf;  // the last level is always staged
   const int64_t tail_off = level_offset(Ls);
   T* TL = R + m * P;  // LDS copy of the factors of levels >= Ls
-  // copies to LDS keep 8 loads per thread in flight (a load-store loop would
-  // wait for every load before the next one is issued)
-  constexpr int CB = 8;
-  for (int b0 = t; b0 < m * P; b0 += nt * CB) {
-    T v[CB];
+  // copies to LDS keep about 8 loads per thread in flight (a load-store loop
+  // would wait for every load before the next one is issued)
+  constexpr int CBP = P >= 8 ? 1 : 8 / P;
+  for (int i0 = t; i0 < m; i0 += nt * CBP) {
+    T v[CBP][P];
 #pragma unroll
-    for (int u = 0; u < CB; ++u) {
-      const int idx = b0 + u * nt;
-      if (idx < m * P) {
-        const int i = idx / P, r = idx - i * P;
-        v[u] = rin[(base + stride * i) * P + r];
+    for (int u = 0; u < CBP; ++u) {
+      const int i = i0 + u * nt;
+      if (i < m) {
+        const T* src = rin + (base + stride * i) * P;
+#pragma unroll
+        for (int r = 0; r < P; ++r) v[u][r] = src[r];
       }
     }
 #pragma unroll
-    for (int u = 0; u < CB; ++u) {
-      const int idx = b0 + u * nt;
-      if (idx < m * P) {
-        const int i = idx / P, r = idx - i * P;
+    for (int u = 0; u < CBP; ++u) {
+      const int i = i0 + u * nt;
+      if (i < m) {
         int rs;
         const int w = slot(0, i, rs);
-        R[w + r * rs] = v[u];
+#pragma unroll
+        for (int r = 0; r < P; ++r) R[w + r * rs] = v[u][r];
       }
     }
   }
+  constexpr int CB = 8;
   const int64_t tail_len = a.cstride - tail_off;
   for (int64_t b0 = t; b0 < tail_len; b0 += (int64_t)nt * CB) {
     T v[CB];
@@ -681,164 +709,311 @@ __global__ __launch_bounds__(1024) void k_chain(ChainArgs a) {
     for (int u = 0; u < CB; ++u)
       if (b0 + u * nt < tail_len) TL[b0 + u * nt] = v[u];
   }
-  __syncthreads();
-  auto lvl = [&](int l, int64_t off_l) -> const T* { return l >= Ls ? TL + (off_l - tail_off) : F + off_l; };
-  // ---- forward reduction
-  T pm[KB][P], pp[KB][P];
-  // row r of M-_j and M+_j of even position j = 2 tt: column r of Z at odd
-  // index tt - 1 and of W at odd index tt
-  auto load_fwd = [&](const T* O, int ml_, int c0) {
-    const int ne = (ml_ + 1) >> 1, no = ml_ >> 1;
+  lds_barrier();
+  // Factors of level l come from HBM (l < Ls: loaded in register batches, the
+  // first batch of a level before the barrier that ends the previous one) or
+  // from LDS (l >= Ls: read where they are used).  The two never share a
+  // pointer, so the compiler emits global or LDS loads rather than flat ones.
+  // ---- forward reduction.  Rows r of M-_j and M+_j (j = 2 tt): column r of Z
+  // at odd index tt - 1 and of W at odd index tt.
+  constexpr int KB = CS::KBF, RB = CS::RBF, NRB = CS::NRBF;
+  T zm[KB][RB][P], wp[KB][RB][P];
+  // Loads are unconditional, at indices clamped into the level's arrays (whose
+  // entries are all finite), and masked afterwards: a load under a branch makes
+  // the compiler wait for it before the branch joins.
+  auto load_fwd = [&](const T* O, int ml_, int rb, int c0) __attribute__((always_inline)) {
+    const int ne_ = (ml_ + 1) >> 1, no_ = ml_ >> 1;  // no_ >= 1
 #pragma unroll
     for (int kk = 0; kk < KB; ++kk) {
-      const int it = c0 + kk * nt;
-      if (it < ne * P) {
-        const int r = it / ne, tt = it - r * ne;
+      const int tt = c0 + kk * nt;
+      const unsigned zi = (unsigned)min(max(tt - 1, 0), no_ - 1), wi = (unsigned)min(tt, no_ - 1);
+      const bool zok = tt >= 1 && tt < ne_, wok = tt < no_;
+#pragma unroll
+      for (int rr = 0; rr < RB; ++rr) {
+        const int r = rb * RB + rr;
 #pragma unroll
         for (int q = 0; q < P; ++q) {
-          pm[kk][q] = tt >= 1 ? O[(int64_t)(2 * P2 + q * P + r) * no + tt - 1] : T(0);
-          pp[kk][q] = tt < no ? O[(int64_t)(P2 + q * P + r) * no + tt] : T(0);
+          if (r < P) {  // resolved at compile time
+            const T z = O[(int64_t)(2 * P2 + q * P + r) * no_ + zi];
+            const T w = O[(int64_t)(P2 + q * P + r) * no_ + wi];
+            zm[kk][rr][q] = zok ? z : T(0);
+            wp[kk][rr][q] = wok ? w : T(0);
+          } else {
+            zm[kk][rr][q] = wp[kk][rr][q] = T(0);
+          }
+        }
+      }
+    }
+  };
+  auto fwd_compute = [&](int ml_, int lev_, int rb, int c0) __attribute__((always_inline)) {
+    const int ne_ = (ml_ + 1) >> 1, no_ = ml_ >> 1;
+    const int ob = P * (m - ml_);  // level lev_'s odd positions: [row][o]
+#pragma unroll
+    for (int kk = 0; kk < KB; ++kk) {
+      const int tt = c0 + kk * nt;
+      if (tt < ne_) {
+        T lv[P], rv[P];
+        const int li = max(tt - 1, 0), ri = min(tt, no_ - 1);
+#pragma unroll
+        for (int q = 0; q < P; ++q) {
+          const T x = R[ob + q * no_ + li], y = R[ob + q * no_ + ri];
+          lv[q] = tt >= 1 ? x : T(0);
+          rv[q] = tt < no_ ? y : T(0);
+        }
+        int rs;
+        const int w = slot(lev_ + 1, tt, rs);
+#pragma unroll
+        for (int rr = 0; rr < RB; ++rr) {
+          const int r = rb * RB + rr;
+          if (r < P) {
+            T v = R[w + r * rs];
+#pragma unroll
+            for (int q = 0; q < P; ++q) v -= zm[kk][rr][q] * lv[q] + wp[kk][rr][q] * rv[q];
+            R[w + r * rs] = v;
+          }
         }
       }
     }
   };
   int ml = m, lev = 0;
   int64_t off = 0;
-  if (ml > 1) load_fwd(lvl(0, 0), ml, t);
-  while (ml > 1) {
-    const int ne = (ml + 1) >> 1;
-    const T* E = lvl(lev, off);
-    for (int c0 = t; c0 < ne * P; c0 += nt * KB) {
-      if (c0 != t) load_fwd(E, ml, c0);
+  // forward level with factors in LDS: one position (all rows) per item
+  auto fwd_level_lds = [&](const T* O) __attribute__((always_inline)) {
+    const int ne_ = (ml + 1) >> 1, no_ = ml >> 1;
+    const int ob = P * (m - ml);
+    for (int tt = t; tt < ne_; tt += nt) {
+      T lv[P], rv[P];
+      const int li = max(tt - 1, 0), ri = min(tt, no_ - 1);
 #pragma unroll
-      for (int kk = 0; kk < KB; ++kk) {
-        const int it = c0 + kk * nt;
-        if (it < ne * P) {
-          const int r = it / ne, tt = it - r * ne;
-          const int j = 2 * tt;
-          const int no = ml >> 1;
-          const int ob = P * (m - ml);  // level lev's odd positions: [row][o]
-          int rs;
-          const int w = slot(lev + 1, tt, rs) + r * rs;
-          T v = R[w];
-          if (j >= 1) {
+      for (int q = 0; q < P; ++q) {
+        const T x = R[ob + q * no_ + li], y = R[ob + q * no_ + ri];
+        lv[q] = tt >= 1 ? x : T(0);  // a missing neighbour contributes 0 times a finite factor
+        rv[q] = tt < no_ ? y : T(0);
+      }
+      int rs;
+      const int w = slot(lev + 1, tt, rs);
 #pragma unroll
-            for (int q = 0; q < P; ++q) v -= pm[kk][q] * R[ob + q * no + tt - 1];
-          }
-          if (j + 1 < ml) {
+      for (int r = 0; r < P; ++r) {
+        T v = R[w + r * rs];
 #pragma unroll
-            for (int q = 0; q < P; ++q) v -= pp[kk][q] * R[ob + q * no + tt];
-          }
-          R[w] = v;
-        }
+        for (int q = 0; q < P; ++q)
+          v -= O[(2 * P2 + q * P + r) * no_ + li] * lv[q] + O[(P2 + q * P + r) * no_ + ri] * rv[q];
+        R[w + r * rs] = v;
       }
     }
+  };
+  // levels in HBM, then levels in LDS
+  if (ml > 1 && Ls > 0) load_fwd(F, ml, 0, t);
+  while (ml > 1 && lev < Ls) {
+    const T* O = F + off;
+    const int ne = (ml + 1) >> 1;
+    bool first = true;
+#pragma unroll
+    for (int rb = 0; rb < NRB; ++rb)
+      for (int c0 = t; c0 < ne; c0 += nt * KB) {
+        if (!first) load_fwd(O, ml, rb, c0);
+        first = false;
+        fwd_compute(ml, lev, rb, c0);
+      }
     off += (int64_t)3 * P2 * (ml >> 1);
     ml = ne;
     ++lev;
-    if (ml > 1) load_fwd(lvl(lev, off), ml, t);
-    __syncthreads();
+    if (ml > 1 && lev < Ls) load_fwd(F + off, ml, 0, t);
+    lds_barrier();
+  }
+  while (ml > 1) {
+    fwd_level_lds(TL + (off - tail_off));
+    off += (int64_t)3 * P2 * (ml >> 1);
+    ml = (ml + 1) >> 1;
+    ++lev;
+    lds_barrier();
   }
   T xr = T(0);
   const int top = P * (m - 1);
   if (t < P) {
-    const T* D = lvl(lev, off);
+    if (lev >= Ls) {
+      const T* D = TL + (off - tail_off);
 #pragma unroll
-    for (int q = 0; q < P; ++q) xr += D[t * P + q] * R[top + q];
+      for (int q = 0; q < P; ++q) xr += D[t * P + q] * R[top + q];
+    } else {
+      const T* D = F + off;
+#pragma unroll
+      for (int q = 0; q < P; ++q) xr += D[t * P + q] * R[top + q];
+    }
   }
-  __syncthreads();
+  lds_barrier();
   if (t < P) R[top + t] = xr;
-  __syncthreads();
+  lds_barrier();
   // ---- back substitution: values of all items first, then a barrier, then writes
-  T od[KB][P], ow[KB][P], oz[KB][P];
-  auto load_bwd = [&](int l, int c0) {
-    const int mlv = (m + (1 << l) - 1) >> l;
-    const int no = mlv >> 1;
-    const T* O = lvl(l, level_offset(l));
+  constexpr int KBB = CS::KBB, RBB = CS::RBB, NRBB = CS::NRBB;
+  T od[KBB][RBB][P], ow[KBB][RBB][P], oz[KBB][RBB][P];
+  auto load_bwd_from = [&](const T* O, int mlv, int rb, int c0) __attribute__((always_inline)) {
+    const int no_ = mlv >> 1;
 #pragma unroll
-    for (int kk = 0; kk < KB; ++kk) {
-      const int it = c0 + kk * nt;
-      if (it < no * P) {
-        const int r = it / no, tt = it - r * no;
-        const int j = 2 * tt + 1;
+    for (int kk = 0; kk < KBB; ++kk) {
+      const int tt = c0 + kk * nt;
+      const bool ok = tt < no_;
+      const bool right = 2 * tt + 2 < mlv;
+      const unsigned ti = (unsigned)min(tt, no_ - 1);
+#pragma unroll
+      for (int rr = 0; rr < RBB; ++rr) {
+        const int r = rb * RBB + rr;
 #pragma unroll
         for (int q = 0; q < P; ++q) {
-          od[kk][q] = O[(int64_t)(r * P + q) * no + tt];
-          ow[kk][q] = O[(int64_t)(P2 + r * P + q) * no + tt];
-          oz[kk][q] = (j + 1 < mlv) ? O[(int64_t)(2 * P2 + r * P + q) * no + tt] : T(0);
+          if (r < P) {  // resolved at compile time
+            const T d = O[(int64_t)(r * P + q) * no_ + ti];
+            const T w = O[(int64_t)(P2 + r * P + q) * no_ + ti];
+            const T z = O[(int64_t)(2 * P2 + r * P + q) * no_ + ti];
+            od[kk][rr][q] = ok ? d : T(0);
+            ow[kk][rr][q] = ok ? w : T(0);
+            oz[kk][rr][q] = (ok && right) ? z : T(0);
+          } else {
+            od[kk][rr][q] = ow[kk][rr][q] = oz[kk][rr][q] = T(0);
+          }
         }
       }
     }
   };
-  if (lev > 0) load_bwd(lev - 1, t);
+  auto load_bwd = [&](int l, int rb, int c0) __attribute__((always_inline)) {
+    load_bwd_from(F + level_offset(l), (m + (1 << l) - 1) >> l, rb, c0);
+  };
+  // back substitution of a level with factors in LDS: one position per item,
+  // results written after the barrier
+  auto bwd_level_lds = [&](const T* O, int no, int ob0) __attribute__((always_inline)) {
+    T res[MAXPOS][P];
+#pragma unroll
+    for (int pi = 0; pi < MAXPOS; ++pi) {
+      const int tt = t + pi * nt;
+      if (tt < no) {
+        T own[P], xl[P], xrt[P];
+        int rl, rr2;
+        const int wl = slot(lev + 1, tt, rl);
+        const bool right = 2 * tt + 2 < ml;
+        const int wr = right ? slot(lev + 1, tt + 1, rr2) : (rr2 = rl, wl);
+#pragma unroll
+        for (int q = 0; q < P; ++q) {
+          own[q] = R[ob0 + tt + q * no];
+          xl[q] = R[wl + q * rl];
+          const T x = R[wr + q * rr2];
+          xrt[q] = right ? x : T(0);  // Z is finite, so a missing neighbour contributes 0
+        }
+#pragma unroll
+        for (int r = 0; r < P; ++r) {
+          T s = T(0);
+#pragma unroll
+          for (int q = 0; q < P; ++q)
+            s += O[(r * P + q) * no + tt] * own[q] - O[(P2 + r * P + q) * no + tt] * xl[q] -
+                 O[(2 * P2 + r * P + q) * no + tt] * xrt[q];
+          res[pi][r] = s;
+        }
+      }
+    }
+    lds_barrier();
+#pragma unroll
+    for (int pi = 0; pi < MAXPOS; ++pi) {
+      const int tt = t + pi * nt;
+      if (tt < no) {
+#pragma unroll
+        for (int r = 0; r < P; ++r) R[ob0 + tt + r * no] = res[pi][r];
+      }
+    }
+    lds_barrier();
+  };
+  // levels in LDS, then levels in HBM
+  while (lev > 0 && lev - 1 >= Ls) {
+    --lev;
+    ml = (m + (1 << lev) - 1) >> lev;
+    bwd_level_lds(TL + (level_offset(lev) - tail_off), ml >> 1, P * (m - ml));
+  }
+  if (lev > 0) load_bwd(lev - 1, 0, t);
   while (lev > 0) {
     --lev;
     ml = (m + (1 << lev) - 1) >> lev;
     const int no = ml >> 1;
-    T res[kChainMaxRes];
-    int cnt = 0;
-    for (int c0 = t; c0 < no * P; c0 += nt * KB) {
-      if (c0 != t) load_bwd(lev, c0);
+    const int ob0 = P * (m - ml);
+    T res[MAXPOS][P];
+    bool first = true;
 #pragma unroll
-      for (int kk = 0; kk < KB; ++kk) {
-        const int it = c0 + kk * nt;
-        if (it < no * P && cnt < kChainMaxRes) {
-          const int r = it / no, tt = it - r * no;
-          const int j = 2 * tt + 1;
-          const int ob = P * (m - ml) + tt;  // own right-hand side, row stride no
-          int rl, rr;
-          const int wl = slot(lev + 1, tt, rl);
-          // oz = 0 when there is no right neighbour: reuse the left one
-          const int wr = (j + 1 < ml) ? slot(lev + 1, tt + 1, rr) : (rr = rl, wl);
-          T s = T(0);
+    for (int rb = 0; rb < NRBB; ++rb)
 #pragma unroll
-          for (int q = 0; q < P; ++q)
-            s += od[kk][q] * R[ob + q * no] - ow[kk][q] * R[wl + q * rl] - oz[kk][q] * R[wr + q * rr];
-          res[cnt++] = s;
+      for (int pb = 0; pb < MAXPOS; pb += KBB) {
+        const int c0 = t + pb * nt;
+        if (c0 < no) {
+          if (!first) load_bwd(lev, rb, c0);
+          first = false;
+#pragma unroll
+          for (int kk = 0; kk < KBB; ++kk) {
+            const int tt = c0 + kk * nt;
+            if (pb + kk < MAXPOS && tt < no) {
+              T own[P], xl[P], xrt[P];
+              int rl, rr2;
+              const int wl = slot(lev + 1, tt, rl);
+              const bool right = 2 * tt + 2 < ml;
+              const int wr = right ? slot(lev + 1, tt + 1, rr2) : (rr2 = rl, wl);
+#pragma unroll
+              for (int q = 0; q < P; ++q) {
+                own[q] = R[ob0 + tt + q * no];
+                xl[q] = R[wl + q * rl];
+                xrt[q] = R[wr + q * rr2];  // oz = 0 when there is no right neighbour
+              }
+#pragma unroll
+              for (int rr = 0; rr < RBB; ++rr) {
+                const int r = rb * RBB + rr;
+                if (r < P) {
+                  T s = T(0);
+#pragma unroll
+                  for (int q = 0; q < P; ++q) s += od[kk][rr][q] * own[q] - ow[kk][rr][q] * xl[q] - oz[kk][rr][q] * xrt[q];
+                  res[pb + kk][r] = s;
+                }
+              }
+            }
+          }
         }
       }
-    }
-    if (lev > 0) load_bwd(lev - 1, t);
-    __syncthreads();
-    cnt = 0;
-    for (int it = t; it < no * P && cnt < kChainMaxRes; it += nt, ++cnt) {
-      const int r = it / no, tt = it - r * no;
-      R[P * (m - ml) + tt + r * no] = res[cnt];
-    }
-    __syncthreads();
-  }
-  for (int b0 = t; b0 < m * P; b0 += nt * CB) {
-    T v[CB];
-    int64_t g[CB];
+    if (lev > 0) load_bwd(lev - 1, 0, t);
+    lds_barrier();
 #pragma unroll
-    for (int u = 0; u < CB; ++u) {
-      const int idx = b0 + u * nt;
-      if (idx < m * P) {
-        const int i = idx / P, r = idx - i * P;
-        g[u] = (base + stride * i) * P + r;
-        v[u] = xin ? xin[g[u]] : T(0);
+    for (int pi = 0; pi < MAXPOS; ++pi) {
+      const int tt = t + pi * nt;
+      if (tt < no) {
+#pragma unroll
+        for (int r = 0; r < P; ++r) R[ob0 + tt + r * no] = res[pi][r];
+      }
+    }
+    lds_barrier();
+  }
+  for (int i0 = t; i0 < m; i0 += nt * CBP) {
+    T v[CBP][P];
+#pragma unroll
+    for (int u = 0; u < CBP; ++u) {
+      const int i = i0 + u * nt;
+      if (i < m) {
+#pragma unroll
+        for (int r = 0; r < P; ++r) v[u][r] = xin ? xin[(base + stride * i) * P + r] : T(0);
       }
     }
 #pragma unroll
-    for (int u = 0; u < CB; ++u) {
-      const int idx = b0 + u * nt;
-      if (idx < m * P) {
-        const int i = idx / P, r = idx - i * P;
+    for (int u = 0; u < CBP; ++u) {
+      const int i = i0 + u * nt;
+      if (i < m) {
         int rs;
         const int w = slot(0, i, rs);
-        out[g[u]] = v[u] + T(a.omega) * R[w + r * rs];
+        T* dst = out + (base + stride * i) * P;
+#pragma unroll
+        for (int r = 0; r < P; ++r) dst[r] = v[u][r] + T(a.omega) * R[w + r * rs];
       }
     }
   }
 }
 
-// Bytes of the factors of the levels >= l of one chain (element size es).
+// Bytes of the factors of the levels >= l of one chain (element size es); the
+// last level's record (one block) is always included, as the kernel stages it.
 static int64_t chain_tail_bytes(int P, int n, int l, size_t es) {
   int64_t tot = 0;
   int q = 0;
   for (int s = n - 1;; s = (s + 1) >> 1, ++q) {
     const int64_t rec = s == 1 ? (int64_t)P * P : (int64_t)3 * P * P * (s >> 1);
-    if (q >= l) tot += rec;
+    if (q >= l || s == 1) tot += rec;
     if (s == 1) break;
   }
   return tot * (int64_t)es;
@@ -847,7 +1022,7 @@ static int64_t chain_tail_bytes(int P, int n, int l, size_t es) {
 int chain_lds_level(int P, int n, size_t es, int64_t budget) {
   if (budget < 0) budget = 0;
   int l = 0;
-  while (chain_tail_bytes(P, n, l, es) > budget) ++l;
+  while (l < 64 && chain_tail_bytes(P, n, l, es) > budget) ++l;
   return l;
 }
 
@@ -855,13 +1030,26 @@ size_t chain_lds_bytes(int P, int n, size_t es, int lds_level) {
   return (size_t)(n - 1) * P * es + (size_t)chain_tail_bytes(P, n, lds_level, es);
 }
 
-// Workgroup size: measured best at n = 256 and 1024 is 128 threads for P <= 2 and
-// 256 for larger P (more threads per chain lengthen every phase), raised only as
-// far as the back substitution's kChainMaxRes items per thread require.
+static int chain_maxpos(int P) {
+  static constexpr int t[] = {0, ChainShape<1>::MAXPOS, ChainShape<2>::MAXPOS, ChainShape<3>::MAXPOS,
+                              ChainShape<4>::MAXPOS, ChainShape<5>::MAXPOS, ChainShape<6>::MAXPOS,
+                              ChainShape<7>::MAXPOS, ChainShape<8>::MAXPOS, ChainShape<9>::MAXPOS};
+  return P >= 1 && P <= 9 ? t[P] : 0;
+}
+int chain_max_threads(int P) {
+  static constexpr int t[] = {0, ChainShape<1>::MAXT, ChainShape<2>::MAXT, ChainShape<3>::MAXT,
+                              ChainShape<4>::MAXT, ChainShape<5>::MAXT, ChainShape<6>::MAXT,
+                              ChainShape<7>::MAXT, ChainShape<8>::MAXT, ChainShape<9>::MAXT};
+  return P >= 1 && P <= 9 ? t[P] : 0;
+}
+
+// Workgroup size: 128 threads for P <= 2 and 256 for larger P (more threads
+// per chain lengthen every phase), raised only as far as the back
+// substitution's MAXPOS positions per thread require.
 int chain_threads(int P, int n) {
-  const int64_t bwd = (int64_t)((n - 1) / 2) * P;  // items of the first backward level
+  const int64_t bwd = (int64_t)((n - 1) / 2);  // positions of the first backward level
   int64_t th = P <= 2 ? 128 : 256;
-  while (th < 1024 && bwd > th * kChainMaxRes) th += 64;
+  while (th < chain_max_threads(P) && bwd > th * chain_maxpos(P)) th += 64;
   return (int)th;
 }
 
@@ -874,8 +1062,9 @@ hipError_t launch_chain_solve(Prec pr, int P, const ChainArgs& a, hipStream_t s)
   const int threads = a.threads > 0 ? a.threads : chain_threads(P, a.n);
   const size_t lds = chain_lds_bytes(P, a.n, vec_bytes(pr), a.lds_level);
   if (lds > 65536) return hipErrorInvalidValue;
-  // the back substitution keeps at most kChainMaxRes (position, row) items per thread
-  if ((int64_t)((a.n - 1) / 2) * P > (int64_t)threads * kChainMaxRes || threads > 1024 || threads % 64)
+  // the back substitution keeps at most MAXPOS positions per thread
+  if (chain_maxpos(P) == 0 || (int64_t)((a.n - 1) / 2) > (int64_t)threads * chain_maxpos(P) ||
+      threads > chain_max_threads(P) || threads % 64)
     return hipErrorInvalidValue;
   if (pr == Prec::F64) {
     HDG_DISPATCH_P(P, hipLaunchKernelGGL((k_chain<PP, double>), dim3((unsigned)nch), dim3(threads), lds, s, a));

@@ -102,6 +102,7 @@ struct ChainArgs {
   int remap;            // 1: XCD-aware chain order (consecutive chains on one XCD)
 };
 int chain_threads(int P, int n);
+int chain_max_threads(int P);  // launch bound of the chain kernel at P
 int chain_remap(int P);
 // first level whose factors (and all later ones) fit in `budget` bytes of LDS
 int chain_lds_level(int P, int n, size_t elem_bytes, int64_t budget);

@@ -83,6 +83,21 @@ def test_reduced_precision_face_smoother_needs_omega(prec):
     assert not h.value
 
 
+@pytest.mark.parametrize("k,prec,n", [(7, 0, 1018), (3, 0, 2046), (3, 1, 4094)])
+def test_chain_smoother_rejects_chains_beyond_lds(k, prec, n):
+    """One chain's right-hand side plus one factor block must fit 64 KiB of LDS:
+    ((n-1)(k+1) + (k+1)^2) * (8 or 4 bytes) <= 65536; each case is the first n past it."""
+    P, vb = k + 1, 8 if prec == 0 else 4
+    assert ((n - 1) * P + P * P) * vb > 65536 >= ((n - 2) * P + P * P) * vb
+    cfg = H.Config()
+    H.lib.hdg_config_default(n, k, ctypes.byref(cfg))
+    cfg.precision = prec
+    kap = np.ones(n * n)
+    h = ctypes.c_void_p()
+    assert H.lib.hdg_create(ctypes.byref(cfg), kap.ctypes.data_as(H._PD), None, ctypes.byref(h)) == -1
+    assert not h.value
+
+
 def test_config_layout_matches_header():
     """The Python mirror of hdg_config_t has the C layout (size and field offsets)."""
     import re
