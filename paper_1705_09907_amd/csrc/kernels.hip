@@ -16,6 +16,7 @@
 #include <hip/hip_ext.h>
 #include <hip/hip_runtime.h>
 
+#include "device.hpp"
 #include "kernels.hpp"
 
 namespace hdg {
@@ -613,16 +614,6 @@ struct ChainShape {
   static constexpr int MAXPOS = P <= 1 ? 8 : (P <= 3 ? 4 : 2);
   static constexpr int MAXT = P <= 4 ? 1024 : 512;  // workgroup size bound (registers)
 };
-
-// Workgroup barrier that orders LDS accesses only: global loads issued before it
-// (the prefetched factors of the next level) stay in flight across it, where
-// __syncthreads() would wait for them.  For kernels whose waves never read
-// global memory written by another wave of the workgroup.
-__device__ __forceinline__ void lds_barrier() {
-  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup", "local");
-  __builtin_amdgcn_s_barrier();
-  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
-}
 
 template <int P, typename T>
 __global__ __launch_bounds__(ChainShape<P>::MAXT) void k_chain(ChainArgs a) {

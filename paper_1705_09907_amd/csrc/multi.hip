@@ -8,6 +8,7 @@
 // factors, stencils, transfer tables) are read once per launch for all columns.
 #include <hip/hip_runtime.h>
 
+#include "device.hpp"
 #include "kernels.hpp"
 
 namespace hdg {
@@ -269,16 +270,27 @@ hipError_t launch_dense_gemm_m(Prec pr, const double* A, const void* b, void* y,
 
 // ----------------------------------------------------------- chain Schwarz
 // out = x + omega M^{-1} r for R right-hand sides: the block cyclic reduction of
-// k_chain with a chunk of RC right-hand sides per workgroup.  A work item
-// (position, row) loads its factor row once and applies it to every right-hand
-// side of the chunk held in LDS [position][row][RC].  The chunks of one chain are
-// consecutive workgroups of one XCD (workgroups are dealt round-robin to the 8
-// XCDs), so the factor re-reads of later chunks come from that XCD's L2.
-static constexpr int kChainMaxResM = 8;
-
+// k_chain for a chunk of RC (a power of two) right-hand sides per workgroup.
+// The chunk sits in LDS in k_chain's level order: word w (a position's row)
+// holds the RC columns at w RCP + c, RCP = RC + 1 (odd) for RC > 1, so lanes
+// whose words are consecutive fall in different banks.  Forward reduction:
+// a work item is one (row, position) pair, which loads its factor row once and
+// loops over the columns.  Back substitution: a work item is one (position,
+// column) pair, column fastest, computing every row of its position for its
+// column; it owns those values, so results are written as soon as they are
+// computed (the RC lanes of one position load the same factor entries, one
+// transaction for all).  Factors come by buffer loads (one register offset per
+// lane, a wave-uniform offset per entry), unconditional at clamped indices and
+// masked afterwards (the factors are finite).  The chunks of one chain are
+// consecutive workgroups of one XCD (workgroups are dealt round-robin to the
+// 8 XCDs), so the factor re-reads of later chunks come from that XCD's L2.
+// At most 256 threads and at least 2 waves per SIMD (256 registers): a chunk
+// of up to 64 KiB of LDS allows 2 workgroups per CU, so more registers cost no
+// occupancy.
 template <int P, typename T>
-__global__ __launch_bounds__(1024) void k_chain_m(ChainMultiArgs a) {
+__global__ __launch_bounds__(256, 2) void k_chain_m(ChainMultiArgs a) {
   constexpr int P2 = P * P;
+  constexpr int S = (int)sizeof(T);
   extern __shared__ unsigned char lds_raw_m[];
   T* Rl = reinterpret_cast<T*>(lds_raw_m);
   const T* rin = static_cast<const T*>(a.r);
@@ -291,6 +303,8 @@ __global__ __launch_bounds__(1024) void k_chain_m(ChainMultiArgs a) {
   const int64_t c = pair / a.nchunks;
   const int chunk = (int)(pair - c * a.nchunks);
   const int RC = a.rc;
+  const int lg = __builtin_ctz((unsigned)RC);
+  const int RCP = RC == 1 ? 1 : RC + 1;
   const int R = a.R;
   const int col0 = chunk * RC;
   const int m = a.n - 1;
@@ -299,123 +313,163 @@ __global__ __launch_bounds__(1024) void k_chain_m(ChainMultiArgs a) {
   const int64_t base = vert ? c * (a.n - 1) : nv + (c - a.n);
   const int64_t stride = vert ? 1 : a.n;
   const T* F = static_cast<const T*>(a.factors) + c * a.cstride;
+  const __amdgpu_buffer_rsrc_t fr = buffer_rsrc(F, (int)(a.cstride * S));
   const int t = threadIdx.x;
   const int nt = blockDim.x;
-  for (int idx = t; idx < m * P * RC; idx += nt) {
-    const int ir = idx / RC, q = idx - ir * RC;
-    const int i = ir / P, row = ir - i * P;
-    const int col = col0 + q;
-    Rl[idx] = col < R ? rin[((base + stride * i) * P + row) * R + col] : T(0);
+  auto slot = [m](int l, int pos, int& rs) -> int {  // as in k_chain
+    if (pos == 0) {
+      rs = 1;
+      return P * (m - 1);
+    }
+    const int z = __builtin_ctz((unsigned)pos);
+    const int lv = l + z;
+    const int mlv = (m + (1 << lv) - 1) >> lv;
+    rs = mlv >> 1;
+    return P * (m - mlv) + (pos >> (z + 1));
+  };
+  // chunk in: lanes over (position, column), column fastest
+  for (int j = t; j < m * RC; j += nt) {
+    const int i = j >> lg, q0 = j & (RC - 1);
+    const int col = col0 + q0;
+    int rs;
+    const int w = slot(0, i, rs);
+    T v[P];
+#pragma unroll
+    for (int r = 0; r < P; ++r) v[r] = col < R ? rin[((base + stride * i) * P + r) * R + col] : T(0);
+#pragma unroll
+    for (int r = 0; r < P; ++r) Rl[(w + r * rs) * RCP + q0] = v[r];
   }
-  __syncthreads();
+  lds_barrier();
+  // forward reduction: M-_j = Z_{j-1}^T, M+_j = W_{j+1}^T
   int ml = m, lev = 0;
   int64_t off = 0;
   while (ml > 1) {
     const int ne = (ml + 1) >> 1, no = ml >> 1;
-    const T* O = F + off;
-    for (int it = t; it < ne * P; it += nt) {
-      const int row = it / ne, tt = it - row * ne;
-      const int j = 2 * tt;
-      const int i = j << lev;
-      // M-_j = Z_{j-1}^T, M+_j = W_{j+1}^T (odd indices tt - 1 and tt)
-      T pm[P], pp[P];
+    const int ob = P * (m - ml);
+    const int ob8 = (int)off * S;  // byte offset of the level's records
 #pragma unroll
-      for (int q = 0; q < P; ++q) {
-        pm[q] = tt >= 1 ? O[(int64_t)(2 * P2 + q * P + row) * no + tt - 1] : T(0);
-        pp[q] = tt < no ? O[(int64_t)(P2 + q * P + row) * no + tt] : T(0);
-      }
-      for (int q0 = 0; q0 < RC; ++q0) {
-        T v = Rl[(i * P + row) * RC + q0];
-        if (j >= 1) {
-          const int il = (j - 1) << lev;
+    for (int r = 0; r < P; ++r)
+      for (int tt = t; tt < ne; tt += nt) {
+        const int zi = min(max(tt - 1, 0), no - 1), wi = min(tt, no - 1);
+        const bool zok = tt >= 1, wok = tt < no;
+        T zm[P], wp[P];  // row r of M-_j and M+_j
 #pragma unroll
-          for (int q = 0; q < P; ++q) v -= pm[q] * Rl[(il * P + q) * RC + q0];
+        for (int q = 0; q < P; ++q) {
+          const T z = buffer_load<T>(fr, zi * S, ob8 + (2 * P2 + q * P + r) * no * S);
+          const T w = buffer_load<T>(fr, wi * S, ob8 + (P2 + q * P + r) * no * S);
+          zm[q] = zok ? z : T(0);
+          wp[q] = wok ? w : T(0);
         }
-        if (j + 1 < ml) {
-          const int ir2 = (j + 1) << lev;
+        int rs;
+        const int wo = (slot(lev + 1, tt, rs) + r * rs) * RCP;
+        for (int q0 = 0; q0 < RC; ++q0) {
+          T v = Rl[wo + q0];
 #pragma unroll
-          for (int q = 0; q < P; ++q) v -= pp[q] * Rl[(ir2 * P + q) * RC + q0];
+          for (int q = 0; q < P; ++q)
+            v -= zm[q] * Rl[(ob + q * no + zi) * RCP + q0] + wp[q] * Rl[(ob + q * no + wi) * RCP + q0];
+          Rl[wo + q0] = v;
         }
-        Rl[(i * P + row) * RC + q0] = v;
       }
-    }
     off += (int64_t)3 * P2 * no;
     ml = ne;
     ++lev;
-    __syncthreads();
+    lds_barrier();
   }
-  // last level: x_0 = Dinv r_0 for every right-hand side of the chunk
-  T xr = T(0);
-  const bool lastw = t < P * RC;
-  if (lastw) {
-    const int row = t / RC, q0 = t - row * RC;
+  // last level: x_0 = Dinv r_0 for every column of the chunk
+  {
+    const int top = P * (m - 1);
+    for (int q0 = t; q0 < RC; q0 += nt) {
+      T v[P], xr[P];
 #pragma unroll
-    for (int q = 0; q < P; ++q) xr += F[off + row * P + q] * Rl[q * RC + q0];
+      for (int q = 0; q < P; ++q) v[q] = Rl[(top + q) * RCP + q0];
+#pragma unroll
+      for (int r = 0; r < P; ++r) {
+        xr[r] = T(0);
+#pragma unroll
+        for (int q = 0; q < P; ++q) xr[r] += F[off + r * P + q] * v[q];
+      }
+#pragma unroll
+      for (int r = 0; r < P; ++r) Rl[(top + r) * RCP + q0] = xr[r];
+    }
   }
-  __syncthreads();
-  if (lastw) Rl[t] = xr;
-  __syncthreads();
+  lds_barrier();
+  // back substitution: x_j = Dinv_j r_j - W_j x_{j-1} - Z_j x_{j+1} (j odd)
   while (lev > 0) {
     --lev;
     ml = (m + (1 << lev) - 1) >> lev;
     const int no = ml >> 1;
+    const int ob = P * (m - ml);
     int64_t lo = 0;
     for (int l = 0, s = m; l < lev; ++l, s = (s + 1) >> 1) lo += (int64_t)3 * P2 * (s >> 1);
-    const T* O = F + lo;
-    // values of all (item, right-hand side) pairs first, then a barrier, then writes
-    T res[kChainMaxResM];
-    int cnt = 0;
-    for (int it = t; it < no * P * RC && cnt < kChainMaxResM; it += nt, ++cnt) {
-      const int item = it / RC, q0 = it - item * RC;
-      const int row = item / no, tt = item - row * no;
-      const int j = 2 * tt + 1;
-      const int i = j << lev;
-      const int il = (j - 1) << lev;
-      T s = T(0);
+    const int lo8 = (int)lo * S;
+    for (int j = t; j < no * RC; j += nt) {
+      const int tt = j >> lg, q0 = j & (RC - 1);
+      int rl, rr;
+      const int wl = slot(lev + 1, tt, rl);
+      const bool right = 2 * tt + 2 < ml;
+      const int wr = right ? slot(lev + 1, tt + 1, rr) : (rr = rl, wl);
+      T own[P], xl[P], xrt[P];
 #pragma unroll
-      for (int q = 0; q < P; ++q)
-        s += O[(int64_t)(row * P + q) * no + tt] * Rl[(i * P + q) * RC + q0] -
-             O[(int64_t)(P2 + row * P + q) * no + tt] * Rl[(il * P + q) * RC + q0];
-      if (j + 1 < ml) {
-        const int ir2 = (j + 1) << lev;
-#pragma unroll
-        for (int q = 0; q < P; ++q) s -= O[(int64_t)(2 * P2 + row * P + q) * no + tt] * Rl[(ir2 * P + q) * RC + q0];
+      for (int q = 0; q < P; ++q) {
+        own[q] = Rl[(ob + q * no + tt) * RCP + q0];
+        xl[q] = Rl[(wl + q * rl) * RCP + q0];
+        const T x = Rl[(wr + q * rr) * RCP + q0];
+        xrt[q] = right ? x : T(0);
       }
-      res[cnt] = s;
+      T res[P];
+#pragma unroll
+      for (int r = 0; r < P; ++r) {
+        T s = T(0);
+#pragma unroll
+        for (int q = 0; q < P; ++q)
+          s += buffer_load<T>(fr, tt * S, lo8 + (r * P + q) * no * S) * own[q] -
+               buffer_load<T>(fr, tt * S, lo8 + (P2 + r * P + q) * no * S) * xl[q] -
+               buffer_load<T>(fr, tt * S, lo8 + (2 * P2 + r * P + q) * no * S) * xrt[q];
+        res[r] = s;
+      }
+#pragma unroll
+      for (int r = 0; r < P; ++r) Rl[(ob + r * no + tt) * RCP + q0] = res[r];
     }
-    __syncthreads();
-    cnt = 0;
-    for (int it = t; it < no * P * RC && cnt < kChainMaxResM; it += nt, ++cnt) {
-      const int item = it / RC, q0 = it - item * RC;
-      const int row = item / no, tt = item - row * no;
-      Rl[(((2 * tt + 1) << lev) * P + row) * RC + q0] = res[cnt];
-    }
-    __syncthreads();
+    lds_barrier();
   }
-  for (int idx = t; idx < m * P * RC; idx += nt) {
-    const int ir = idx / RC, q = idx - ir * RC;
-    const int i = ir / P, row = ir - i * P;
-    const int col = col0 + q;
+  for (int j = t; j < m * RC; j += nt) {
+    const int i = j >> lg, q0 = j & (RC - 1);
+    const int col = col0 + q0;
     if (col >= R) continue;
-    const int64_t g = ((base + stride * i) * P + row) * R + col;
-    out[g] = (xin ? xin[g] : T(0)) + T(a.omega) * Rl[idx];
+    int rs;
+    const int w = slot(0, i, rs);
+#pragma unroll
+    for (int r = 0; r < P; ++r) {
+      const int64_t g = ((base + stride * i) * P + r) * R + col;
+      out[g] = (xin ? xin[g] : T(0)) + T(a.omega) * Rl[(w + r * rs) * RCP + q0];
+    }
   }
 }
 
+// LDS bytes of a chunk of rc right-hand sides (column stride rc + 1 for rc > 1)
+static size_t chain_multi_lds(int P, int n, int rc, size_t es) {
+  return (size_t)(n - 1) * P * (size_t)(rc == 1 ? 1 : rc + 1) * es;
+}
+
+// Largest power-of-two chunk (at most 16 and at most R rounded up to a power
+// of two) whose right-hand sides fit 64 KiB of LDS; 0 if one column does not fit.
 int chain_multi_chunk(int P, int n, int R, size_t es) {
-  int64_t rc = 65536 / ((int64_t)(n - 1) * P * (int64_t)es);
-  if (rc > R) rc = R;
-  if (rc > 16) rc = 16;
-  return (int)(rc < 1 ? 1 : rc);
+  if (chain_multi_lds(P, n, 1, es) > 65536) return 0;
+  int rc = 1;
+  while (rc < 16 && rc < R && chain_multi_lds(P, n, 2 * rc, es) <= 65536) rc *= 2;
+  return rc;
 }
 
 hipError_t launch_chain_solve_m(Prec pr, int P, const ChainMultiArgs& a, hipStream_t s) {
-  const size_t lds = (size_t)(a.n - 1) * P * a.rc * vec_bytes(pr);
-  if (lds > 65536 || a.rc < 1 || a.nchunks * a.rc < a.R) return hipErrorInvalidValue;
-  const int64_t bwd = (int64_t)((a.n - 1) / 2) * P * a.rc;
-  int threads = a.threads > 0 ? a.threads : 256;
-  while (threads < 1024 && bwd > (int64_t)threads * kChainMaxResM) threads *= 2;
-  if (bwd > (int64_t)threads * kChainMaxResM || P * a.rc > threads) return hipErrorInvalidValue;
+  if (a.rc < 1 || (a.rc & (a.rc - 1)) || a.nchunks * a.rc < a.R) return hipErrorInvalidValue;
+  const size_t lds = chain_multi_lds(P, a.n, a.rc, vec_bytes(pr));
+  if (lds > 65536) return hipErrorInvalidValue;
+  // one (position, column) pair per lane: the first forward level has
+  // ceil((n-1)/2) positions
+  const int64_t items = (int64_t)(a.n / 2) * a.rc;
+  int threads = a.threads > 0 ? a.threads : 64;
+  while (a.threads <= 0 && threads < 256 && threads < items) threads *= 2;
+  if (threads > 256 || threads % 64) return hipErrorInvalidValue;
   const dim3 grid((unsigned)(2LL * a.n * a.nchunks));
   if (pr == Prec::F64) {
     HDG_MDISPATCH_P(P, hipLaunchKernelGGL((k_chain_m<PP, double>), grid, dim3(threads), lds, s, a));
