@@ -712,8 +712,13 @@ __global__ __launch_bounds__(ChainShape<P>::MAXT) void k_chain(ChainArgs a) {
   // Loads are unconditional, at indices clamped into the level's arrays (whose
   // entries are all finite), and masked afterwards: a load under a branch makes
   // the compiler wait for it before the branch joins.
-  auto load_fwd = [&](const T* O, int ml_, int rb, int c0) __attribute__((always_inline)) {
+  constexpr int S = (int)sizeof(T);
+  // HBM factors by buffer loads: one register offset per lane, a wave-uniform
+  // byte offset per entry
+  const __amdgpu_buffer_rsrc_t fr = buffer_rsrc(F, (int)(a.cstride * S));
+  auto load_fwd = [&](int64_t off_l, int ml_, int rb, int c0) __attribute__((always_inline)) {
     const int ne_ = (ml_ + 1) >> 1, no_ = ml_ >> 1;  // no_ >= 1
+    const int o8 = (int)off_l * S;
 #pragma unroll
     for (int kk = 0; kk < KB; ++kk) {
       const int tt = c0 + kk * nt;
@@ -725,8 +730,8 @@ __global__ __launch_bounds__(ChainShape<P>::MAXT) void k_chain(ChainArgs a) {
 #pragma unroll
         for (int q = 0; q < P; ++q) {
           if (r < P) {  // resolved at compile time
-            const T z = O[(int64_t)(2 * P2 + q * P + r) * no_ + zi];
-            const T w = O[(int64_t)(P2 + q * P + r) * no_ + wi];
+            const T z = buffer_load<T>(fr, (int)zi * S, o8 + (2 * P2 + q * P + r) * no_ * S);
+            const T w = buffer_load<T>(fr, (int)wi * S, o8 + (P2 + q * P + r) * no_ * S);
             zm[kk][rr][q] = zok ? z : T(0);
             wp[kk][rr][q] = wok ? w : T(0);
           } else {
@@ -794,22 +799,21 @@ __global__ __launch_bounds__(ChainShape<P>::MAXT) void k_chain(ChainArgs a) {
     }
   };
   // levels in HBM, then levels in LDS
-  if (ml > 1 && Ls > 0) load_fwd(F, ml, 0, t);
+  if (ml > 1 && Ls > 0) load_fwd(0, ml, 0, t);
   while (ml > 1 && lev < Ls) {
-    const T* O = F + off;
     const int ne = (ml + 1) >> 1;
     bool first = true;
 #pragma unroll
     for (int rb = 0; rb < NRB; ++rb)
       for (int c0 = t; c0 < ne; c0 += nt * KB) {
-        if (!first) load_fwd(O, ml, rb, c0);
+        if (!first) load_fwd(off, ml, rb, c0);
         first = false;
         fwd_compute(ml, lev, rb, c0);
       }
     off += (int64_t)3 * P2 * (ml >> 1);
     ml = ne;
     ++lev;
-    if (ml > 1 && lev < Ls) load_fwd(F + off, ml, 0, t);
+    if (ml > 1 && lev < Ls) load_fwd(off, ml, 0, t);
     lds_barrier();
   }
   while (ml > 1) {
@@ -838,8 +842,9 @@ __global__ __launch_bounds__(ChainShape<P>::MAXT) void k_chain(ChainArgs a) {
   // ---- back substitution: values of all items first, then a barrier, then writes
   constexpr int KBB = CS::KBB, RBB = CS::RBB, NRBB = CS::NRBB;
   T od[KBB][RBB][P], ow[KBB][RBB][P], oz[KBB][RBB][P];
-  auto load_bwd_from = [&](const T* O, int mlv, int rb, int c0) __attribute__((always_inline)) {
+  auto load_bwd_from = [&](int64_t lo, int mlv, int rb, int c0) __attribute__((always_inline)) {
     const int no_ = mlv >> 1;
+    const int o8 = (int)lo * S;
 #pragma unroll
     for (int kk = 0; kk < KBB; ++kk) {
       const int tt = c0 + kk * nt;
@@ -852,9 +857,9 @@ __global__ __launch_bounds__(ChainShape<P>::MAXT) void k_chain(ChainArgs a) {
 #pragma unroll
         for (int q = 0; q < P; ++q) {
           if (r < P) {  // resolved at compile time
-            const T d = O[(int64_t)(r * P + q) * no_ + ti];
-            const T w = O[(int64_t)(P2 + r * P + q) * no_ + ti];
-            const T z = O[(int64_t)(2 * P2 + r * P + q) * no_ + ti];
+            const T d = buffer_load<T>(fr, (int)ti * S, o8 + (r * P + q) * no_ * S);
+            const T w = buffer_load<T>(fr, (int)ti * S, o8 + (P2 + r * P + q) * no_ * S);
+            const T z = buffer_load<T>(fr, (int)ti * S, o8 + (2 * P2 + r * P + q) * no_ * S);
             od[kk][rr][q] = ok ? d : T(0);
             ow[kk][rr][q] = ok ? w : T(0);
             oz[kk][rr][q] = (ok && right) ? z : T(0);
@@ -866,7 +871,7 @@ __global__ __launch_bounds__(ChainShape<P>::MAXT) void k_chain(ChainArgs a) {
     }
   };
   auto load_bwd = [&](int l, int rb, int c0) __attribute__((always_inline)) {
-    load_bwd_from(F + level_offset(l), (m + (1 << l) - 1) >> l, rb, c0);
+    load_bwd_from(level_offset(l), (m + (1 << l) - 1) >> l, rb, c0);
   };
   // back substitution of a level with factors in LDS: one position per item,
   // results written after the barrier
