@@ -286,3 +286,66 @@ def test_full_size_apply_sampled(name, n, k, sigma, seed):
         assert np.abs(one[f_int * (k + 1):(f_int + 1) * (k + 1)]).max() < 1e-10 * np.abs(y).max()
     finally:
         S.close()
+
+
+def _oracle_chain_matrix(n, k, kap, faces):
+    """Block-tridiagonal restriction of S to one chain of faces (consecutive faces
+    share one element), from the oracle's element blocks."""
+    P = k + 1
+    m = len(faces)
+    T = np.zeros((m * P, m * P))
+    blocks = {}
+
+    def K(e):
+        if e not in blocks:
+            blocks[e] = hdg.condensed_block(*hdg.local_matrices(
+                hdg.RefOps(k), 1.0 / n, 1.0, np.full((k + 2) ** 2, 1.0 / kap[e])), 1.0)
+        return blocks[e]
+
+    pos = {f: i for i, f in enumerate(faces)}
+    for i, f in enumerate(faces):
+        lo, hi, _ = ms.face_elements(n, f)
+        llo, lhi = ms.face_local_index(n, f)
+        for e, lf in ((lo, llo), (hi, lhi)):
+            ex, ey = e % n, e // n
+            for g, gf in enumerate(ms.element_faces(n, ex, ey)):
+                if gf in pos:
+                    j = pos[gf]
+                    T[i * P:(i + 1) * P, j * P:(j + 1) * P] += K(e)[lf * P:(lf + 1) * P, g * P:(g + 1) * P]
+    return T
+
+
+@pytest.mark.parametrize("name,n,k,sigma,seed", [("lognormal_n256_k4", 256, 4, 1.0, 2),
+                                                  ("lognormal_n1024_k3", 1024, 3, 2.0, 3)])
+@pytest.mark.parametrize("autotune", [False, True])
+def test_full_size_chain_solve_sampled(name, n, k, sigma, seed, autotune):
+    """Full-size workloads: one chain sweep from x = 0 gives omega M^{-1} b, M the
+    block-diagonal (over chains) restriction of S.  At these sizes the reduction's
+    first levels read their factors from HBM and the last ones from LDS (with the
+    autotuned launch shape: as bench.py runs it).  For sampled chains (first, last,
+    interior; vertical and horizontal) the result is checked against the chain
+    matrix rebuilt from the oracle's element blocks: backward error of the chain
+    solve <= 1e-14 (normwise), and agreement with a dense solve <= 1e-9 relative."""
+    print(f"case full-size chain {name} autotune={autotune}", flush=True)
+    kap = kappa_lognormal(n, sigma, seed)
+    omega = 0.7
+    S = H.Solver(n, k, kap, smoother="chain", omega=omega, autotune=autotune)
+    try:
+        N = S.num_dofs()
+        b = normal_vector(N, 23)
+        x = torch.zeros(N, dtype=torch.float64, device="cuda")
+        S.smooth(k, dev(b), x, 1)
+        xg = host(x) / omega
+        P = k + 1
+        chains = mg.chains(n)
+        for c in (0, n // 2 + 1, n - 1, n, n + n // 3, 2 * n - 1):
+            faces = chains[c]
+            idx = np.concatenate([np.arange(f * P, (f + 1) * P) for f in faces])
+            T = _oracle_chain_matrix(n, k, kap, faces)
+            xc, bc = xg[idx], b[idx]
+            berr = np.abs(T @ xc - bc).max() / (np.abs(T).sum(axis=1).max() * np.abs(xc).max() + np.abs(bc).max())
+            assert berr <= 1e-14, (c, berr)
+            xd = np.linalg.solve(T, bc)
+            assert rel_inf(xc, xd) <= 1e-9, (c, rel_inf(xc, xd))
+    finally:
+        S.close()
