@@ -370,12 +370,16 @@ __global__ __launch_bounds__(256) void k_trace_multi(MultiArgs a) {
     TV acc[P];
 #pragma unroll
     for (int q = 0; q < P; ++q) acc[q] = TV(0);
+    // missing (boundary) neighbours: the gather reads the face's own row and is
+    // zeroed, so the 7 P steps form one branch-free block the compiler can pipeline
 #pragma unroll
     for (int s = 0; s < 7; ++s) {
-      if (g[s] < 0) continue;
+      const bool ok = g[s] >= 0;
+      const int64_t gs = ok ? g[s] : f;
 #pragma unroll
       for (int c = 0; c < P; ++c) {
-        const TV xv = X[(g[s] * P + c) * R + r];
+        const TV xl = X[(gs * P + c) * R + r];
+        const TV xv = ok ? xl : TV(0);
         const TV* col = &blk[fl][(s * P + c) * PQ];
 #pragma unroll
         for (int q = 0; q < P; ++q) acc[q] += col[q] * xv;
