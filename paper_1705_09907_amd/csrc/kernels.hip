@@ -112,11 +112,19 @@ __global__ __launch_bounds__(kWG) void k_trace(TraceArgs a) {
     const bool valid = f < a.nf;
     int64_t g[7];
     face_neighbours(a.n, nv, valid ? f : 0, g);
+    // missing neighbours (and lanes past the last face) gather an existing row
+    // and zero it: no load sits under a branch
     TV xv[7][P];
 #pragma unroll
-    for (int s = 0; s < 7; ++s)
+    for (int s = 0; s < 7; ++s) {
+      const bool ok = valid && g[s] >= 0;
+      const int64_t gs = ok ? g[s] : 0;
 #pragma unroll
-      for (int c = 0; c < P; ++c) xv[s][c] = (valid && g[s] >= 0) ? x[g[s] * P + c] : TV(0);
+      for (int c = 0; c < P; ++c) {
+        const TV v = x[gs * P + c];
+        xv[s][c] = ok ? v : TV(0);
+      }
+    }
     TV acc[P];
 #pragma unroll
     for (int r = 0; r < P; ++r) acc[r] = TV(0);
