@@ -9,6 +9,11 @@ import ctypes
 import os
 
 import numpy as np
+# torch first: it loads its own HIP runtime, and the library's HIP dependency
+# then resolves to that same runtime.  Loaded the other way round, the process
+# holds two HIP runtimes, and torch's streams and allocations mean nothing to
+# the library's (device calls then fail).
+import torch  # noqa: F401
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libhdggmg.so")

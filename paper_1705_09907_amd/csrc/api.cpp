@@ -837,6 +837,9 @@ void tune_chain(hdg_ctx* h, int p) {
   const int64_t rhs_bytes = (int64_t)(h->n - 1) * L.P * (int64_t)es;
   const int lds_default = L.chain_lds_level;
   const int lds_staged = hdg::chain_lds_level(L.P, h->n, es, std::min<int64_t>(24576, 65536 - rhs_bytes));
+  // as much as fits: at P = 1 the whole factor set of a chain (5 entries per
+  // eliminated position) fits beside the right-hand side
+  const int lds_full = hdg::chain_lds_level(L.P, h->n, es, 65536 - rhs_bytes);
   EventPair ev;
   hipEvent_t e0 = ev.a, e1 = ev.b;
   float best = 1e30f;
@@ -844,7 +847,7 @@ void tune_chain(hdg_ctx* h, int p) {
   for (int th : {64, 128, 256, 512, 1024}) {
     if (th > hdg::chain_max_threads(L.P)) continue;
     for (int rm : {0, 1})
-      for (int ll : {lds_default, lds_staged, 64}) {
+      for (int ll : {lds_default, lds_staged, lds_full, 64}) {
         hdg::ChainArgs c{};
         c.factors = L.chain;
         c.cstride = L.cstride;
