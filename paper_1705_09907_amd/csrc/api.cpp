@@ -104,6 +104,24 @@ struct hdg_ctx {
   hdg::Prec prec = hdg::Prec::F64;      // precision of the multigrid cycle
   int nq = 0;
   std::unique_ptr<MultiWork> mw;        // solve for many right-hand sides
+
+  hdg_ctx() = default;
+  hdg_ctx(const hdg_ctx&) = delete;
+  hdg_ctx& operator=(const hdg_ctx&) = delete;
+  // Releases every resource, also after a failed hdg_create: work still queued
+  // on the stream finishes first.
+  ~hdg_ctx() {
+    const bool on_device = !allocs.empty() || mw || graph_exec || cap_stream || ev0 || scal_h;
+    if (on_device) (void)hipStreamSynchronize(stream);  // a rejected config made no device call
+    if (graph_exec) (void)hipGraphExecDestroy(graph_exec);
+    if (graph) (void)hipGraphDestroy(graph);
+    if (cap_stream) (void)hipStreamDestroy(cap_stream);
+    if (ev0) (void)hipEventDestroy(ev0);
+    if (ev1) (void)hipEventDestroy(ev1);
+    mw.reset();
+    for (void* q : allocs) (void)hipFree(q);
+    if (scal_h) (void)hipHostFree(scal_h);
+  }
 };
 
 namespace {
@@ -1251,15 +1269,7 @@ hdg_status_t hdg_create(const hdg_config_t* cfg, const double* kappa_host, void*
 
 hdg_status_t hdg_destroy(hdg_handle_t h) {
   if (!h) return HDG_ERR_INVALID_ARG;
-  (void)hipStreamSynchronize(h->stream);
-  if (h->graph_exec) (void)hipGraphExecDestroy(h->graph_exec);
-  if (h->graph) (void)hipGraphDestroy(h->graph);
-  if (h->cap_stream) (void)hipStreamDestroy(h->cap_stream);
-  if (h->ev0) (void)hipEventDestroy(h->ev0);
-  if (h->ev1) (void)hipEventDestroy(h->ev1);
-  for (void* p : h->allocs) (void)hipFree(p);
-  if (h->scal_h) (void)hipHostFree(h->scal_h);
-  delete h;
+  delete h;  // ~hdg_ctx releases everything
   return HDG_OK;
 }
 
