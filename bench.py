@@ -75,25 +75,40 @@ def algorithmic_bytes(n, k, prec="f64"):
     return blocks * P * P * MAT_BYTES[prec] + 2 * nf * P * VEC_BYTES[prec], 2 * blocks * P * P
 
 
-def cpu_baseline(sigma, seed, k, budget_s=12.0):
-    """The oracle's assembled-CSR apply (scipy, one thread) on a 64 x 64 sample of the
-    workload (same degree and coefficient law), repeated for about budget_s seconds."""
-    from oracle import hdg
+def cpu_baseline(sigma, seed, k, inner=None, budget_s=12.0):
+    """The oracle on a 64 x 64 sample of the workload (same degree and coefficient
+    law), on one host thread: its assembled-CSR apply (scipy), repeated for about
+    budget_s seconds, and its multigrid solve to 1e-10 (the workload's cycle:
+    flexible CG with the K-cycle when `inner` is set, else CG with the V-cycle)."""
+    from threadpoolctl import threadpool_limits
+    from oracle import hdg, mg
     from workloads import kappa_lognormal, normal_vector
     n = 64
     kap = kappa_lognormal(n, sigma, seed) if sigma else np.ones(n * n)
-    t0 = time.perf_counter()
-    S = hdg.Problem(n, k, kap).assemble()
-    t_setup = time.perf_counter() - t0
-    x = normal_vector(S.shape[0], 1)
-    reps, t0 = 0, time.perf_counter()
-    while time.perf_counter() - t0 < budget_s:
-        S @ x
-        reps += 1
-    dt = (time.perf_counter() - t0) / reps
+    with threadpool_limits(1):
+        t0 = time.perf_counter()
+        pr = hdg.Problem(n, k, kap)
+        S = pr.assemble()
+        t_setup = time.perf_counter() - t0
+        x = normal_vector(S.shape[0], 1)
+        reps, t0 = 0, time.perf_counter()
+        while time.perf_counter() - t0 < budget_s:
+            S @ x
+            reps += 1
+        dt = (time.perf_counter() - t0) / reps
+        b = pr.rhs(np.ones((n * n, (k + 2) ** 2)))
+        Ho = mg.Hierarchy(n, k, kap, inner=inner)
+        mode = "fcg" if inner else "pcg"
+        t0 = time.perf_counter()
+        _, hist = Ho.solve(b, mode=mode, rtol=1e-10, maxit=500)
+        t_solve = time.perf_counter() - t0
     return {"value": S.shape[0] / dt, "unit": "trace-DoF/s", "cores": 1, "kind": "oracle",
             "sample": f"oracle CSR S@x (scipy, 1 thread), n=64 k={k} sample of the workload, "
-                      f"{reps} reps over {budget_s:.0f}s; oracle assembly of that sample {t_setup:.1f}s"}
+                      f"{reps} reps over {budget_s:.0f}s; oracle assembly of that sample {t_setup:.1f}s",
+            "solve": {"value": S.shape[0] / t_solve, "unit": "trace-DoF solved per s",
+                      "solve_ms": t_solve * 1e3, "iters": len(hist) - 1, "cores": 1,
+                      "sample": f"oracle {mode} solve to 1e-10 of the same n=64 sample (f = 1), "
+                                f"{S.shape[0]} trace DoFs, one thread"}}
 
 
 def pmc_summary(fetch_db, write_db, kernel, calib=None):
@@ -476,6 +491,7 @@ def main():
         "apply_us_warm": None if warm_ms is None else warm_ms * 1e3,
         "solve_ms": float(np.median(solve_ms)), "solve_iters": iters, "solve_relres": relres,
         "solve_true_relres": true_relres,
+        "solve_dof_per_s": N / (float(np.median(solve_ms)) * 1e-3),
         "solve_rate": rho, "setup_s": setup_s, "rhs_s": rhs_s,
         "gradient_ms": grad_ms, "batch": batch_out,
         "f64_reference": f64_ref, "plain_vcycle_pcg_reference": plain_ref,
@@ -488,7 +504,7 @@ def main():
     if not lp:
         S.close()
     if not args.no_cpu_baseline:
-        out["cpu_baseline"] = cpu_baseline(w["sigma"], w["seed"], k)
+        out["cpu_baseline"] = cpu_baseline(w["sigma"], w["seed"], k, inner)
     print(json.dumps(out), flush=True)
 
 
