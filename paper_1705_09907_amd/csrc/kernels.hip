@@ -1480,10 +1480,24 @@ __global__ __launch_bounds__(kWG) void k_dot_partials(const double* a, const dou
   if (threadIdx.x == 0) partial[blockIdx.x] = t;
 }
 
+// Sum of np values by one workgroup in a fixed order: each thread keeps 8 loads
+// in flight (8 running sums, added in order at the end), then the fixed tree.
+__device__ __forceinline__ double thread_sum8(const double* v, int np) {
+  double s[8] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+  int i = threadIdx.x;
+  for (; i + 7 * kWG < np; i += 8 * kWG) {
+#pragma unroll
+    for (int u = 0; u < 8; ++u) s[u] += v[i + u * kWG];
+  }
+  for (; i < np; i += kWG) s[0] += v[i];
+  double t = 0.0;
+#pragma unroll
+  for (int u = 0; u < 8; ++u) t += s[u];
+  return t;
+}
+
 __global__ __launch_bounds__(kWG) void k_sum_partials(const double* partial, int np, double* out) {
-  double s = 0.0;
-  for (int i = threadIdx.x; i < np; i += kWG) s += partial[i];
-  const double t = block_sum(s);
+  const double t = block_sum(thread_sum8(partial, np));
   if (threadIdx.x == 0) *out = t;
 }
 
@@ -1504,9 +1518,7 @@ __global__ __launch_bounds__(kWG) void k_dots_partials(DotArgs a, int64_t n, dou
   }
 }
 __global__ __launch_bounds__(kWG) void k_sum_partials_multi(const double* partial, int np, double* out) {
-  double s = 0.0;
-  for (int i = threadIdx.x; i < np; i += kWG) s += partial[(int64_t)blockIdx.x * np + i];
-  const double t = block_sum(s);
+  const double t = block_sum(thread_sum8(partial + (int64_t)blockIdx.x * np, np));
   if (threadIdx.x == 0) out[blockIdx.x] = t;
 }
 
