@@ -1090,9 +1090,13 @@ __device__ __forceinline__ T q1_apply(const T* st, const T* x, int m, int64_t Nv
   for (int dj = -1; dj <= 1; ++dj)
 #pragma unroll
     for (int di = -1; di <= 1; ++di) {
+      // neighbours outside the interior read a clamped (existing) vertex and are
+      // zeroed: no load sits under a branch, and the stencil entries are finite
       const int ii = i + di, jj = j + dj;
-      if (ii >= 1 && jj >= 1 && ii <= m - 1 && jj <= m - 1)
-        s += st[(int64_t)((di + 1) + 3 * (dj + 1)) * Nv + v] * x[(ii - 1) + (int64_t)(m - 1) * (jj - 1)];
+      const bool ok = ii >= 1 && jj >= 1 && ii <= m - 1 && jj <= m - 1;
+      const int ic = min(max(ii, 1), m - 1), jc = min(max(jj, 1), m - 1);
+      const T xv = x[(ic - 1) + (int64_t)(m - 1) * (jc - 1)];
+      s += st[(int64_t)((di + 1) + 3 * (dj + 1)) * Nv + v] * (ok ? xv : T(0));
     }
   return s;
 }
