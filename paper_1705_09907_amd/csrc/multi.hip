@@ -165,17 +165,22 @@ __global__ __launch_bounds__(kMW) void k_q1_prolong_add_m(const T* ec, T* xf, in
   const int64_t v = idx / R;
   const int r = (int)(idx - v * R);
   const int I = (int)(v % (mf - 1)) + 1, J = (int)(v / (mf - 1)) + 1;
-  int xi[2], yi[2];
-  T wx[2], wy[2];
-  int nx, ny;
-  if ((I & 1) == 0) { xi[0] = I / 2; wx[0] = T(1); nx = 1; } else { xi[0] = I / 2; xi[1] = I / 2 + 1; wx[0] = wx[1] = T(0.5); nx = 2; }
-  if ((J & 1) == 0) { yi[0] = J / 2; wy[0] = T(1); ny = 1; } else { yi[0] = J / 2; yi[1] = J / 2 + 1; wy[0] = wy[1] = T(0.5); ny = 2; }
+  // bilinear weights over the 2 x 2 coarse vertices around (I, J): an even index
+  // has one parent (the second weight is 0); parents outside the interior read
+  // a clamped vertex and are zeroed, so no load sits under a branch
+  const int xi[2] = {I / 2, I / 2 + (I & 1)}, yi[2] = {J / 2, J / 2 + (J & 1)};
+  const T wx[2] = {(I & 1) ? T(0.5) : T(1), (I & 1) ? T(0.5) : T(0)};
+  const T wy[2] = {(J & 1) ? T(0.5) : T(1), (J & 1) ? T(0.5) : T(0)};
   T s = T(0);
-  for (int bb = 0; bb < ny; ++bb)
-    for (int aa = 0; aa < nx; ++aa) {
+#pragma unroll
+  for (int bb = 0; bb < 2; ++bb)
+#pragma unroll
+    for (int aa = 0; aa < 2; ++aa) {
       const int ci = xi[aa], cj = yi[bb];
-      if (ci >= 1 && cj >= 1 && ci <= mc - 1 && cj <= mc - 1)
-        s += wx[aa] * wy[bb] * ec[((ci - 1) + (int64_t)(mc - 1) * (cj - 1)) * R + r];
+      const bool ok = ci >= 1 && cj >= 1 && ci <= mc - 1 && cj <= mc - 1;
+      const int cic = min(max(ci, 1), mc - 1), cjc = min(max(cj, 1), mc - 1);
+      const T e = ec[((cic - 1) + (int64_t)(mc - 1) * (cjc - 1)) * R + r];
+      s += wx[aa] * wy[bb] * (ok ? e : T(0));
     }
   xf[idx] += s;
 }
@@ -211,8 +216,14 @@ __global__ __launch_bounds__(kMW) void k_pj_prolong_add_m(const T* ev, T* xface,
     ai = i; aj = j; bi = i + 1; bj = j;
   }
   T s = T(0);
-  if (ai >= 1 && aj >= 1 && ai <= n - 1 && aj <= n - 1) s += ev[((ai - 1) + (int64_t)(n - 1) * (aj - 1)) * R + r];
-  if (bi >= 1 && bj >= 1 && bi <= n - 1 && bj <= n - 1) s += ev[((bi - 1) + (int64_t)(n - 1) * (bj - 1)) * R + r];
+  {  // end vertices on the boundary read a clamped vertex and are zeroed
+    const bool oa = ai >= 1 && aj >= 1 && ai <= n - 1 && aj <= n - 1;
+    const bool ob = bi >= 1 && bj >= 1 && bi <= n - 1 && bj <= n - 1;
+    const T ea = ev[((min(max(ai, 1), n - 1) - 1) + (int64_t)(n - 1) * (min(max(aj, 1), n - 1) - 1)) * R + r];
+    const T eb = ev[((min(max(bi, 1), n - 1) - 1) + (int64_t)(n - 1) * (min(max(bj, 1), n - 1) - 1)) * R + r];
+    s += oa ? ea : T(0);
+    s += ob ? eb : T(0);
+  }
   xface[idx] += T(0.5) * s;
 }
 
