@@ -52,6 +52,7 @@ typedef enum {
 enum { HDG_SMOOTH_CHAIN = 0, HDG_SMOOTH_FACE = 1 };
 enum { HDG_COARSE_GALERKIN = 0, HDG_COARSE_REDISCRETIZE = 1 };
 enum { HDG_SOLVE_PCG = 0, HDG_SOLVE_VCYCLE = 1, HDG_SOLVE_FCG = 2 };
+enum { HDG_CYCLE_V = 0, HDG_CYCLE_W = 1 };
 /* Precision of the multigrid cycle (the preconditioner).  The outer solver, its
  * residuals and the finest-level operator it applies stay FP64 in every mode.
  *   HDG_PREC_F64:  every level, vector and block in FP64 (the paper's setting).
@@ -96,7 +97,8 @@ typedef struct {
                            of the cycle by m steps of flexible CG on S_p, each
                            preconditioned by one cycle from level p (an extension of the
                            paper's V-cycle; the cycle becomes nonlinear, so solve with
-                           HDG_SOLVE_FCG or HDG_SOLVE_VCYCLE).  0 (default): V-cycle.
+                           HDG_SOLVE_FCG or HDG_SOLVE_VCYCLE).  0 (default): the plain
+                           coarse correction of the cycle field below.
                            Range [0, 64]; must be 0 for p >= k.                          */
   int32_t graph;        /* 1: the solver's preconditioner (the whole cycle, Krylov-accelerated
                            levels included) is captured once as a HIP graph on a library
@@ -106,7 +108,12 @@ typedef struct {
                            XCD-aware chain order, LDS staging depth) of every level and keep
                            the fastest; 0 (default): measured fixed defaults.  Results are
                            identical either way (same operations in the same order).     */
-  int32_t reserved[6];
+  int32_t cycle;        /* HDG_CYCLE_V (default): each coarse correction is one cycle of the
+                           coarser level; HDG_CYCLE_W: two, the second started from the
+                           first's result (the W schedule the paper also reports, Sec. 7).
+                           Levels with inner_steps keep their Krylov correction; the
+                           coarsest level's exact solve runs once.                          */
+  int32_t reserved[5];
 } hdg_config_t;
 
 /* Defaults: tau 1, V(2,2), chain smoother, Galerkin p-levels, omega/lmax estimated,
@@ -222,13 +229,14 @@ hdg_status_t hdg_smooth(hdg_handle_t h, int32_t p, const double* b, double* x, i
 hdg_status_t hdg_restrict(hdg_handle_t h, int32_t p_fine, const double* r_fine, double* r_coarse);
 hdg_status_t hdg_prolong(hdg_handle_t h, int32_t p_fine, const double* e_coarse, double* x_fine);
 
-/* One V(nu1, nu2) cycle for S_k x = b starting from x (in place), run in the
- * cycle precision; b and x are FP64 in every mode. */
+/* One (nu1, nu2) multigrid cycle, with the V or W schedule of the handle's
+ * config, for S_k x = b starting from x (in place), run in the cycle
+ * precision; b and x are FP64 in every mode. */
 hdg_status_t hdg_vcycle(hdg_handle_t h, const double* b, double* x);
 
 /* Solve S_k x = b to ||b - S x||_2 <= rtol ||b||_2, x in: initial guess, out:
  * solution.  mode HDG_SOLVE_PCG (conjugate gradients preconditioned by one
- * V-cycle), HDG_SOLVE_FCG (flexible CG, FCG(1), with the same preconditioner;
+ * cycle, V or W by the config), HDG_SOLVE_FCG (flexible CG, FCG(1), with the same preconditioner;
  * required instead of PCG when inner_steps makes the cycle nonlinear -- PCG
  * then returns INVALID_ARG) or HDG_SOLVE_VCYCLE (repeated cycles, the paper's
  * stationary solver, applied as x += B (b - S x)).  iters, relres: host outputs (nullable); history_host: nullable

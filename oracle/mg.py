@@ -43,6 +43,10 @@ nu1 = nu2), so it also serves as a preconditioner for conjugate gradients
 (Sec. 6, p-transfer paragraph).  Convergence monitor: the residual ratio of
 Sec. 7; stop at ||b - S x||_2 <= rtol ||b||_2.
 
+W schedule (Sec. 7 reports W-cycles beside V-cycles): every coarse-grid
+correction is two cycles of the coarser level, the second started from the
+first's result; the coarsest exact solve is not repeated.
+
 Krylov-accelerated coarse levels (not in the paper; an extension of its
 cycle): the K-cycle of Notay and Vassilevski (Numer. Linear Algebra Appl. 15,
 2008).  On the p-levels named in `inner`, the coarse-grid correction is not
@@ -258,7 +262,10 @@ class Hierarchy:
 
     def __init__(self, n, k, kappa, tau=1.0, nu1=2, nu2=2, coarse='galerkin', smoother='chain',
                  omega=None, lmax=None, cheb_lo=0.1, cheb_hi=1.1, coarse_max=2000, blocks_k=None,
-                 inner=None):
+                 inner=None, cycle='V'):
+        if cycle not in ('V', 'W'):
+            raise ValueError("cycle must be 'V' or 'W'")
+        self.cycle = cycle
         self.n, self.k, self.nu1, self.nu2 = n, k, nu1, nu2
         self.inner = dict(inner or {})   # p-level -> flexible-CG steps of its coarse correction
         self.cheb_lo, self.cheb_hi = cheb_lo, cheb_hi
@@ -325,7 +332,8 @@ class Hierarchy:
         return chebyshev(L.A, L.dinv, L.lmax, self.cheb_lo, self.cheb_hi, b, x, nu)
 
     def vcycle(self, b, x, lev=0):
-        """One V(nu1, nu2) cycle at level index lev (Algs. algo_2 then algo_1)."""
+        """One (nu1, nu2) cycle at level index lev (Algs. algo_2 then algo_1), with
+        the V or W schedule of self.cycle."""
         L = self.levels[lev]
         if getattr(L, 'coarsest', False):
             return sla.cho_solve(L.chol, b)
@@ -338,6 +346,8 @@ class Hierarchy:
             ec = self.krylov_correction(lev + 1, rc, m)
         else:
             ec = self.vcycle(rc, np.zeros(rc.shape[0]), lev + 1)
+            if self.cycle == 'W' and not getattr(C, 'coarsest', False):
+                ec = self.vcycle(rc, ec, lev + 1)
         x = x + L.Pmat @ ec
         x = self.smooth(L, b, x, self.nu2)
         return x

@@ -23,6 +23,7 @@ HDG_MAX_HLEVELS = 24
 SMOOTHERS = {"chain": 0, "face": 1}
 COARSE = {"galerkin": 0, "rediscretize": 1}
 MODES = {"pcg": 0, "vcycle": 1, "fcg": 2}
+CYCLES = {"V": 0, "W": 1}
 PRECISIONS = {"f64": 0, "f32": 1, "bf16": 2}
 STATUS = {0: "ok", -1: "invalid argument", -2: "out of memory", -3: "HIP error",
           -4: "not converged", -5: "non-finite value", -6: "invalid state"}
@@ -37,7 +38,8 @@ class Config(ctypes.Structure):
                 ("cheb_lmax", ctypes.c_double * HDG_MAX_HLEVELS),
                 ("coarse_max", ctypes.c_int32), ("nq", ctypes.c_int32),
                 ("precision", ctypes.c_int32), ("inner_steps", ctypes.c_int32 * (HDG_MAX_DEGREE + 1)),
-                ("graph", ctypes.c_int32), ("autotune", ctypes.c_int32), ("reserved", ctypes.c_int32 * 6)]
+                ("graph", ctypes.c_int32), ("autotune", ctypes.c_int32), ("cycle", ctypes.c_int32),
+                ("reserved", ctypes.c_int32 * 5)]
 
 
 _P = ctypes.c_void_p
@@ -156,7 +158,7 @@ class Solver:
 
     def __init__(self, n, k, kappa, tau=1.0, nu1=2, nu2=2, smoother="chain", coarse="galerkin",
                  omega=None, cheb_lmax=None, cheb=(0.1, 1.1), coarse_max=2000, nq=None, stream=None,
-                 precision="f64", inner=None, graph=False, autotune=False):
+                 precision="f64", inner=None, graph=False, autotune=False, cycle="V"):
         import torch
         cfg = Config()
         lib.hdg_config_default(n, k, ctypes.byref(cfg))
@@ -178,6 +180,7 @@ class Solver:
             cfg.inner_steps[p] = m
         cfg.graph = 1 if graph else 0
         cfg.autotune = 1 if autotune else 0
+        cfg.cycle = CYCLES[cycle]
         self.n, self.k, self.nq, self.precision = n, k, cfg.nq, precision
         kap, kp = _host(kappa, "kappa", n * n)
         if stream is None:

@@ -628,18 +628,21 @@ void chebyshev(hdg_ctx* h, QLevel& Q, const void* b, int nu, bool zero) {
   if (cur != Q.x) hipchk(hdg::launch_copy(h->prec, cur, Q.x, Q.Nv, h->stream), "copy");
 }
 
-void qcycle(hdg_ctx* h, int l) {
+// Cycle at Q1 level l for A_l x = b (b in Q.b, x in Q.x); zero: x == 0 on
+// entry.  The W schedule repeats the coarse correction from its first result.
+void qcycle(hdg_ctx* h, int l, bool zero = true) {
   QLevel& Q = h->ql[l];
   const hdg::Prec pr = h->prec;
   if (Q.coarsest) {
     hipchk(hdg::launch_dense_gemv(pr, Q.inv, Q.b, Q.x, (int)Q.Nv, h->stream), "coarse solve");
     return;
   }
-  chebyshev(h, Q, Q.b, h->cfg.nu1, true);
+  chebyshev(h, Q, Q.b, h->cfg.nu1, zero);
   hipchk(hdg::launch_q1_resid(pr, Q.st, Q.b, Q.x, Q.r, Q.m, h->stream), "q1 resid");
   QLevel& C = h->ql[l + 1];
   hipchk(hdg::launch_q1_restrict(pr, Q.r, C.b, Q.m, h->stream), "q1 restrict");
-  qcycle(h, l + 1);
+  qcycle(h, l + 1, true);
+  if (h->cfg.cycle == HDG_CYCLE_W && !C.coarsest) qcycle(h, l + 1, false);
   hipchk(hdg::launch_q1_prolong_add(pr, C.x, Q.x, Q.m, h->stream), "q1 prolong");
   chebyshev(h, Q, Q.b, h->cfg.nu2, false);
 }
@@ -660,14 +663,19 @@ void pcycle(hdg_ctx* h, int p, const void* b, void* x, bool zero) {
     a.b = b;
     a.y = C.b;
     hipchk(hdg::launch_trace(L.mp, L.P, hdg::TM_RESID_RESTRICT, a, h->stream), "resid restrict");
-    if (C.inner > 0) krylov_correction(h, p - 1, C.b, C.x, C.inner);
-    else pcycle(h, p - 1, C.b, C.x, true);
+    if (C.inner > 0) {
+      krylov_correction(h, p - 1, C.b, C.x, C.inner);
+    } else {
+      pcycle(h, p - 1, C.b, C.x, true);
+      if (h->cfg.cycle == HDG_CYCLE_W) pcycle(h, p - 1, C.b, C.x, false);
+    }
     hipchk(hdg::launch_p_prolong_add(pr, L.P, L.pmat, C.x, x, h->nf, h->stream), "p prolong");
   } else {
     residual(h, 0, b, x, L.r, false, pr);
     QLevel& Q = h->ql[0];
     hipchk(hdg::launch_pj_restrict(pr, L.r, Q.b, h->n, h->stream), "pj restrict");
-    qcycle(h, 0);
+    qcycle(h, 0, true);
+    if (h->cfg.cycle == HDG_CYCLE_W && !Q.coarsest) qcycle(h, 0, false);
     hipchk(hdg::launch_pj_prolong_add(pr, Q.x, x, h->n, h->stream), "pj prolong");
   }
   smooth(h, p, b, x, h->cfg.nu2, false);
@@ -1054,22 +1062,23 @@ void chebyshev_m(hdg_ctx* h, MultiWork& W, int l, int nu, bool zero) {
   if (cur != W.qx[l]) hipchk(hdg::launch_copy(h->prec, cur, W.qx[l], Q.Nv * W.R, h->stream), "copy");
 }
 
-void qcycle_m(hdg_ctx* h, MultiWork& W, int l) {
+void qcycle_m(hdg_ctx* h, MultiWork& W, int l, bool zero = true) {
   QLevel& Q = h->ql[l];
   const hdg::Prec pr = h->prec;
   if (Q.coarsest) {
     hipchk(hdg::launch_dense_gemm_m(pr, Q.inv, W.qb[l], W.qx[l], (int)Q.Nv, W.R, h->stream), "coarse solve multi");
     return;
   }
-  chebyshev_m(h, W, l, h->cfg.nu1, true);
+  chebyshev_m(h, W, l, h->cfg.nu1, zero);
   hipchk(hdg::launch_q1_resid_m(pr, Q.st, W.qb[l], W.qx[l], W.qr[l], Q.m, W.R, h->stream), "q1 resid multi");
   hipchk(hdg::launch_q1_restrict_m(pr, W.qr[l], W.qb[l + 1], Q.m, W.R, h->stream), "q1 restrict multi");
-  qcycle_m(h, W, l + 1);
+  qcycle_m(h, W, l + 1, true);
+  if (h->cfg.cycle == HDG_CYCLE_W && !h->ql[l + 1].coarsest) qcycle_m(h, W, l + 1, false);
   hipchk(hdg::launch_q1_prolong_add_m(pr, W.qx[l + 1], W.qx[l], Q.m, W.R, h->stream), "q1 prolong multi");
   chebyshev_m(h, W, l, h->cfg.nu2, false);
 }
 
-// The V-cycle of pcycle for every column at once (chain smoother; Krylov
+// The cycle of pcycle (V or W) for every column at once (chain smoother; Krylov
 // acceleration of coarse levels is not applied here).
 void pcycle_m(hdg_ctx* h, MultiWork& W, int p, const void* b, void* x, bool zero) {
   PLevel& L = h->pl[p];
@@ -1082,6 +1091,7 @@ void pcycle_m(hdg_ctx* h, MultiWork& W, int p, const void* b, void* x, bool zero
     a.Y = W.pb[p - 1];
     hipchk(hdg::launch_trace_multi(L.mp, L.P, a, h->stream, hdg::TM_RESID_RESTRICT), "resid restrict multi");
     pcycle_m(h, W, p - 1, W.pb[p - 1], W.px[p - 1], true);
+    if (h->cfg.cycle == HDG_CYCLE_W) pcycle_m(h, W, p - 1, W.pb[p - 1], W.px[p - 1], false);
     hipchk(hdg::launch_p_prolong_add_m(pr, L.P, L.pmat, W.px[p - 1], x, h->nf, W.R, h->stream), "p prolong multi");
   } else {
     hdg::MultiArgs a = margs(h, L, W.R, false);
@@ -1090,7 +1100,8 @@ void pcycle_m(hdg_ctx* h, MultiWork& W, int p, const void* b, void* x, bool zero
     a.Y = W.pr[0];
     hipchk(hdg::launch_trace_multi(L.mp, L.P, a, h->stream, hdg::TM_RESID), "residual multi");
     hipchk(hdg::launch_pj_restrict_m(pr, W.pr[0], W.qb[0], h->n, W.R, h->stream), "pj restrict multi");
-    qcycle_m(h, W, 0);
+    qcycle_m(h, W, 0, true);
+    if (h->cfg.cycle == HDG_CYCLE_W && !h->ql[0].coarsest) qcycle_m(h, W, 0, false);
     hipchk(hdg::launch_pj_prolong_add_m(pr, W.qx[0], x, h->n, W.R, h->stream), "pj prolong multi");
   }
   smooth_m(h, W, p, b, x, h->cfg.nu2, false);
@@ -1124,6 +1135,7 @@ void validate_config(const hdg_config_t* c) {
     throw ArgError("bad precision");
   if (c->graph != 0 && c->graph != 1) throw ArgError("graph must be 0 or 1");
   if (c->autotune != 0 && c->autotune != 1) throw ArgError("autotune must be 0 or 1");
+  if (c->cycle != HDG_CYCLE_V && c->cycle != HDG_CYCLE_W) throw ArgError("cycle must be HDG_CYCLE_V or HDG_CYCLE_W");
   for (int p = 0; p <= HDG_MAX_DEGREE; ++p) {
     if (c->inner_steps[p] < 0 || c->inner_steps[p] > 64) throw ArgError("inner_steps must be in [0, 64]");
     if (p >= c->k && c->inner_steps[p] != 0) throw ArgError("inner_steps[p] must be 0 for p >= k");

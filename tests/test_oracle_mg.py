@@ -199,3 +199,59 @@ def test_kcycle_solution_matches_direct_in_fewer_iterations(inner):
     assert hk[-1] <= 1e-10 * np.linalg.norm(b)
     assert np.linalg.norm(x - pr.solve_direct(b)) <= 1e-9 * np.linalg.norm(x)
     assert len(hk) < len(hv)
+
+
+def test_wcycle_with_two_levels_is_the_vcycle():
+    """With one coarse level solved exactly, repeating the coarse correction changes
+    nothing: the W schedule skips it, and W equals V to the bit."""
+    n, k = 16, 0
+    kap = kappa_lognormal(n, 1.0, 6)
+    Hv, Hw = mg.Hierarchy(n, k, kap), mg.Hierarchy(n, k, kap, cycle='W')
+    assert len(Hv.levels) == 2 and Hv.levels[1].coarsest
+    b = np.random.default_rng(3).standard_normal(Hv.levels[0].A.shape[0])
+    assert np.array_equal(Hv.vcycle(b, np.zeros_like(b)), Hw.vcycle(b, np.zeros_like(b)))
+
+
+@pytest.mark.parametrize("smoother", ["chain", "face"])
+def test_wcycle_symmetric(smoother):
+    """nu1 = nu2, R = P^T and symmetric smoothers make the W-cycle operator
+    symmetric too (it is then a valid preconditioner for CG)."""
+    n, k = 8, 2
+    H = mg.Hierarchy(n, k, kappa_lognormal(n, 1.0, 6), smoother=smoother, coarse_max=10, cycle='W')
+    assert len(H.levels) >= 5
+    N = ms.n_trace_dofs(n, k)
+    rng = np.random.default_rng(2)
+    x, y = rng.standard_normal(N), rng.standard_normal(N)
+    Bx, By = H.vcycle(x, np.zeros(N)), H.vcycle(y, np.zeros(N))
+    assert abs(Bx @ y - x @ By) < 1e-11 * abs(Bx @ y)
+
+
+def test_wcycle_contracts_faster_than_vcycle():
+    """Stationary iteration on S e = 0 (the error itself): after 4 cycles the
+    W schedule leaves less error in the energy norm than the V schedule, on a
+    hierarchy with 6 levels."""
+    n, k = 16, 2
+    kap = kappa_lognormal(n, 1.0, 6)
+    Hv = mg.Hierarchy(n, k, kap, coarse_max=10)
+    Hw = mg.Hierarchy(n, k, kap, coarse_max=10, cycle='W')
+    assert len(Hv.levels) == 6
+    S = Hv.levels[0].A
+    e0 = np.random.default_rng(4).standard_normal(S.shape[0])
+    ev, ew = e0.copy(), e0.copy()
+    z = np.zeros_like(e0)
+    for _ in range(4):
+        ev, ew = Hv.vcycle(z, ev), Hw.vcycle(z, ew)
+    energy = lambda v: float(np.sqrt(v @ (S @ v)))
+    assert energy(ew) < energy(ev) < energy(e0)
+
+
+def test_wcycle_pcg_matches_direct():
+    n, k = 16, 3
+    kap = kappa_lognormal(n, 1.0, 7)
+    pr = hdg.Problem(n, k, kap)
+    b = pr.rhs(np.ones((n * n, pr.ref.nq ** 2)))
+    H = mg.Hierarchy(n, k, kap, cycle='W')
+    x, hist = H.solve(b, mode='pcg', rtol=1e-10, maxit=200)
+    assert hist[-1] <= 1e-10 * np.linalg.norm(b)
+    xd = pr.solve_direct(b)
+    assert np.linalg.norm(x - xd) <= 1e-9 * np.linalg.norm(xd)
