@@ -1,7 +1,8 @@
 """GPU: trace apply for many right-hand sides at once (Y = S X, X [N, nrhs]).
 
 Bars: FP64 against the oracle's assembled S times X, 1e-12 relative (max norm),
-on every level, ragged tails and nrhs not a multiple of 64; each column equals
+on every level, ragged tails, nrhs a multiple of 64 (whole wavefronts per face,
+one or several 64-column chunks) or not; each column equals
 the single-vector apply to 1e-14 (same summation order); FP32 and bfloat16
 blocks obey the row-wise rounding bound of the reduced-precision apply; the
 full-size batch (n = 512, k = 5, 64 right-hand sides) on sampled faces.
@@ -32,7 +33,8 @@ def rel_inf(a, b):
     return np.abs(a - b).max() / max(np.abs(b).max(), 1e-300)
 
 
-@pytest.mark.parametrize("n,k,R", [(2, 1, 3), (16, 2, 64), (24, 3, 100), (19, 5, 1), (13, 8, 65), (16, 0, 7)])
+@pytest.mark.parametrize("n,k,R", [(2, 1, 3), (16, 2, 64), (24, 3, 100), (19, 5, 1), (13, 8, 65), (16, 0, 7),
+                                   (2, 1, 64), (13, 8, 128), (19, 5, 192), (17, 0, 64)])
 def test_multi_apply_every_level_fp64(n, k, R):
     print(f"case multi apply n={n} k={k} R={R}", flush=True)
     kap = kappa_lognormal(n, 1.0, 3)
@@ -56,8 +58,9 @@ def test_multi_apply_every_level_fp64(n, k, R):
 
 
 @pytest.mark.parametrize("prec", ["f32", "bf16"])
-def test_multi_apply_reduced_precision_bound(prec):
-    n, k, R = 24, 3, 64
+@pytest.mark.parametrize("R", [64, 128, 40])
+def test_multi_apply_reduced_precision_bound(prec, R):
+    n, k = 24, 3
     kap = kappa_lognormal(n, 2.0, 5)
     Ho = mg.Hierarchy(n, k, kap, smoother="face", omega=0.7)
     S = H.Solver(n, k, kap, precision=prec)

@@ -24,7 +24,8 @@ def host(t):
 
 @pytest.mark.parametrize("n,k,sigma,R,prec", [(24, 3, 1.0, 5, "f64"), (16, 2, 2.0, 64, "f64"),
                                               (24, 3, 1.0, 17, "f32"), (2, 1, 1.0, 3, "f64"),
-                                              (16, 0, 1.0, 8, "f64"), (19, 4, 1.0, 2, "bf16")])
+                                              (16, 0, 1.0, 8, "f64"), (19, 4, 1.0, 2, "bf16"),
+                                              (24, 3, 1.0, 128, "f32"), (17, 4, 1.0, 64, "bf16")])
 def test_multi_solve_matches_direct_and_single(n, k, sigma, R, prec):
     print(f"case multi solve n={n} k={k} R={R} {prec}", flush=True)
     kap = kappa_lognormal(n, sigma, 12)
