@@ -234,6 +234,16 @@ hdg_status_t hdg_prolong(hdg_handle_t h, int32_t p_fine, const double* e_coarse,
  * precision; b and x are FP64 in every mode. */
 hdg_status_t hdg_vcycle(hdg_handle_t h, const double* b, double* x);
 
+/* One full-multigrid pass (Sec. 7) for S_k x = b from nothing: b is restricted
+ * to every level (R = P^T, the right-hand sides of the Galerkin coarse systems),
+ * the coarsest Q1 system is solved exactly, and on each finer level (Q1 levels,
+ * then p = 0 .. k) the prolonged coarser result starts `cycles` cycles of that
+ * level (V or W by the config).  b, x: device FP64 [N(k)]; x is written, not
+ * read, and must not alias b; cycles in [1, 64], else INVALID_ARG.  Runs in the
+ * cycle precision.  An exact solution in the range of the prolongations from
+ * the coarsest level is reproduced to rounding. */
+hdg_status_t hdg_fmg(hdg_handle_t h, const double* b, double* x, int32_t cycles);
+
 /* Solve S_k x = b to ||b - S x||_2 <= rtol ||b||_2, x in: initial guess, out:
  * solution.  mode HDG_SOLVE_PCG (conjugate gradients preconditioned by one
  * cycle, V or W by the config), HDG_SOLVE_FCG (flexible CG, FCG(1), with the same preconditioner;

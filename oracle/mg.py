@@ -371,6 +371,22 @@ class Hierarchy:
             r = r - alpha * q
         return e
 
+    def fmg(self, b, cycles=1):
+        """One full-multigrid pass (Sec. 7) for S x = b from nothing: b is
+        restricted to every level (b_{l+1} = P_l^T b_l, the right-hand sides of
+        the Galerkin coarse systems), the coarsest system is solved exactly, and
+        on each finer level the prolonged coarser result starts `cycles` cycles
+        of that level (V or W by self.cycle).  Returns the finest iterate."""
+        bs = [b]
+        for L in self.levels[:-1]:
+            bs.append(L.Pmat.T @ bs[-1])
+        x = sla.cho_solve(self.levels[-1].chol, bs[-1])
+        for lev in range(len(self.levels) - 2, -1, -1):
+            x = self.levels[lev].Pmat @ x
+            for _ in range(cycles):
+                x = self.vcycle(bs[lev], x, lev)
+        return x
+
     def solve(self, b, x0=None, rtol=1e-10, maxit=200, mode='pcg'):
         """Solve S x = b to ||r||_2 <= rtol ||b||_2.
 

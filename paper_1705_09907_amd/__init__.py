@@ -71,6 +71,7 @@ SIGNATURES = {
     "hdg_restrict": [_P, _I32, _P, _P],
     "hdg_prolong": [_P, _I32, _P, _P],
     "hdg_vcycle": [_P, _P, _P],
+    "hdg_fmg": [_P, _P, _P, _I32],
     "hdg_solve": [_P, _P, _P, _D, _I32, _I32, _PI32, _PD, _PD],
     "hdg_solve_multi": [_P, _I32, _P, _P, _D, _I32, _PI32, _PD],
     "hdg_reconstruct": [_P, _P, _P, _P],
@@ -84,7 +85,7 @@ _RESTYPES = {"hdg_last_error": ctypes.c_char_p, "hdg_status_string": ctypes.c_ch
 
 def load_library(path=LIB_PATH):
     if not os.path.exists(path):
-        raise ImportError(f"{path} is missing: build it with `python -m paper_1705_09907_amd.build` "
+        raise ImportError(f"{path} is missing: build it with `python paper_1705_09907_amd/build.py` "
                           "(there is no CPU fallback)")
     lib = ctypes.CDLL(path)
     for name, args in SIGNATURES.items():
@@ -325,6 +326,14 @@ class Solver:
     def vcycle(self, b, x):
         N = self.num_dofs()
         self._check(lib.hdg_vcycle(self._h, _dptr(b, "b", N), _dptr(x, "x", N)))
+        return x
+
+    def fmg(self, b, x=None, cycles=1):
+        """One full-multigrid pass for S_k x = b (x is overwritten); returns x."""
+        N = self.num_dofs()
+        if x is None:
+            x = torch.empty_like(b)
+        self._check(lib.hdg_fmg(self._h, _dptr(b, "b", N), _dptr(x, "x", N), int(cycles)))
         return x
 
     # ------------------------------------------------ misfit gradient (adjoint)

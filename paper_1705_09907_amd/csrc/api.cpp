@@ -681,6 +681,45 @@ void pcycle(hdg_ctx* h, int p, const void* b, void* x, bool zero) {
   smooth(h, p, b, x, h->cfg.nu2, false);
 }
 
+// Full multigrid (Sec. 7) in the cycle precision: b restricted to every level
+// (the right-hand sides of the Galerkin coarse systems), the coarsest solved
+// exactly, then on each finer level the prolonged coarser result starts
+// `cycles` cycles of that level.  x (finest) is written, not read.  Each coarse
+// level's b and x are its own work vectors, which the cycles of the finer
+// levels reuse only after that level is done.
+void fmg(hdg_ctx* h, const void* b, void* x, int cycles) {
+  const hdg::Prec pr = h->prec;
+  const int k = h->k;
+  const void* bf = b;
+  for (int p = k; p >= 1; --p) {
+    hipchk(hdg::launch_p_restrict(pr, h->pl[p].P, h->pl[p].pmat, bf, h->pl[p - 1].b, h->nf, h->stream),
+           "fmg p restrict");
+    bf = h->pl[p - 1].b;
+  }
+  hipchk(hdg::launch_pj_restrict(pr, bf, h->ql[0].b, h->n, h->stream), "fmg pj restrict");
+  int lq = 0;
+  for (; !h->ql[lq].coarsest; ++lq)
+    hipchk(hdg::launch_q1_restrict(pr, h->ql[lq].b, h->ql[lq + 1].b, h->ql[lq].m, h->stream), "fmg q1 restrict");
+  qcycle(h, lq, true);  // the coarsest level's exact solve
+  for (int l = lq - 1; l >= 0; --l) {
+    QLevel& Q = h->ql[l];
+    hipchk(hdg::launch_zero(pr, Q.x, Q.Nv, h->stream), "zero");
+    hipchk(hdg::launch_q1_prolong_add(pr, h->ql[l + 1].x, Q.x, Q.m, h->stream), "fmg q1 prolong");
+    for (int c = 0; c < cycles; ++c) qcycle(h, l, false);
+  }
+  for (int p = 0; p <= k; ++p) {
+    PLevel& L = h->pl[p];
+    void* xp = p == k ? x : L.x;
+    const void* bp = p == k ? b : L.b;
+    hipchk(hdg::launch_zero(pr, xp, L.N, h->stream), "zero");
+    if (p == 0)
+      hipchk(hdg::launch_pj_prolong_add(pr, h->ql[0].x, xp, h->n, h->stream), "fmg pj prolong");
+    else
+      hipchk(hdg::launch_p_prolong_add(pr, L.P, L.pmat, h->pl[p - 1].x, xp, h->nf, h->stream), "fmg p prolong");
+    for (int c = 0; c < cycles; ++c) pcycle(h, p, bp, xp, false);
+  }
+}
+
 // K-cycle coarse correction (Notay-Vassilevski): m steps of flexible CG, FCG(1),
 // for S_p e = r from e = 0, each preconditioned by one cycle started at level p.
 // r is overwritten (it becomes the running residual).  Direction update
@@ -1609,6 +1648,20 @@ hdg_status_t hdg_prolong(hdg_handle_t h, int32_t p_fine, const double* e_coarse,
     hipchk(hdg::launch_p_prolong_add(hdg::Prec::F64, p_fine + 1, h->pl[p_fine].pmat64, e_coarse, x_fine, h->nf,
                                      h->stream),
            "prolong");
+    return HDG_OK;
+  });
+}
+
+hdg_status_t hdg_fmg(hdg_handle_t h, const double* b, double* x, int32_t cycles) {
+  if (!h || !b || !x || b == x || cycles < 1 || cycles > 64) return HDG_ERR_INVALID_ARG;
+  return guarded(h, [&]() -> hdg_status_t {
+    const int64_t N = h->pl[h->k].N;
+    if (h->prec == hdg::Prec::F64) {
+      fmg(h, b, x, cycles);
+    } else {
+      fmg(h, stage_in(h, b, h->cva, N), h->cvb, cycles);
+      stage_out(h, h->cvb, x, N);
+    }
     return HDG_OK;
   });
 }

@@ -255,3 +255,40 @@ def test_wcycle_pcg_matches_direct():
     assert hist[-1] <= 1e-10 * np.linalg.norm(b)
     xd = pr.solve_direct(b)
     assert np.linalg.norm(x - xd) <= 1e-9 * np.linalg.norm(xd)
+
+
+@pytest.mark.parametrize("n,k", [(16, 2), (8, 3), (16, 0)])
+def test_fmg_reproduces_solutions_in_the_coarsest_range(n, k):
+    """With Galerkin coarse systems, x* = P_0 P_1 ... y on the coarsest level makes
+    the coarsest system's solution y itself; prolonged, it is x*, and the cycles
+    leave an exact solution alone.  A wrong restriction, a prolongation paired
+    with the wrong level or a skipped level breaks this."""
+    H = mg.Hierarchy(n, k, kappa_lognormal(n, 1.0, 8), coarse_max=10)
+    assert len(H.levels) >= 3
+    x = np.random.default_rng(n + k).standard_normal(H.levels[-1].A.shape[0])
+    for lev in range(len(H.levels) - 2, -1, -1):
+        x = H.levels[lev].Pmat @ x
+    xf = H.fmg(H.levels[0].A @ x)
+    assert np.linalg.norm(xf - x) <= 1e-12 * np.linalg.norm(x)
+
+
+def _sinsin_errors(n, k, lam, pr, fq, lam_bd):
+    Qs, Us = pr.reconstruct(lam, fq, lam_bd)
+    return np.array(pr.l2_errors(Qs, Us, SinSin.u, SinSin.q))
+
+
+@pytest.mark.parametrize("n", [16, 32])
+def test_fmg_reaches_discretization_error_at_k1(n):
+    """Sec. 7: one FMG pass lands at the discretization error.  For k = 1 with the
+    chain-Schwarz V(2,2) cycle, ||u - u_h|| and ||q - q_h|| after one pass with two
+    cycles per level are within 1% of those of the exact discrete solution, and
+    within 40% with one cycle per level (the manufactured sin-sin solution)."""
+    k = 1
+    pr = hdg.Problem(n, k, np.ones(n * n))
+    fq = pr.f_at_points(SinSin.f)
+    lam_bd = pr.boundary_trace(SinSin.u)
+    b = pr.rhs(fq, lam_bd=lam_bd)
+    e0 = _sinsin_errors(n, k, pr.solve_direct(b), pr, fq, lam_bd)
+    H = mg.Hierarchy(n, k, np.ones(n * n))
+    assert np.all(_sinsin_errors(n, k, H.fmg(b, cycles=2), pr, fq, lam_bd) <= 1.01 * e0)
+    assert np.all(_sinsin_errors(n, k, H.fmg(b, cycles=1), pr, fq, lam_bd) <= 1.4 * e0)
