@@ -25,6 +25,24 @@ def test_library_exports_every_declared_symbol():
         assert name in H.SIGNATURES, f"binding lacks {name}"
 
 
+def _handle_entries():
+    out = []
+    for name in declared_functions():
+        args = H.SIGNATURES[name]
+        if args and args[0] is H._P and name not in ("hdg_last_error", "hdg_apply_trace_operator_batch"):
+            out.append(name)
+    return out
+
+
+@pytest.mark.parametrize("name", _handle_entries())
+def test_null_handle_is_rejected_before_any_device_call(name):
+    """Every entry point that takes a handle returns HDG_ERR_INVALID_ARG for a null
+    handle (all other arguments zero or null), touching neither host nor device memory."""
+    zero = {H._P: None, H._PD: None, H._PI32: None, H._PI64: None, H._I32: 0, H._I64: 0, H._D: 0.0}
+    args = [zero[t] for t in H.SIGNATURES[name]]
+    assert getattr(H.lib, name)(*args) == -1, name
+
+
 @pytest.mark.parametrize("n,k,p,kappa,coarse", [
     (4, 0, 0, 1.0, "galerkin"), (16, 1, 1, 3.7, "galerkin"), (256, 4, 4, 0.3, "galerkin"),
     (1024, 3, 3, 57.0, "galerkin"), (8, 3, 1, 2.0, "galerkin"), (8, 4, 0, 0.01, "galerkin"),
