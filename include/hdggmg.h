@@ -52,7 +52,7 @@ typedef enum {
 enum { HDG_SMOOTH_CHAIN = 0, HDG_SMOOTH_FACE = 1 };
 enum { HDG_COARSE_GALERKIN = 0, HDG_COARSE_REDISCRETIZE = 1 };
 enum { HDG_SOLVE_PCG = 0, HDG_SOLVE_VCYCLE = 1, HDG_SOLVE_FCG = 2 };
-enum { HDG_CYCLE_V = 0, HDG_CYCLE_W = 1 };
+enum { HDG_CYCLE_V = 0, HDG_CYCLE_W = 1, HDG_CYCLE_WH = 2 };
 /* Precision of the multigrid cycle (the preconditioner).  The outer solver, its
  * residuals and the finest-level operator it applies stay FP64 in every mode.
  *   HDG_PREC_F64:  every level, vector and block in FP64 (the paper's setting).
@@ -110,7 +110,9 @@ typedef struct {
                            identical either way (same operations in the same order).     */
   int32_t cycle;        /* HDG_CYCLE_V (default): each coarse correction is one cycle of the
                            coarser level; HDG_CYCLE_W: two, the second started from the
-                           first's result (the W schedule the paper also reports, Sec. 7).
+                           first's result (the W schedule the paper also reports, Sec. 7);
+                           HDG_CYCLE_WH: W on the corrections onto Q1 levels (the p = 0 -> Q1
+                           step and the h-levels), V on the p-levels (not in the paper).
                            Levels with inner_steps keep their Krylov correction; the
                            coarsest level's exact solve runs once.                          */
   int32_t reserved[5];

@@ -45,7 +45,10 @@ Sec. 7; stop at ||b - S x||_2 <= rtol ||b||_2.
 
 W schedule (Sec. 7 reports W-cycles beside V-cycles): every coarse-grid
 correction is two cycles of the coarser level, the second started from the
-first's result; the coarsest exact solve is not repeated.
+first's result; the coarsest exact solve is not repeated.  The hybrid 'WH'
+(not in the paper) repeats only corrections onto Q1 levels (the p = 0 -> Q1
+step and the h-levels), where each level costs a quarter of the one above, and
+keeps the V schedule on the p-levels.
 
 Krylov-accelerated coarse levels (not in the paper; an extension of its
 cycle): the K-cycle of Notay and Vassilevski (Numer. Linear Algebra Appl. 15,
@@ -263,8 +266,8 @@ class Hierarchy:
     def __init__(self, n, k, kappa, tau=1.0, nu1=2, nu2=2, coarse='galerkin', smoother='chain',
                  omega=None, lmax=None, cheb_lo=0.1, cheb_hi=1.1, coarse_max=2000, blocks_k=None,
                  inner=None, cycle='V'):
-        if cycle not in ('V', 'W'):
-            raise ValueError("cycle must be 'V' or 'W'")
+        if cycle not in ('V', 'W', 'WH'):
+            raise ValueError("cycle must be 'V', 'W' or 'WH'")
         self.cycle = cycle
         self.n, self.k, self.nu1, self.nu2 = n, k, nu1, nu2
         self.inner = dict(inner or {})   # p-level -> flexible-CG steps of its coarse correction
@@ -331,6 +334,13 @@ class Hierarchy:
             return x
         return chebyshev(L.A, L.dinv, L.lmax, self.cheb_lo, self.cheb_hi, b, x, nu)
 
+    def _repeat(self, C):
+        """Whether the coarse correction onto level C is taken twice: every level
+        under 'W', the Q1 levels only under 'WH'; never the coarsest."""
+        if getattr(C, 'coarsest', False):
+            return False
+        return self.cycle == 'W' or (self.cycle == 'WH' and C.kind == 'q')
+
     def vcycle(self, b, x, lev=0):
         """One (nu1, nu2) cycle at level index lev (Algs. algo_2 then algo_1), with
         the V or W schedule of self.cycle."""
@@ -346,7 +356,7 @@ class Hierarchy:
             ec = self.krylov_correction(lev + 1, rc, m)
         else:
             ec = self.vcycle(rc, np.zeros(rc.shape[0]), lev + 1)
-            if self.cycle == 'W' and not getattr(C, 'coarsest', False):
+            if self._repeat(C):
                 ec = self.vcycle(rc, ec, lev + 1)
         x = x + L.Pmat @ ec
         x = self.smooth(L, b, x, self.nu2)

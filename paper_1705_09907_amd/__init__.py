@@ -23,7 +23,7 @@ HDG_MAX_HLEVELS = 24
 SMOOTHERS = {"chain": 0, "face": 1}
 COARSE = {"galerkin": 0, "rediscretize": 1}
 MODES = {"pcg": 0, "vcycle": 1, "fcg": 2}
-CYCLES = {"V": 0, "W": 1}
+CYCLES = {"V": 0, "W": 1, "WH": 2}
 PRECISIONS = {"f64": 0, "f32": 1, "bf16": 2}
 STATUS = {0: "ok", -1: "invalid argument", -2: "out of memory", -3: "HIP error",
           -4: "not converged", -5: "non-finite value", -6: "invalid state"}

@@ -629,7 +629,7 @@ void chebyshev(hdg_ctx* h, QLevel& Q, const void* b, int nu, bool zero) {
 }
 
 // Cycle at Q1 level l for A_l x = b (b in Q.b, x in Q.x); zero: x == 0 on
-// entry.  The W schedule repeats the coarse correction from its first result.
+// entry.  The W and WH schedules repeat the coarse correction from its first result.
 void qcycle(hdg_ctx* h, int l, bool zero = true) {
   QLevel& Q = h->ql[l];
   const hdg::Prec pr = h->prec;
@@ -642,7 +642,7 @@ void qcycle(hdg_ctx* h, int l, bool zero = true) {
   QLevel& C = h->ql[l + 1];
   hipchk(hdg::launch_q1_restrict(pr, Q.r, C.b, Q.m, h->stream), "q1 restrict");
   qcycle(h, l + 1, true);
-  if (h->cfg.cycle == HDG_CYCLE_W && !C.coarsest) qcycle(h, l + 1, false);
+  if (h->cfg.cycle != HDG_CYCLE_V && !C.coarsest) qcycle(h, l + 1, false);
   hipchk(hdg::launch_q1_prolong_add(pr, C.x, Q.x, Q.m, h->stream), "q1 prolong");
   chebyshev(h, Q, Q.b, h->cfg.nu2, false);
 }
@@ -675,7 +675,7 @@ void pcycle(hdg_ctx* h, int p, const void* b, void* x, bool zero) {
     QLevel& Q = h->ql[0];
     hipchk(hdg::launch_pj_restrict(pr, L.r, Q.b, h->n, h->stream), "pj restrict");
     qcycle(h, 0, true);
-    if (h->cfg.cycle == HDG_CYCLE_W && !Q.coarsest) qcycle(h, 0, false);
+    if (h->cfg.cycle != HDG_CYCLE_V && !Q.coarsest) qcycle(h, 0, false);
     hipchk(hdg::launch_pj_prolong_add(pr, Q.x, x, h->n, h->stream), "pj prolong");
   }
   smooth(h, p, b, x, h->cfg.nu2, false);
@@ -1112,7 +1112,7 @@ void qcycle_m(hdg_ctx* h, MultiWork& W, int l, bool zero = true) {
   hipchk(hdg::launch_q1_resid_m(pr, Q.st, W.qb[l], W.qx[l], W.qr[l], Q.m, W.R, h->stream), "q1 resid multi");
   hipchk(hdg::launch_q1_restrict_m(pr, W.qr[l], W.qb[l + 1], Q.m, W.R, h->stream), "q1 restrict multi");
   qcycle_m(h, W, l + 1, true);
-  if (h->cfg.cycle == HDG_CYCLE_W && !h->ql[l + 1].coarsest) qcycle_m(h, W, l + 1, false);
+  if (h->cfg.cycle != HDG_CYCLE_V && !h->ql[l + 1].coarsest) qcycle_m(h, W, l + 1, false);
   hipchk(hdg::launch_q1_prolong_add_m(pr, W.qx[l + 1], W.qx[l], Q.m, W.R, h->stream), "q1 prolong multi");
   chebyshev_m(h, W, l, h->cfg.nu2, false);
 }
@@ -1140,7 +1140,7 @@ void pcycle_m(hdg_ctx* h, MultiWork& W, int p, const void* b, void* x, bool zero
     hipchk(hdg::launch_trace_multi(L.mp, L.P, a, h->stream, hdg::TM_RESID), "residual multi");
     hipchk(hdg::launch_pj_restrict_m(pr, W.pr[0], W.qb[0], h->n, W.R, h->stream), "pj restrict multi");
     qcycle_m(h, W, 0, true);
-    if (h->cfg.cycle == HDG_CYCLE_W && !h->ql[0].coarsest) qcycle_m(h, W, 0, false);
+    if (h->cfg.cycle != HDG_CYCLE_V && !h->ql[0].coarsest) qcycle_m(h, W, 0, false);
     hipchk(hdg::launch_pj_prolong_add_m(pr, W.qx[0], x, h->n, W.R, h->stream), "pj prolong multi");
   }
   smooth_m(h, W, p, b, x, h->cfg.nu2, false);
@@ -1174,7 +1174,8 @@ void validate_config(const hdg_config_t* c) {
     throw ArgError("bad precision");
   if (c->graph != 0 && c->graph != 1) throw ArgError("graph must be 0 or 1");
   if (c->autotune != 0 && c->autotune != 1) throw ArgError("autotune must be 0 or 1");
-  if (c->cycle != HDG_CYCLE_V && c->cycle != HDG_CYCLE_W) throw ArgError("cycle must be HDG_CYCLE_V or HDG_CYCLE_W");
+  if (c->cycle != HDG_CYCLE_V && c->cycle != HDG_CYCLE_W && c->cycle != HDG_CYCLE_WH)
+    throw ArgError("cycle must be HDG_CYCLE_V, HDG_CYCLE_W or HDG_CYCLE_WH");
   for (int p = 0; p <= HDG_MAX_DEGREE; ++p) {
     if (c->inner_steps[p] < 0 || c->inner_steps[p] > 64) throw ArgError("inner_steps must be in [0, 64]");
     if (p >= c->k && c->inner_steps[p] != 0) throw ArgError("inner_steps[p] must be 0 for p >= k");

@@ -1,10 +1,11 @@
-"""GPU: the W schedule of the multigrid cycle (Sec. 7 reports W- beside V-cycles).
+"""GPU: the W schedule of the multigrid cycle (Sec. 7 reports W- beside V-cycles),
+and the hybrid WH (W on the Q1 levels, V on the p-levels).
 
-Bars: three W-cycle iterates from zero match the oracle's W-cycle to 1e-11
+Bars: three W- (and WH-) cycle iterates from zero match the oracle's to 1e-11
 relative (same smoother, omega and Chebyshev bounds; edge meshes n = 2, k = 0);
 W-cycle PCG and stationary W-cycles reach 1e-10 and match the direct solve to
 1e-9, in no more iterations than the V-cycle; the multi-column solve with the W
-schedule matches the direct solve and the single-vector W solve per column.
+or WH schedule matches the direct solve and the single-vector solve per column.
 """
 import numpy as np
 import pytest
@@ -37,13 +38,13 @@ def rel_inf(a, b):
 
 @pytest.mark.parametrize("n,k,sigma", [(16, 1, None), (24, 3, 1.0), (32, 2, 2.0), (16, 0, 1.0), (2, 1, None),
                                        (10, 6, 1.0)])
-@pytest.mark.parametrize("smoother", ["chain", "face"])
-def test_wcycle_iterates(n, k, sigma, smoother):
-    print(f"case wcycle {smoother} n={n} k={k}", flush=True)
+@pytest.mark.parametrize("smoother,cycle", [("chain", "W"), ("face", "W"), ("chain", "WH")])
+def test_wcycle_iterates(n, k, sigma, smoother, cycle):
+    print(f"case wcycle {cycle} {smoother} n={n} k={k}", flush=True)
     kap = _kappa(n, sigma)
-    Ho = mg.Hierarchy(n, k, kap, smoother=smoother, omega=0.8, cycle='W')
+    Ho = mg.Hierarchy(n, k, kap, smoother=smoother, omega=0.8, cycle=cycle)
     lmax = [Ho.lmax[L.name] for L in Ho.levels if L.kind == 'q' and not L.coarsest]
-    S = H.Solver(n, k, kap, smoother=smoother, omega=Ho.omega, cheb_lmax=lmax, cycle="W")
+    S = H.Solver(n, k, kap, smoother=smoother, omega=Ho.omega, cheb_lmax=lmax, cycle=cycle)
     try:
         N = ms.n_trace_dofs(n, k)
         b = normal_vector(N, 11)
@@ -79,14 +80,16 @@ def test_wcycle_solve_matches_direct(n, k, sigma, mode):
     assert its["W"] <= its["V"], its
 
 
-@pytest.mark.parametrize("n,k,sigma,R,prec", [(24, 3, 1.0, 5, "f64"), (16, 2, 2.0, 9, "f32"), (2, 1, 1.0, 3, "f64")])
-def test_wcycle_multi_solve(n, k, sigma, R, prec):
-    print(f"case wcycle multi n={n} k={k} R={R} {prec}", flush=True)
+@pytest.mark.parametrize("n,k,sigma,R,prec,cycle", [(24, 3, 1.0, 5, "f64", "W"), (16, 2, 2.0, 9, "f32", "W"),
+                                                    (2, 1, 1.0, 3, "f64", "W"), (32, 2, 2.0, 64, "f32", "WH"),
+                                                    (24, 3, 1.0, 7, "f64", "WH")])
+def test_wcycle_multi_solve(n, k, sigma, R, prec, cycle):
+    print(f"case wcycle multi {cycle} n={n} k={k} R={R} {prec}", flush=True)
     kap = kappa_lognormal(n, sigma, 12)
     pr = hdg.Problem(n, k, kap)
     rng = np.random.default_rng(n + R)
     Bh = np.stack([pr.rhs(1.0 + rng.standard_normal((n * n, pr.ref.nq ** 2))) for _ in range(R)], axis=1)
-    S = H.Solver(n, k, kap, precision=prec, cycle="W")
+    S = H.Solver(n, k, kap, precision=prec, cycle=cycle)
     try:
         B = torch.tensor(Bh, device="cuda")
         X, its, rr = S.solve_multi(B, rtol=1e-10, maxit=300)

@@ -212,12 +212,12 @@ def test_wcycle_with_two_levels_is_the_vcycle():
     assert np.array_equal(Hv.vcycle(b, np.zeros_like(b)), Hw.vcycle(b, np.zeros_like(b)))
 
 
-@pytest.mark.parametrize("smoother", ["chain", "face"])
-def test_wcycle_symmetric(smoother):
+@pytest.mark.parametrize("smoother,cycle", [("chain", "W"), ("face", "W"), ("chain", "WH")])
+def test_wcycle_symmetric(smoother, cycle):
     """nu1 = nu2, R = P^T and symmetric smoothers make the W-cycle operator
     symmetric too (it is then a valid preconditioner for CG)."""
     n, k = 8, 2
-    H = mg.Hierarchy(n, k, kappa_lognormal(n, 1.0, 6), smoother=smoother, coarse_max=10, cycle='W')
+    H = mg.Hierarchy(n, k, kappa_lognormal(n, 1.0, 6), smoother=smoother, coarse_max=10, cycle=cycle)
     assert len(H.levels) >= 5
     N = ms.n_trace_dofs(n, k)
     rng = np.random.default_rng(2)
@@ -292,3 +292,27 @@ def test_fmg_reaches_discretization_error_at_k1(n):
     H = mg.Hierarchy(n, k, np.ones(n * n))
     assert np.all(_sinsin_errors(n, k, H.fmg(b, cycles=2), pr, fq, lam_bd) <= 1.01 * e0)
     assert np.all(_sinsin_errors(n, k, H.fmg(b, cycles=1), pr, fq, lam_bd) <= 1.4 * e0)
+
+
+def test_hybrid_wcycle_reduces_to_w_or_v():
+    """'WH' repeats only corrections onto Q1 levels: with k = 0 every coarse level
+    is a Q1 level and WH is W to the bit; with a single (coarsest) Q1 level below
+    the p-levels nothing is repeated and WH is V to the bit.  Between the two, WH
+    contracts at least as well as V."""
+    kap = kappa_lognormal(16, 1.0, 6)
+    b = np.random.default_rng(5).standard_normal(ms.n_trace_dofs(16, 0))
+    Hw, Hh = mg.Hierarchy(16, 0, kap, coarse_max=10, cycle='W'), mg.Hierarchy(16, 0, kap, coarse_max=10, cycle='WH')
+    assert len(Hw.levels) >= 3
+    assert np.array_equal(Hw.vcycle(b, np.zeros_like(b)), Hh.vcycle(b, np.zeros_like(b)))
+    b2 = np.random.default_rng(6).standard_normal(ms.n_trace_dofs(16, 2))
+    Hv, Hh = mg.Hierarchy(16, 2, kap, cycle='V'), mg.Hierarchy(16, 2, kap, cycle='WH')
+    assert Hv.levels[-1].coarsest and Hv.levels[-2].kind == 'p'
+    assert np.array_equal(Hv.vcycle(b2, np.zeros_like(b2)), Hh.vcycle(b2, np.zeros_like(b2)))
+    Hv, Hh = mg.Hierarchy(16, 2, kap, coarse_max=10), mg.Hierarchy(16, 2, kap, coarse_max=10, cycle='WH')
+    S = Hv.levels[0].A
+    e0 = np.random.default_rng(7).standard_normal(S.shape[0])
+    ev, eh, z = e0.copy(), e0.copy(), np.zeros_like(e0)
+    for _ in range(4):
+        ev, eh = Hv.vcycle(z, ev), Hh.vcycle(z, eh)
+    energy = lambda v: float(np.sqrt(v @ (S @ v)))
+    assert energy(eh) <= energy(ev)
