@@ -43,7 +43,7 @@ WORKLOADS = {
     "poisson_sin_n16_k1": dict(n=16, k=1, sigma=None, seed=None, inner=""),
     # misfit gradient: theta ~ N(0,1) (seed 5); data U(theta + 0.5 N(0,1) (seed 6)) plus
     # 1% noise (seed 7); each step adds one gradient (forward + adjoint solve) to the solve
-    "adjoint_n512_k2": dict(n=512, k=2, sigma=1.0, seed=5, inner="1:2,0:3", adjoint=True),
+    "adjoint_n512_k2": dict(n=512, k=2, sigma=1.0, seed=5, inner="1:2,0:2", adjoint=True),
     # many right-hand sides: 64 vectors N(0,1) (seed 4), FP32 blocks; each step adds one
     # cold apply Y = S X for all 64 at once (batch_us_cold, RHS-DoF/s)
     "batch_n512_k5_r64": dict(n=512, k=5, sigma=1.0, seed=4, inner="1:2,0:2", nrhs=64, precision="f32"),
