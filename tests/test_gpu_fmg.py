@@ -2,7 +2,8 @@
 
 Bars: the FMG iterate matches the oracle's FMG to 1e-11 relative (same
 smoother, omega and Chebyshev bounds; V and W schedules; 1 and 2 cycles per
-level; n = 2 and k = 0 edges); an exact solution in the range of the
+level; n = 2 and k = 0 edges; 1e-10 with K-cycle levels, as for the K-cycle
+itself); an exact solution in the range of the
 prolongations from the coarsest level comes back to 1e-11; an FP32 cycle stays
 within 1e-5 of the FP64 pass; cycles outside [1, 64] are rejected.
 """
@@ -90,3 +91,20 @@ def test_fmg_fp32_cycle_and_argument_checks():
     finally:
         S64.close()
         S32.close()
+
+
+@pytest.mark.parametrize("n,k,inner,cycle", [(24, 3, {1: 2, 0: 2}, "V"), (16, 2, {0: 3}, "WH")])
+def test_fmg_with_krylov_levels_matches_oracle(n, k, inner, cycle):
+    """FMG on a hierarchy whose p = 1 / p = 0 corrections are K-cycle FCG steps."""
+    print(f"case fmg kcycle {inner} {cycle} n={n} k={k}", flush=True)
+    kap = kappa_lognormal(n, 1.0, 10)
+    Ho = mg.Hierarchy(n, k, kap, omega=0.8, inner=inner, cycle=cycle)
+    lmax = [Ho.lmax[L.name] for L in Ho.levels if L.kind == 'q' and not L.coarsest]
+    S = H.Solver(n, k, kap, omega=Ho.omega, cheb_lmax=lmax, inner=inner, cycle=cycle)
+    try:
+        b = normal_vector(ms.n_trace_dofs(n, k), 7)
+        xo = Ho.fmg(b)
+        xg = host(S.fmg(dev(b)))
+        assert rel_inf(xg, xo) <= 1e-10, rel_inf(xg, xo)
+    finally:
+        S.close()
