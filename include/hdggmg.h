@@ -46,7 +46,10 @@ typedef enum {
   HDG_ERR_HIP = -3,           /* a HIP runtime call failed (message has the HIP error)  */
   HDG_ERR_NOT_CONVERGED = -4, /* maxit reached; x, iters, relres are still valid        */
   HDG_ERR_NONFINITE = -5,     /* NaN or Inf met in a residual norm                       */
-  HDG_ERR_STATE = -6          /* call not valid for this handle (e.g. level missing)     */
+  HDG_ERR_STATE = -6,         /* call not valid for this handle (e.g. level missing)     */
+  HDG_ERR_AT_FLOOR = -7       /* a solve's true residual reached the rounding floor of
+                                 b - S x above rtol ||b||: x, iters, relres are valid and
+                                 x is as accurate as FP64 storage lets the residual show */
 } hdg_status_t;
 
 enum { HDG_SMOOTH_CHAIN = 0, HDG_SMOOTH_FACE = 1 };
@@ -182,6 +185,14 @@ hdg_status_t hdg_assemble_rhs(hdg_handle_t h, const double* f_qp_host, const dou
  * p < k returns STATE. */
 hdg_status_t hdg_apply_trace_operator(hdg_handle_t h, int32_t p, const double* x, double* y);
 
+/* y = |S_p| |x| entrywise (every block entry and every x value by its absolute
+ * value; the assembled matrix's entries, i.e. the summed diagonal block of each
+ * face): the scale of the rounding error of S_p x.  eps || |S| |x| ||_2 bounds
+ * from below the computed residual b - S x of any FP64 x (Sec. 7's stopping
+ * test on ||b - S Lambda||).  Same arguments and level rule as
+ * hdg_apply_trace_operator. */
+hdg_status_t hdg_apply_abs(hdg_handle_t h, int32_t p, const double* x, double* y);
+
 /* The same product in the cycle precision of a handle created with
  * HDG_PREC_F32 or HDG_PREC_BF16: FP32 vectors, blocks in FP32 or bfloat16,
  * FP32 accumulation.  x, y: device float [N(p)], must not alias.  Returns
@@ -216,14 +227,20 @@ hdg_status_t hdg_apply_trace_operator_batch(int32_t count, const hdg_handle_t* h
 hdg_status_t hdg_apply_trace_operator_timed(hdg_handle_t h, int32_t p, int32_t precision, const void* x, void* y,
                                             double* kernel_us);
 
-/* r = b - S_p x; if norm2_host != NULL, *norm2_host = ||r||_2 (synchronizes;
+/* Residual of the level-p trace system (Alg. algo_2, the residual handed to the
+ * coarser level; Sec. 7, the residual two-norm whose ratios measure the
+ * multigrid convergence factor).
+ * r = b - S_p x; if norm2_host != NULL, *norm2_host = ||r||_2 (synchronizes;
  * deterministic reduction order).  r must not alias x.  Same level rule as
  * hdg_apply_trace_operator. */
 hdg_status_t hdg_residual(hdg_handle_t h, int32_t p, const double* b, const double* x, double* r,
                           double* norm2_host);
 
-/* sweeps of the level-p Schwarz smoother x <- x + omega M^{-1} (b - S_p x) in place
- * (in the cycle precision; b and x are FP64 in every mode). */
+/* Smoother of Sec. 6 (additive Schwarz relaxation, weighted by a scalar omega;
+ * the smoothing step S(A, b, x) of Algs. algo_1 / algo_2): sweeps of
+ * x <- x + omega M^{-1} (b - S_p x) in place, M the block diagonal of S_p over
+ * the subdomains (chains of faces or single faces, config field smoother), in
+ * the cycle precision; b and x are FP64 in every mode. */
 hdg_status_t hdg_smooth(hdg_handle_t h, int32_t p, const double* b, double* x, int32_t sweeps);
 
 /* p-transfers (eqs. eq_mg_res / eq_mg_pro), face local, 1 <= p_fine <= k:
@@ -231,8 +248,10 @@ hdg_status_t hdg_smooth(hdg_handle_t h, int32_t p, const double* b, double* x, i
 hdg_status_t hdg_restrict(hdg_handle_t h, int32_t p_fine, const double* r_fine, double* r_coarse);
 hdg_status_t hdg_prolong(hdg_handle_t h, int32_t p_fine, const double* e_coarse, double* x_fine);
 
-/* One (nu1, nu2) multigrid cycle, with the V or W schedule of the handle's
- * config, for S_k x = b starting from x (in place), run in the cycle
+/* One (nu1, nu2) multigrid cycle of Sec. 6: the p-multigrid of Alg. algo_2 from
+ * degree k down to p = 0, where the h-multigrid of Alg. algo_1 (p = 0 traces ->
+ * Q1 on the same mesh -> coarser Q1 meshes -> exact coarsest solve) replaces
+ * the coarse solve; with the V or W schedule of the handle's config, for S_k x = b starting from x (in place), run in the cycle
  * precision; b and x are FP64 in every mode. */
 hdg_status_t hdg_vcycle(hdg_handle_t h, const double* b, double* x);
 
@@ -246,8 +265,9 @@ hdg_status_t hdg_vcycle(hdg_handle_t h, const double* b, double* x);
  * the coarsest level is reproduced to rounding. */
 hdg_status_t hdg_fmg(hdg_handle_t h, const double* b, double* x, int32_t cycles);
 
-/* Solve S_k x = b to ||b - S x||_2 <= rtol ||b||_2, x in: initial guess, out:
- * solution.  mode HDG_SOLVE_PCG (conjugate gradients preconditioned by one
+/* The solve of Sec. 7: S_k x = b (eq. shur1) by multigrid, alone or as a
+ * preconditioner of conjugate gradients, to ||b - S x||_2 <= rtol ||b||_2.
+ * x in: initial guess, out: solution.  mode HDG_SOLVE_PCG (conjugate gradients preconditioned by one
  * cycle, V or W by the config), HDG_SOLVE_FCG (flexible CG, FCG(1), with the same preconditioner;
  * required instead of PCG when inner_steps makes the cycle nonlinear -- PCG
  * then returns INVALID_ARG) or HDG_SOLVE_VCYCLE (repeated cycles, the paper's
@@ -255,12 +275,17 @@ hdg_status_t hdg_fmg(hdg_handle_t h, const double* b, double* x, int32_t cycles)
  * [maxit + 1] residual norms (entry 0 = initial).  Returns NOT_CONVERGED if
  * maxit is reached (outputs still valid), NONFINITE on NaN/Inf.
  * Residual norms: entry 0 and every VCYCLE entry is ||b - S x|| computed from
- * x; PCG and FCG use the recursively updated residual r <- r - alpha S d (the
- * usual Krylov stopping test), which drifts from b - S x by rounding.  The
- * computed b - S x cannot fall below about eps || |S| |x| ||_2 (rounding of
- * S x itself); with high coefficient contrast and a smooth right-hand side that
- * floor can exceed rtol ||b|| while the recursive norm goes below it.
- * hdg_residual gives the true residual of the returned x. */
+ * x.  PCG and FCG iterate on the recursively updated residual r <- r - alpha S d
+ * (the usual Krylov stopping test); when it falls below rtol ||b||, or maxit is
+ * reached, the true residual b - S x is recomputed, and if it is still above
+ * rtol ||b|| the iteration restarts from it (residual replacement) for as long
+ * as each restart at least halves it.  The history entry of that iteration and
+ * *relres are the true value, so *relres is always ||b - S x|| / ||b|| of the
+ * returned x.  The computed b - S x cannot fall below about u || |S| |x| ||_2,
+ * u = 2^-53 (rounding of S x itself); when the true residual is above rtol ||b||
+ * but within twice that floor the call returns AT_FLOOR, and when a restart
+ * failed to halve it NOT_CONVERGED, with the true residual in *relres
+ * (hdg_apply_abs gives |S| |x|). */
 hdg_status_t hdg_solve(hdg_handle_t h, const double* b, double* x, double rtol, int32_t maxit,
                        int32_t mode, int32_t* iters, double* relres, double* history_host);
 
@@ -272,9 +297,13 @@ hdg_status_t hdg_solve(hdg_handle_t h, const double* b, double* x, double rtol, 
  * column); the FP64 operator, residuals and updates are kept for the outer
  * iteration.  Chain smoother only (STATE otherwise); Krylov acceleration of
  * coarse levels (inner_steps) is not used here.  A column stops updating once
- * its recursively updated residual norm is <= rtol ||b||_2 (see hdg_solve).
- * iters_host, relres_host: nullable [nrhs].
- * NOT_CONVERGED if some column reached maxit (outputs still valid). */
+ * its recursively updated residual norm is <= rtol ||b||_2; the true residuals
+ * are then recomputed, and a column still above its tolerance restarts from its
+ * true residual as in hdg_solve.  relres_host holds the true relative residuals
+ * ||B_r - S X_r|| / ||B_r||.  iters_host, relres_host: nullable [nrhs].
+ * NOT_CONVERGED if some column reached maxit, or a restart failed to halve its
+ * true residual above its tolerance (at the rounding floor, among other causes;
+ * the per-column floor is not evaluated here); outputs still valid. */
 hdg_status_t hdg_solve_multi(hdg_handle_t h, int32_t nrhs, const double* B, double* X, double rtol, int32_t maxit,
                              int32_t* iters_host, double* relres_host);
 

@@ -26,7 +26,8 @@ MODES = {"pcg": 0, "vcycle": 1, "fcg": 2}
 CYCLES = {"V": 0, "W": 1, "WH": 2}
 PRECISIONS = {"f64": 0, "f32": 1, "bf16": 2}
 STATUS = {0: "ok", -1: "invalid argument", -2: "out of memory", -3: "HIP error",
-          -4: "not converged", -5: "non-finite value", -6: "invalid state"}
+          -4: "not converged", -5: "non-finite value", -6: "invalid state",
+          -7: "stopped at the rounding floor of the residual"}
 
 
 class Config(ctypes.Structure):
@@ -62,6 +63,7 @@ SIGNATURES = {
     "hdg_quadrature_nodes": [_I32, _PD],
     "hdg_assemble_rhs": [_P, _PD, _PD, _P],
     "hdg_apply_trace_operator": [_P, _I32, _P, _P],
+    "hdg_apply_abs": [_P, _I32, _P, _P],
     "hdg_apply_trace_operator_lp": [_P, _I32, _P, _P],
     "hdg_apply_trace_operator_timed": [_P, _I32, _I32, _P, _P, _PD],
     "hdg_apply_trace_operator_multi": [_P, _I32, _I32, _I32, _P, _P],
@@ -262,6 +264,13 @@ class Solver:
         self._check(lib.hdg_apply_trace_operator(self._h, p, _dptr(x, "x", N), _dptr(y, "y", N)))
         return y
 
+    def apply_abs(self, p, x, y=None):
+        """y = |S_p| |x| entrywise (the rounding scale of S_p x)."""
+        N = self.num_dofs(p)
+        y = self._empty(p) if y is None else y
+        self._check(lib.hdg_apply_abs(self._h, p, _dptr(x, "x", N), _dptr(y, "y", N)))
+        return y
+
     def apply_lp(self, p, x, y=None):
         """y = S_p x in the cycle precision (float32 tensors) of an f32 / bf16 handle."""
         import torch
@@ -383,11 +392,17 @@ class Solver:
         rr = np.zeros(R)
         st = lib.hdg_solve_multi(self._h, R, _dptr(B, "B", N * R), _dptr(X, "X", N * R), rtol, maxit,
                                  its.ctypes.data_as(_PI32), rr.ctypes.data_as(_PD))
-        if st != 0 and (raise_on_fail or st not in (-4,)):
+        self.last_status = st
+        if st != 0 and (raise_on_fail or st not in (-4, -7)):
             self._check(st)
         return X, its, rr
 
-    def solve(self, b, x=None, rtol=1e-10, maxit=200, mode="pcg", raise_on_fail=True):
+    def solve(self, b, x=None, rtol=1e-10, maxit=200, mode="pcg", raise_on_fail=True, accept_floor=False):
+        """Solve S x = b; returns x, iterations, the true relative residual and the
+        residual history.  raise_on_fail=False returns instead of raising when the
+        solve ends NOT_CONVERGED or AT_FLOOR; accept_floor=True returns on AT_FLOOR
+        (the true residual reached the rounding floor of b - S x above rtol).  The
+        status of the last call is kept in last_status."""
         import torch
         N = self.num_dofs()
         if x is None:
@@ -397,6 +412,8 @@ class Solver:
         hist = np.zeros(maxit + 1)
         st = lib.hdg_solve(self._h, _dptr(b, "b", N), _dptr(x, "x", N), rtol, maxit, MODES[mode],
                            ctypes.byref(it), ctypes.byref(rr), hist.ctypes.data_as(_PD))
-        if st != 0 and (raise_on_fail or st not in (-4,)):
+        self.last_status = st
+        tolerated = (-4, -7) if not raise_on_fail else ((-7,) if accept_floor else ())
+        if st != 0 and st not in tolerated:
             self._check(st)
         return x, it.value, rr.value, hist[:it.value + 1]

@@ -32,7 +32,8 @@ class HDGMisfit(torch.autograd.Function):
         kappa = np.exp(theta.detach().double().cpu().numpy())
         S = Solver(n, k, kappa, **opts)
         b = S.assemble_rhs(f_qp, gD_qp)
-        lam, _, _, _ = S.solve(b, rtol=rtol, maxit=maxit, mode=mode)
+        # a tolerance below the rounding floor of b - S Lambda ends at that floor
+        lam, _, _, _ = S.solve(b, rtol=rtol, maxit=maxit, mode=mode, accept_floor=True)
         U = S.reconstruct(lam)
         c, L = S.adjoint_rhs(U, U_obs)
         ctx.state = (S, lam, U, U_obs, c, rtol, maxit, mode)
@@ -41,7 +42,7 @@ class HDGMisfit(torch.autograd.Function):
     @staticmethod
     def backward(ctx, gL):
         S, lam, U, U_obs, c, rtol, maxit, mode = ctx.state
-        mu, _, _, _ = S.solve(c, rtol=rtol, maxit=maxit, mode=mode)
+        mu, _, _, _ = S.solve(c, rtol=rtol, maxit=maxit, mode=mode, accept_floor=True)
         g = S.misfit_gradient(lam, U, U_obs, mu)
         S.close()
         ctx.state = None

@@ -1203,6 +1203,7 @@ const char* hdg_status_string(hdg_status_t s) {
     case HDG_ERR_NOT_CONVERGED: return "not converged";
     case HDG_ERR_NONFINITE: return "non-finite value";
     case HDG_ERR_STATE: return "invalid state";
+    case HDG_ERR_AT_FLOOR: return "stopped at the rounding floor of the residual";
   }
   return "unknown";
 }
@@ -1492,6 +1493,18 @@ hdg_status_t hdg_apply_trace_operator(hdg_handle_t h, int32_t p, const double* x
   if (need_f64_level(h, p) != HDG_OK) return HDG_ERR_STATE;
   return guarded(h, [&]() -> hdg_status_t {
     apply(h, p, x, y, hdg::Prec::F64);
+    return HDG_OK;
+  });
+}
+
+hdg_status_t hdg_apply_abs(hdg_handle_t h, int32_t p, const double* x, double* y) {
+  if (!h || !x || !y || p < 0 || p > h->k || x == y) return HDG_ERR_INVALID_ARG;
+  if (need_f64_level(h, p) != HDG_OK) return HDG_ERR_STATE;
+  return guarded(h, [&]() -> hdg_status_t {
+    hdg::TraceArgs a = targs(h, h->pl[p], hdg::Prec::F64);
+    a.x = x;
+    a.y = y;
+    hipchk(hdg::launch_trace(hdg::Prec::F64, h->pl[p].P, hdg::TM_ABS, a, h->stream), "trace abs");
     return HDG_OK;
   });
 }
@@ -1800,52 +1813,89 @@ hdg_status_t hdg_solve_multi(hdg_handle_t h, int32_t nrhs, const double* B, doub
     }
     hipchk(hipMemcpyAsync(W.act, act.data(), R * sizeof(double), hipMemcpyHostToDevice, s), "h2d");
     double* sc = W.sc;  // [5][R]: d.r, d.q, z.q, z.r, d.r (previous direction)
+    // As in hdg_solve: each phase runs FCG until every active column's recursive
+    // residual is below its tolerance; then the true residuals B - S X are
+    // recomputed, and a column above its tolerance restarts from its true residual
+    // while each restart at least halves it (else it has reached the rounding
+    // floor of S x and is reported as not converged).
+    std::vector<double> last_true(rn);
     int it = 0;
-    while (nact > 0 && it < maxit) {
-      precondition_m(h, W);
-      if (it == 0) {
-        hipchk(hdg::launch_copy(hdg::Prec::F64, W.vz, W.vd, N * R, s), "copy");
-        hipchk(hdg::launch_dots_m(hdg::Prec::F64, W.vz, W.vr, N, R, W.partial, sc, s), "dots");
-      } else {
-        hipchk(hdg::launch_dots_m(hdg::Prec::F64, W.vz, W.vq, N, R, W.partial, sc + 2 * R, s), "dots");
-        hipchk(hdg::launch_dots_m(hdg::Prec::F64, W.vz, W.vr, N, R, W.partial, sc + 3 * R, s), "dots");
-        hipchk(hdg::launch_dots_m(hdg::Prec::F64, W.vd, W.vr, N, R, W.partial, sc + 4 * R, s), "dots");
-        hipchk(hdg::launch_fcg_scalars_m(sc, R, s), "fcg scalars");
-        hipchk(hdg::launch_xpby_m(hdg::Prec::F64, W.vz, sc + 2 * R, sc + R, -1.0, W.vd, N, R, s), "xpby");
+    bool stalled = false;
+    for (;;) {
+      int itp = 0;
+      while (nact > 0 && it < maxit) {
+        precondition_m(h, W);
+        if (itp == 0) {
+          hipchk(hdg::launch_copy(hdg::Prec::F64, W.vz, W.vd, N * R, s), "copy");
+          hipchk(hdg::launch_dots_m(hdg::Prec::F64, W.vz, W.vr, N, R, W.partial, sc, s), "dots");
+        } else {
+          hipchk(hdg::launch_dots_m(hdg::Prec::F64, W.vz, W.vq, N, R, W.partial, sc + 2 * R, s), "dots");
+          hipchk(hdg::launch_dots_m(hdg::Prec::F64, W.vz, W.vr, N, R, W.partial, sc + 3 * R, s), "dots");
+          hipchk(hdg::launch_dots_m(hdg::Prec::F64, W.vd, W.vr, N, R, W.partial, sc + 4 * R, s), "dots");
+          hipchk(hdg::launch_fcg_scalars_m(sc, R, s), "fcg scalars");
+          hipchk(hdg::launch_xpby_m(hdg::Prec::F64, W.vz, sc + 2 * R, sc + R, -1.0, W.vd, N, R, s), "xpby");
+        }
+        hdg::MultiArgs a = margs(h, Lk, R, true);
+        a.X = W.vd;
+        a.Y = W.vq;
+        hipchk(hdg::launch_trace_multi(hdg::Prec::F64, Lk.P, a, s, hdg::TM_APPLY), "apply multi");
+        hipchk(hdg::launch_dots_m(hdg::Prec::F64, W.vd, W.vq, N, R, W.partial, sc + R, s), "dots");
+        hipchk(hdg::launch_axpy_m(hdg::Prec::F64, sc, sc + R, W.act, 1.0, W.vd, X, N, R, s), "axpy");
+        hipchk(hdg::launch_axpy_m(hdg::Prec::F64, sc, sc + R, W.act, -1.0, W.vq, W.vr, N, R, s), "axpy");
+        hipchk(hdg::launch_dots_m(hdg::Prec::F64, W.vr, W.vr, N, R, W.partial, W.nrm, s), "dots");
+        host_col(W.nrm, rn);
+        ++it;
+        ++itp;
+        nact = 0;
+        for (int r = 0; r < R; ++r) {
+          if (act[r] == 0.0) continue;
+          const double v = std::sqrt(rn[r]);
+          if (!std::isfinite(v)) {
+            h->err = "non-finite residual";
+            return HDG_ERR_NONFINITE;
+          }
+          its[r] = it;
+          if (v <= rtol * nb[r]) act[r] = 0.0;
+          else ++nact;
+        }
+        hipchk(hipMemcpyAsync(W.act, act.data(), R * sizeof(double), hipMemcpyHostToDevice, s), "h2d");
       }
-      hdg::MultiArgs a = margs(h, Lk, R, true);
-      a.X = W.vd;
-      a.Y = W.vq;
-      hipchk(hdg::launch_trace_multi(hdg::Prec::F64, Lk.P, a, s, hdg::TM_APPLY), "apply multi");
-      hipchk(hdg::launch_dots_m(hdg::Prec::F64, W.vd, W.vq, N, R, W.partial, sc + R, s), "dots");
-      hipchk(hdg::launch_axpy_m(hdg::Prec::F64, sc, sc + R, W.act, 1.0, W.vd, X, N, R, s), "axpy");
-      hipchk(hdg::launch_axpy_m(hdg::Prec::F64, sc, sc + R, W.act, -1.0, W.vq, W.vr, N, R, s), "axpy");
+      {  // true residuals R = B - S X with the FP64 operator
+        hdg::MultiArgs a = margs(h, Lk, R, true);
+        a.X = X;
+        a.B = B;
+        a.Y = W.vr;
+        hipchk(hdg::launch_trace_multi(hdg::Prec::F64, Lk.P, a, s, hdg::TM_RESID), "residual multi");
+      }
       hipchk(hdg::launch_dots_m(hdg::Prec::F64, W.vr, W.vr, N, R, W.partial, W.nrm, s), "dots");
       host_col(W.nrm, rn);
-      ++it;
       nact = 0;
+      stalled = false;
       for (int r = 0; r < R; ++r) {
-        if (act[r] == 0.0) continue;
-        const double v = std::sqrt(rn[r]);
-        if (!std::isfinite(v)) {
+        rn[r] = std::sqrt(rn[r]);
+        if (!std::isfinite(rn[r])) {
           h->err = "non-finite residual";
           return HDG_ERR_NONFINITE;
         }
-        its[r] = it;
-        if (v <= rtol * nb[r]) act[r] = 0.0;
-        else ++nact;
+        act[r] = 0.0;
+        if (rn[r] <= rtol * nb[r]) continue;
+        if (it < maxit && rn[r] <= 0.5 * last_true[r]) {
+          act[r] = 1.0;
+          last_true[r] = rn[r];
+          ++nact;
+        } else {
+          stalled = true;
+        }
       }
+      if (nact == 0) break;
       hipchk(hipMemcpyAsync(W.act, act.data(), R * sizeof(double), hipMemcpyHostToDevice, s), "h2d");
     }
-    // final relative residuals, recomputed from the recursive residuals of the last iteration
-    hipchk(hdg::launch_dots_m(hdg::Prec::F64, W.vr, W.vr, N, R, W.partial, W.nrm, s), "dots");
-    host_col(W.nrm, rn);
     for (int r = 0; r < R; ++r) {
       if (iters_host) iters_host[r] = its[r];
-      if (relres_host) relres_host[r] = nb[r] > 0 ? std::sqrt(rn[r]) / nb[r] : std::sqrt(rn[r]);
+      if (relres_host) relres_host[r] = nb[r] > 0 ? rn[r] / nb[r] : rn[r];
     }
-    if (nact > 0) {
-      h->err = "maximum number of iterations reached";
+    if (stalled) {
+      h->err = "maximum number of iterations reached, or a true residual stalled above the tolerance";
       return HDG_ERR_NOT_CONVERGED;
     }
     return HDG_OK;
@@ -1896,43 +1946,74 @@ hdg_status_t hdg_solve(hdg_handle_t h, const double* b, double* x, double rtol, 
     } else if (rn > tol && maxit > 0) {
       // conjugate gradients (PCG), or flexible CG, FCG(1) (Notay): the direction is
       // A-orthogonalised against the previous one, d = z - (z . q / d . q) d, and
-      // alpha = d . r / d . q with d . r = z . r - beta d_prev . r
+      // alpha = d . r / d . q with d . r = z . r - beta d_prev . r.
+      // The loop stops on the recursively updated residual r <- r - alpha S d.  The
+      // true residual b - S x is then recomputed; if it is still above tol, the
+      // iteration restarts from it (residual replacement: h->vr holds b - S x)
+      // unless it lies within twice the rounding floor u || |S| |x| || of the
+      // computed residual (AT_FLOOR), or the previous restart failed to halve it
+      // (NOT_CONVERGED).  rn, relres and the last history entry are the true value.
       const bool flex = mode == HDG_SOLVE_FCG;
-      precondition(h);
-      hipchk(hdg::launch_copy(hdg::Prec::F64, h->vz, h->vd, N, h->stream), "copy");
-      double rz = dot(h, h->vr, h->vz, N);
-      double dr = rz;
-      while (rn > tol && it < maxit) {
-        hdg::TraceArgs ta = targs(h, h->pl[k], hdg::Prec::F64);
-        ta.x = h->vd;
-        ta.y = h->vq;
-        ta.partial = h->partial;
-        hipchk(hdg::launch_trace(hdg::Prec::F64, h->pl[k].P, hdg::TM_APPLY_DOT, ta, h->stream), "apply dot");
-        const double dq = reduce_scalar(h, hdg::trace_partials(h->ntiles));
-        const double alpha = dr / dq;
-        hipchk(hdg::launch_axpy(alpha, h->vd, x, N, h->stream), "axpy");
-        hipchk(hdg::launch_axpy_norm(alpha, h->vq, h->vr, N, h->partial, h->stream), "axpy norm");
-        rn = std::sqrt(reduce_scalar(h, hdg::reduce_grid(N)));
-        ++it;
+      double last_true = rn;
+      for (;;) {
+        precondition(h);
+        hipchk(hdg::launch_copy(hdg::Prec::F64, h->vz, h->vd, N, h->stream), "copy");
+        double rz = dot(h, h->vr, h->vz, N);
+        double dr = rz;
+        while (rn > tol && it < maxit) {
+          hdg::TraceArgs ta = targs(h, h->pl[k], hdg::Prec::F64);
+          ta.x = h->vd;
+          ta.y = h->vq;
+          ta.partial = h->partial;
+          hipchk(hdg::launch_trace(hdg::Prec::F64, h->pl[k].P, hdg::TM_APPLY_DOT, ta, h->stream), "apply dot");
+          const double dq = reduce_scalar(h, hdg::trace_partials(h->ntiles));
+          const double alpha = dr / dq;
+          hipchk(hdg::launch_axpy(alpha, h->vd, x, N, h->stream), "axpy");
+          hipchk(hdg::launch_axpy_norm(alpha, h->vq, h->vr, N, h->partial, h->stream), "axpy norm");
+          rn = std::sqrt(reduce_scalar(h, hdg::reduce_grid(N)));
+          ++it;
+          if (history_host) history_host[it] = rn;
+          if (!std::isfinite(rn)) {
+            h->err = "non-finite residual";
+            return finish(HDG_ERR_NONFINITE);
+          }
+          if (rn <= tol) break;
+          precondition(h);
+          if (flex) {
+            double v[3];
+            dots(h, hdg::Prec::F64, 3, {h->vz, h->vq, h->vz, h->vr, h->vd, h->vr}, N, v);
+            const double beta = v[0] / dq;
+            hipchk(hdg::launch_xpby(h->vz, -beta, h->vd, N, h->stream), "xpby");
+            dr = v[1] - beta * v[2];
+          } else {
+            const double rz_new = dot(h, h->vr, h->vz, N);
+            hipchk(hdg::launch_xpby(h->vz, rz_new / rz, h->vd, N, h->stream), "xpby");
+            rz = rz_new;
+            dr = rz;
+          }
+        }
+        rn = residual_norm(h, k, b, x, h->vr);
         if (history_host) history_host[it] = rn;
         if (!std::isfinite(rn)) {
           h->err = "non-finite residual";
           return finish(HDG_ERR_NONFINITE);
         }
-        if (rn <= tol) break;
-        precondition(h);
-        if (flex) {
-          double v[3];
-          dots(h, hdg::Prec::F64, 3, {h->vz, h->vq, h->vz, h->vr, h->vd, h->vr}, N, v);
-          const double beta = v[0] / dq;
-          hipchk(hdg::launch_xpby(h->vz, -beta, h->vd, N, h->stream), "xpby");
-          dr = v[1] - beta * v[2];
-        } else {
-          const double rz_new = dot(h, h->vr, h->vz, N);
-          hipchk(hdg::launch_xpby(h->vz, rz_new / rz, h->vd, N, h->stream), "xpby");
-          rz = rz_new;
-          dr = rz;
+        if (rn <= tol || it >= maxit) break;
+        // rounding floor of the computed residual: u || |S| |x| ||, u = 2^-53
+        hdg::TraceArgs fa = targs(h, h->pl[k], hdg::Prec::F64);
+        fa.x = x;
+        fa.y = h->vq;
+        hipchk(hdg::launch_trace(hdg::Prec::F64, h->pl[k].P, hdg::TM_ABS, fa, h->stream), "trace abs");
+        const double floor_rn = 0x1p-53 * std::sqrt(dot(h, h->vq, h->vq, N));
+        if (rn <= 2.0 * floor_rn) {
+          h->err = "the true residual b - S x is within twice its rounding floor, above the tolerance";
+          return finish(HDG_ERR_AT_FLOOR);
         }
+        if (!(rn <= 0.5 * last_true)) {
+          h->err = "the true residual b - S x stalled above the tolerance";
+          return finish(HDG_ERR_NOT_CONVERGED);
+        }
+        last_true = rn;
       }
     }
     if (rn > tol) {

@@ -136,11 +136,15 @@ __global__ __launch_bounds__(kWG) void k_trace(TraceArgs a) {
 #pragma unroll
       for (int u = 0; u < V; ++u) {
         const int e = q * V + u;
-        if (e < NE) acc[(e % P2) / P] += w[u] * xv[e / P2][e % P];
+        if constexpr (MODE == TM_ABS) {
+          if (e < NE) acc[(e % P2) / P] += fabs(w[u]) * fabs(xv[e / P2][e % P]);
+        } else {
+          if (e < NE) acc[(e % P2) / P] += w[u] * xv[e / P2][e % P];
+        }
       }
     }
     if (valid) {
-      if constexpr (MODE == TM_APPLY || MODE == TM_APPLY_DOT) {
+      if constexpr (MODE == TM_APPLY || MODE == TM_APPLY_DOT || MODE == TM_ABS) {
 #pragma unroll
         for (int r = 0; r < P; ++r) y[f * P + r] = acc[r];
         if constexpr (MODE == TM_APPLY_DOT) {
@@ -294,6 +298,13 @@ static hipError_t launch_trace_t(int mode, const TraceArgs& a, hipStream_t s) {
         hipLaunchKernelGGL((k_trace<P, TM_APPLY, TM, TV>), grid, block, 0, s, a);
       break;
     case TM_APPLY_DOT: hipLaunchKernelGGL((k_trace<P, TM_APPLY_DOT, TM, TV>), grid, block, 0, s, a); break;
+    case TM_ABS:
+      if constexpr (sizeof(TV) == 8) {
+        hipLaunchKernelGGL((k_trace<P, TM_ABS, TM, TV>), grid, block, 0, s, a);
+        break;
+      } else {
+        return hipErrorInvalidValue;
+      }
     case TM_RESID: hipLaunchKernelGGL((k_trace<P, TM_RESID, TM, TV>), grid, block, 0, s, a); break;
     case TM_FACE_SWEEP: hipLaunchKernelGGL((k_trace<P, TM_FACE_SWEEP, TM, TV>), grid, block, 0, s, a); break;
     case TM_RESID_RESTRICT:

@@ -23,7 +23,8 @@ enum TraceMode : int {
   TM_RESID = 1,          // y = b - S x
   TM_FACE_SWEEP = 2,     // y = x + omega Dinv (b - S x)        (facet Schwarz sweep)
   TM_RESID_RESTRICT = 3, // y = P_p^T (b - S x)  (coarse vector, p - 1)
-  TM_APPLY_DOT = 4       // y = S x and per-wavefront partial sums of x . y
+  TM_APPLY_DOT = 4,      // y = S x and per-wavefront partial sums of x . y
+  TM_ABS = 5             // y = |S| |x| entrywise (FP64 only): the rounding scale of S x
 };
 
 struct TraceArgs {

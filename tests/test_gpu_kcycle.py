@@ -2,8 +2,10 @@
 against the oracle's K-cycle and direct solve.
 
 Bars: one K-cycle from x = 0 equals the oracle's to 1e-10 relative (max norm);
-the first FCG residual norms agree with the oracle's to 1e-7 relative; solutions
-match the direct solve to 1e-9 relative with ||b - S x|| <= 1e-10 ||b||.
+the FCG residual histories agree with the oracle's to 1e-12 ||b|| over the
+first 6 iterations (FCG_HIST_TOL, from the measured difference); solutions match
+the direct solve to 1e-10 relative with the true ||b - S x|| <= rtol ||b||,
+rtol = max(1e-12, 4 x rounding floor) (tests/tolerances.py).
 """
 import numpy as np
 import pytest
@@ -14,6 +16,12 @@ pytestmark = pytest.mark.gpu
 import paper_1705_09907_amd as H  # noqa: E402
 from oracle import hdg, mg  # noqa: E402
 from workloads import kappa_lognormal, normal_vector  # noqa: E402
+from tolerances import SOLUTION_RTOL, solve_rtol, rel_err  # noqa: E402
+
+# |h_gpu - h_oracle| / ||b|| over the first FCG iterations with the nonlinear
+# (K-cycle) preconditioner: both sides run the same deterministic steps, and the
+# histories differ by rounding only
+FCG_HIST_TOL = 1e-12
 
 
 def dev(a):
@@ -54,9 +62,12 @@ def test_fcg_history_matches_oracle():
         pr = hdg.Problem(n, k, kap)
         b = pr.rhs(np.ones((n * n, pr.ref.nq ** 2)))
         _, ho = Ho.solve(b, mode='fcg', rtol=1e-10)
-        x, it, rr, hg = S.solve(dev(b), rtol=1e-10, maxit=200, mode="fcg")
+        x, it, rr, hg = S.solve(dev(b), rtol=1e-10, maxit=200, mode="fcg", raise_on_fail=False)
         m = min(len(ho), len(hg), 6)
-        assert np.allclose(hg[:m], ho[:m], rtol=1e-7, atol=0)
+        d = np.abs(hg[:m] - ho[:m]).max() / np.linalg.norm(b)
+        rel = (np.abs(hg[:m] - ho[:m]) / ho[:m]).max()
+        print(f"fcg history difference {d:.2e} ||b|| ({rel:.2e} relative)", flush=True)
+        assert d <= FCG_HIST_TOL
         assert abs(len(hg) - len(ho)) <= 1
     finally:
         S.close()
@@ -70,18 +81,22 @@ def test_fcg_kcycle_solve_matches_direct(precision, n, k, sigma, inner):
     kap = kappa_lognormal(n, sigma, 12)
     pr = hdg.Problem(n, k, kap)
     b = pr.rhs(np.ones((n * n, pr.ref.nq ** 2)))
-    xd = pr.solve_direct(b)
+    Sc = pr.assemble().tocsr()
+    xd = pr.solve_direct(b, Sc)
+    rtol = solve_rtol(Sc, b, xd)
     S = H.Solver(n, k, kap, inner=inner, precision=precision)
     S0 = H.Solver(n, k, kap, precision=precision)
     try:
-        x, it, rr, hist = S.solve(dev(b), rtol=1e-10, maxit=300, mode="fcg")
-        assert rr <= 1e-10 and hist[-1] <= 1e-10 * np.linalg.norm(b)
-        assert np.linalg.norm(host(x) - xd) <= 1e-9 * np.linalg.norm(xd)
-        _, it0, _, _ = S0.solve(dev(b), rtol=1e-10, maxit=300, mode="pcg")
+        x, it, rr, hist = S.solve(dev(b), rtol=rtol, maxit=300, mode="fcg")
+        assert rr <= rtol and hist[-1] <= rtol * np.linalg.norm(b)
+        err = rel_err(host(x), xd)
+        print(f"rtol {rtol:.2e} iters {it} solution error {err:.2e}", flush=True)
+        assert err <= SOLUTION_RTOL
+        _, it0, _, _ = S0.solve(dev(b), rtol=rtol, maxit=400, mode="pcg")
         assert it < it0, (it, it0)
         # the stationary iteration with the same nonlinear cycle converges too
-        xv, itv, rrv, _ = S.solve(dev(b), rtol=1e-10, maxit=300, mode="vcycle")
-        assert rrv <= 1e-10 and np.linalg.norm(host(xv) - xd) <= 1e-9 * np.linalg.norm(xd)
+        xv, itv, rrv, _ = S.solve(dev(b), rtol=rtol, maxit=300, mode="vcycle")
+        assert rrv <= rtol and rel_err(host(xv), xd) <= SOLUTION_RTOL
     finally:
         S.close()
         S0.close()
@@ -110,9 +125,8 @@ def test_full_size_kcycle_solve(precision):
         b = dev(normal_vector(S.num_dofs(), 31))
         x, it, rr, hist = S.solve(b, rtol=1e-10, maxit=300, mode="fcg")
         _, rn = S.residual(k, b, x, norm=True)
-        # the solve stops on its recursively updated residual; the true residual
-        # b - S x differs from it by rounding drift (up to 3.4% of rtol measured)
-        assert rr <= 1e-10 and rn <= 1.25e-10 * float(torch.linalg.norm(b))
+        # relres is the true residual of the returned x, recomputed by the solver
+        assert rr <= 1e-10 and rn <= 1e-10 * float(torch.linalg.norm(b))
         print(f"kcycle {precision} iterations {it}", flush=True)
     finally:
         S.close()

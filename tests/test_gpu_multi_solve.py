@@ -1,8 +1,9 @@
 """GPU: the solve for many right-hand sides at once (hdg_solve_multi).
 
-Bars: every column matches the oracle's direct solve to 1e-9 relative with
-||b - S x|| <= 1e-10 ||b|| (FP64 and FP32 cycles), and matches the single-vector
-solve of the same column to 1e-9; edge meshes (n = 2, k = 0, ragged tails);
+Bars: every column matches the oracle's direct solve to 1e-10 relative with its
+true ||b - S x|| <= rtol ||b||, rtol = max(1e-12, 4 x rounding floor) over the
+columns (tests/tolerances.py) (FP64 and FP32 cycles), and matches the
+single-vector solve of the same column to 1e-10; edge meshes (n = 2, k = 0, ragged tails);
 full size n = 512, k = 5, 64 right-hand sides with the FP64 residual of sampled
 columns recomputed by the single-vector operator.
 """
@@ -15,6 +16,7 @@ pytestmark = pytest.mark.gpu
 import paper_1705_09907_amd as H  # noqa: E402
 from oracle import hdg  # noqa: E402
 from workloads import kappa_lognormal  # noqa: E402
+from tolerances import SOLUTION_RTOL, solve_rtol, rel_err  # noqa: E402
 
 
 def host(t):
@@ -34,17 +36,22 @@ def test_multi_solve_matches_direct_and_single(n, k, sigma, R, prec):
     Bh = np.stack([pr.rhs(1.0 + rng.standard_normal((n * n, pr.ref.nq ** 2))) for _ in range(R)], axis=1)
     S = H.Solver(n, k, kap, precision=prec)
     try:
+        A = pr.assemble().tocsr()
+        XD = [pr.solve_direct(Bh[:, r], A) for r in range(R)]
+        rtol = max(solve_rtol(A, Bh[:, r], XD[r]) for r in range(R))
         B = torch.tensor(Bh, device="cuda")
-        X, its, rr = S.solve_multi(B, rtol=1e-10, maxit=300)
+        X, its, rr = S.solve_multi(B, rtol=rtol, maxit=400)
         Xh = host(X)
-        A = pr.assemble()
+        worst = 0.0
         for r in range(R):
-            xd = pr.solve_direct(Bh[:, r], A)
-            assert np.linalg.norm(Xh[:, r] - xd) <= 1e-9 * np.linalg.norm(xd), r
-            assert rr[r] <= 1e-10 and np.linalg.norm(Bh[:, r] - A @ Xh[:, r]) <= 1.0001e-10 * np.linalg.norm(Bh[:, r])
+            err = rel_err(Xh[:, r], XD[r])
+            worst = max(worst, err)
+            assert err <= SOLUTION_RTOL, (r, err)
+            assert rr[r] <= rtol and np.linalg.norm(Bh[:, r] - A @ Xh[:, r]) <= 1.5 * rtol * np.linalg.norm(Bh[:, r])
+        print(f"rtol {rtol:.2e} worst solution error {worst:.2e}", flush=True)
         for r in (0, R - 1):
-            xs, _, _, _ = S.solve(B[:, r].contiguous(), rtol=1e-10, maxit=300)
-            assert np.linalg.norm(Xh[:, r] - host(xs)) <= 1e-9 * np.linalg.norm(host(xs))
+            xs, _, _, _ = S.solve(B[:, r].contiguous(), rtol=rtol, maxit=400)
+            assert rel_err(Xh[:, r], host(xs)) <= SOLUTION_RTOL
     finally:
         S.close()
 
@@ -74,9 +81,9 @@ def test_full_size_multi_solve():
         for r in (0, 31, 63):
             b = B[:, r].contiguous()
             res, nrm = S.residual(k, b, X[:, r].contiguous(), norm=True)
-            # the solve stops on its recursively updated residual; the true residual
-            # b - S x differs from it by rounding drift (up to 3.4% of rtol measured)
-            assert nrm <= 1.25e-10 * float(torch.linalg.norm(b)), r
+            # relres is the true residual (multi-column operator); the single-vector
+            # operator's residual of the same column differs by rounding only
+            assert nrm <= 1.01e-10 * float(torch.linalg.norm(b)), r
         print("iterations", its.min(), its.max(), flush=True)
     finally:
         S.close()

@@ -3,8 +3,9 @@ and the hybrid WH (W on the Q1 levels, V on the p-levels).
 
 Bars: three W- (and WH-) cycle iterates from zero match the oracle's to 1e-11
 relative (same smoother, omega and Chebyshev bounds; edge meshes n = 2, k = 0);
-W-cycle PCG and stationary W-cycles reach 1e-10 and match the direct solve to
-1e-9, in no more iterations than the V-cycle; the multi-column solve with the W
+W-cycle PCG and stationary W-cycles reach rtol = max(1e-12, 4 x rounding floor)
+on the true residual and match the direct solve to 1e-10, in no more iterations
+than the V-cycle; the multi-column solve with the W
 or WH schedule matches the direct solve and the single-vector solve per column.
 """
 import numpy as np
@@ -16,6 +17,7 @@ pytestmark = pytest.mark.gpu
 import paper_1705_09907_amd as H  # noqa: E402
 from oracle import hdg, mg  # noqa: E402
 from oracle import mesh as ms  # noqa: E402
+from tolerances import SOLUTION_RTOL, solve_rtol, rel_err  # noqa: E402
 from workloads import kappa_const, kappa_lognormal, normal_vector  # noqa: E402
 
 
@@ -66,16 +68,18 @@ def test_wcycle_solve_matches_direct(n, k, sigma, mode):
     kap = _kappa(n, sigma)
     pr = hdg.Problem(n, k, kap)
     b = pr.rhs(np.ones((n * n, pr.ref.nq ** 2)))
-    xd = pr.solve_direct(b)
+    Sc = pr.assemble().tocsr()
+    xd = pr.solve_direct(b, Sc)
+    rtol = solve_rtol(Sc, b, xd)
     its = {}
     for cyc in ("V", "W"):
         S = H.Solver(n, k, kap, cycle=cyc)
         try:
-            x, it, rr, hist = S.solve(dev(b), rtol=1e-10, maxit=300, mode=mode)
+            x, it, rr, hist = S.solve(dev(b), rtol=rtol, maxit=400, mode=mode)
         finally:
             S.close()
-        assert rr <= 1e-10 and hist[-1] <= 1e-10 * np.linalg.norm(b), cyc
-        assert np.linalg.norm(host(x) - xd) <= 1e-9 * np.linalg.norm(xd), cyc
+        assert rr <= rtol and hist[-1] <= rtol * np.linalg.norm(b), cyc
+        assert rel_err(host(x), xd) <= SOLUTION_RTOL, cyc
         its[cyc] = it
     assert its["W"] <= its["V"], its
 
@@ -91,16 +95,17 @@ def test_wcycle_multi_solve(n, k, sigma, R, prec, cycle):
     Bh = np.stack([pr.rhs(1.0 + rng.standard_normal((n * n, pr.ref.nq ** 2))) for _ in range(R)], axis=1)
     S = H.Solver(n, k, kap, precision=prec, cycle=cycle)
     try:
+        A = pr.assemble().tocsr()
+        XD = [pr.solve_direct(Bh[:, r], A) for r in range(R)]
+        rtol = max(solve_rtol(A, Bh[:, r], XD[r]) for r in range(R))
         B = torch.tensor(Bh, device="cuda")
-        X, its, rr = S.solve_multi(B, rtol=1e-10, maxit=300)
+        X, its, rr = S.solve_multi(B, rtol=rtol, maxit=400)
         Xh = host(X)
-        A = pr.assemble()
         for r in range(R):
-            xd = pr.solve_direct(Bh[:, r], A)
-            assert np.linalg.norm(Xh[:, r] - xd) <= 1e-9 * np.linalg.norm(xd), r
-            assert rr[r] <= 1e-10, r
+            assert rel_err(Xh[:, r], XD[r]) <= SOLUTION_RTOL, r
+            assert rr[r] <= rtol, r
         for r in (0, R - 1):
-            xs, _, _, _ = S.solve(B[:, r].contiguous(), rtol=1e-10, maxit=300)
-            assert np.linalg.norm(Xh[:, r] - host(xs)) <= 1e-9 * np.linalg.norm(host(xs))
+            xs, _, _, _ = S.solve(B[:, r].contiguous(), rtol=rtol, maxit=400)
+            assert rel_err(Xh[:, r], host(xs)) <= SOLUTION_RTOL
     finally:
         S.close()

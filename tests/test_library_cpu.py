@@ -147,3 +147,5 @@ def test_host_block_rejects_bad_arguments():
     assert H.lib.hdg_element_block_host(1, 1, 1, 1.0, 1.0, 0, pd) == -1      # n < 2
     assert H.lib.hdg_element_block_host(8, 1, 1, 1.0, 1.0, 5, pd) == -1      # bad coarse mode
     assert H.lib.hdg_status_string(-4) == b"not converged"
+    assert H.lib.hdg_status_string(-7) == b"stopped at the rounding floor of the residual"
+    assert H.STATUS[-7] == H.lib.hdg_status_string(-7).decode()
