@@ -1310,12 +1310,7 @@ hdg_status_t hdg_create(const hdg_config_t* cfg, const double* kappa_host, void*
     hipchk(hipStreamSynchronize(h->stream), "setup sync");
     return HDG_OK;
   });
-  if (st != HDG_OK) {
-    for (void* p : h->allocs) (void)hipFree(p);
-    if (h->scal_h) (void)hipHostFree(h->scal_h);
-    // keep the message reachable: report through stderr-free path by returning status only
-    return st;
-  }
+  if (st != HDG_OK) return st;  // ~hdg_ctx releases what setup allocated
   *out = h.release();
   return HDG_OK;
 }

@@ -24,5 +24,25 @@ def solve_rtol(S, b, x):
     return max(RESID_RTOL, 4.0 * residual_floor(S, b, x))
 
 
+def residual_agreement_bound(S, b, x):
+    """Largest ||r1 - r2||_2 between two FP64 evaluations of b - S x that sum in
+    different orders, with S's entries themselves rounded independently on the
+    two sides: per row each evaluation is within gamma_m (|b| + |S| |x|) of the
+    exact value, gamma_m = m u / (1 - m u), m = nonzeros of the row + 2 (the
+    standard bound for a rounded inner product, e.g. Higham, Accuracy and
+    Stability of Numerical Algorithms, Sec. 3.1)."""
+    u = 2.0 ** -53
+    m = int(np.diff(S.indptr).max()) + 2
+    gamma = m * u / (1 - m * u)
+    return 2.0 * gamma * np.linalg.norm(np.abs(b) + abs(S) @ np.abs(x))
+
+
+def true_residual_ok(S, b, x, relres_gpu):
+    """The oracle's b - S x of the GPU's x agrees with the residual the GPU
+    reported for it, to the rounding of the two evaluations."""
+    r = np.linalg.norm(b - S @ x)
+    return r <= relres_gpu * np.linalg.norm(b) + residual_agreement_bound(S, b, x), r
+
+
 def rel_err(x, xd):
     return np.linalg.norm(x - xd) / np.linalg.norm(xd)
