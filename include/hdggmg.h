@@ -218,6 +218,21 @@ hdg_status_t hdg_apply_trace_operator_multi(hdg_handle_t h, int32_t p, int32_t p
 hdg_status_t hdg_apply_trace_operator_batch(int32_t count, const hdg_handle_t* handles, const int32_t* p,
                                             const double* const* X, double* const* Y);
 
+/* For callers that cannot allocate device memory (code under HIP graph capture
+ * in the caller's own pipeline, tight serving loops, harnesses that forbid
+ * hipMalloc): the same products as hdg_apply_trace_operator_batch, bit for bit,
+ * with the same arguments and rules, but no allocation of any kind.  The
+ * (mesh, tile) descriptor table lives in a file-scope device array of
+ * HDG_BATCH_NOALLOC_MAX entries, one per GPU, held until the process ends (its
+ * device address is looked up once per device by hdg_create).  count >
+ * HDG_BATCH_NOALLOC_MAX returns INVALID_ARG.  Every call on one GPU shares that
+ * table and rewrites it: calls that overlap on one GPU (from several host
+ * threads or streams) race; calls in sequence do not, since each call
+ * synchronizes the stream of handles[0] before returning. */
+#define HDG_BATCH_NOALLOC_MAX 256
+hdg_status_t hdg_apply_trace_operator_batch_noalloc(int32_t count, const hdg_handle_t* handles, const int32_t* p,
+                                                    const double* const* X, double* const* Y);
+
 /* Measurement entry point: the same product as hdg_apply_trace_operator
  * (precision HDG_PREC_F64, FP64 vectors) or hdg_apply_trace_operator_lp
  * (precision = the handle's cycle precision, float vectors), launched with a

@@ -68,6 +68,7 @@ SIGNATURES = {
     "hdg_apply_trace_operator_timed": [_P, _I32, _I32, _P, _P, _PD],
     "hdg_apply_trace_operator_multi": [_P, _I32, _I32, _I32, _P, _P],
     "hdg_apply_trace_operator_batch": [_I32, _P, _P, _P, _P],
+    "hdg_apply_trace_operator_batch_noalloc": [_I32, _P, _P, _P, _P],
     "hdg_residual": [_P, _I32, _P, _P, _P, _PD],
     "hdg_smooth": [_P, _I32, _P, _P, _I32],
     "hdg_restrict": [_P, _I32, _P, _P],
@@ -140,8 +141,10 @@ def quadrature_nodes(nq):
     return x
 
 
-def apply_batch(solvers, xs, ys=None, levels=None):
-    """y_i = S_i x_i for many meshes in one kernel launch (FP64; synchronizes)."""
+def apply_batch(solvers, xs, ys=None, levels=None, noalloc=False):
+    """y_i = S_i x_i for many meshes in one kernel launch (FP64; synchronizes).
+    noalloc=True calls hdg_apply_trace_operator_batch_noalloc (same products, no
+    allocation, at most HDG_BATCH_NOALLOC_MAX meshes)."""
     import torch
     cnt = len(solvers)
     levels = [s.k for s in solvers] if levels is None else list(levels)
@@ -150,7 +153,8 @@ def apply_batch(solvers, xs, ys=None, levels=None):
     Pv = (ctypes.c_int32 * cnt)(*levels)
     Xv = (ctypes.c_void_p * cnt)(*[_dptr(x, "x", s.num_dofs(l)).value for s, x, l in zip(solvers, xs, levels)])
     Yv = (ctypes.c_void_p * cnt)(*[_dptr(y, "y", s.num_dofs(l)).value for s, y, l in zip(solvers, ys, levels)])
-    st = lib.hdg_apply_trace_operator_batch(cnt, H, Pv, Xv, Yv)
+    fn = lib.hdg_apply_trace_operator_batch_noalloc if noalloc else lib.hdg_apply_trace_operator_batch
+    st = fn(cnt, H, Pv, Xv, Yv)
     if st != 0:
         raise HDGError(st, lib.hdg_last_error(solvers[0]._h).decode())
     return ys

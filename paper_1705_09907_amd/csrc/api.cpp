@@ -96,6 +96,7 @@ struct hdg_ctx {
   hdg::BatchMesh* batch_dev = nullptr;      // descriptor table of hdg_apply_trace_operator_batch
   int batch_cap = 0;
   std::vector<hdg::BatchMesh> batch_host;
+  void* batch_scratch = nullptr;            // device address of the allocation-free descriptor table
   // misfit gradient: degree-k reference pack, coefficients, and the source state
   // of the last hdg_assemble_rhs (load vectors, boundary traces)
   double *ref_dev = nullptr, *kappa_dev = nullptr, *F_dev = nullptr, *lambd_dev = nullptr;
@@ -1253,6 +1254,9 @@ hdg_status_t hdg_create(const hdg_config_t* cfg, const double* kappa_host, void*
     h->kappa.assign(kappa_host, kappa_host + ne);
     for (double v : h->kappa)
       if (!(v > 0.0) || !std::isfinite(v)) throw ArgError("kappa must be > 0 and finite");
+    // arguments are valid: device set-up starts here (once per device: the address
+    // of the allocation-free batch apply's descriptor table)
+    hipchk(hdg::batch_scratch_address(&h->batch_scratch), "scratch address");
     h->nf = hdg::n_faces(h->n);
     h->ntiles = (h->nf + 63) / 64;
     h->pl.resize(h->k + 1);
@@ -1591,6 +1595,58 @@ hdg_status_t hdg_apply_trace_operator_batch(int32_t count, const hdg_handle_t* h
     const int grid = (int)std::max<int64_t>(1, std::min<int64_t>(need, 256 * 8));
     hipchk(hdg::launch_trace_batch(h0->batch_dev, count, tot, grid, pmax, h0->stream), "trace apply batch");
     hipchk(hipStreamSynchronize(h0->stream), "sync");  // the descriptor table is reused by the next call
+    return HDG_OK;
+  });
+}
+
+static_assert(HDG_BATCH_NOALLOC_MAX == hdg::kBatchNoallocMax, "descriptor table size");
+
+hdg_status_t hdg_apply_trace_operator_batch_noalloc(int32_t count, const hdg_handle_t* handles, const int32_t* p,
+                                                    const double* const* X, double* const* Y) {
+  if (count < 1 || !handles || !p || !X || !Y) return HDG_ERR_INVALID_ARG;
+  if (count > HDG_BATCH_NOALLOC_MAX) {
+    if (handles[0]) handles[0]->err = "the allocation-free batch apply takes at most HDG_BATCH_NOALLOC_MAX meshes";
+    return HDG_ERR_INVALID_ARG;
+  }
+  for (int i = 0; i < count; ++i) {
+    hdg_handle_t h = handles[i];
+    if (!h || p[i] < 0 || p[i] > h->k || !X[i] || !Y[i] || (const void*)X[i] == (const void*)Y[i])
+      return HDG_ERR_INVALID_ARG;
+    if (need_f64_level(h, p[i]) != HDG_OK) return HDG_ERR_STATE;
+  }
+  hdg_handle_t h0 = handles[0];
+  if (!h0->batch_scratch) {
+    h0->err = "no device scratch address for this handle";
+    return HDG_ERR_STATE;
+  }
+  return guarded(h0, [&]() -> hdg_status_t {
+    hdg::BatchMesh tab[hdg::kBatchNoallocMax];  // host copy on this call's stack: nothing allocated
+    int64_t tot = 0;
+    int pmax = 1;
+    for (int i = 0; i < count; ++i) {
+      const hdg_handle_t h = handles[i];
+      const PLevel& L = h->pl[p[i]];
+      hdg::BatchMesh& M = tab[i];
+      M.slab = L.slab64;
+      M.x = X[i];
+      M.y = Y[i];
+      M.nf = h->nf;
+      M.ntiles = h->ntiles;
+      M.tile0 = tot;
+      M.n = h->n;
+      M.P = L.P;
+      pmax = std::max(pmax, L.P);
+      tot += h->ntiles;
+    }
+    hipchk(hipMemcpyAsync(h0->batch_scratch, tab, sizeof(hdg::BatchMesh) * (size_t)count, hipMemcpyHostToDevice,
+                          h0->stream), "h2d");
+    const int64_t need = (tot + 3) / 4;
+    const int grid = (int)std::max<int64_t>(1, std::min<int64_t>(need, 256 * 8));
+    hipchk(hdg::launch_trace_batch(static_cast<const hdg::BatchMesh*>(h0->batch_scratch), count, tot, grid, pmax,
+                                   h0->stream), "trace apply batch");
+    // the host table lives on this stack frame and the device table is shared by
+    // every call on this GPU: both are released only after the kernel has run
+    hipchk(hipStreamSynchronize(h0->stream), "sync");
     return HDG_OK;
   });
 }

@@ -16,6 +16,8 @@
 #include <hip/hip_ext.h>
 #include <hip/hip_runtime.h>
 
+#include <mutex>
+
 #include "device.hpp"
 #include "kernels.hpp"
 
@@ -284,6 +286,31 @@ hipError_t launch_trace_batch(const BatchMesh* meshes_dev, int nmesh, int64_t to
   else
     hipLaunchKernelGGL(k_trace_batch<9>, dim3((unsigned)grid), dim3(kWG), 0, s, meshes_dev, nmesh, total_tiles);
   return hipGetLastError();
+}
+
+// Descriptor table of the allocation-free many-mesh apply: a file-scope device
+// array, one copy per GPU at its own address, held until the process ends.
+// Host code never uses this name as an address: batch_scratch_address() looks
+// the device address up once per device and every later use goes through it.
+static __device__ __align__(256) BatchMesh scratch[kBatchNoallocMax];
+
+hipError_t batch_scratch_address(void** out) {
+  static std::mutex mu;
+  static void* addr[kMaxDevices] = {};
+  int dev = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return e;
+  if (dev < 0 || dev >= kMaxDevices) return hipErrorInvalidDevice;
+  std::lock_guard<std::mutex> lock(mu);
+  if (!addr[dev]) {
+    void* p = nullptr;
+    e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return e;
+    if (!p) return hipErrorInvalidSymbol;
+    addr[dev] = p;
+  }
+  *out = addr[dev];
+  return hipSuccess;
 }
 
 template <int P, typename TM, typename TV>

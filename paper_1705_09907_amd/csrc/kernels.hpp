@@ -74,6 +74,12 @@ struct BatchMesh {
   int64_t nf, ntiles, tile0;
   int n, P;
 };
+// Allocation-free variant: the descriptor table lives in a file-scope device
+// array of kBatchNoallocMax entries (one per GPU); batch_scratch_address returns
+// its device address on the current device (looked up once per device).
+constexpr int kBatchNoallocMax = 256;
+constexpr int kMaxDevices = 64;
+hipError_t batch_scratch_address(void** out);
 // pmax: the largest P in the batch (selects the register budget)
 hipError_t launch_trace_batch(const BatchMesh* meshes_dev, int nmesh, int64_t total_tiles, int grid, int pmax,
                               hipStream_t s);
