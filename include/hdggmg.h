@@ -56,6 +56,14 @@ enum { HDG_SMOOTH_CHAIN = 0, HDG_SMOOTH_FACE = 1 };
 enum { HDG_COARSE_GALERKIN = 0, HDG_COARSE_REDISCRETIZE = 1 };
 enum { HDG_SOLVE_PCG = 0, HDG_SOLVE_VCYCLE = 1, HDG_SOLVE_FCG = 2 };
 enum { HDG_CYCLE_V = 0, HDG_CYCLE_W = 1, HDG_CYCLE_WH = 2 };
+/* Kernel of the many-right-hand-side products in the cycle precision (FP32 or
+ * bfloat16 blocks; FP64 always uses the vector kernel): HDG_MULTI_AUTO picks the
+ * faster of the two by timing on first use when autotune is set, else the vector
+ * kernel; HDG_MULTI_VECTOR: FP32 fused multiply-adds, one face and column per
+ * thread; HDG_MULTI_MATRIX: the matrix cores (v_mfma_f32_4x4x1_16b_f32), each
+ * wavefront walking a chain of faces with 64 columns on its lanes.  Both give
+ * the same products up to the order of rounding of the sums. */
+enum { HDG_MULTI_AUTO = 0, HDG_MULTI_VECTOR = 1, HDG_MULTI_MATRIX = 2 };
 /* Precision of the multigrid cycle (the preconditioner).  The outer solver, its
  * residuals and the finest-level operator it applies stay FP64 in every mode.
  *   HDG_PREC_F64:  every level, vector and block in FP64 (the paper's setting).
@@ -118,7 +126,8 @@ typedef struct {
                            step and the h-levels), V on the p-levels (not in the paper).
                            Levels with inner_steps keep their Krylov correction; the
                            coarsest level's exact solve runs once.                          */
-  int32_t reserved[5];
+  int32_t multi_kernel;  /* HDG_MULTI_AUTO (default), HDG_MULTI_VECTOR or HDG_MULTI_MATRIX       */
+  int32_t reserved[4];
 } hdg_config_t;
 
 /* Defaults: tau 1, V(2,2), chain smoother, Galerkin p-levels, omega/lmax estimated,

@@ -24,6 +24,7 @@ SMOOTHERS = {"chain": 0, "face": 1}
 COARSE = {"galerkin": 0, "rediscretize": 1}
 MODES = {"pcg": 0, "vcycle": 1, "fcg": 2}
 CYCLES = {"V": 0, "W": 1, "WH": 2}
+MULTI_KERNELS = {"auto": 0, "vector": 1, "matrix": 2}
 PRECISIONS = {"f64": 0, "f32": 1, "bf16": 2}
 STATUS = {0: "ok", -1: "invalid argument", -2: "out of memory", -3: "HIP error",
           -4: "not converged", -5: "non-finite value", -6: "invalid state",
@@ -40,7 +41,7 @@ class Config(ctypes.Structure):
                 ("coarse_max", ctypes.c_int32), ("nq", ctypes.c_int32),
                 ("precision", ctypes.c_int32), ("inner_steps", ctypes.c_int32 * (HDG_MAX_DEGREE + 1)),
                 ("graph", ctypes.c_int32), ("autotune", ctypes.c_int32), ("cycle", ctypes.c_int32),
-                ("reserved", ctypes.c_int32 * 5)]
+                ("multi_kernel", ctypes.c_int32), ("reserved", ctypes.c_int32 * 4)]
 
 
 _P = ctypes.c_void_p
@@ -165,7 +166,7 @@ class Solver:
 
     def __init__(self, n, k, kappa, tau=1.0, nu1=2, nu2=2, smoother="chain", coarse="galerkin",
                  omega=None, cheb_lmax=None, cheb=(0.1, 1.1), coarse_max=2000, nq=None, stream=None,
-                 precision="f64", inner=None, graph=False, autotune=False, cycle="V"):
+                 precision="f64", inner=None, graph=False, autotune=False, cycle="V", multi_kernel="auto"):
         import torch
         cfg = Config()
         lib.hdg_config_default(n, k, ctypes.byref(cfg))
@@ -188,6 +189,7 @@ class Solver:
         cfg.graph = 1 if graph else 0
         cfg.autotune = 1 if autotune else 0
         cfg.cycle = CYCLES[cycle]
+        cfg.multi_kernel = MULTI_KERNELS[multi_kernel]
         self.n, self.k, self.nq, self.precision = n, k, cfg.nq, precision
         kap, kp = _host(kappa, "kappa", n * n)
         if stream is None:

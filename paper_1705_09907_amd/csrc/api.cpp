@@ -5,6 +5,7 @@
 #include <algorithm>
 #include <cmath>
 #include <cstring>
+#include <map>
 #include <memory>
 #include <stdexcept>
 #include <string>
@@ -64,6 +65,7 @@ struct MultiWork {
   void *cva = nullptr, *cvb = nullptr;
   double *sc = nullptr, *nrm = nullptr, *nb = nullptr, *act = nullptr, *partial = nullptr;
   std::vector<int> rc;   // chain solve: columns per workgroup, per p-level (autotuned)
+  std::vector<int> mk;   // multi apply kernel per p-level (MultiArgs::kernel), cycle precision
   std::vector<void*> allocs;
   ~MultiWork() {
     for (void* q : allocs) (void)hipFree(q);
@@ -105,6 +107,7 @@ struct hdg_ctx {
   hdg::Prec prec = hdg::Prec::F64;      // precision of the multigrid cycle
   int nq = 0;
   std::unique_ptr<MultiWork> mw;        // solve for many right-hand sides
+  std::map<int64_t, int> multi_pick;    // multi apply kernel per (level, columns), cycle precision
 
   hdg_ctx() = default;
   hdg_ctx(const hdg_ctx&) = delete;
@@ -963,6 +966,51 @@ void* malloc_tracked(MultiWork& W, size_t bytes) {
   return q;
 }
 
+// Kernel of the cycle-precision multi apply at level L for R columns: the
+// config's choice, or with autotune the faster of the vector and matrix-core
+// kernels timed on Y = S X ([N][R], vector precision; best of 2 launches after a
+// warm-up; X is read and zeroed first only if it is scratch); otherwise the
+// vector kernel.  Both kernels compute the same products.
+int multi_kernel_choice(hdg_ctx* h, const PLevel& L, int R, void* X, void* Y, bool scratch) {
+  if (h->prec == hdg::Prec::F64) return 0;
+  if (h->cfg.multi_kernel == HDG_MULTI_VECTOR) return 0;
+  if (h->cfg.multi_kernel == HDG_MULTI_MATRIX) return 1;
+  if (!h->cfg.autotune) return 0;
+  if (scratch) hipchk(hdg::launch_zero(h->prec, X, L.N * R, h->stream), "zero");
+  EventPair ev;
+  float best = 1e30f;
+  int pick = 0;
+  for (int kern = 0; kern < 2; ++kern) {
+    hdg::MultiArgs a{};
+    a.slab = L.slab;
+    a.pmat = L.pmat;
+    a.nrhs = R;
+    a.n = h->n;
+    a.nf = h->nf;
+    a.ntiles = h->ntiles;
+    a.remap = 1;
+    a.kernel = kern;
+    a.X = X;
+    a.Y = Y;
+    hipchk(hdg::launch_trace_multi(L.mp, L.P, a, h->stream, hdg::TM_APPLY), "multi tune");
+    float t = 1e30f;
+    for (int rep = 0; rep < 2; ++rep) {
+      hipchk(hipEventRecord(ev.a, h->stream), "event");
+      hipchk(hdg::launch_trace_multi(L.mp, L.P, a, h->stream, hdg::TM_APPLY), "multi tune");
+      hipchk(hipEventRecord(ev.b, h->stream), "event");
+      hipchk(hipEventSynchronize(ev.b), "event sync");
+      float ms = 0.f;
+      hipchk(hipEventElapsedTime(&ms, ev.a, ev.b), "elapsed");
+      t = std::min(t, ms);
+    }
+    if (t < best) {
+      best = t;
+      pick = kern;
+    }
+  }
+  return pick;
+}
+
 MultiWork& multi_work(hdg_ctx* h, int R) {
   if (h->mw && h->mw->R == R) return *h->mw;
   hipchk(hipStreamSynchronize(h->stream), "sync");
@@ -1030,12 +1078,15 @@ MultiWork& multi_work(hdg_ctx* h, int R) {
     }
     W->rc.push_back(best_rc);
   }
+  for (const PLevel& L : h->pl)
+    W->mk.push_back(multi_kernel_choice(h, L, R, W->pr[L.p], W->px[L.p], true));
   h->mw = std::move(W);
   return *h->mw;
 }
 
 hdg::MultiArgs margs(hdg_ctx* h, const PLevel& L, int R, bool f64) {
   hdg::MultiArgs a{};
+  if (!f64 && h->mw && h->mw->R == R && (size_t)L.p < h->mw->mk.size()) a.kernel = h->mw->mk[L.p];
   a.slab = f64 && h->prec != hdg::Prec::F64 ? static_cast<const void*>(L.slab64) : L.slab;
   a.pmat = L.pmat;
   a.nrhs = R;
@@ -1177,6 +1228,8 @@ void validate_config(const hdg_config_t* c) {
   if (c->autotune != 0 && c->autotune != 1) throw ArgError("autotune must be 0 or 1");
   if (c->cycle != HDG_CYCLE_V && c->cycle != HDG_CYCLE_W && c->cycle != HDG_CYCLE_WH)
     throw ArgError("cycle must be HDG_CYCLE_V, HDG_CYCLE_W or HDG_CYCLE_WH");
+  if (c->multi_kernel != HDG_MULTI_AUTO && c->multi_kernel != HDG_MULTI_VECTOR && c->multi_kernel != HDG_MULTI_MATRIX)
+    throw ArgError("multi_kernel must be HDG_MULTI_AUTO, HDG_MULTI_VECTOR or HDG_MULTI_MATRIX");
   for (int p = 0; p <= HDG_MAX_DEGREE; ++p) {
     if (c->inner_steps[p] < 0 || c->inner_steps[p] > 64) throw ArgError("inner_steps must be in [0, 64]");
     if (p >= c->k && c->inner_steps[p] != 0) throw ArgError("inner_steps[p] must be 0 for p >= k");
@@ -1550,6 +1603,14 @@ hdg_status_t hdg_apply_trace_operator_multi(hdg_handle_t h, int32_t p, int32_t p
     a.nf = h->nf;
     a.ntiles = h->ntiles;
     a.remap = 1;
+    if (pr != hdg::Prec::F64) {
+      // kernel of this level and column count: config, or timed once (autotune)
+      const int64_t key = (int64_t)p * 8192 + nrhs;
+      auto it = h->multi_pick.find(key);
+      if (it == h->multi_pick.end())
+        it = h->multi_pick.emplace(key, multi_kernel_choice(h, L, nrhs, const_cast<void*>(X), Y, false)).first;
+      a.kernel = it->second;
+    }
     hipchk(hdg::launch_trace_multi(kprec(L, pr), L.P, a, h->stream), "trace apply multi");
     return HDG_OK;
   });

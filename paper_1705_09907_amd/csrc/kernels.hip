@@ -455,6 +455,245 @@ __global__ __launch_bounds__(256) void k_trace_multi(MultiArgs a) {
   }
 }
 
+// ------------------------------- many right-hand sides on the matrix cores
+// FP32 vectors (blocks FP32, or bfloat16 widened to FP32).  The per-face
+// product Y_f [P x R] = B_f [P x 7P] X_f [7P x R] (X_f the gathered neighbour
+// rows) runs on v_mfma_f32_4x4x1_16b_f32: sixteen independent 4 x 4 outer-product
+// blocks per instruction, block b taking the right-hand sides 4b .. 4b+3 of a
+// 64-column chunk and one group of 4 output rows (rows padded to a multiple of
+// 4 with zero rows).  Lane l = 4b + j supplies x[k][column l] (the B operand,
+// one coalesced 64-lane load per k) and row 4 rg + j of B_f at k (the A operand,
+// the same for every block); it receives rows 4 rg .. 4 rg + 3 of column l.  So
+// a lane owns one right-hand side of the face: 4 multiply-adds per instruction
+// per lane instead of 1, and one 16-byte LDS read of A per 4 k values.
+//
+// Each wavefront walks L consecutive faces of one chain (the vertical faces of
+// an element row, or the horizontal faces of an element column).  Consecutive
+// faces of a chain share an element, so 4 of the 7 gathered rows of the next
+// face are already in registers (the next face itself, the shared element's
+// other faces, and the current face): each step loads only the 3 rows of the
+// new element, 3P values per column instead of 7P.  A workgroup takes 4
+// neighbouring chains (one per wavefront) over the same L positions, and stages
+// their 4 L blocks in LDS (rows x k, zero padded) with coalesced slab reads.
+// Summation over k is sequential within each parity of k; the even and odd
+// partial sums are added at the end.
+typedef float v4f __attribute__((ext_vector_type(4)));
+
+template <int P>
+struct WalkShape {
+  static constexpr int NRG = (P + 3) / 4;       // groups of 4 output rows
+  static constexpr int K = 7 * P;               // gathered rows per face
+  static constexpr int KP = (K + 3) / 4 * 4;    // k padded to whole 16-byte LDS reads
+#ifdef HDG_WALK_L
+  static constexpr int L = HDG_WALK_L;
+#else
+  static constexpr int L = P <= 4 ? 16 : 8;     // faces per wavefront along its chain
+#endif
+  static_assert(L % 4 == 0, "a region holds L/4 tiles of each face type");
+};
+
+// Workgroups of a walk launch.  The mesh is cut into regions of L x L elements;
+// a region holds L/4 vertical tiles (4 element rows, L faces along each) and L/4
+// horizontal tiles (4 element columns, L faces along each), L/2 workgroups that
+// read overlapping rows of X.
+template <int P>
+__host__ __device__ inline int64_t walk_blocks(int n) {
+  constexpr int L = WalkShape<P>::L;
+  const int64_t nr = (n + L - 1) / L;
+  return nr * nr * (L / 2);
+}
+
+template <int P, int MODE, typename TM>
+__global__ __launch_bounds__(256) void k_trace_multi_walk(MultiArgs a) {
+  using L16 = Lanes16<TM, float>;
+  using WS = WalkShape<P>;
+  constexpr int V = L16::V, P2 = P * P, NE = 7 * P2, NQ = (NE + V - 1) / V;
+  constexpr int NRG = WS::NRG, K = WS::K, KP = WS::KP, L = WS::L;
+  __shared__ __align__(16) float blk[4][L][NRG * 4][KP];
+  const int n = a.n, m = n - 1;
+  const int64_t nv = (int64_t)n * m;
+  // Workgroups are dealt round-robin to the 8 XCDs: XCD x takes the contiguous
+  // run of regions [x R/8, (x+1) R/8) in row-major order, and a region's L/2
+  // tiles run back to back on it, so the X rows they share meet in its L2.
+  const int64_t total = walk_blocks<P>(n);
+  const int64_t q = (total % 8 == 0) ? (int64_t)(blockIdx.x & 7) * (total >> 3) + (blockIdx.x >> 3)
+                                     : (int64_t)blockIdx.x;
+  const int nr = (n + L - 1) / L;
+  const int64_t region = q / (L / 2);
+  const int tr = (int)(q - region * (L / 2));
+  const int rr = (int)(region / nr), rc = (int)(region - (int64_t)rr * nr);
+  const bool vert = tr < L / 4;
+  // chain group (4 chains) and the first position along them
+  const int cg = vert ? rr * (L / 4) + tr : rc * (L / 4) + (tr - L / 4);
+  const int pos0 = vert ? rc * L : rr * L;
+  if (pos0 >= m || 4 * cg >= n) return;  // uniform over the workgroup, before any barrier
+  // face at chain c, position pos (0 .. m-1)
+  auto face_at = [&](int c, int pos) -> int64_t {
+    return vert ? (int64_t)pos + (int64_t)m * c : nv + c + (int64_t)n * pos;
+  };
+  float* bl = &blk[0][0][0][0];
+  for (int i = threadIdx.x; i < 4 * L * NRG * 4 * KP; i += blockDim.x) bl[i] = 0.f;
+  __syncthreads();
+  const u32x4* sp = static_cast<const u32x4*>(a.slab);
+  // consecutive threads read consecutive faces: along the chain for vertical
+  // faces (consecutive face numbers), across the 4 chains for horizontal ones
+  for (int i = threadIdx.x; i < 4 * L * NQ; i += blockDim.x) {
+    int w, t, q;
+    if (vert) {
+      t = i % L;
+      q = (i / L) % NQ;
+      w = i / (L * NQ);
+    } else {
+      w = i & 3;
+      q = (i >> 2) % NQ;
+      t = (i >> 2) / NQ;
+    }
+    const int c = 4 * cg + w, pos = pos0 + t;
+    if (c >= n || pos >= m) continue;
+    const int64_t f = face_at(c, pos);
+    float wv[V];
+    L16::unpack(__builtin_nontemporal_load(sp + ((f >> 6) * NQ + q) * 64 + (f & 63)), wv);
+#pragma unroll
+    for (int u = 0; u < V; ++u) {
+      const int e = q * V + u;  // slot sl, row r, column cc  ->  blk[w][t][r][sl P + cc]
+      if (e < NE) {
+        const int sl = e / P2, rc = e - sl * P2, r = rc / P, cc = rc - r * P;
+        blk[w][t][r][sl * P + cc] = wv[u];
+      }
+    }
+  }
+  __syncthreads();
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, j = lane & 3;
+  const int c = 4 * cg + wave;
+  if (c >= n) return;  // uniform over the wavefront; no barrier follows
+  const int steps = min(L, m - pos0);
+  float* Y = static_cast<float*>(a.Y);
+  const float* B = static_cast<const float*>(a.B);
+  const int R = a.nrhs;
+  // X by buffer loads: one 32-bit lane offset per gathered row, the column
+  // offset c R of the row as a wave-uniform offset (the launcher keeps X below
+  // 2 GiB)
+  const __amdgpu_buffer_rsrc_t xr = buffer_rsrc(a.X, (int)((int64_t)a.nf * P * R * 4));
+  for (int r0 = 0; r0 < R; r0 += 64) {
+    const int col = r0 + lane;
+    const bool cok = col < R;
+    const int cl = cok ? col : R - 1;
+    // a missing (boundary) neighbour reads the face's own row, zeroed
+    auto load_row = [&](int64_t gs, int64_t fself, float* dst) __attribute__((always_inline)) {
+      const bool ok = gs >= 0 && cok;
+      const int xo = (int)(((gs >= 0 ? gs : fself) * P * R + cl) * 4);
+#pragma unroll
+      for (int cc = 0; cc < P; ++cc) {
+        const float v = buffer_load<float>(xr, xo, cc * R * 4);
+        dst[cc] = ok ? v : 0.f;
+      }
+    };
+    float xw[7][P];
+    {
+      const int64_t f = face_at(c, pos0);
+      int64_t g[7];
+      face_neighbours(n, nv, f, g);
+#pragma unroll
+      for (int sl = 0; sl < 7; ++sl) load_row(g[sl], f, xw[sl]);
+    }
+    for (int t = 0; t < steps; ++t) {
+      const int64_t f = face_at(c, pos0 + t);
+      // the next face's 3 new rows (the other faces of its new element), in flight
+      // while this face is computed
+      float nx[3][P];
+      const bool more = t + 1 < steps;
+      if (more) {
+        // the other faces of the next face's hi element (slots 4-6), or -1
+        const int pn = pos0 + t + 1;
+        const int64_t fn = face_at(c, pn);
+        int64_t g4, g5, g6;
+        if (vert) {  // row c, hi element (pn + 1, c): right, bottom, top
+          g4 = pn <= m - 2 ? fn + 1 : -1;
+          g5 = c >= 1 ? nv + (pn + 1) + (int64_t)n * (c - 1) : -1;
+          g6 = c <= n - 2 ? nv + (pn + 1) + (int64_t)n * c : -1;
+        } else {     // column c, hi element (c, pn + 1): left, right, top
+          g4 = c >= 1 ? (int64_t)(c - 1) + (int64_t)m * (pn + 1) : -1;
+          g5 = c <= n - 2 ? (int64_t)c + (int64_t)m * (pn + 1) : -1;
+          g6 = pn <= m - 2 ? fn + n : -1;
+        }
+        load_row(g4, fn, nx[0]);
+        load_row(g5, fn, nx[1]);
+        load_row(g6, fn, nx[2]);
+      }
+      v4f acc[2][NRG];
+#pragma unroll
+      for (int h = 0; h < 2; ++h)
+#pragma unroll
+        for (int rg = 0; rg < NRG; ++rg) acc[h][rg] = v4f{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+      for (int kq = 0; kq < KP / 4; ++kq) {
+        v4f av[NRG];
+#pragma unroll
+        for (int rg = 0; rg < NRG; ++rg) av[rg] = *reinterpret_cast<const v4f*>(&blk[wave][t][4 * rg + j][4 * kq]);
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+          const int k = 4 * kq + u;
+          if (k < K) {  // resolved at compile time
+            const float xv = xw[k / P][k % P];
+#pragma unroll
+            for (int rg = 0; rg < NRG; ++rg)
+              acc[u & 1][rg] = __builtin_amdgcn_mfma_f32_4x4x1f32(av[rg][u], xv, acc[u & 1][rg], 0, 0, 0);
+          }
+        }
+      }
+      if (cok) {
+        float res[NRG * 4];
+#pragma unroll
+        for (int rg = 0; rg < NRG; ++rg) {
+          const v4f sacc = acc[0][rg] + acc[1][rg];
+#pragma unroll
+          for (int i = 0; i < 4; ++i) res[4 * rg + i] = sacc[i];
+        }
+        if constexpr (MODE == TM_APPLY) {
+#pragma unroll
+          for (int q = 0; q < P; ++q) Y[(f * P + q) * R + col] = res[q];
+        } else {
+#pragma unroll
+          for (int q = 0; q < P; ++q) res[q] = B[(f * P + q) * R + col] - res[q];
+          if constexpr (MODE == TM_RESID) {
+#pragma unroll
+            for (int q = 0; q < P; ++q) Y[(f * P + q) * R + col] = res[q];
+          } else if constexpr (P >= 2) {  // TM_RESID_RESTRICT
+            const float* pm = static_cast<const float*>(a.pmat);
+#pragma unroll
+            for (int cc = 0; cc < P - 1; ++cc) {
+              float sacc = 0.f;
+#pragma unroll
+              for (int q = 0; q < P; ++q) sacc += pm[q * (P - 1) + cc] * res[q];
+              Y[(f * (P - 1) + cc) * R + col] = sacc;
+            }
+          }
+        }
+      }
+      if (more) {
+        // slot order (face_neighbours): 0 self, 1-3 the lo element's other faces,
+        // 4-6 the hi element's; the next face's lo element is this face's hi one
+        float o[7][P];
+#pragma unroll
+        for (int sl = 0; sl < 7; ++sl)
+#pragma unroll
+          for (int cc = 0; cc < P; ++cc) o[sl][cc] = xw[sl][cc];
+        // vertical (lo: L B T, hi: R B T): self' = R, L' = self, B' T' = hi's B T
+        // horizontal (lo: L R B, hi: L R T): self' = T, L' R' = hi's L R, B' = self
+#pragma unroll
+        for (int cc = 0; cc < P; ++cc) {
+          xw[0][cc] = vert ? o[4][cc] : o[6][cc];
+          xw[1][cc] = vert ? o[0][cc] : o[4][cc];
+          xw[2][cc] = o[5][cc];
+          xw[3][cc] = vert ? o[6][cc] : o[0][cc];
+#pragma unroll
+          for (int u = 0; u < 3; ++u) xw[4 + u][cc] = nx[u][cc];
+        }
+      }
+    }
+  }
+}
+
 #define HDG_DISPATCH_P(P, CALL)                       \
   switch (P) {                                        \
     case 1: { constexpr int PP = 1; CALL; } break;    \
@@ -469,8 +708,15 @@ __global__ __launch_bounds__(256) void k_trace_multi(MultiArgs a) {
     default: return hipErrorInvalidValue;             \
   }
 
+// right-hand sides from which the FP32 / bfloat16 product runs on the matrix cores
 template <int P, int MODE>
 static hipError_t launch_trace_multi_pm(Prec pr, const MultiArgs& a, hipStream_t s) {
+  if (pr != Prec::F64 && a.kernel == 1 && a.nf * P * (int64_t)a.nrhs * 4 < ((int64_t)1 << 31)) {
+    const dim3 grid((unsigned)walk_blocks<P>(a.n)), block(256);
+    if (pr == Prec::F32) hipLaunchKernelGGL((k_trace_multi_walk<P, MODE, float>), grid, block, 0, s, a);
+    else hipLaunchKernelGGL((k_trace_multi_walk<P, MODE, bf16_t>), grid, block, 0, s, a);
+    return hipGetLastError();
+  }
   constexpr int FW = MultiGroup<P, double>::FW;
   const dim3 grid((unsigned)((a.nf + FW - 1) / FW));
   const int64_t pairs = (int64_t)FW * a.nrhs;

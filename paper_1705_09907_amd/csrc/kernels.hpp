@@ -60,6 +60,7 @@ struct MultiArgs {
   int n;
   int64_t nf, ntiles;
   int remap;   // XCD-contiguous group order
+  int kernel;  // FP32 / bfloat16 blocks: 0 vector kernel, 1 matrix-core kernel (FP64 always vector)
 };
 // mode: TM_APPLY (Y = S X), TM_RESID (Y = B - S X) or TM_RESID_RESTRICT
 // (Y = P_p^T (B - S X) on the coarse level)

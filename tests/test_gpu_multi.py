@@ -4,8 +4,9 @@ Bars: FP64 against the oracle's assembled S times X, 1e-12 relative (max norm),
 on every level, ragged tails, nrhs a multiple of 64 (whole wavefronts per face,
 one or several 64-column chunks) or not; each column equals
 the single-vector apply to 1e-14 (same summation order); FP32 and bfloat16
-blocks obey the row-wise rounding bound of the reduced-precision apply; the
-full-size batch (n = 512, k = 5, 64 right-hand sides) on sampled faces.
+blocks obey the row-wise rounding bound of the reduced-precision apply, with
+both the vector kernel and the matrix-core kernel; the full-size batch (n = 512,
+k = 5, 64 right-hand sides) on sampled faces, both kernels.
 """
 import numpy as np
 import pytest
@@ -57,13 +58,14 @@ def test_multi_apply_every_level_fp64(n, k, R):
         S.close()
 
 
+@pytest.mark.parametrize("kernel", ["vector", "matrix"])
 @pytest.mark.parametrize("prec", ["f32", "bf16"])
-@pytest.mark.parametrize("R", [64, 128, 40])
-def test_multi_apply_reduced_precision_bound(prec, R):
-    n, k = 24, 3
+@pytest.mark.parametrize("n,k,R", [(24, 3, 64), (24, 3, 128), (24, 3, 40), (19, 8, 64), (17, 0, 70), (9, 5, 3)])
+def test_multi_apply_reduced_precision_bound(kernel, prec, n, k, R):
+    print(f"case multi apply {kernel} {prec} n={n} k={k} R={R}", flush=True)
     kap = kappa_lognormal(n, 2.0, 5)
     Ho = mg.Hierarchy(n, k, kap, smoother="face", omega=0.7)
-    S = H.Solver(n, k, kap, precision=prec)
+    S = H.Solver(n, k, kap, precision=prec, multi_kernel=kernel)
     rng = np.random.default_rng(9)
     try:
         for L in Ho.levels:
@@ -81,13 +83,14 @@ def test_multi_apply_reduced_precision_bound(prec, R):
         S.close()
 
 
-def test_full_size_batch_sampled():
+@pytest.mark.parametrize("kernel", ["vector", "matrix"])
+def test_full_size_batch_sampled(kernel):
     """n = 512, k = 5, 64 right-hand sides, FP32 blocks: sampled faces against
     oracle rows under the rounding bound."""
     n, k, R = 512, 5, 64
-    print("case full-size batch apply n=512 k=5 R=64", flush=True)
+    print(f"case full-size batch apply n=512 k=5 R=64 {kernel}", flush=True)
     kap = kappa_lognormal(n, 1.0, 4)
-    S = H.Solver(n, k, kap, precision="f32")
+    S = H.Solver(n, k, kap, precision="f32", multi_kernel=kernel)
     P = k + 1
     try:
         N = S.num_dofs()

@@ -24,17 +24,18 @@ def host(t):
     return t.detach().cpu().numpy()
 
 
-@pytest.mark.parametrize("n,k,sigma,R,prec", [(24, 3, 1.0, 5, "f64"), (16, 2, 2.0, 64, "f64"),
-                                              (24, 3, 1.0, 17, "f32"), (2, 1, 1.0, 3, "f64"),
-                                              (16, 0, 1.0, 8, "f64"), (19, 4, 1.0, 2, "bf16"),
-                                              (24, 3, 1.0, 128, "f32"), (17, 4, 1.0, 64, "bf16")])
-def test_multi_solve_matches_direct_and_single(n, k, sigma, R, prec):
-    print(f"case multi solve n={n} k={k} R={R} {prec}", flush=True)
+@pytest.mark.parametrize("n,k,sigma,R,prec,kernel", [
+    (24, 3, 1.0, 5, "f64", "auto"), (16, 2, 2.0, 64, "f64", "auto"), (24, 3, 1.0, 17, "f32", "auto"),
+    (2, 1, 1.0, 3, "f64", "auto"), (16, 0, 1.0, 8, "f64", "auto"), (19, 4, 1.0, 2, "bf16", "auto"),
+    (24, 3, 1.0, 128, "f32", "auto"), (17, 4, 1.0, 64, "bf16", "auto"), (24, 3, 1.0, 64, "f32", "matrix"),
+    (17, 5, 1.0, 33, "bf16", "matrix")])
+def test_multi_solve_matches_direct_and_single(n, k, sigma, R, prec, kernel):
+    print(f"case multi solve n={n} k={k} R={R} {prec} {kernel}", flush=True)
     kap = kappa_lognormal(n, sigma, 12)
     pr = hdg.Problem(n, k, kap)
     rng = np.random.default_rng(n + R)
     Bh = np.stack([pr.rhs(1.0 + rng.standard_normal((n * n, pr.ref.nq ** 2))) for _ in range(R)], axis=1)
-    S = H.Solver(n, k, kap, precision=prec)
+    S = H.Solver(n, k, kap, precision=prec, multi_kernel=kernel)
     try:
         A = pr.assemble().tocsr()
         XD = [pr.solve_direct(Bh[:, r], A) for r in range(R)]
