@@ -421,6 +421,42 @@ def main():
     wall = time.perf_counter() - t0
     apply_ms = np.array([r[0] * 1e-3 for r in rec])
     grad_ms = None if adj is None else float(np.median([r[1][0].elapsed_time(r[1][1]) for r in rec]))
+    per_theta = None
+    if adj is not None:
+        # a gradient loop over new coefficients on the same handle, after the timed
+        # region: set-up for theta (device rebuild of every level), right-hand side
+        # (host), then forward solve, reconstruction, adjoint solve and gradient
+        rngt = np.random.default_rng(8)
+        theta0 = np.log(kap)
+        upd, rhs_t, grd = [], [], []
+        for j in range(4):
+            th = theta0 + 0.1 * rngt.standard_normal(n * n)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            S.update_coefficients(np.exp(th))
+            t1 = time.perf_counter()
+            bj = S.assemble_rhs(np.ones((n * n, nq * nq)))
+            torch.cuda.synchronize()
+            t2 = time.perf_counter()
+            lam.zero_()
+            S.solve(bj, lam, rtol=1e-10, maxit=500, mode=args.mode, raise_on_fail=False)
+            U = S.reconstruct(lam)
+            c, _ = S.adjoint_rhs(U, adj["U_obs"])
+            mu = torch.zeros_like(c)
+            S.solve(c, mu, rtol=1e-10, maxit=500, mode=args.mode, raise_on_fail=False)
+            S.misfit_gradient(lam, U, adj["U_obs"], mu, adj["grad"])
+            torch.cuda.synchronize()
+            t3 = time.perf_counter()
+            if j:
+                upd.append(t1 - t0)
+                rhs_t.append(t2 - t1)
+                grd.append(t3 - t2)
+        per_theta = {"update_coefficients_ms": float(np.median(upd)) * 1e3, "rhs_ms": float(np.median(rhs_t)) * 1e3,
+                     "gradient_ms": float(np.median(grd)) * 1e3,
+                     "total_ms": float(np.median(np.array(upd) + np.array(rhs_t) + np.array(grd))) * 1e3,
+                     "note": "per new theta on one handle: hdg_update_coefficients, hdg_assemble_rhs, "
+                             "forward solve, reconstruction, adjoint solve, gradient (wall clock)"}
+        S.update_coefficients(kap)
     batch_out = None
     if batch is not None:
         bus = float(np.mean([r[7][0].elapsed_time(r[7][1]) for r in rec])) * 1e3
@@ -602,7 +638,7 @@ def main():
         "solve_true_relres": true_relres, "solve_floor_relres": floor_relres, "solve_status": solve_status,
         "solve_dof_per_s": N / (float(np.median(solve_ms)) * 1e-3),
         "solve_rate": rho, "setup_s": setup_s, "rhs_s": rhs_s,
-        "gradient_ms": grad_ms, "batch": batch_out,
+        "gradient_ms": grad_ms, "gradient_per_theta": per_theta, "batch": batch_out,
         "f64_reference": f64_ref, "vcycle_reference": vref,
         "roofline": {"bound": "hbm", "kernel": f"k_trace<P={k + 1}, APPLY, {args.precision}>", "achieved": achieved,
                      "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,

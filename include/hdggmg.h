@@ -127,7 +127,11 @@ typedef struct {
                            Levels with inner_steps keep their Krylov correction; the
                            coarsest level's exact solve runs once.                          */
   int32_t multi_kernel;  /* HDG_MULTI_AUTO (default), HDG_MULTI_VECTOR or HDG_MULTI_MATRIX       */
-  int32_t reserved[4];
+  int32_t setup_on_host; /* 0 (default): element blocks, face slabs, smoother factors and the Q1
+                            hierarchy are built on the device (coefficient updates supported);
+                            1: the host set-up (multi-threaded C++), the reference it is
+                            checked against                                                    */
+  int32_t reserved[3];
 } hdg_config_t;
 
 /* Defaults: tau 1, V(2,2), chain smoother, Galerkin p-levels, omega/lmax estimated,
@@ -136,15 +140,33 @@ hdg_status_t hdg_config_default(int32_t n, int32_t k, hdg_config_t* cfg);
 
 /* Setup (Sec. 3 steps (i)-(ii) and the multigrid hierarchy of Sec. 6).
  * kappa_host: [n*n] per-element coefficient K_e > 0 (host memory, read only,
- * not retained).  hip_stream: a hipStream_t (NULL = default stream).  Builds on
- * the host the condensed element blocks of every level, uploads face-major
- * blocks, smoother factors, transfer tables, Q1 stencils and the coarsest
- * inverse, then estimates any missing omega / lambda_max on the device.
+ * not retained).  hip_stream: a hipStream_t (NULL = default stream).  Builds
+ * the condensed element blocks of every level (Sec. 8: one independent local
+ * solve per element, all elements at once on the device unless setup_on_host),
+ * the face-major blocks, smoother factors, transfer tables, Q1 stencils and the
+ * coarsest inverse (host), then estimates any missing omega / lambda_max on the
+ * device.
  * Errors: INVALID_ARG (n < 2, k out of range, tau or any kappa not > 0 and
  * finite, bad config), OOM, HIP. */
 hdg_status_t hdg_create(const hdg_config_t* cfg, const double* kappa_host, void* hip_stream,
                         hdg_handle_t* out);
 hdg_status_t hdg_destroy(hdg_handle_t h);
+
+/* New per-element coefficient on an existing handle (same mesh, degree and
+ * config; nothing is reallocated): rebuilds on the device every level's blocks,
+ * smoother factors and Q1 hierarchy, and re-estimates the omega / lambda_max the
+ * config leaves to estimation.  Right-hand sides depend on the coefficient:
+ * call hdg_assemble_rhs again (the source state kept for hdg_reconstruct does
+ * not).  STATE for a handle made with setup_on_host = 1. */
+hdg_status_t hdg_update_coefficients(hdg_handle_t h, const double* kappa_host);
+
+/* The 7 blocks of interior face f at level p as stored on the device (Sec. 8,
+ * Alg. algo_mv's per-face data): out_host [7][p+1][p+1], slot 0 the summed
+ * diagonal block K_lo[f,f] + K_hi[f,f], slots 1-3 the lo element's blocks
+ * coupling f to its other faces in local order, slots 4-6 the hi element's
+ * (zero where that face is on the boundary), in the storage precision of the
+ * level widened to double (FP64 where an FP64 copy is kept). */
+hdg_status_t hdg_get_face_blocks(hdg_handle_t h, int32_t p, int64_t f, double* out_host);
 
 /* N(p) = 2 n (n-1) (p+1), the trace-vector length at degree p (0 <= p <= k). */
 hdg_status_t hdg_num_dofs(hdg_handle_t h, int32_t p, int64_t* n_lambda);

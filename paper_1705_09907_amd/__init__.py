@@ -41,7 +41,8 @@ class Config(ctypes.Structure):
                 ("coarse_max", ctypes.c_int32), ("nq", ctypes.c_int32),
                 ("precision", ctypes.c_int32), ("inner_steps", ctypes.c_int32 * (HDG_MAX_DEGREE + 1)),
                 ("graph", ctypes.c_int32), ("autotune", ctypes.c_int32), ("cycle", ctypes.c_int32),
-                ("multi_kernel", ctypes.c_int32), ("reserved", ctypes.c_int32 * 4)]
+                ("multi_kernel", ctypes.c_int32), ("setup_on_host", ctypes.c_int32),
+                ("reserved", ctypes.c_int32 * 3)]
 
 
 _P = ctypes.c_void_p
@@ -54,6 +55,8 @@ SIGNATURES = {
     "hdg_config_default": [_I32, _I32, ctypes.POINTER(Config)],
     "hdg_create": [ctypes.POINTER(Config), _PD, _P, ctypes.POINTER(_P)],
     "hdg_destroy": [_P],
+    "hdg_update_coefficients": [_P, _PD],
+    "hdg_get_face_blocks": [_P, _I32, _I64, _PD],
     "hdg_num_dofs": [_P, _I32, _PI64],
     "hdg_num_hlevels": [_P, _PI32],
     "hdg_hlevel_mesh": [_P, _I32, _PI32],
@@ -166,7 +169,8 @@ class Solver:
 
     def __init__(self, n, k, kappa, tau=1.0, nu1=2, nu2=2, smoother="chain", coarse="galerkin",
                  omega=None, cheb_lmax=None, cheb=(0.1, 1.1), coarse_max=2000, nq=None, stream=None,
-                 precision="f64", inner=None, graph=False, autotune=False, cycle="V", multi_kernel="auto"):
+                 precision="f64", inner=None, graph=False, autotune=False, cycle="V", multi_kernel="auto",
+                 host_setup=False):
         import torch
         cfg = Config()
         lib.hdg_config_default(n, k, ctypes.byref(cfg))
@@ -190,6 +194,7 @@ class Solver:
         cfg.autotune = 1 if autotune else 0
         cfg.cycle = CYCLES[cycle]
         cfg.multi_kernel = MULTI_KERNELS[multi_kernel]
+        cfg.setup_on_host = 1 if host_setup else 0
         self.n, self.k, self.nq, self.precision = n, k, cfg.nq, precision
         kap, kp = _host(kappa, "kappa", n * n)
         if stream is None:
@@ -249,6 +254,17 @@ class Solver:
         out = np.zeros((4 * (p + 1), 4 * (p + 1)))
         self._check(lib.hdg_get_element_block(self._h, p, e, out.ctypes.data_as(_PD)))
         return out
+
+    def face_blocks(self, p, f):
+        """The 7 blocks [7, p+1, p+1] of face f at level p as stored on the device."""
+        out = np.zeros((7, p + 1, p + 1))
+        self._check(lib.hdg_get_face_blocks(self._h, p, f, out.ctypes.data_as(_PD)))
+        return out
+
+    def update_coefficients(self, kappa):
+        """New per-element coefficient on this handle (device set-up, no reallocation)."""
+        kap, kp = _host(kappa, "kappa", self.n * self.n)
+        self._check(lib.hdg_update_coefficients(self._h, kp))
 
     def _empty(self, p):
         import torch

@@ -3,7 +3,10 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <chrono>
 #include <cmath>
+#include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <map>
 #include <memory>
@@ -455,6 +458,24 @@ Vec q1_from_p0(hdg_ctx* h, const Vec& b0) {
   return st;
 }
 
+// The coarsest Q1 level: dense Cholesky inverse of its matrix A (host), uploaded
+// (update: into the existing buffer).
+void coarsest_level(hdg_ctx* h, QLevel& Q, const hdg::Csr& A, bool update) {
+  if (Q.Nv > 20000) throw ArgError("coarsest Q1 level too large; use a mesh size with more factors of 2");
+  Q.coarsest = true;
+  Vec dense((size_t)Q.Nv * Q.Nv, 0.0);
+  for (int64_t r = 0; r < A.nrows; ++r)
+    for (int64_t kk = A.ptr[r]; kk < A.ptr[r + 1]; ++kk) dense[(size_t)r * Q.Nv + A.col[kk]] = A.val[kk];
+  if (!hdg::cholesky_inverse((int)Q.Nv, dense)) throw std::runtime_error("coarsest Q1 matrix not SPD");
+  if (update) {
+    hipchk(hipMemcpy(Q.inv, dense.data(), dense.size() * sizeof(double), hipMemcpyHostToDevice), "upload");
+    return;
+  }
+  Q.inv = upload(h, dense);
+  Q.x = valloc(h, Q.Nv);
+  Q.b = valloc(h, Q.Nv);
+}
+
 void build_hlevels(hdg_ctx* h, const Vec& b0) {
   Vec st = q1_from_p0(h, b0);
   int m = h->n;
@@ -466,15 +487,7 @@ void build_hlevels(hdg_ctx* h, const Vec& b0) {
     hdg::Csr A = hdg::stencil_to_csr(m, st);
     const bool last = Q.Nv <= h->cfg.coarse_max || (m % 2) == 1 || m < 4 || lev + 1 >= HDG_MAX_HLEVELS;
     if (last) {
-      if (Q.Nv > 20000) throw ArgError("coarsest Q1 level too large; use a mesh size with more factors of 2");
-      Q.coarsest = true;
-      Vec dense((size_t)Q.Nv * Q.Nv, 0.0);
-      for (int64_t r = 0; r < A.nrows; ++r)
-        for (int64_t kk = A.ptr[r]; kk < A.ptr[r + 1]; ++kk) dense[(size_t)r * Q.Nv + A.col[kk]] = A.val[kk];
-      if (!hdg::cholesky_inverse((int)Q.Nv, dense)) throw std::runtime_error("coarsest Q1 matrix not SPD");
-      Q.inv = upload(h, dense);
-      Q.x = valloc(h, Q.Nv);
-      Q.b = valloc(h, Q.Nv);
+      coarsest_level(h, Q, A, false);
       h->ql.push_back(Q);
       break;
     }
@@ -826,6 +839,237 @@ void precondition(hdg_ctx* h) {
 }
 
 // Largest eigenvalue of D^{-1} S_p (facet blocks) by Lanczos in the D inner product.
+// Wall-clock breakdown of hdg_create, printed to stderr when the environment
+// variable HDG_SETUP_TIMES is set (a diagnostic; no effect otherwise).
+struct SetupClock {
+  bool on = std::getenv("HDG_SETUP_TIMES") != nullptr;
+  std::chrono::steady_clock::time_point t0 = std::chrono::steady_clock::now(), last = t0;
+  std::string log;
+  void mark(const std::string& what) {
+    if (!on) return;
+    const auto now = std::chrono::steady_clock::now();
+    log += "  " + what + ": " + std::to_string(std::chrono::duration<double>(now - last).count()) + " s\n";
+    last = now;
+  }
+  void report() {
+    if (!on) return;
+    const double tot = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+    std::fprintf(stderr, "hdg_create %.3f s\n%s", tot, log.c_str());
+  }
+};
+
+// Largest eigenvalue of the Lanczos tridiagonal matrix (diagonal al, off-diagonal
+// be), by bisection on its Sturm sequence.
+double tridiag_max(const std::vector<double>& al, const std::vector<double>& be) {
+  const int m = (int)al.size();
+  double lo = 1e300, hi = -1e300;
+  for (int i = 0; i < m; ++i) {
+    const double r = (i > 0 ? std::fabs(be[i - 1]) : 0.0) + (i < m - 1 ? std::fabs(be[i]) : 0.0);
+    lo = std::min(lo, al[i] - r);
+    hi = std::max(hi, al[i] + r);
+  }
+  for (int it = 0; it < 200; ++it) {
+    const double mid = 0.5 * (lo + hi);
+    int c = 0;
+    double d = 1.0;
+    for (int i = 0; i < m; ++i) {
+      d = al[i] - mid - (i > 0 ? be[i - 1] * be[i - 1] / d : 0.0);
+      if (d == 0.0) d = 1e-300;
+      if (d < 0) ++c;
+    }
+    if (c >= m) hi = mid; else lo = mid;
+  }
+  return hi;
+}
+
+// Device memory of one set-up pass, released when it ends.
+struct DevScratch {
+  hipStream_t s = nullptr;
+  std::vector<void*> ptrs;
+  explicit DevScratch(hipStream_t st) : s(st) {}
+  template <typename T>
+  T* alloc(int64_t count) {
+    void* q = nullptr;
+    if (hipMalloc(&q, (size_t)std::max<int64_t>(count, 1) * sizeof(T)) != hipSuccess) {
+      (void)hipGetLastError();
+      throw std::bad_alloc();
+    }
+    ptrs.push_back(q);
+    return static_cast<T*>(q);
+  }
+  ~DevScratch() {
+    if (!ptrs.empty()) (void)hipStreamSynchronize(s);
+    for (void* q : ptrs) (void)hipFree(q);
+  }
+  DevScratch(const DevScratch&) = delete;
+  DevScratch& operator=(const DevScratch&) = delete;
+};
+
+// lambda_max(diag^{-1} A) of a Q1 level by 30 Lanczos steps on the device (FP64
+// stencil st, 1 / diagonal dinv), from the start vector of the host estimate.
+double estimate_q1_lmax(hdg_ctx* h, const double* st, const double* dinv, int m, DevScratch& tmp, int steps = 30) {
+  const int64_t N = (int64_t)(m - 1) * (m - 1);
+  hipStream_t s = h->stream;
+  double *v = tmp.alloc<double>(N), *z = tmp.alloc<double>(N), *w = tmp.alloc<double>(N),
+         *vold = tmp.alloc<double>(N), *r = tmp.alloc<double>(N), *zero = tmp.alloc<double>(N);
+  Vec hv(N);
+  for (int64_t i = 0; i < N; ++i) hv[i] = 1.0 + 0.25 * std::cos(0.7 * (double)i);
+  hipchk(hipMemcpyAsync(v, hv.data(), N * sizeof(double), hipMemcpyHostToDevice, s), "h2d");
+  hipchk(hdg::launch_fill(0.0, vold, N, s), "fill");
+  hipchk(hdg::launch_fill(0.0, zero, N, s), "fill");
+  hipchk(hdg::launch_vmul(dinv, v, z, N, s), "vmul");
+  const double beta = std::sqrt(dot(h, v, z, N));
+  hipchk(hdg::launch_xpby(v, 1.0 / beta - 1.0, v, N, s), "scale");
+  hipchk(hdg::launch_xpby(z, 1.0 / beta - 1.0, z, N, s), "scale");
+  std::vector<double> al, be;
+  double bprev = 0.0;
+  for (int it = 0; it < steps && it < N; ++it) {
+    hipchk(hdg::launch_q1_resid(hdg::Prec::F64, st, zero, z, r, m, s), "q1 apply");  // r = -A z
+    hipchk(hdg::launch_fill(0.0, w, N, s), "fill");
+    hipchk(hdg::launch_axpy(-1.0, r, w, N, s), "axpy");
+    const double alpha = dot(h, w, z, N);
+    hipchk(hdg::launch_axpy(-alpha, v, w, N, s), "axpy");
+    hipchk(hdg::launch_axpy(-bprev, vold, w, N, s), "axpy");
+    hipchk(hdg::launch_vmul(dinv, w, z, N, s), "vmul");
+    const double bn = std::sqrt(std::max(dot(h, w, z, N), 0.0));
+    al.push_back(alpha);
+    if (bn < 1e-14 * std::fabs(alpha)) break;
+    be.push_back(bn);
+    hipchk(hdg::launch_copy(hdg::Prec::F64, v, vold, N, s), "copy");
+    hipchk(hdg::launch_fill(0.0, v, N, s), "fill");
+    hipchk(hdg::launch_axpy(1.0 / bn, w, v, N, s), "axpy");
+    hipchk(hdg::launch_xpby(z, 1.0 / bn - 1.0, z, N, s), "scale");
+    bprev = bn;
+  }
+  return tridiag_max(al, be);
+}
+
+// Q1 hierarchy on the device from the p = 0 element blocks EB0 [n*n][4][4]
+// (update: the level buffers exist).
+void device_hlevels(hdg_ctx* h, const double* EB0, bool update, DevScratch& tmp) {
+  hipStream_t s = h->stream;
+  int m = h->n;
+  double* st = tmp.alloc<double>(9LL * (m - 1) * (m - 1));
+  hipchk(hdg::launch_q1_stencil0(EB0, h->n, st, s), "q1 stencil");
+  for (int lev = 0;; ++lev) {
+    if (!update) h->ql.emplace_back();
+    QLevel& Q = h->ql[lev];
+    Q.m = m;
+    Q.Nv = (int64_t)(m - 1) * (m - 1);
+    const bool last = Q.Nv <= h->cfg.coarse_max || (m % 2) == 1 || m < 4 || lev + 1 >= HDG_MAX_HLEVELS;
+    if (last) {
+      Vec sth((size_t)9 * Q.Nv);
+      hipchk(hipMemcpyAsync(sth.data(), st, sth.size() * sizeof(double), hipMemcpyDeviceToHost, s), "d2h");
+      hipchk(hipStreamSynchronize(s), "sync");
+      coarsest_level(h, Q, hdg::stencil_to_csr(m, sth), update);
+      break;
+    }
+    if (!update) {
+      Q.st = valloc(h, 9 * Q.Nv);
+      Q.dinv = valloc(h, Q.Nv);
+      for (void** q : {&Q.x, &Q.b, &Q.r, &Q.d, &Q.t}) *q = valloc(h, Q.Nv);
+    }
+    double* dinv64 = tmp.alloc<double>(Q.Nv);
+    hipchk(hdg::launch_q1_finish(h->prec, st, Q.Nv, Q.st, Q.dinv, dinv64, s), "q1 finish");
+    Q.lmax = h->cfg.cheb_lmax[lev] > 0 ? h->cfg.cheb_lmax[lev] : estimate_q1_lmax(h, st, dinv64, m, tmp);
+    double* stc = tmp.alloc<double>(9LL * (m / 2 - 1) * (m / 2 - 1));
+    hipchk(hdg::launch_q1_galerkin(st, m, stc, s), "q1 galerkin");
+    st = stc;
+    m /= 2;
+  }
+}
+
+// Device set-up of every p-level (element blocks, face slabs, facet inverses or
+// chain factors) and of the Q1 hierarchy from the coefficient in h->kappa_dev.
+// update: the level buffers exist (a new coefficient on an existing handle).
+void device_levels(hdg_ctx* h, SetupClock& clk, bool update) {
+  const int n = h->n, k = h->k;
+  const int64_t ne = (int64_t)n * n, nf = h->nf, nch = 2LL * n;
+  hipStream_t s = h->stream;
+  const bool redisc = h->cfg.coarse == HDG_COARSE_REDISCRETIZE;
+  const bool face = h->cfg.smoother == HDG_SMOOTH_FACE;
+  DevScratch tmp(s);
+  double* EBcur = tmp.alloc<double>(ne * 16LL * (k + 1) * (k + 1));
+  double* EBnext = k >= 1 ? tmp.alloc<double>(ne * 16LL * k * k) : nullptr;
+  int* fail = tmp.alloc<int>(1);
+  hipchk(hipMemsetAsync(fail, 0, sizeof(int), s), "memset");
+  for (int p = k; p >= 0; --p) {
+    PLevel& L = h->pl[p];
+    const int P = p + 1, P2 = P * P;
+    if (p == k || redisc) {
+      hdg::RefDegree rd;
+      rd.build(p, 1.0 / n, h->cfg.tau);
+      const hdg::PencilRef pc = hdg::pencil_reference(rd);
+      Vec pack;
+      std::vector<size_t> at;
+      for (const Vec* v : std::initializer_list<const Vec*>{&pc.V, &pc.delta, &pc.mu, &rd.Dm, &rd.G, &rd.H, &rd.E,
+                                                            &rd.Mb, &rd.P1}) {
+        at.push_back(pack.size());
+        pack.insert(pack.end(), v->begin(), v->end());
+      }
+      double* rdev = tmp.alloc<double>((int64_t)pack.size());
+      hipchk(hipMemcpyAsync(rdev, pack.data(), pack.size() * sizeof(double), hipMemcpyHostToDevice, s), "h2d");
+      hdg::ElemGenRef r{rdev + at[0], rdev + at[1], rdev + at[2], rdev + at[3], rdev + at[4],
+                        rdev + at[5], rdev + at[6], rdev + at[7], rdev + at[8], h->cfg.tau};
+      hipchk(hdg::launch_elem_rows(P, r, h->kappa_dev, EBcur, ne, s), "element blocks");
+      hipchk(hipStreamSynchronize(s), "sync");  // pack (a host vector) is released below
+    } else {
+      const Vec Pp = hdg::p_prolongation(p + 1);
+      double* pdev = tmp.alloc<double>((int64_t)Pp.size());
+      hipchk(hipMemcpyAsync(pdev, Pp.data(), Pp.size() * sizeof(double), hipMemcpyHostToDevice, s), "h2d");
+      hipchk(hdg::launch_elem_galerkin(p + 2, pdev, EBcur, EBnext, ne, s), "galerkin blocks");
+      std::swap(EBcur, EBnext);
+      hipchk(hipStreamSynchronize(s), "sync");
+    }
+    clk.mark("element blocks p=" + std::to_string(p));
+    // face slab in the cycle's matrix precision (+ FP64 copy of the finest level)
+    if (!update) L.mp = (h->prec == hdg::Prec::BF16 && p == k) ? hdg::Prec::F32 : h->prec;
+    const int V = hdg::mat_lanes16(L.mp);
+    const int64_t nq = (7LL * P2 + V - 1) / V, nq64 = (7LL * P2 + 1) / 2;
+    const bool copy64 = h->prec != hdg::Prec::F64 && p == k;
+    if (!update) {
+      L.slab = balloc(h, (size_t)(h->ntiles * nq * 64 * 16));
+      if (h->prec == hdg::Prec::F64) L.slab64 = static_cast<double*>(L.slab);
+      else if (copy64) L.slab64 = static_cast<double*>(balloc(h, (size_t)(h->ntiles * nq64 * 64 * 16)));
+      if (copy64) hipchk(hipMemsetAsync(L.slab64, 0, (size_t)(h->ntiles * nq64 * 64 * 16), s), "memset");
+    }
+    hipchk(hdg::launch_pack_slab(L.mp, P, EBcur, n, nf, L.slab, copy64 ? L.slab64 : nullptr, s), "pack slab");
+    if (face) {
+      const int64_t nqd = (P2 + V - 1) / V;
+      if (!update) L.dinv = balloc(h, (size_t)(h->ntiles * nqd * 64 * 16));
+      hipchk(hdg::launch_face_dinv(L.mp, P, EBcur, n, nf, L.dinv, fail, s), "facet inverses");
+    } else {
+      int64_t tot = 0;
+      for (int ml = n - 1;; ml = (ml + 1) / 2) {
+        tot += ml == 1 ? (int64_t)P2 : (int64_t)3 * P2 * (ml / 2);
+        if (ml == 1) break;
+      }
+      if (!update) {
+        L.cstride = tot;
+        L.chain = valloc(h, nch * tot);
+        const size_t es = hdg::vec_bytes(h->prec);
+        const int64_t rhs_bytes = (int64_t)(n - 1) * P * (int64_t)es;
+        L.chain_lds_level = hdg::chain_lds_level(P, n, es, std::min<int64_t>(8192, 65536 - rhs_bytes));
+      }
+      const int64_t wpc = hdg::chain_factor_work_doubles(P, n);
+      const int64_t batch = std::max<int64_t>(1, std::min<int64_t>(nch, ((int64_t)256 << 20) / 8 / wpc));
+      double* work = tmp.alloc<double>(batch * wpc);
+      for (int64_t c0 = 0; c0 < nch; c0 += batch)
+        hipchk(hdg::launch_chain_factor(h->prec, P, EBcur, n, c0, (int)std::min<int64_t>(batch, nch - c0), work,
+                                        L.chain, L.cstride, fail, s), "chain factors");
+    }
+    clk.mark("face data and smoother factors p=" + std::to_string(p));
+    if (p == 0) {
+      device_hlevels(h, EBcur, update, tmp);
+      clk.mark("Q1 hierarchy");
+    }
+  }
+  int failed = 0;
+  hipchk(hipMemcpyAsync(&failed, fail, sizeof(int), hipMemcpyDeviceToHost, s), "d2h");
+  hipchk(hipStreamSynchronize(s), "sync");
+  if (failed) throw std::runtime_error("a face or chain pivot block is not SPD");
+}
+
 double estimate_face_lmax(hdg_ctx* h, int p, int steps) {
   PLevel& L = h->pl[p];
   const int64_t N = L.N;
@@ -856,26 +1100,7 @@ double estimate_face_lmax(hdg_ctx* h, int p, int steps) {
     hipchk(hdg::launch_xpby(z, 1.0 / bn - 1.0, z, N, h->stream), "scale");
     bprev = bn;
   }
-  // tridiagonal eigen-bound by bisection
-  const int m = (int)al.size();
-  double lo = 1e300, hi = -1e300;
-  for (int i = 0; i < m; ++i) {
-    const double r = (i > 0 ? std::fabs(be[i - 1]) : 0.0) + (i < m - 1 ? std::fabs(be[i]) : 0.0);
-    lo = std::min(lo, al[i] - r);
-    hi = std::max(hi, al[i] + r);
-  }
-  for (int it = 0; it < 200; ++it) {
-    const double mid = 0.5 * (lo + hi);
-    int c = 0;
-    double d = 1.0;
-    for (int i = 0; i < m; ++i) {
-      d = al[i] - mid - (i > 0 ? be[i - 1] * be[i - 1] / d : 0.0);
-      if (d == 0.0) d = 1e-300;
-      if (d < 0) ++c;
-    }
-    if (c >= m) hi = mid; else lo = mid;
-  }
-  return hi;
+  return tridiag_max(al, be);
 }
 
 // A pair of timing events, destroyed on every exit path.
@@ -1228,6 +1453,7 @@ void validate_config(const hdg_config_t* c) {
   if (c->autotune != 0 && c->autotune != 1) throw ArgError("autotune must be 0 or 1");
   if (c->cycle != HDG_CYCLE_V && c->cycle != HDG_CYCLE_W && c->cycle != HDG_CYCLE_WH)
     throw ArgError("cycle must be HDG_CYCLE_V, HDG_CYCLE_W or HDG_CYCLE_WH");
+  if (c->setup_on_host != 0 && c->setup_on_host != 1) throw ArgError("setup_on_host must be 0 or 1");
   if (c->multi_kernel != HDG_MULTI_AUTO && c->multi_kernel != HDG_MULTI_VECTOR && c->multi_kernel != HDG_MULTI_MATRIX)
     throw ArgError("multi_kernel must be HDG_MULTI_AUTO, HDG_MULTI_VECTOR or HDG_MULTI_MATRIX");
   for (int p = 0; p <= HDG_MAX_DEGREE; ++p) {
@@ -1303,6 +1529,7 @@ hdg_status_t hdg_create(const hdg_config_t* cfg, const double* kappa_host, void*
     h->stream = (hipStream_t)hip_stream;
     h->prec = cfg->precision == HDG_PREC_F64 ? hdg::Prec::F64
               : (cfg->precision == HDG_PREC_F32 ? hdg::Prec::F32 : hdg::Prec::BF16);
+    SetupClock clk;
     const int64_t ne = (int64_t)h->n * h->n;
     h->kappa.assign(kappa_host, kappa_host + ne);
     for (double v : h->kappa)
@@ -1313,15 +1540,35 @@ hdg_status_t hdg_create(const hdg_config_t* cfg, const double* kappa_host, void*
     h->nf = hdg::n_faces(h->n);
     h->ntiles = (h->nf + 63) / 64;
     h->pl.resize(h->k + 1);
+    h->kappa_dev = upload(h.get(), h->kappa);
+    // reduction buffers first: the device set-up's Lanczos estimates use them
+    h->npartial = std::max(hdg::trace_partials(h->ntiles), 3 * 1024);
+    h->partial = dalloc(h.get(), h->npartial);
+    h->scal = dalloc(h.get(), 4);
+    hipchk(hipHostMalloc((void**)&h->scal_h, 4 * sizeof(double), hipHostMallocDefault), "pinned");
+    const bool host = cfg->setup_on_host != 0;
+    if (!host) {
+      for (int p = h->k; p >= 0; --p) {
+        PLevel& L = h->pl[p];
+        L.p = p;
+        L.P = p + 1;
+        L.N = h->nf * L.P;
+      }
+      device_levels(h.get(), clk, false);
+    }
     Vec blocks;
     for (int p = h->k; p >= 0; --p) {
       PLevel& L = h->pl[p];
       L.p = p;
       L.P = p + 1;
       L.N = h->nf * L.P;
-      if (p == h->k || cfg->coarse == HDG_COARSE_REDISCRETIZE) blocks = blocks_finest(h.get(), p);
-      else blocks = blocks_galerkin(h.get(), p + 1, blocks);
-      build_face_data(h.get(), L, blocks);
+      if (host) {
+        if (p == h->k || cfg->coarse == HDG_COARSE_REDISCRETIZE) blocks = blocks_finest(h.get(), p);
+        else blocks = blocks_galerkin(h.get(), p + 1, blocks);
+        clk.mark("element blocks p=" + std::to_string(p));
+        build_face_data(h.get(), L, blocks);
+        clk.mark("face data and chain factors p=" + std::to_string(p));
+      }
       if (p >= 1) {
         const Vec Pp = hdg::p_prolongation(p);
         L.pmat64 = upload(h.get(), Pp);
@@ -1332,13 +1579,12 @@ hdg_status_t hdg_create(const hdg_config_t* cfg, const double* kappa_host, void*
       L.inner = cfg->inner_steps[p];
       if (L.inner > 0)
         for (void** q : {&L.kz, &L.kd, &L.kq}) *q = valloc(h.get(), L.N);
-      if (p == 0) build_hlevels(h.get(), blocks);
+      if (p == 0 && host) {
+        build_hlevels(h.get(), blocks);
+        clk.mark("Q1 hierarchy");
+      }
     }
     const int64_t Nk = h->pl[h->k].N;
-    h->npartial = std::max(hdg::trace_partials(h->ntiles), 3 * 1024);
-    h->partial = dalloc(h.get(), h->npartial);
-    h->scal = dalloc(h.get(), 4);
-    hipchk(hipHostMalloc((void**)&h->scal_h, 4 * sizeof(double), hipHostMallocDefault), "pinned");
     h->vr = dalloc(h.get(), Nk);
     h->vz = dalloc(h.get(), Nk);
     h->vd = dalloc(h.get(), Nk);
@@ -1346,6 +1592,7 @@ hdg_status_t hdg_create(const hdg_config_t* cfg, const double* kappa_host, void*
     h->dsc = dalloc(h.get(), 8LL * (h->k + 1));
     if (cfg->autotune && cfg->smoother == HDG_SMOOTH_CHAIN)
       for (int p = 0; p <= h->k; ++p) tune_chain(h.get(), p);
+    clk.mark("chain autotune");
     if (h->prec != hdg::Prec::F64) {
       h->cva = valloc(h.get(), Nk);
       h->cvb = valloc(h.get(), Nk);
@@ -1362,14 +1609,88 @@ hdg_status_t hdg_create(const hdg_config_t* cfg, const double* kappa_host, void*
                                                             &rd.Mvinv})
         pack.insert(pack.end(), v->begin(), v->end());
       h->ref_dev = upload(h.get(), pack);
-      h->kappa_dev = upload(h.get(), h->kappa);
     }
     hipchk(hipStreamSynchronize(h->stream), "setup sync");
+    clk.mark("reference data and sync");
+    clk.report();
     return HDG_OK;
   });
   if (st != HDG_OK) return st;  // ~hdg_ctx releases what setup allocated
   *out = h.release();
   return HDG_OK;
+}
+
+hdg_status_t hdg_update_coefficients(hdg_handle_t h, const double* kappa_host) {
+  if (!h || !kappa_host) return HDG_ERR_INVALID_ARG;
+  const int64_t ne = (int64_t)h->n * h->n;
+  for (int64_t e = 0; e < ne; ++e)
+    if (!(kappa_host[e] > 0.0) || !std::isfinite(kappa_host[e])) {
+      h->err = "kappa must be > 0 and finite";
+      return HDG_ERR_INVALID_ARG;
+    }
+  if (h->cfg.setup_on_host) {
+    h->err = "coefficient updates need the device set-up (setup_on_host = 0)";
+    return HDG_ERR_STATE;
+  }
+  return guarded(h, [&]() -> hdg_status_t {
+    SetupClock clk;
+    hipchk(hipStreamSynchronize(h->stream), "sync");
+    h->kappa.assign(kappa_host, kappa_host + ne);
+    hipchk(hipMemcpy(h->kappa_dev, h->kappa.data(), ne * sizeof(double), hipMemcpyHostToDevice), "upload");
+    device_levels(h, clk, true);
+    if (h->cfg.smoother == HDG_SMOOTH_FACE)
+      for (int p = 0; p <= h->k; ++p)
+        if (!(h->cfg.omega[p] > 0)) h->pl[p].omega = 4.0 / (3.0 * estimate_face_lmax(h, p, 30));
+    // a captured cycle holds the old Chebyshev and damping scalars: capture again on next use
+    if (h->graph_exec) {
+      (void)hipGraphExecDestroy(h->graph_exec);
+      h->graph_exec = nullptr;
+    }
+    if (h->graph) {
+      (void)hipGraphDestroy(h->graph);
+      h->graph = nullptr;
+    }
+    hipchk(hipStreamSynchronize(h->stream), "sync");
+    clk.report();
+    return HDG_OK;
+  });
+}
+
+hdg_status_t hdg_get_face_blocks(hdg_handle_t h, int32_t p, int64_t f, double* out_host) {
+  if (!h || !out_host || p < 0 || p > h->k || f < 0 || f >= h->nf) return HDG_ERR_INVALID_ARG;
+  return guarded(h, [&]() -> hdg_status_t {
+    const PLevel& L = h->pl[p];
+    const bool f64 = L.slab64 != nullptr;
+    const hdg::Prec mp = f64 ? hdg::Prec::F64 : L.mp;
+    const int V = hdg::mat_lanes16(mp), NE = 7 * L.P * L.P;
+    const int64_t nq = (NE + V - 1) / V;
+    std::vector<unsigned char> raw((size_t)nq * 16);
+    const unsigned char* base = static_cast<const unsigned char*>(f64 ? static_cast<const void*>(L.slab64) : L.slab);
+    const int64_t tile = f >> 6, lane = f & 63;
+    hipchk(hipStreamSynchronize(h->stream), "sync");
+    hipchk(hipMemcpy2D(raw.data(), 16, base + ((tile * nq) * 64 + lane) * 16, 64 * 16, 16, (size_t)nq,
+                       hipMemcpyDeviceToHost), "d2h");
+    for (int e = 0; e < NE; ++e) {
+      const unsigned char* w = raw.data() + (size_t)(e / V) * 16;
+      double v;
+      if (mp == hdg::Prec::F64) {
+        std::memcpy(&v, w + (e % V) * 8, 8);
+      } else if (mp == hdg::Prec::F32) {
+        float x;
+        std::memcpy(&x, w + (e % V) * 4, 4);
+        v = x;
+      } else {
+        uint16_t b;
+        std::memcpy(&b, w + (e % V) * 2, 2);
+        const uint32_t u = (uint32_t)b << 16;
+        float x;
+        std::memcpy(&x, &u, 4);
+        v = x;
+      }
+      out_host[e] = v;
+    }
+    return HDG_OK;
+  });
 }
 
 hdg_status_t hdg_destroy(hdg_handle_t h) {

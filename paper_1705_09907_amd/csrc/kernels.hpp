@@ -206,6 +206,41 @@ hipError_t launch_xpby_m(Prec pr, const void* x, const double* num, const double
 // sc = [5][R]: sc[0][r] = sc[3][r] - (sc[2][r] / sc[1][r]) sc[4][r]
 hipError_t launch_fcg_scalars_m(double* sc, int R, hipStream_t s);
 
+// ---- device setup (setup_dev.hip)
+// Reference matrices of one degree for the element-block generator (FP64,
+// device): pencil basis V [P2][P2] (column i), delta, mu [P2], the local U
+// system D [P2][P2] and G [P2][P2], H [P2][4P], E [P2][4P], the trace mass Mb
+// [4P][4P] and C^T A0^{-1} C [4P][4P]; so that with W = kappa H - E
+//   K_e = tau Mb + kappa P1 - W^T (D + kappa G)^{-1} W.
+struct ElemGenRef {
+  const double *V, *delta, *mu, *Dm, *G, *H, *E, *Mb, *P1;
+  double tau;
+};
+// EB [ne][4P][4P]: condensed blocks of every element (one thread per column)
+hipError_t launch_elem_rows(int P, const ElemGenRef& r, const double* kappa, double* EB, int64_t ne, hipStream_t s);
+// Kc = P4^T Kf P4 per element (P4 = blockdiag(Pp), Pp [Pfine x (Pfine - 1)])
+hipError_t launch_elem_galerkin(int Pfine, const double* Pp, const double* Kf, double* Kc, int64_t ne,
+                                hipStream_t s);
+// face-major slab of level P from the element blocks, in matrix precision mp
+// (zero padding included); slab64 (optional, mp != F64): the FP64 copy
+hipError_t launch_pack_slab(Prec mp, int P, const double* EB, int n, int64_t nf, void* slab, double* slab64,
+                            hipStream_t s);
+// facet inverses in the slab layout (P^2 entries per face); *fail = 1 if a block is not SPD
+hipError_t launch_face_dinv(Prec mp, int P, const double* EB, int n, int64_t nf, void* dinv, int* fail,
+                            hipStream_t s);
+// chain cyclic-reduction factors of chains [chain0, chain0 + nchains), records
+// in vector precision vp; work: nchains * chain_factor_work_doubles(P, n)
+int64_t chain_factor_work_doubles(int P, int n);
+hipError_t launch_chain_factor(Prec vp, int P, const double* EB, int n, int64_t chain0, int nchains, double* work,
+                               void* fac, int64_t cstride, int* fail, hipStream_t s);
+// Q1 stencils [9][Nv] (FP64): from the p = 0 blocks, Galerkin coarsening, and
+// the cycle copies (vector precision stencil, 1 / diagonal, FP64 1 / diagonal)
+hipError_t launch_q1_stencil0(const double* EB0, int n, double* st, hipStream_t s);
+hipError_t launch_q1_galerkin(const double* stf, int mf, double* stc, hipStream_t s);
+hipError_t launch_q1_finish(Prec vp, const double* st64, int64_t Nv, void* st, void* dinv, double* dinv64,
+                            hipStream_t s);
+hipError_t launch_vmul(const double* a, const double* b, double* out, int64_t n, hipStream_t s);  // out = a .* b
+
 // deterministic reductions (FP64 vectors)
 int reduce_grid(int64_t n);
 hipError_t launch_dot_partials(const double* a, const double* b, int64_t n, double* partial,

@@ -167,7 +167,69 @@ static void inverse_by_columns(int N, const double* L, double* X) {
   });
 }
 
+// Cholesky factor of an SPD matrix with lower bandwidth bw (A[i][j] = 0 for
+// |i - j| > bw): the factor keeps the band, so the loops of cholesky() run over
+// the band only.  The terms skipped are exact zeros, so the factor is the one
+// cholesky() computes, to the bit, in O(N bw^2) instead of O(N^3).
+static bool cholesky_band(int N, int bw, double* A) {
+  for (int j = 0; j < N; ++j) {
+    const int k0 = std::max(0, j - bw);
+    double d = A[(size_t)j * N + j];
+    for (int k = k0; k < j; ++k) d -= A[(size_t)j * N + k] * A[(size_t)j * N + k];
+    if (!(d > 0.0)) return false;
+    d = std::sqrt(d);
+    A[(size_t)j * N + j] = d;
+    const int i1 = std::min(N - 1, j + bw);
+    for (int i = j + 1; i <= i1; ++i) {
+      double s = A[(size_t)i * N + j];
+      for (int k = std::max(0, i - bw); k < j; ++k) s -= A[(size_t)i * N + k] * A[(size_t)j * N + k];
+      A[(size_t)i * N + j] = s / d;
+    }
+    for (int i = i1 + 1; i < N; ++i) A[(size_t)i * N + j] = 0.0;
+  }
+  return true;
+}
+
+// Columns of A^{-1} from a banded factor (inverse_by_columns restricted to the
+// band of L; the same operations on the nonzero terms, so the same result).
+static void inverse_by_columns_band(int N, int bw, const double* L, double* X) {
+  parallel_for(N, [&](int64_t c0, int64_t c1) {
+    Vec y(N);
+    for (int64_t c = c0; c < c1; ++c) {
+      for (int i = 0; i < N; ++i) {
+        const double inv = 1.0 / L[(size_t)i * N + i];
+        double s = i == c ? 1.0 : 0.0;
+        const double* Li = L + (size_t)i * N;
+        for (int k = std::max(0, i - bw); k < i; ++k) s -= Li[k] * y[k];
+        y[i] = s * inv;
+      }
+      for (int i = N - 1; i >= 0; --i) {
+        const double inv = 1.0 / L[(size_t)i * N + i];
+        double s = y[i];
+        const int k1 = std::min(N - 1, i + bw);
+        for (int k = i + 1; k <= k1; ++k) s -= L[(size_t)k * N + i] * y[k];
+        y[i] = s * inv;
+      }
+      for (int i = 0; i < N; ++i) X[(size_t)i * N + c] = y[i];
+    }
+  });
+}
+
 bool cholesky_inverse(int N, Vec& A) {
+  int bw = 0;  // lower bandwidth
+  for (int i = 0; i < N; ++i)
+    for (int j = 0; j < i - bw; ++j)
+      if (A[(size_t)i * N + j] != 0.0) {
+        bw = i - j;
+        break;
+      }
+  if (N > 64 && 4 * bw < N) {
+    if (!cholesky_band(N, bw, A.data())) return false;
+    Vec I((size_t)N * N, 0.0);
+    inverse_by_columns_band(N, bw, A.data(), I.data());
+    A.swap(I);
+    return true;
+  }
   if (!cholesky(N, A.data())) return false;
   Vec L(A);
   Vec I((size_t)N * N, 0.0);
