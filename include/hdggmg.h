@@ -52,7 +52,7 @@ typedef enum {
                                  x is as accurate as FP64 storage lets the residual show */
 } hdg_status_t;
 
-enum { HDG_SMOOTH_CHAIN = 0, HDG_SMOOTH_FACE = 1 };
+enum { HDG_SMOOTH_CHAIN = 0, HDG_SMOOTH_FACE = 1, HDG_SMOOTH_PATCH = 2 };
 enum { HDG_COARSE_GALERKIN = 0, HDG_COARSE_REDISCRETIZE = 1 };
 enum { HDG_SOLVE_PCG = 0, HDG_SOLVE_VCYCLE = 1, HDG_SOLVE_FCG = 2 };
 enum { HDG_CYCLE_V = 0, HDG_CYCLE_W = 1, HDG_CYCLE_WH = 2 };
@@ -91,10 +91,15 @@ typedef struct {
                            of an element column), solved in LDS: needs
                            ((n-1)(k+1) + (k+1)^2) * (8 bytes FP64, 4 otherwise) <= 65536;
                            HDG_SMOOTH_FACE: one subdomain per facet
-                           (Sec. 6, additive Schwarz relaxation, zero overlap)           */
+                           (Sec. 6, additive Schwarz relaxation, zero overlap);
+                           HDG_SMOOTH_PATCH: one subdomain per element, its interior
+                           faces (Sec. 6 with overlap: neighbouring patches share a face),
+                           weighted by the inverse counting matrix W = 1/2 (each face
+                           lies in two patches), x <- x + omega W M (b - S x); device
+                           set-up only; omega default 1                                  */
   int32_t coarse;       /* p-level coarse operators: HDG_COARSE_GALERKIN (element-wise
                            P^T K P) or HDG_COARSE_REDISCRETIZE (degree-p HDG, Sec. 6)     */
-  double omega[HDG_MAX_DEGREE + 1]; /* Schwarz damping per p; <= 0: 0.8 (chain) or
+  double omega[HDG_MAX_DEGREE + 1]; /* Schwarz damping per p; <= 0: 1 (patch), 0.8 (chain) or
                            4 / (3 lambda_max(D^-1 S_p)) estimated on the device (face)    */
   double cheb_lo, cheb_hi;          /* Chebyshev interval [lo, hi] * lambda_max on Q1 levels */
   double cheb_lmax[HDG_MAX_HLEVELS];/* lambda_max(diag^-1 A) per Q1 level (0 = finest Q1);

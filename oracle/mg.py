@@ -179,6 +179,27 @@ class ChainSolver:
         return z
 
 
+def patch_schwarz(A, n, P):
+    """Sec. 6, additive Schwarz relaxation with overlap: one subdomain per element,
+    the trace unknowns of its interior faces (neighbouring subdomains share the
+    face between them), and the weighting W of the inverse counting matrix:
+    every interior face lies in exactly two subdomains, so W = 1/2 and
+        W M = 1/2 sum_K R_K^T (R_K A R_K^T)^{-1} R_K.
+    Returns W M as a sparse matrix."""
+    A = A.tocsr()
+    rows, cols, vals = [], [], []
+    for j in range(n):
+        for i in range(n):
+            faces = [f for f in ms.element_faces(n, i, j) if f >= 0]
+            idx = (np.asarray(faces)[:, None] * P + np.arange(P)[None, :]).reshape(-1)
+            MK = np.linalg.inv(A[idx][:, idx].toarray())
+            rows.append(np.repeat(idx, idx.size))
+            cols.append(np.tile(idx, idx.size))
+            vals.append(MK.reshape(-1))
+    M = sp.coo_matrix((np.concatenate(vals), (np.concatenate(rows), np.concatenate(cols))), shape=A.shape).tocsr()
+    return 0.5 * M
+
+
 def chebyshev(A, dinv, lmax, lo, hi, b, x, steps):
     """Chebyshev iteration on the interval [lo, hi] lmax for diag^{-1} A (Saad, Alg. 12.1).
 
@@ -256,7 +277,7 @@ class Hierarchy:
     """Nested p/h multigrid for per-element kappa on the n x n mesh at degree k.
 
     coarse:   'galerkin' (element-wise P4^T Kc P4) or 'rediscretize' (paper)
-    smoother: 'chain' or 'face' additive Schwarz on the p-levels
+    smoother: 'chain', 'face' or 'patch' additive Schwarz on the p-levels
     omega:    damping per p (dict) or scalar; default 0.8 for 'chain' and
               4 / (3 lambda_max(D^{-1} S_p)) for 'face'
     lmax:     dict name -> lambda_max(diag^{-1} A) on the Q1 levels (names
@@ -297,6 +318,9 @@ class Hierarchy:
             if smoother == 'chain':
                 L.M = ChainSolver(L.A, n, L.P)
                 om.setdefault(p, 0.8)
+            elif smoother == 'patch':
+                L.M = (lambda r, W=patch_schwarz(L.A, n, L.P): W @ r)
+                om.setdefault(p, 1.0)
             else:
                 L.Dinv = np.linalg.inv(face_blocks(L.A, L.P))
                 L.M = (lambda r, Di=L.Dinv: block_apply(Di, r))

@@ -20,7 +20,7 @@ LIB_PATH = os.path.join(_HERE, "libhdggmg.so")
 
 HDG_MAX_DEGREE = 8
 HDG_MAX_HLEVELS = 24
-SMOOTHERS = {"chain": 0, "face": 1}
+SMOOTHERS = {"chain": 0, "face": 1, "patch": 2}
 COARSE = {"galerkin": 0, "rediscretize": 1}
 MODES = {"pcg": 0, "vcycle": 1, "fcg": 2}
 CYCLES = {"V": 0, "W": 1, "WH": 2}

@@ -34,6 +34,7 @@ struct PLevel {
   double* slab64 = nullptr;
   void* dinv = nullptr;                                           // facet Schwarz
   void* chain = nullptr;                                          // chain Schwarz factors
+  void* pslab = nullptr;                                          // element-patch Schwarz inverses (slab layout)
   int64_t cstride = 0;
   void* pmat = nullptr;                                           // P_p (p >= 1)
   double* pmat64 = nullptr;
@@ -586,7 +587,23 @@ void smooth(hdg_ctx* h, int p, const void* b, void* x, int nu, bool zero) {
   const hdg::Prec pr = h->prec;
   for (int s = 0; s < nu; ++s) {
     const bool z = zero && s == 0;
-    if (h->cfg.smoother == HDG_SMOOTH_FACE) {
+    if (h->cfg.smoother == HDG_SMOOTH_PATCH) {
+      // x <- x + omega W M (b - S x), W = 1/2 (every interior face lies in two
+      // element patches): residual, then the patch-inverse slab applied face by face
+      hdg::TraceArgs a = targs(h, L, pr);
+      a.slab = L.pslab;
+      a.omega = 0.5 * L.omega;
+      a.y = x;
+      if (z) {
+        a.x = b;
+        a.b = nullptr;
+      } else {
+        residual(h, p, b, x, L.r, false, pr);
+        a.x = L.r;
+        a.b = x;
+      }
+      hipchk(hdg::launch_trace(L.mp, L.P, hdg::TM_UPDATE, a, h->stream), "patch update");
+    } else if (h->cfg.smoother == HDG_SMOOTH_FACE) {
       if (z) {
         hipchk(hdg::launch_dinv_apply(L.mp, L.P, L.dinv, b, L.omega, x, h->nf, h->stream), "dinv");
       } else {
@@ -1038,6 +1055,11 @@ void device_levels(hdg_ctx* h, SetupClock& clk, bool update) {
       const int64_t nqd = (P2 + V - 1) / V;
       if (!update) L.dinv = balloc(h, (size_t)(h->ntiles * nqd * 64 * 16));
       hipchk(hdg::launch_face_dinv(L.mp, P, EBcur, n, nf, L.dinv, fail, s), "facet inverses");
+    } else if (h->cfg.smoother == HDG_SMOOTH_PATCH) {
+      double* MB = tmp.alloc<double>(ne * 16LL * P2);
+      hipchk(hdg::launch_patch_inverse(P, EBcur, n, MB, fail, s), "patch inverses");
+      if (!update) L.pslab = balloc(h, (size_t)(h->ntiles * nq * 64 * 16));
+      hipchk(hdg::launch_pack_slab(L.mp, P, MB, n, nf, L.pslab, nullptr, s), "pack patch inverses");
     } else {
       int64_t tot = 0;
       for (int ml = n - 1;; ml = (ml + 1) / 2) {
@@ -1441,7 +1463,10 @@ void validate_config(const hdg_config_t* c) {
   if (c->k < 0 || c->k > HDG_MAX_DEGREE) throw ArgError("k out of range [0, 8]");
   if (!(c->tau > 0.0) || !std::isfinite(c->tau)) throw ArgError("tau must be > 0 and finite");
   if (c->nu1 < 1 || c->nu2 < 1 || c->nu1 > 64 || c->nu2 > 64) throw ArgError("nu1, nu2 must be in [1, 64]");
-  if (c->smoother != HDG_SMOOTH_CHAIN && c->smoother != HDG_SMOOTH_FACE) throw ArgError("bad smoother");
+  if (c->smoother != HDG_SMOOTH_CHAIN && c->smoother != HDG_SMOOTH_FACE && c->smoother != HDG_SMOOTH_PATCH)
+    throw ArgError("bad smoother");
+  if (c->smoother == HDG_SMOOTH_PATCH && c->setup_on_host)
+    throw ArgError("the element-patch smoother is built by the device set-up (setup_on_host = 0)");
   if (c->coarse != HDG_COARSE_GALERKIN && c->coarse != HDG_COARSE_REDISCRETIZE) throw ArgError("bad coarse");
   if (!(c->cheb_lo > 0.0) || !(c->cheb_hi > c->cheb_lo)) throw ArgError("need 0 < cheb_lo < cheb_hi");
   if (c->coarse_max < 1) throw ArgError("coarse_max must be >= 1");
@@ -1574,7 +1599,7 @@ hdg_status_t hdg_create(const hdg_config_t* cfg, const double* kappa_host, void*
         L.pmat64 = upload(h.get(), Pp);
         L.pmat = h->prec == hdg::Prec::F64 ? static_cast<void*>(L.pmat64) : upload_vec(h.get(), Pp);
       }
-      L.omega = cfg->omega[p] > 0 ? cfg->omega[p] : 0.8;
+      L.omega = cfg->omega[p] > 0 ? cfg->omega[p] : (cfg->smoother == HDG_SMOOTH_PATCH ? 1.0 : 0.8);
       for (void** q : {&L.x, &L.b, &L.r, &L.t}) *q = valloc(h.get(), L.N);
       L.inner = cfg->inner_steps[p];
       if (L.inner > 0)

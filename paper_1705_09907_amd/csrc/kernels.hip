@@ -146,7 +146,13 @@ __global__ __launch_bounds__(kWG) void k_trace(TraceArgs a) {
       }
     }
     if (valid) {
-      if constexpr (MODE == TM_APPLY || MODE == TM_APPLY_DOT || MODE == TM_ABS) {
+      if constexpr (MODE == TM_UPDATE) {
+#pragma unroll
+        for (int r = 0; r < P; ++r) {
+          const TV base = b != nullptr ? b[f * P + r] : TV(0);
+          y[f * P + r] = base + TV(a.omega) * acc[r];
+        }
+      } else if constexpr (MODE == TM_APPLY || MODE == TM_APPLY_DOT || MODE == TM_ABS) {
 #pragma unroll
         for (int r = 0; r < P; ++r) y[f * P + r] = acc[r];
         if constexpr (MODE == TM_APPLY_DOT) {
@@ -325,6 +331,7 @@ static hipError_t launch_trace_t(int mode, const TraceArgs& a, hipStream_t s) {
         hipLaunchKernelGGL((k_trace<P, TM_APPLY, TM, TV>), grid, block, 0, s, a);
       break;
     case TM_APPLY_DOT: hipLaunchKernelGGL((k_trace<P, TM_APPLY_DOT, TM, TV>), grid, block, 0, s, a); break;
+    case TM_UPDATE: hipLaunchKernelGGL((k_trace<P, TM_UPDATE, TM, TV>), grid, block, 0, s, a); break;
     case TM_ABS:
       if constexpr (sizeof(TV) == 8) {
         hipLaunchKernelGGL((k_trace<P, TM_ABS, TM, TV>), grid, block, 0, s, a);

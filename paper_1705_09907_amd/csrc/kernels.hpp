@@ -24,7 +24,8 @@ enum TraceMode : int {
   TM_FACE_SWEEP = 2,     // y = x + omega Dinv (b - S x)        (facet Schwarz sweep)
   TM_RESID_RESTRICT = 3, // y = P_p^T (b - S x)  (coarse vector, p - 1)
   TM_APPLY_DOT = 4,      // y = S x and per-wavefront partial sums of x . y
-  TM_ABS = 5             // y = |S| |x| entrywise (FP64 only): the rounding scale of S x
+  TM_ABS = 5,            // y = |S| |x| entrywise (FP64 only): the rounding scale of S x
+  TM_UPDATE = 6          // y = b + omega S x (b nullable: 0); y may alias b (element-patch Schwarz)
 };
 
 struct TraceArgs {
@@ -228,6 +229,9 @@ hipError_t launch_pack_slab(Prec mp, int P, const double* EB, int n, int64_t nf,
 // facet inverses in the slab layout (P^2 entries per face); *fail = 1 if a block is not SPD
 hipError_t launch_face_dinv(Prec mp, int P, const double* EB, int n, int64_t nf, void* dinv, int* fail,
                             hipStream_t s);
+// element-patch Schwarz: MB[e] = (R_e S R_e^T)^{-1} on the interior faces of element
+// e (rows and columns of boundary faces zero), [ne][4P][4P]; *fail = 1 if not SPD
+hipError_t launch_patch_inverse(int P, const double* EB, int n, double* MB, int* fail, hipStream_t s);
 // chain cyclic-reduction factors of chains [chain0, chain0 + nchains), records
 // in vector precision vp; work: nchains * chain_factor_work_doubles(P, n)
 int64_t chain_factor_work_doubles(int P, int n);

@@ -374,6 +374,54 @@ hipError_t launch_face_dinv(Prec mp, int P, const double* EB, int n, int64_t nf,
   return hipGetLastError();
 }
 
+// ------------------------------------------------ element-patch Schwarz
+// Subdomain of element e: its interior faces.  S restricted to them is e's own
+// block plus, on the diagonal block of each face, the neighbour's diagonal block
+// of that face (two distinct faces share one element at most).  The inverse is
+// stored as an element block (zero rows and columns for boundary faces), so the
+// smoother sum_e R_e^T (R_e S R_e^T)^{-1} R_e has the layout of S and is packed
+// and applied face by face like it.  Thread = element.
+template <int P>
+__global__ __launch_bounds__(kSW) void k_patch_inverse(const double* __restrict__ EB, int n, double* __restrict__ MB,
+                                                       int* fail) {
+  constexpr int F4 = 4 * P, F2 = F4 * F4;
+  const int64_t ne = (int64_t)n * n;
+  const int64_t e = (int64_t)blockIdx.x * kSW + threadIdx.x;
+  if (e >= ne) return;
+  const int64_t j = e / n, i = e - j * n;
+  bool in[4];
+  int64_t nb[4];
+  in[0] = i >= 1, nb[0] = e - 1;        // left: neighbour's right face (local 1)
+  in[1] = i <= n - 2, nb[1] = e + 1;    // right: neighbour's local 0
+  in[2] = j >= 1, nb[2] = e - n;        // bottom: neighbour's local 3
+  in[3] = j <= n - 2, nb[3] = e + n;    // top: neighbour's local 2
+  double A[F2], X[F2];
+  const double* K = EB + e * F2;
+  for (int r = 0; r < F4; ++r)
+    for (int c = 0; c < F4; ++c) {
+      const bool ok = in[r / P] && in[c / P];
+      A[r * F4 + c] = ok ? K[r * F4 + c] : (r == c ? 1.0 : 0.0);
+    }
+  for (int lf = 0; lf < 4; ++lf) {
+    if (!in[lf]) continue;
+    const int nlf = lf ^ 1;  // the same face seen from the neighbour
+    const double* Kn = EB + nb[lf] * F2;
+    for (int a = 0; a < P; ++a)
+      for (int c = 0; c < P; ++c) A[(lf * P + a) * F4 + lf * P + c] += Kn[(nlf * P + a) * F4 + nlf * P + c];
+  }
+  if (!spd_inverse<F4>(A, X)) *fail = 1;
+  double* out = MB + e * F2;
+  for (int r = 0; r < F4; ++r)
+    for (int c = 0; c < F4; ++c) out[r * F4 + c] = (in[r / P] && in[c / P]) ? X[r * F4 + c] : 0.0;
+}
+
+hipError_t launch_patch_inverse(int P, const double* EB, int n, double* MB, int* fail, hipStream_t s) {
+  const int64_t ne = (int64_t)n * n;
+  if (ne == 0) return hipSuccess;
+  HDG_SETUP_DISPATCH_P(P, hipLaunchKernelGGL(k_patch_inverse<PP>, sgrid(ne), dim3(kSW), 0, s, EB, n, MB, fail));
+  return hipGetLastError();
+}
+
 // ------------------------------------------------- chain cyclic reduction
 // Factors of the block-tridiagonal matrix of every chain of faces (the SPD
 // principal submatrix of S on the vertical faces of an element row, or the

@@ -89,8 +89,8 @@ def test_apply_is_deterministic():
     S.close()
 
 
-@pytest.mark.parametrize("n,k,sigma", [(16, 1, None), (24, 3, 1.0), (40, 4, 1.0)])
-@pytest.mark.parametrize("smoother", ["face", "chain"])
+@pytest.mark.parametrize("n,k,sigma", [(16, 1, None), (24, 3, 1.0), (40, 4, 1.0), (7, 8, 1.0)])
+@pytest.mark.parametrize("smoother", ["face", "chain", "patch"])
 def test_smoother_sweeps(n, k, sigma, smoother):
     print(f"case smooth {smoother} n={n} k={k}", flush=True)
     kap = _kappa(n, sigma)
@@ -131,7 +131,7 @@ def test_p_transfers(k):
 
 @pytest.mark.parametrize("n,k,sigma", [(16, 1, None), (24, 3, 1.0), (64, 2, 2.0), (16, 0, 1.0), (2, 1, None),
                                        (10, 7, 1.0)])
-@pytest.mark.parametrize("smoother", ["face", "chain"])
+@pytest.mark.parametrize("smoother", ["face", "chain", "patch"])
 def test_vcycle_iterates(n, k, sigma, smoother):
     print(f"case vcycle {smoother} n={n} k={k}", flush=True)
     kap = _kappa(n, sigma)
@@ -191,7 +191,7 @@ def test_rhs_assembly(n, k, kind):
 @pytest.mark.parametrize("n,k,sigma,mode,smoother", [
     (16, 1, None, "vcycle", "chain"), (16, 1, None, "pcg", "chain"), (24, 3, 1.0, "pcg", "chain"),
     (40, 4, 1.0, "pcg", "chain"), (64, 2, 2.0, "pcg", "chain"), (24, 3, 1.0, "pcg", "face"),
-    (24, 2, 1.0, "vcycle", "face")])
+    (24, 2, 1.0, "vcycle", "face"), (24, 3, 1.0, "pcg", "patch"), (16, 1, None, "vcycle", "patch")])
 def test_solve_matches_direct(n, k, sigma, mode, smoother):
     print(f"case solve {mode} {smoother} n={n} k={k}", flush=True)
     kap = _kappa(n, sigma)

@@ -2,6 +2,7 @@
 import numpy as np
 import pytest
 import scipy.sparse as sp
+import scipy.sparse.linalg as spla
 
 from oracle import hdg, mg, mesh as ms, quadrature as qd
 from workloads import kappa_lognormal, normal_vector, SinSin
@@ -158,6 +159,37 @@ def test_convergence_factor_is_independent_of_h():
     assert max(rho["chain"]) <= 0.2, rho
     assert rho["chain"][-1] <= 1.5 * rho["chain"][0], rho
     assert rho["face"][0] < rho["face"][1] < rho["face"][2], rho
+
+
+@pytest.mark.parametrize("n,k,sigma", [(4, 1, 1.0), (6, 2, 2.0), (5, 3, 1.0)])
+def test_patch_schwarz_decomposition(n, k, sigma):
+    """Element-patch Schwarz with overlap (Sec. 6, counting weight W = 1/2):
+    (i) W M e_f = 1/2 (y_1 + y_2), y_i solving the restriction of S to the
+    interior faces of f's two elements with right-hand side R e_f (sparse LU of
+    the restricted matrix, another route than the dense inverse of the oracle),
+    and zero on every other face; (ii) W M is symmetric; (iii) the eigenvalues of
+    W M S are real, positive and below 2, so x <- x + W M (b - S x) contracts."""
+    import scipy.linalg as sla
+    kap = kappa_lognormal(n, sigma, 3)
+    P = k + 1
+    S = hdg.Problem(n, k, kap).assemble().tocsr()
+    WM = mg.patch_schwarz(S, n, P)
+    nf = ms.n_faces(n)
+    for f in (0, nf // 2, nf - 1, n):
+        lo, hi, _ = ms.face_elements(n, f)
+        expect = np.zeros(S.shape[0])
+        for e in (lo, hi):
+            faces = [g for g in ms.element_faces(n, e % n, e // n) if g >= 0]
+            idx = (np.asarray(faces)[:, None] * P + np.arange(P)[None, :]).reshape(-1)
+            rhs = (idx == f * P).astype(float)   # R e_f for the first trace DoF of face f
+            expect[idx] += 0.5 * spla.spsolve(S[idx][:, idx].tocsc(), rhs)
+        got = WM @ np.eye(S.shape[0])[:, f * P]
+        assert np.abs(got - expect).max() <= 1e-12 * np.abs(expect).max(), f
+    W = WM.toarray()
+    assert np.abs(W - W.T).max() <= 1e-12 * np.abs(W).max()
+    ev = sla.eigvals(W @ S.toarray())
+    assert np.abs(ev.imag).max() <= 1e-8 * np.abs(ev.real).max()
+    assert ev.real.min() > 0 and ev.real.max() < 2.0, (ev.real.min(), ev.real.max())
 
 
 def test_rediscretized_coarse_level_amplifies_rough_modes():
