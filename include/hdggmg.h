@@ -64,6 +64,9 @@ enum { HDG_CYCLE_V = 0, HDG_CYCLE_W = 1, HDG_CYCLE_WH = 2 };
  * wavefront walking a chain of faces with 64 columns on its lanes.  Both give
  * the same products up to the order of rounding of the sums. */
 enum { HDG_MULTI_AUTO = 0, HDG_MULTI_VECTOR = 1, HDG_MULTI_MATRIX = 2 };
+
+/* Launch schedules of the chain Schwarz solve (hdg_config_t.chain_shape). */
+enum { HDG_CHAIN_AUTO = 0, HDG_CHAIN_LEAN = 1, HDG_CHAIN_WIDE = 2, HDG_CHAIN_FLAT = 3 };
 /* Precision of the multigrid cycle (the preconditioner).  The outer solver, its
  * residuals and the finest-level operator it applies stay FP64 in every mode.
  *   HDG_PREC_F64:  every level, vector and block in FP64 (the paper's setting).
@@ -89,7 +92,8 @@ typedef struct {
   int32_t smoother;     /* HDG_SMOOTH_CHAIN: additive Schwarz with one subdomain per chain
                            of faces (vertical faces of an element row / horizontal faces
                            of an element column), solved in LDS: needs
-                           ((n-1)(k+1) + (k+1)^2) * (8 bytes FP64, 4 otherwise) <= 65536;
+                           ((n-1)(k+1) + (k+1)^2) * (8 bytes FP64, 4 otherwise) bytes, at
+                           most the LDS one workgroup may use (160 KiB on gfx950);
                            HDG_SMOOTH_FACE: one subdomain per facet
                            (Sec. 6, additive Schwarz relaxation, zero overlap);
                            HDG_SMOOTH_PATCH: one subdomain per element, its interior
@@ -120,8 +124,8 @@ typedef struct {
                            levels included) is captured once as a HIP graph on a library
                            stream and replayed on the handle's stream; 0 (default): eager
                            launches.  Same kernels in the same order either way.         */
-  int32_t autotune;     /* 1: at setup, time the chain Schwarz launch shapes (workgroup size,
-                           XCD-aware chain order, LDS staging depth) of every level and keep
+  int32_t autotune;     /* 1: at setup, time the chain Schwarz launch shapes (schedule, workgroup
+                           size, XCD-aware chain order, LDS staging depth) of every level and keep
                            the fastest; 0 (default): measured fixed defaults.  Results are
                            identical either way (same operations in the same order).     */
   int32_t cycle;        /* HDG_CYCLE_V (default): each coarse correction is one cycle of the
@@ -136,7 +140,13 @@ typedef struct {
                             hierarchy are built on the device (coefficient updates supported);
                             1: the host set-up (multi-threaded C++), the reference it is
                             checked against                                                    */
-  int32_t reserved[3];
+  int32_t chain_shape;   /* launch schedule of the chain Schwarz solve (HDG_CHAIN_*): AUTO
+                            (default) picks by degree and mesh (or the autotuner, when on);
+                            LEAN / WIDE: factors fetched level by level in register batches
+                            (WIDE: every row of a position per batch, P = 3 ... 5); FLAT: every
+                            factor of a sweep requested at once into registers (P <= 5, while
+                            they fit).  Same operations in the same order, identical results. */
+  int32_t reserved[2];
 } hdg_config_t;
 
 /* Defaults: tau 1, V(2,2), chain smoother, Galerkin p-levels, omega/lmax estimated,

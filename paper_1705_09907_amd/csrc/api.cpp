@@ -43,6 +43,7 @@ struct PLevel {
   int chain_lds_level = 64;                           // chain factors of levels >= this are staged in LDS
   int chain_threads = 0;                              // chain launch shape (0: chain_threads default)
   int chain_remap = -1;                               // -1: chain_remap default
+  int chain_shape = 0;                                // launch shape (ChainArgs::shape; 0: by the mesh)
   int inner = 0;                                      // K-cycle: FCG steps of this level's correction
   void *kz = nullptr, *kd = nullptr, *kq = nullptr;   // K-cycle work vectors
 };
@@ -110,6 +111,7 @@ struct hdg_ctx {
   bool have_source = false;
   hdg::Prec prec = hdg::Prec::F64;      // precision of the multigrid cycle
   int nq = 0;
+  int64_t lds_cap = 65536;              // LDS bytes per workgroup on this device
   std::unique_ptr<MultiWork> mw;        // solve for many right-hand sides
   std::map<int64_t, int> multi_pick;    // multi apply kernel per (level, columns), cycle precision
 
@@ -414,10 +416,10 @@ void build_face_data(hdg_ctx* h, PLevel& L, const Vec& blocks) {
     }
   });
   L.chain = upload_vec(h, fac);
-  // stage the small levels' factors in LDS: at most 8 KiB, within 64 KiB in all
+  // stage the small levels' factors in LDS: at most 8 KiB beside the chain
   const size_t es = hdg::vec_bytes(h->prec);
   const int64_t rhs_bytes = (int64_t)(n - 1) * P * (int64_t)es;
-  L.chain_lds_level = hdg::chain_lds_level(P, n, es, std::min<int64_t>(8192, 65536 - rhs_bytes));
+  L.chain_lds_level = hdg::chain_lds_level(P, n, es, std::min<int64_t>(8192, h->lds_cap - rhs_bytes));
 }
 
 // Q1 stencil of P_J^T S0 P_J from the p = 0 element blocks (4 x 4).
@@ -616,8 +618,10 @@ void smooth(hdg_ctx* h, int p, const void* b, void* x, int nu, bool zero) {
       }
     } else {
       hdg::ChainArgs c{};
+      c.lds_cap = h->lds_cap;
       c.lds_level = L.chain_lds_level;
       c.threads = L.chain_threads;
+      c.shape = L.chain_shape;
       c.remap = L.chain_remap >= 0 ? L.chain_remap : hdg::chain_remap(L.P);
       c.factors = L.chain;
       c.cstride = L.cstride;
@@ -1071,7 +1075,7 @@ void device_levels(hdg_ctx* h, SetupClock& clk, bool update) {
         L.chain = valloc(h, nch * tot);
         const size_t es = hdg::vec_bytes(h->prec);
         const int64_t rhs_bytes = (int64_t)(n - 1) * P * (int64_t)es;
-        L.chain_lds_level = hdg::chain_lds_level(P, n, es, std::min<int64_t>(8192, 65536 - rhs_bytes));
+        L.chain_lds_level = hdg::chain_lds_level(P, n, es, std::min<int64_t>(8192, h->lds_cap - rhs_bytes));
       }
       const int64_t wpc = hdg::chain_factor_work_doubles(P, n);
       const int64_t batch = std::max<int64_t>(1, std::min<int64_t>(nch, ((int64_t)256 << 20) / 8 / wpc));
@@ -1141,7 +1145,8 @@ struct EventPair {
 };
 
 // Autotuner of the chain Schwarz launch shape of level p: workgroup size,
-// XCD-aware chain order and LDS staging depth.  Every candidate solves each chain
+// XCD-aware chain order, LDS staging depth and (P = 3 ... 5) the lean or wide
+// batch shape of the factor loads.  Every candidate solves each chain
 // with the same operations in the same order, so the choice changes the time
 // only, never the result.  Each candidate is timed (best of 3, after one warm-up
 // launch) on the level's scratch vectors; the fastest is kept.
@@ -1152,19 +1157,27 @@ void tune_chain(hdg_ctx* h, int p) {
   const size_t es = hdg::vec_bytes(pr);
   const int64_t rhs_bytes = (int64_t)(h->n - 1) * L.P * (int64_t)es;
   const int lds_default = L.chain_lds_level;
-  const int lds_staged = hdg::chain_lds_level(L.P, h->n, es, std::min<int64_t>(24576, 65536 - rhs_bytes));
+  const int lds_staged = hdg::chain_lds_level(L.P, h->n, es, std::min<int64_t>(24576, h->lds_cap - rhs_bytes));
+  const int lds_half = hdg::chain_lds_level(L.P, h->n, es, std::min<int64_t>(65536, h->lds_cap) - rhs_bytes);
   // as much as fits: at P = 1 the whole factor set of a chain (5 entries per
   // eliminated position) fits beside the right-hand side
-  const int lds_full = hdg::chain_lds_level(L.P, h->n, es, 65536 - rhs_bytes);
+  const int lds_full = hdg::chain_lds_level(L.P, h->n, es, h->lds_cap - rhs_bytes);
   EventPair ev;
   hipEvent_t e0 = ev.a, e1 = ev.b;
   float best = 1e30f;
-  int bt = 0, br = -1, bl = lds_default;
+  int bt = 0, br = -1, bl = lds_default, bw = L.chain_shape;
+  const bool log = std::getenv("HDG_TUNE_LOG") != nullptr;  // a diagnostic: every candidate's time
+  for (int wd : {1, 2, 3})
   for (int th : {64, 128, 256, 512, 1024}) {
-    if (th > hdg::chain_max_threads(L.P)) continue;
+    if (h->cfg.chain_shape != HDG_CHAIN_AUTO && wd != h->cfg.chain_shape) continue;  // the caller's schedule
+    if (hdg::chain_shape_kind(L.P, h->n, wd) != wd) continue;  // that shape does not exist at P
+    if (wd != 3 && th > hdg::chain_max_threads(L.P, wd == 2)) continue;
     for (int rm : {0, 1})
-      for (int ll : {lds_default, lds_staged, lds_full, 64}) {
+      for (int ll : {lds_default, lds_staged, lds_half, lds_full, 64}) {
+        if (wd == 3 && ll != lds_default) continue;  // the flat schedule stages no factors
         hdg::ChainArgs c{};
+        c.lds_cap = h->lds_cap;
+        c.shape = wd;
         c.factors = L.chain;
         c.cstride = L.cstride;
         c.omega = L.omega;
@@ -1189,17 +1202,23 @@ void tune_chain(hdg_ctx* h, int p) {
           hipchk(hipEventElapsedTime(&ms, e0, e1), "elapsed");
           t = std::min(t, ms);
         }
+        if (log)
+          std::fprintf(stderr, "chain tune p=%d shape=%s threads=%d remap=%d lds_level=%d lds=%zu B: %.2f us\n", p,
+                       wd == 3 ? "flat" : (wd == 2 ? "wide" : "lean"), th, rm, ll,
+                       wd == 3 ? (size_t)(h->n - 1) * L.P * es : hdg::chain_lds_bytes(L.P, h->n, es, ll), 1e3 * t);
         if (t < best) {
           best = t;
           bt = th;
           br = rm;
           bl = ll;
+          bw = wd;
         }
       }
   }
   L.chain_threads = bt;
   L.chain_remap = br;
   L.chain_lds_level = bl;
+  L.chain_shape = bw;
 }
 
 // ------------------------------------------ many right-hand sides (chain smoother)
@@ -1288,12 +1307,13 @@ MultiWork& multi_work(hdg_ctx* h, int R) {
   EventPair ev;
   hipEvent_t e0 = ev.a, e1 = ev.b;
   for (const PLevel& L : h->pl) {
-    const int rmax = hdg::chain_multi_chunk(L.P, h->n, R, vbytes);
+    const int rmax = hdg::chain_multi_chunk(L.P, h->n, R, vbytes, h->lds_cap);
     int best_rc = rmax;
     float best = 1e30f;
     hipchk(hdg::launch_zero(h->prec, W->pr[L.p], L.N * R, h->stream), "zero");
     for (int rc = 1; rc <= rmax; rc *= 2) {
       hdg::ChainMultiArgs c{};
+      c.lds_cap = h->lds_cap;
       c.factors = L.chain;
       c.cstride = L.cstride;
       c.omega = L.omega;
@@ -1350,6 +1370,7 @@ void smooth_m(hdg_ctx* h, MultiWork& W, int p, const void* b, void* x, int nu, b
   for (int s = 0; s < nu; ++s) {
     const bool z = zero && s == 0;
     hdg::ChainMultiArgs c{};
+    c.lds_cap = h->lds_cap;
     c.factors = L.chain;
     c.cstride = L.cstride;
     c.omega = L.omega;
@@ -1457,6 +1478,11 @@ void precondition_m(hdg_ctx* h, MultiWork& W) {
   hipchk(hdg::launch_to_f64(static_cast<const float*>(W.cvb), W.vz, NR, h->stream), "to f64");
 }
 
+// LDS bytes of one chain's right-hand side and its last block (chain smoother)
+int64_t chain_lds_need(int n, int k, int64_t vb) {
+  return ((int64_t)(n - 1) * (k + 1) + (int64_t)(k + 1) * (k + 1)) * vb;
+}
+
 void validate_config(const hdg_config_t* c) {
   if (!c) throw ArgError("cfg is NULL");
   if (c->n < 2) throw ArgError("n must be >= 2");
@@ -1479,6 +1505,8 @@ void validate_config(const hdg_config_t* c) {
   if (c->cycle != HDG_CYCLE_V && c->cycle != HDG_CYCLE_W && c->cycle != HDG_CYCLE_WH)
     throw ArgError("cycle must be HDG_CYCLE_V, HDG_CYCLE_W or HDG_CYCLE_WH");
   if (c->setup_on_host != 0 && c->setup_on_host != 1) throw ArgError("setup_on_host must be 0 or 1");
+  if (c->chain_shape < HDG_CHAIN_AUTO || c->chain_shape > HDG_CHAIN_FLAT)
+    throw ArgError("chain_shape must be HDG_CHAIN_AUTO, _LEAN, _WIDE or _FLAT");
   if (c->multi_kernel != HDG_MULTI_AUTO && c->multi_kernel != HDG_MULTI_VECTOR && c->multi_kernel != HDG_MULTI_MATRIX)
     throw ArgError("multi_kernel must be HDG_MULTI_AUTO, HDG_MULTI_VECTOR or HDG_MULTI_MATRIX");
   for (int p = 0; p <= HDG_MAX_DEGREE; ++p) {
@@ -1486,9 +1514,10 @@ void validate_config(const hdg_config_t* c) {
     if (p >= c->k && c->inner_steps[p] != 0) throw ArgError("inner_steps[p] must be 0 for p >= k");
   }
   const int64_t vb = c->precision == HDG_PREC_F64 ? 8 : 4;
-  if (c->smoother == HDG_SMOOTH_CHAIN && ((int64_t)(c->n - 1) * (c->k + 1) + (int64_t)(c->k + 1) * (c->k + 1)) * vb > 65536)
+  if (c->smoother == HDG_SMOOTH_CHAIN && chain_lds_need(c->n, c->k, vb) > hdg::kMaxLdsBytes)
     throw ArgError("chain smoother keeps one chain and one block in LDS: needs ((n-1)(k+1) + (k+1)^2) * "
-                   "(8 bytes FP64, 4 bytes otherwise) <= 65536; use the face smoother or a reduced precision");
+                   "(8 bytes FP64, 4 bytes otherwise) <= 163840 (160 KiB); use the face smoother or a reduced "
+                   "precision");
   if (c->smoother == HDG_SMOOTH_FACE && c->precision != HDG_PREC_F64)
     for (int p = 0; p <= c->k; ++p)
       if (!(c->omega[p] > 0)) throw ArgError("facet smoother in reduced precision needs omega[p] > 0 for every p");
@@ -1562,6 +1591,21 @@ hdg_status_t hdg_create(const hdg_config_t* cfg, const double* kappa_host, void*
     // arguments are valid: device set-up starts here (once per device: the address
     // of the allocation-free batch apply's descriptor table)
     hipchk(hdg::batch_scratch_address(&h->batch_scratch), "scratch address");
+    {  // LDS a workgroup may use (with the opt-in above the default per-block size)
+      int dev = 0, dflt = 0, optin = 0;
+      hipchk(hipGetDevice(&dev), "device");
+      hipchk(hipDeviceGetAttribute(&dflt, hipDeviceAttributeMaxSharedMemoryPerBlock, dev), "LDS size");
+      if (hipDeviceGetAttribute(&optin, hipDeviceAttributeSharedMemPerBlockOptin, dev) != hipSuccess) {
+        (void)hipGetLastError();
+        optin = 0;
+      }
+      h->lds_cap = std::min<int64_t>(hdg::kMaxLdsBytes, std::max(dflt, optin));
+      const int64_t vb = cfg->precision == HDG_PREC_F64 ? 8 : 4;
+      if (cfg->smoother == HDG_SMOOTH_CHAIN && chain_lds_need(cfg->n, cfg->k, vb) > h->lds_cap)
+        throw ArgError("chain smoother needs ((n-1)(k+1) + (k+1)^2) * (8 bytes FP64, 4 otherwise) = " +
+                       std::to_string(chain_lds_need(cfg->n, cfg->k, vb)) + " bytes of LDS; this device allows " +
+                       std::to_string(h->lds_cap));
+    }
     h->nf = hdg::n_faces(h->n);
     h->ntiles = (h->nf + 63) / 64;
     h->pl.resize(h->k + 1);
@@ -1600,6 +1644,7 @@ hdg_status_t hdg_create(const hdg_config_t* cfg, const double* kappa_host, void*
         L.pmat = h->prec == hdg::Prec::F64 ? static_cast<void*>(L.pmat64) : upload_vec(h.get(), Pp);
       }
       L.omega = cfg->omega[p] > 0 ? cfg->omega[p] : (cfg->smoother == HDG_SMOOTH_PATCH ? 1.0 : 0.8);
+      L.chain_shape = cfg->chain_shape;
       for (void** q : {&L.x, &L.b, &L.r, &L.t}) *q = valloc(h.get(), L.N);
       L.inner = cfg->inner_steps[p];
       if (L.inner > 0)

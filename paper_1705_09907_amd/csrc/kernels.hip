@@ -892,37 +892,62 @@ hipError_t launch_p_prolong_add(Prec pr, int P, const void* pm, const void* ec, 
 // takes the last P words.  Every phase then reads and writes its operands at
 // unit stride across a wavefront, where the position-major order had lanes
 // 2^(l+1) P words apart and serialised the LDS banks.
-// The reduction has 2 log2(n) dependent phases.  Work item = (position, block
-// of RB rows): a thread loads the item's factor rows once, reads the position's
-// neighbours from LDS once and updates RB rows, so the index arithmetic of an
-// item is shared by its P RB multiply-adds.  The factors of the small levels
-// l >= a.lds_level (a few KiB) are copied to LDS together with the right-hand
-// side, so only the first lds_level levels of each sweep wait on HBM; there a
-// thread issues the loads of a batch of KB positions before using any of them,
-// and loads the first batch of the next level before the barrier that ends the
-// current one.
-template <int P>
+// The reduction has 2 log2(n) dependent phases, one barrier each (a level of
+// the back substitution writes only its own odd positions, which no other
+// thread reads in that phase).  Work item = (position, block of RB rows): a
+// thread loads the item's factor rows once, reads the position's neighbours
+// from LDS once and updates RB rows, so the index arithmetic of an item is
+// shared by its P RB multiply-adds.  The factors of the small levels
+// l >= a.lds_level are copied to LDS together with the right-hand side, so only
+// the first lds_level levels of each sweep wait on HBM; there a thread issues
+// the loads of a batch of KB positions before using any of them, and loads the
+// next batch (or the next level's first) once the current one is used, before
+// the barrier.  Level 0's first batch is requested before the staging copies,
+// the backward sweep's first HBM batch before the top solve (few registers) or
+// at the end of the last staged level.  A second kernel, k_chain_flat, requests
+// every factor of a sweep at once where the registers allow it.
+// The multiply-adds of the chain solve, written out as fused operations in a
+// fixed order: every launch schedule then rounds alike, so their results are
+// bit-identical (left to itself the compiler may contract a*b + c*d either way).
+__device__ __forceinline__ double fma_t(double a, double b, double c) { return __builtin_fma(a, b, c); }
+__device__ __forceinline__ float fma_t(float a, float b, float c) { return __builtin_fmaf(a, b, c); }
+// forward: v - (z l + w r)
+template <typename T>
+__device__ __forceinline__ T chain_fwd_step(T v, T z, T l, T w, T r) {
+  return fma_t(-w, r, fma_t(-z, l, v));
+}
+// backward: s + d o - w l - z r
+template <typename T>
+__device__ __forceinline__ T chain_bwd_step(T s, T d, T o, T w, T l, T z, T r) {
+  return fma_t(-z, r, fma_t(-w, l, fma_t(d, o, s)));
+}
+
+template <int P, bool WIDE>
 struct ChainShape {
   // Rows per item (RBF forward, RBB backward) and positions whose loads are in
   // flight together (KBF, KBB): a batch holds KBF RBF 2P forward or KBB RBB 3P
-  // backward factor entries, at most 32 and 27 doubles.
-  static constexpr int RBF = P <= 4 ? P : (P <= 5 ? 3 : (P <= 8 ? 2 : 1));
-  static constexpr int RBB = P <= 3 ? P : (P <= 4 ? 2 : 1);
+  // backward factor entries.  The lean shape keeps a thread within 128
+  // registers (4 waves per SIMD, for meshes with many chains per CU); the wide
+  // shape (P = 3 ... 5) loads every row of a position in one batch, so a level
+  // whose positions fit the workgroup costs one load round trip, at up to 256
+  // registers (for meshes with few chains per CU).
+  static constexpr bool W = WIDE && P >= 3 && P <= 5;
+  static constexpr int RBF = W ? P : (P <= 4 ? P : (P <= 5 ? 3 : (P <= 8 ? 2 : 1)));
+  static constexpr int RBB = W ? P : (P <= 2 ? P : (P <= 4 ? 2 : 1));
   static constexpr int NRBF = (P + RBF - 1) / RBF;
   static constexpr int NRBB = (P + RBB - 1) / RBB;
-  static constexpr int KBF = P <= 1 ? 8 : (P <= 2 ? 4 : 1);
-  static constexpr int KBB = P <= 1 ? 8 : (P <= 2 ? 2 : 1);
-  // positions per thread in the back substitution, whose results wait in
-  // registers for the barrier: the launcher keeps floor((n-1)/2) <= threads MAXPOS
-  static constexpr int MAXPOS = P <= 1 ? 8 : (P <= 3 ? 4 : 2);
-  static constexpr int MAXT = P <= 4 ? 1024 : 512;  // workgroup size bound (registers)
+  static constexpr int KBF = P <= 1 ? 8 : (P <= 2 ? 2 : 1);
+  static constexpr int KBB = P <= 1 ? 4 : (P <= 2 ? 2 : 1);
+  // the first backward batch is requested before the top solve when its
+  // registers are few, else at the end of the last level staged in LDS
+  static constexpr bool EARLYB = 3 * KBB * RBB * P + 3 * P * P <= 40;
+  static constexpr int MAXT = W ? 512 : (P <= 4 ? 1024 : 512);  // workgroup size bound (registers)
 };
 
-template <int P, typename T>
-__global__ __launch_bounds__(ChainShape<P>::MAXT) void k_chain(ChainArgs a) {
+template <int P, typename T, bool WIDE>
+__global__ __launch_bounds__((ChainShape<P, WIDE>::MAXT)) void k_chain(ChainArgs a) {
   constexpr int P2 = P * P;
-  using CS = ChainShape<P>;
-  constexpr int MAXPOS = CS::MAXPOS;
+  using CS = ChainShape<P, WIDE>;
   extern __shared__ unsigned char lds_raw[];
   T* R = reinterpret_cast<T*>(lds_raw);
   const T* rin = static_cast<const T*>(a.r);
@@ -967,9 +992,126 @@ __global__ __launch_bounds__(ChainShape<P>::MAXT) void k_chain(ChainArgs a) {
   const int Ls = a.lds_level < Lf ? a.lds_level : Lf;  // the last level is always staged
   const int64_t tail_off = level_offset(Ls);
   T* TL = R + m * P;  // LDS copy of the factors of levels >= Ls
+  // Factors of level l come from HBM (l < Ls: loaded in register batches, the
+  // first batch of a level before the barrier that ends the previous one) or
+  // from LDS (l >= Ls: read where they are used).  The two never share a
+  // pointer, so the compiler emits global or LDS loads rather than flat ones.
+  // ---- forward reduction.  Rows r of M-_j and M+_j (j = 2 tt): column r of Z
+  // at odd index tt - 1 and of W at odd index tt.
+  constexpr int KB = CS::KBF, RB = CS::RBF, NRB = CS::NRBF;
+  T zm[KB][RB][P], wp[KB][RB][P];
+  // Loads are unconditional, at indices clamped into the level's arrays (whose
+  // entries are all finite), and the operand they multiply is masked where the
+  // product is used: a load under a branch makes the compiler wait for it before
+  // the branch joins, and so does a select on the loaded value placed next to
+  // the load, which would turn every prefetch into a synchronous load.
+  constexpr int S = (int)sizeof(T);
+  // HBM factors by buffer loads: one register offset per lane, a wave-uniform
+  // byte offset per entry
+  const __amdgpu_buffer_rsrc_t fr = buffer_rsrc(F, (int)(a.cstride * S));
+  // an empty range: loads through it return 0 and touch no memory, so a
+  // pipelined load with nothing left to fetch needs no branch around it
+  const __amdgpu_buffer_rsrc_t fr0 = buffer_rsrc(F, 0);
+  auto load_fwd = [&](__amdgpu_buffer_rsrc_t rs, int64_t off_l, int ml_, int rb, int c0) __attribute__((always_inline)) {
+    const int ne_ = (ml_ + 1) >> 1, no_ = ml_ >> 1;  // no_ >= 1
+    const int o8 = (int)off_l * S;
+#pragma unroll
+    for (int kk = 0; kk < KB; ++kk) {
+      const int tt = c0 + kk * nt;
+      const unsigned zi = (unsigned)min(max(tt - 1, 0), no_ - 1), wi = (unsigned)min(tt, no_ - 1);
+#pragma unroll
+      for (int rr = 0; rr < RB; ++rr) {
+        const int r = rb * RB + rr;
+#pragma unroll
+        for (int q = 0; q < P; ++q) {
+          if (r < P) {  // resolved at compile time; the missing neighbours' values are masked in fwd_compute
+            zm[kk][rr][q] = buffer_load<T>(rs, (int)zi * S, o8 + (2 * P2 + q * P + r) * no_ * S);
+            wp[kk][rr][q] = buffer_load<T>(rs, (int)wi * S, o8 + (P2 + q * P + r) * no_ * S);
+          } else {
+            zm[kk][rr][q] = wp[kk][rr][q] = T(0);
+          }
+        }
+      }
+    }
+  };
+  auto fwd_compute = [&](int ml_, int lev_, int rb, int c0) __attribute__((always_inline)) {
+    const int ne_ = (ml_ + 1) >> 1, no_ = ml_ >> 1;
+    const int ob = P * (m - ml_);  // level lev_'s odd positions: [row][o]
+#pragma unroll
+    for (int kk = 0; kk < KB; ++kk) {
+      const int tt = c0 + kk * nt;
+      if (tt < ne_) {
+        T lv[P], rv[P];
+        const int li = max(tt - 1, 0), ri = min(tt, no_ - 1);
+#pragma unroll
+        for (int q = 0; q < P; ++q) {
+          const T x = R[ob + q * no_ + li], y = R[ob + q * no_ + ri];
+          lv[q] = tt >= 1 ? x : T(0);
+          rv[q] = tt < no_ ? y : T(0);
+        }
+        int rs;
+        const int w = slot(lev_ + 1, tt, rs);
+#pragma unroll
+        for (int rr = 0; rr < RB; ++rr) {
+          const int r = rb * RB + rr;
+          if (r < P) {
+            T v = R[w + r * rs];
+#pragma unroll
+            for (int q = 0; q < P; ++q) v = chain_fwd_step(v, zm[kk][rr][q], lv[q], wp[kk][rr][q], rv[q]);
+            R[w + r * rs] = v;
+          }
+        }
+      }
+    }
+  };
+  int ml = m, lev = 0;
+  int64_t off = 0;
+  // forward level with factors in LDS: one position (all rows) per item
+  auto fwd_level_lds = [&](const T* O) __attribute__((always_inline)) {
+    const int ne_ = (ml + 1) >> 1, no_ = ml >> 1;
+    const int ob = P * (m - ml);
+    for (int tt = t; tt < ne_; tt += nt) {
+      T lv[P], rv[P];
+      const int li = max(tt - 1, 0), ri = min(tt, no_ - 1);
+#pragma unroll
+      for (int q = 0; q < P; ++q) {
+        const T x = R[ob + q * no_ + li], y = R[ob + q * no_ + ri];
+        lv[q] = tt >= 1 ? x : T(0);  // a missing neighbour contributes 0 times a finite factor
+        rv[q] = tt < no_ ? y : T(0);
+      }
+      int rs;
+      const int w = slot(lev + 1, tt, rs);
+#pragma unroll
+      for (int r = 0; r < P; ++r) {
+        T v = R[w + r * rs];
+#pragma unroll
+        for (int q = 0; q < P; ++q)
+          v = chain_fwd_step(v, O[(2 * P2 + q * P + r) * no_ + li], lv[q], O[(P2 + q * P + r) * no_ + ri], rv[q]);
+        R[w + r * rs] = v;
+      }
+    }
+  };
+  // The first batch of level 0's factors and this thread's first values of x
+  // (read again only by the final update) are requested before the staging
+  // copies, so their latency overlaps the staging's.
+  if (ml > 1 && Ls > 0) load_fwd(fr, 0, ml, 0, t);
+  constexpr int CBP = P >= 8 ? 1 : 8 / P;
+  constexpr bool XPRE = P <= 1;  // registers held across the whole kernel
+  T xpre[CBP][P];
+#pragma unroll
+  for (int u = 0; u < CBP; ++u)
+#pragma unroll
+    for (int r = 0; r < P; ++r) xpre[u][r] = T(0);
+  if (XPRE && xin) {
+#pragma unroll
+    for (int u = 0; u < CBP; ++u) {
+      const int i = t + u * nt;
+#pragma unroll
+      for (int r = 0; r < P; ++r) xpre[u][r] = xin[(base + stride * min(i, m - 1)) * P + r];  // used for i < m only
+    }
+  }
   // copies to LDS keep about 8 loads per thread in flight (a load-store loop
   // would wait for every load before the next one is issued)
-  constexpr int CBP = P >= 8 ? 1 : 8 / P;
   for (int i0 = t; i0 < m; i0 += nt * CBP) {
     T v[CBP][P];
 #pragma unroll
@@ -1004,119 +1146,34 @@ __global__ __launch_bounds__(ChainShape<P>::MAXT) void k_chain(ChainArgs a) {
       if (b0 + u * nt < tail_len) TL[b0 + u * nt] = v[u];
   }
   lds_barrier();
-  // Factors of level l come from HBM (l < Ls: loaded in register batches, the
-  // first batch of a level before the barrier that ends the previous one) or
-  // from LDS (l >= Ls: read where they are used).  The two never share a
-  // pointer, so the compiler emits global or LDS loads rather than flat ones.
-  // ---- forward reduction.  Rows r of M-_j and M+_j (j = 2 tt): column r of Z
-  // at odd index tt - 1 and of W at odd index tt.
-  constexpr int KB = CS::KBF, RB = CS::RBF, NRB = CS::NRBF;
-  T zm[KB][RB][P], wp[KB][RB][P];
-  // Loads are unconditional, at indices clamped into the level's arrays (whose
-  // entries are all finite), and masked afterwards: a load under a branch makes
-  // the compiler wait for it before the branch joins.
-  constexpr int S = (int)sizeof(T);
-  // HBM factors by buffer loads: one register offset per lane, a wave-uniform
-  // byte offset per entry
-  const __amdgpu_buffer_rsrc_t fr = buffer_rsrc(F, (int)(a.cstride * S));
-  auto load_fwd = [&](int64_t off_l, int ml_, int rb, int c0) __attribute__((always_inline)) {
-    const int ne_ = (ml_ + 1) >> 1, no_ = ml_ >> 1;  // no_ >= 1
-    const int o8 = (int)off_l * S;
-#pragma unroll
-    for (int kk = 0; kk < KB; ++kk) {
-      const int tt = c0 + kk * nt;
-      const unsigned zi = (unsigned)min(max(tt - 1, 0), no_ - 1), wi = (unsigned)min(tt, no_ - 1);
-      const bool zok = tt >= 1 && tt < ne_, wok = tt < no_;
-#pragma unroll
-      for (int rr = 0; rr < RB; ++rr) {
-        const int r = rb * RB + rr;
-#pragma unroll
-        for (int q = 0; q < P; ++q) {
-          if (r < P) {  // resolved at compile time
-            const T z = buffer_load<T>(fr, (int)zi * S, o8 + (2 * P2 + q * P + r) * no_ * S);
-            const T w = buffer_load<T>(fr, (int)wi * S, o8 + (P2 + q * P + r) * no_ * S);
-            zm[kk][rr][q] = zok ? z : T(0);
-            wp[kk][rr][q] = wok ? w : T(0);
-          } else {
-            zm[kk][rr][q] = wp[kk][rr][q] = T(0);
-          }
-        }
-      }
-    }
-  };
-  auto fwd_compute = [&](int ml_, int lev_, int rb, int c0) __attribute__((always_inline)) {
-    const int ne_ = (ml_ + 1) >> 1, no_ = ml_ >> 1;
-    const int ob = P * (m - ml_);  // level lev_'s odd positions: [row][o]
-#pragma unroll
-    for (int kk = 0; kk < KB; ++kk) {
-      const int tt = c0 + kk * nt;
-      if (tt < ne_) {
-        T lv[P], rv[P];
-        const int li = max(tt - 1, 0), ri = min(tt, no_ - 1);
-#pragma unroll
-        for (int q = 0; q < P; ++q) {
-          const T x = R[ob + q * no_ + li], y = R[ob + q * no_ + ri];
-          lv[q] = tt >= 1 ? x : T(0);
-          rv[q] = tt < no_ ? y : T(0);
-        }
-        int rs;
-        const int w = slot(lev_ + 1, tt, rs);
-#pragma unroll
-        for (int rr = 0; rr < RB; ++rr) {
-          const int r = rb * RB + rr;
-          if (r < P) {
-            T v = R[w + r * rs];
-#pragma unroll
-            for (int q = 0; q < P; ++q) v -= zm[kk][rr][q] * lv[q] + wp[kk][rr][q] * rv[q];
-            R[w + r * rs] = v;
-          }
-        }
-      }
-    }
-  };
-  int ml = m, lev = 0;
-  int64_t off = 0;
-  // forward level with factors in LDS: one position (all rows) per item
-  auto fwd_level_lds = [&](const T* O) __attribute__((always_inline)) {
-    const int ne_ = (ml + 1) >> 1, no_ = ml >> 1;
-    const int ob = P * (m - ml);
-    for (int tt = t; tt < ne_; tt += nt) {
-      T lv[P], rv[P];
-      const int li = max(tt - 1, 0), ri = min(tt, no_ - 1);
-#pragma unroll
-      for (int q = 0; q < P; ++q) {
-        const T x = R[ob + q * no_ + li], y = R[ob + q * no_ + ri];
-        lv[q] = tt >= 1 ? x : T(0);  // a missing neighbour contributes 0 times a finite factor
-        rv[q] = tt < no_ ? y : T(0);
-      }
-      int rs;
-      const int w = slot(lev + 1, tt, rs);
-#pragma unroll
-      for (int r = 0; r < P; ++r) {
-        T v = R[w + r * rs];
-#pragma unroll
-        for (int q = 0; q < P; ++q)
-          v -= O[(2 * P2 + q * P + r) * no_ + li] * lv[q] + O[(P2 + q * P + r) * no_ + ri] * rv[q];
-        R[w + r * rs] = v;
-      }
-    }
-  };
   // levels in HBM, then levels in LDS
-  if (ml > 1 && Ls > 0) load_fwd(0, ml, 0, t);
+  // Software pipeline: a batch's registers hold its factors on entry; once used
+  // they receive the next batch of the level, or after the level the first
+  // batch of the next one.  The batch loop runs the same number of times in
+  // every lane (items past the level are masked), so the loads sit under
+  // uniform branches only, and the scheduling barriers keep them after the
+  // use: the registers are reused rather than doubled.
   while (ml > 1 && lev < Ls) {
     const int ne = (ml + 1) >> 1;
-    bool first = true;
+    const int64_t off_next = off + (int64_t)3 * P2 * (ml >> 1);
+    for (int cb = 0; cb < ne; cb += nt * KB) {
+      const int c0 = cb + t;
 #pragma unroll
-    for (int rb = 0; rb < NRB; ++rb)
-      for (int c0 = t; c0 < ne; c0 += nt * KB) {
-        if (!first) load_fwd(off, ml, rb, c0);
-        first = false;
+      for (int rb = 0; rb < NRB; ++rb) {
+        if (rb > 0) {
+          __builtin_amdgcn_sched_barrier(0);
+          load_fwd(fr, off, ml, rb, c0);
+        }
         fwd_compute(ml, lev, rb, c0);
       }
-    off += (int64_t)3 * P2 * (ml >> 1);
+      // the next batch of this level, else the first of the next level in HBM
+      const bool more = cb + nt * KB < ne, next = ne > 1 && lev + 1 < Ls;
+      __builtin_amdgcn_sched_barrier(0);
+      load_fwd(more || next ? fr : fr0, more ? off : off_next, more ? ml : max(ne, 2), 0, more ? c0 + nt * KB : t);
+    }
+    off = off_next;
     ml = ne;
     ++lev;
-    if (ml > 1 && lev < Ls) load_fwd(off, ml, 0, t);
     lds_barrier();
   }
   while (ml > 1) {
@@ -1126,46 +1183,29 @@ __global__ __launch_bounds__(ChainShape<P>::MAXT) void k_chain(ChainArgs a) {
     ++lev;
     lds_barrier();
   }
-  T xr = T(0);
-  const int top = P * (m - 1);
-  if (t < P) {
-    if (lev >= Ls) {
-      const T* D = TL + (off - tail_off);
-#pragma unroll
-      for (int q = 0; q < P; ++q) xr += D[t * P + q] * R[top + q];
-    } else {
-      const T* D = F + off;
-#pragma unroll
-      for (int q = 0; q < P; ++q) xr += D[t * P + q] * R[top + q];
-    }
-  }
-  lds_barrier();
-  if (t < P) R[top + t] = xr;
-  lds_barrier();
-  // ---- back substitution: values of all items first, then a barrier, then writes
+  // ---- back substitution.  Level l writes the solution of its odd positions,
+  // which no other thread reads in that phase (their neighbours are even
+  // positions, solved at deeper levels), so a thread computes all rows of its
+  // positions, writes them, and one barrier ends the level.
   constexpr int KBB = CS::KBB, RBB = CS::RBB, NRBB = CS::NRBB;
   T od[KBB][RBB][P], ow[KBB][RBB][P], oz[KBB][RBB][P];
-  auto load_bwd_from = [&](int64_t lo, int mlv, int rb, int c0) __attribute__((always_inline)) {
+  auto load_bwd_from = [&](__amdgpu_buffer_rsrc_t rs, int64_t lo, int mlv, int rb, int c0) __attribute__((always_inline)) {
+    (void)mlv;
     const int no_ = mlv >> 1;
     const int o8 = (int)lo * S;
 #pragma unroll
     for (int kk = 0; kk < KBB; ++kk) {
       const int tt = c0 + kk * nt;
-      const bool ok = tt < no_;
-      const bool right = 2 * tt + 2 < mlv;
       const unsigned ti = (unsigned)min(tt, no_ - 1);
 #pragma unroll
       for (int rr = 0; rr < RBB; ++rr) {
         const int r = rb * RBB + rr;
 #pragma unroll
         for (int q = 0; q < P; ++q) {
-          if (r < P) {  // resolved at compile time
-            const T d = buffer_load<T>(fr, (int)ti * S, o8 + (r * P + q) * no_ * S);
-            const T w = buffer_load<T>(fr, (int)ti * S, o8 + (P2 + r * P + q) * no_ * S);
-            const T z = buffer_load<T>(fr, (int)ti * S, o8 + (2 * P2 + r * P + q) * no_ * S);
-            od[kk][rr][q] = ok ? d : T(0);
-            ow[kk][rr][q] = ok ? w : T(0);
-            oz[kk][rr][q] = (ok && right) ? z : T(0);
+          if (r < P) {  // resolved at compile time; a missing right neighbour's value is masked at use
+            od[kk][rr][q] = buffer_load<T>(rs, (int)ti * S, o8 + (r * P + q) * no_ * S);
+            ow[kk][rr][q] = buffer_load<T>(rs, (int)ti * S, o8 + (P2 + r * P + q) * no_ * S);
+            oz[kk][rr][q] = buffer_load<T>(rs, (int)ti * S, o8 + (2 * P2 + r * P + q) * no_ * S);
           } else {
             od[kk][rr][q] = ow[kk][rr][q] = oz[kk][rr][q] = T(0);
           }
@@ -1173,18 +1213,29 @@ __global__ __launch_bounds__(ChainShape<P>::MAXT) void k_chain(ChainArgs a) {
       }
     }
   };
-  auto load_bwd = [&](int l, int rb, int c0) __attribute__((always_inline)) {
-    load_bwd_from(level_offset(l), (m + (1 << l) - 1) >> l, rb, c0);
+  auto load_bwd = [&](__amdgpu_buffer_rsrc_t rs, int l, int rb, int c0) __attribute__((always_inline)) {
+    load_bwd_from(rs, level_offset(l), (m + (1 << l) - 1) >> l, rb, c0);
   };
-  // back substitution of a level with factors in LDS: one position per item,
-  // results written after the barrier
-  auto bwd_level_lds = [&](const T* O, int no, int ob0) __attribute__((always_inline)) {
-    T res[MAXPOS][P];
+  // The first batch of the first level whose factors are in HBM is requested
+  // now (the top solve and the levels staged in LDS do not use these registers,
+  // and hide the load's latency), or before the barrier of the last staged level.
+  const bool staged_bwd = Lf - 1 >= Ls;
+  if (CS::EARLYB && Ls > 0) load_bwd(fr, Ls - 1, 0, t);
+  T xr = T(0);
+  const int top = P * (m - 1);
+  if (t < P) {  // the last level is always staged (Ls <= Lf = lev)
+    const T* D = TL + (off - tail_off);
 #pragma unroll
-    for (int pi = 0; pi < MAXPOS; ++pi) {
-      const int tt = t + pi * nt;
-      if (tt < no) {
-        T own[P], xl[P], xrt[P];
+    for (int q = 0; q < P; ++q) xr = fma_t(D[t * P + q], R[top + q], xr);
+  }
+  lds_barrier();
+  if (t < P) R[top + t] = xr;
+  lds_barrier();
+  // back substitution of a level with factors in LDS: one position per item
+  auto bwd_level_lds = [&](const T* O, int no, int ob0, bool pre) __attribute__((always_inline)) {
+    for (int tt = t; tt < no; tt += nt) {
+      {
+        T own[P], xl[P], xrt[P], res[P];
         int rl, rr2;
         const int wl = slot(lev + 1, tt, rl);
         const bool right = 2 * tt + 2 < ml;
@@ -1201,82 +1252,354 @@ __global__ __launch_bounds__(ChainShape<P>::MAXT) void k_chain(ChainArgs a) {
           T s = T(0);
 #pragma unroll
           for (int q = 0; q < P; ++q)
-            s += O[(r * P + q) * no + tt] * own[q] - O[(P2 + r * P + q) * no + tt] * xl[q] -
-                 O[(2 * P2 + r * P + q) * no + tt] * xrt[q];
-          res[pi][r] = s;
+            s = chain_bwd_step(s, O[(r * P + q) * no + tt], own[q], O[(P2 + r * P + q) * no + tt], xl[q],
+                               O[(2 * P2 + r * P + q) * no + tt], xrt[q]);
+          res[r] = s;
         }
+#pragma unroll
+        for (int r = 0; r < P; ++r) R[ob0 + tt + r * no] = res[r];
       }
     }
-    lds_barrier();
-#pragma unroll
-    for (int pi = 0; pi < MAXPOS; ++pi) {
-      const int tt = t + pi * nt;
-      if (tt < no) {
-#pragma unroll
-        for (int r = 0; r < P; ++r) R[ob0 + tt + r * no] = res[pi][r];
-      }
+    if (pre) {
+      __builtin_amdgcn_sched_barrier(0);
+      load_bwd(fr, Ls - 1, 0, t);
     }
     lds_barrier();
   };
-  // levels in LDS, then levels in HBM
-  while (lev > 0 && lev - 1 >= Ls) {
+  // levels in LDS, then levels in HBM.  The last staged level is peeled off,
+  // so the prefetch it issues keeps its registers out of the other staged levels.
+  while (lev > 0 && lev - 1 > Ls) {
     --lev;
     ml = (m + (1 << lev) - 1) >> lev;
-    bwd_level_lds(TL + (level_offset(lev) - tail_off), ml >> 1, P * (m - ml));
+    bwd_level_lds(TL + (level_offset(lev) - tail_off), ml >> 1, P * (m - ml), false);
   }
-  if (lev > 0) load_bwd(lev - 1, 0, t);
+  if (lev > 0 && lev - 1 == Ls) {
+    --lev;
+    ml = (m + (1 << lev) - 1) >> lev;
+    bwd_level_lds(TL + (level_offset(lev) - tail_off), ml >> 1, P * (m - ml), !CS::EARLYB && Ls > 0);
+  }
+  if (!CS::EARLYB && Ls > 0 && !staged_bwd) load_bwd(fr, Ls - 1, 0, t);  // no staged level to hide it
   while (lev > 0) {
     --lev;
     ml = (m + (1 << lev) - 1) >> lev;
     const int no = ml >> 1;
     const int ob0 = P * (m - ml);
-    T res[MAXPOS][P];
-    bool first = true;
+    for (int cb = 0; cb < no; cb += nt * KBB) {
+      const int c0 = cb + t;
+      // a position's right-hand side and neighbours are read once, before any
+      // of its rows is written
+      T own[KBB][P], xl[KBB][P], xrt[KBB][P];
 #pragma unroll
-    for (int rb = 0; rb < NRBB; ++rb)
+      for (int kk = 0; kk < KBB; ++kk) {
+        const int tt = min(c0 + kk * nt, no - 1);
+        int rl, rr2;
+        const int wl = slot(lev + 1, tt, rl);
+        const bool right = 2 * tt + 2 < ml;
+        const int wr = right ? slot(lev + 1, tt + 1, rr2) : (rr2 = rl, wl);
 #pragma unroll
-      for (int pb = 0; pb < MAXPOS; pb += KBB) {
-        const int c0 = t + pb * nt;
-        if (c0 < no) {
-          if (!first) load_bwd(lev, rb, c0);
-          first = false;
+        for (int q = 0; q < P; ++q) {
+          own[kk][q] = R[ob0 + tt + q * no];
+          xl[kk][q] = R[wl + q * rl];
+          const T x = R[wr + q * rr2];
+          xrt[kk][q] = right ? x : T(0);  // Z is finite, so a missing neighbour contributes 0
+        }
+      }
 #pragma unroll
-          for (int kk = 0; kk < KBB; ++kk) {
-            const int tt = c0 + kk * nt;
-            if (pb + kk < MAXPOS && tt < no) {
-              T own[P], xl[P], xrt[P];
-              int rl, rr2;
-              const int wl = slot(lev + 1, tt, rl);
-              const bool right = 2 * tt + 2 < ml;
-              const int wr = right ? slot(lev + 1, tt + 1, rr2) : (rr2 = rl, wl);
+      for (int rb = 0; rb < NRBB; ++rb) {
+        if (rb > 0) {
+          __builtin_amdgcn_sched_barrier(0);
+          load_bwd(fr, lev, rb, c0);
+        }
 #pragma unroll
-              for (int q = 0; q < P; ++q) {
-                own[q] = R[ob0 + tt + q * no];
-                xl[q] = R[wl + q * rl];
-                xrt[q] = R[wr + q * rr2];  // oz = 0 when there is no right neighbour
-              }
+        for (int kk = 0; kk < KBB; ++kk) {
+          const int tt = c0 + kk * nt;
+          if (tt < no) {
 #pragma unroll
-              for (int rr = 0; rr < RBB; ++rr) {
-                const int r = rb * RBB + rr;
-                if (r < P) {
-                  T s = T(0);
+            for (int rr = 0; rr < RBB; ++rr) {
+              const int r = rb * RBB + rr;
+              if (r < P) {
+                T s = T(0);
 #pragma unroll
-                  for (int q = 0; q < P; ++q) s += od[kk][rr][q] * own[q] - ow[kk][rr][q] * xl[q] - oz[kk][rr][q] * xrt[q];
-                  res[pb + kk][r] = s;
-                }
+                for (int q = 0; q < P; ++q)
+                  s = chain_bwd_step(s, od[kk][rr][q], own[kk][q], ow[kk][rr][q], xl[kk][q], oz[kk][rr][q], xrt[kk][q]);
+                R[ob0 + tt + r * no] = s;
               }
             }
           }
         }
       }
-    if (lev > 0) load_bwd(lev - 1, 0, t);
+      // as in the forward sweep: the next batch of this level, else the first of the next
+      const bool more = cb + nt * KBB < no;
+      __builtin_amdgcn_sched_barrier(0);
+      load_bwd(more || lev > 0 ? fr : fr0, more ? lev : max(lev - 1, 0), 0, more ? c0 + nt * KBB : t);
+    }
     lds_barrier();
+  }
+  for (int i0 = t; i0 < m; i0 += nt * CBP) {
+    T v[CBP][P];
 #pragma unroll
-    for (int pi = 0; pi < MAXPOS; ++pi) {
-      const int tt = t + pi * nt;
-      if (tt < no) {
+    for (int u = 0; u < CBP; ++u) {
+      const int i = i0 + u * nt;
+      if (i < m) {
 #pragma unroll
-        for (int r = 0; r < P; ++r) R[ob0 + tt + r * no] = res[pi][r];
+        for (int r = 0; r < P; ++r) v[u][r] = XPRE && i0 == t ? xpre[u][r] : (xin ? xin[(base + stride * i) * P + r] : T(0));
+      }
+    }
+#pragma unroll
+    for (int u = 0; u < CBP; ++u) {
+      const int i = i0 + u * nt;
+      if (i < m) {
+        int rs;
+        const int w = slot(0, i, rs);
+        T* dst = out + (base + stride * i) * P;
+#pragma unroll
+        for (int r = 0; r < P; ++r) dst[r] = v[u][r] + T(a.omega) * R[w + r * rs];
+      }
+    }
+  }
+}
+
+// Chain solve with every factor load of a sweep requested at once (the flat
+// schedule), for chains whose factors fit the workgroup's registers.  The items
+// of all levels of a sweep are numbered consecutively (forward: the ne_l even
+// positions of level l, level 0 first; backward: the no_l odd positions, the
+// deepest level first, so the first slots' loads are the first ones waited
+// for), and item g is held by thread g mod nt in slot g / nt (K slots).  Before
+// a sweep a thread requests the factors of all its slots, so each sweep waits
+// on memory about once instead of once per level; the levels then run from
+// registers and the LDS copy of the right-hand side, one barrier each.  Each
+// item computes exactly the expressions of k_chain, so the results are the
+// same.  Registers: 2 K P^2 factor entries in the forward sweep, 3 K P^2 in the
+// backward one.
+template <int P, int K>
+struct ChainFlat {
+  static constexpr int MAXT = 3 * K * P * P <= 24 ? 1024 : 512;  // also chain_flat_maxt
+};
+
+template <int P, typename T, int K>
+__global__ __launch_bounds__((ChainFlat<P, K>::MAXT)) void k_chain_flat(ChainArgs a) {
+  constexpr int P2 = P * P;
+  constexpr int S = (int)sizeof(T);
+  extern __shared__ unsigned char lds_raw[];
+  T* R = reinterpret_cast<T*>(lds_raw);
+  const T* rin = static_cast<const T*>(a.r);
+  const T* xin = static_cast<const T*>(a.x);
+  T* out = static_cast<T*>(a.out);
+  const int64_t nch = 2LL * a.n;  // chain order as in k_chain
+  const int64_t c = (a.remap && nch % 8 == 0) ? (int64_t)(blockIdx.x & 7) * (nch >> 3) + (blockIdx.x >> 3)
+                                                : (int64_t)blockIdx.x;
+  const int m = a.n - 1;
+  const int64_t nv = (int64_t)a.n * (a.n - 1);
+  const bool vert = c < a.n;
+  const int64_t base = vert ? c * (a.n - 1) : nv + (c - a.n);
+  const int64_t stride = vert ? 1 : a.n;
+  const T* F = static_cast<const T*>(a.factors) + c * a.cstride;
+  const __amdgpu_buffer_rsrc_t fr = buffer_rsrc(F, (int)(a.cstride * S));
+  const int t = threadIdx.x;
+  const int nt = blockDim.x;
+  auto slot = [m](int l, int pos, int& rs) -> int {  // as in k_chain
+    if (pos == 0) {
+      rs = 1;
+      return P * (m - 1);
+    }
+    const int z = __builtin_ctz((unsigned)pos);
+    const int lv = l + z;
+    const int mlv = (m + (1 << lv) - 1) >> lv;
+    rs = mlv >> 1;
+    return P * (m - mlv) + (pos >> (z + 1));
+  };
+  auto level_size = [m](int l) { return (m + (1 << l) - 1) >> l; };
+  int Lf = 0;
+  for (int q = m; q > 1; q = (q + 1) >> 1) ++Lf;
+  // The first chunk of the right-hand side is requested first, then the
+  // factors (and, when registers allow, the backward sweep's factors and x),
+  // so the chunk can be stored to LDS while the rest is in flight.
+  constexpr int CBP = P >= 8 ? 1 : 8 / P;
+  T v0[CBP][P];
+#pragma unroll
+  for (int u = 0; u < CBP; ++u) {
+    const T* src = rin + (base + stride * min(t + u * nt, m - 1)) * P;
+#pragma unroll
+    for (int r = 0; r < P; ++r) v0[u][r] = src[r];
+  }
+  // ---- forward items: level and even index of each slot, and their factors
+  int fl[K], ft[K];
+  T zm[K][P][P], wp[K][P][P];
+  {
+    int ntot = 0;  // sum over levels of ne_l = m (m >= 1)
+    for (int l = 0; l < Lf; ++l) ntot += (level_size(l) + 1) >> 1;
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+      const int g0 = t + k * nt;
+      const int g = min(g0, max(ntot - 1, 0));  // past the last item: a copy of it, masked below
+      int l = 0, acc = 0;
+      int64_t lo = 0;
+      while (l < Lf - 1 && g >= acc + ((level_size(l) + 1) >> 1)) {
+        acc += (level_size(l) + 1) >> 1;
+        lo += (int64_t)3 * P2 * (level_size(l) >> 1);
+        ++l;
+      }
+      fl[k] = (g0 < ntot && Lf > 0) ? l : -1;
+      ft[k] = g - acc;
+      const int no_ = max(level_size(l) >> 1, 1);
+      const int zi = min(max(ft[k] - 1, 0), no_ - 1), wi = min(ft[k], no_ - 1);
+      const int zb = (int)lo + zi, wb = (int)lo + wi;
+#pragma unroll
+      for (int r = 0; r < P; ++r)
+#pragma unroll
+        for (int q = 0; q < P; ++q) {
+          zm[k][r][q] = buffer_load<T>(fr, (zb + (2 * P2 + q * P + r) * no_) * S, 0);
+          wp[k][r][q] = buffer_load<T>(fr, (wb + (P2 + q * P + r) * no_) * S, 0);
+        }
+    }
+  }
+  // the last level's single block, for the threads that solve it
+  T dtop[P];
+  {
+    int64_t lo = 0;
+    for (int l = 0; l < Lf; ++l) lo += (int64_t)3 * P2 * (level_size(l) >> 1);
+    const int tr = min(t, P - 1);
+#pragma unroll
+    for (int q = 0; q < P; ++q) dtop[q] = buffer_load<T>(fr, ((int)lo + tr * P + q) * S, 0);
+  }
+  // ---- backward items (deepest level first) and their factors
+  int bl[K], bt[K];
+  T od[K][P][P], ow[K][P][P], oz[K][P][P];
+  auto load_bwd_all = [&]() __attribute__((always_inline)) {
+    int ntot = 0;
+    for (int l = 0; l < Lf; ++l) ntot += level_size(l) >> 1;
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+      const int g0 = t + k * nt;
+      const int g = min(g0, max(ntot - 1, 0));
+      int l = Lf - 1, acc = 0;
+      while (l > 0 && g >= acc + (level_size(l) >> 1)) {
+        acc += level_size(l) >> 1;
+        --l;
+      }
+      int64_t lo = 0;
+      for (int q = 0; q < l; ++q) lo += (int64_t)3 * P2 * (level_size(q) >> 1);
+      bl[k] = (g0 < ntot && Lf > 0) ? l : -1;
+      bt[k] = g - acc;
+      const int no_ = max(level_size(l) >> 1, 1);
+      const int tb = (int)lo + min(bt[k], no_ - 1);
+#pragma unroll
+      for (int r = 0; r < P; ++r)
+#pragma unroll
+        for (int q = 0; q < P; ++q) {
+          od[k][r][q] = buffer_load<T>(fr, (tb + (r * P + q) * no_) * S, 0);
+          ow[k][r][q] = buffer_load<T>(fr, (tb + (P2 + r * P + q) * no_) * S, 0);
+          oz[k][r][q] = buffer_load<T>(fr, (tb + (2 * P2 + r * P + q) * no_) * S, 0);
+        }
+    }
+  };
+  // with few factor entries per thread the backward sweep's are requested at
+  // once too: the forward levels then run while they arrive
+  constexpr bool EARLY = 5 * K * P * P <= 20;
+  if constexpr (EARLY) load_bwd_all();
+  // ---- the right-hand side into LDS, in k_chain's level order
+#pragma unroll
+  for (int u = 0; u < CBP; ++u) {
+    const int i = t + u * nt;
+    if (i < m) {
+      int rs;
+      const int w = slot(0, i, rs);
+#pragma unroll
+      for (int r = 0; r < P; ++r) R[w + r * rs] = v0[u][r];
+    }
+  }
+  for (int i0 = t + nt * CBP; i0 < m; i0 += nt * CBP) {
+    T v[CBP][P];
+#pragma unroll
+    for (int u = 0; u < CBP; ++u) {
+      const int i = i0 + u * nt;
+      if (i < m) {
+        const T* src = rin + (base + stride * i) * P;
+#pragma unroll
+        for (int r = 0; r < P; ++r) v[u][r] = src[r];
+      }
+    }
+#pragma unroll
+    for (int u = 0; u < CBP; ++u) {
+      const int i = i0 + u * nt;
+      if (i < m) {
+        int rs;
+        const int w = slot(0, i, rs);
+#pragma unroll
+        for (int r = 0; r < P; ++r) R[w + r * rs] = v[u][r];
+      }
+    }
+  }
+  lds_barrier();
+  // ---- forward reduction, level by level
+  for (int l = 0; l < Lf; ++l) {
+    const int ml = level_size(l);
+    const int ne_ = (ml + 1) >> 1, no_ = ml >> 1;
+    const int ob = P * (m - ml);
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+      if (fl[k] == l) {
+        const int tt = ft[k];
+        T lv[P], rv[P];
+        const int li = max(tt - 1, 0), ri = min(tt, no_ - 1);
+#pragma unroll
+        for (int q = 0; q < P; ++q) {
+          const T x = R[ob + q * no_ + li], y = R[ob + q * no_ + ri];
+          lv[q] = tt >= 1 ? x : T(0);
+          rv[q] = tt < no_ ? y : T(0);
+        }
+        int rs;
+        const int w = slot(l + 1, tt, rs);
+#pragma unroll
+        for (int r = 0; r < P; ++r) {
+          T v = R[w + r * rs];
+#pragma unroll
+          for (int q = 0; q < P; ++q) v = chain_fwd_step(v, zm[k][r][q], lv[q], wp[k][r][q], rv[q]);
+          R[w + r * rs] = v;
+        }
+      }
+    }
+    (void)ne_;
+    lds_barrier();
+  }
+  if constexpr (!EARLY) load_bwd_all();  // registers are free now; the top solve hides part of the wait
+  T xr = T(0);
+  const int top = P * (m - 1);
+  if (t < P) {
+#pragma unroll
+    for (int q = 0; q < P; ++q) xr = fma_t(dtop[q], R[top + q], xr);
+  }
+  lds_barrier();
+  if (t < P) R[top + t] = xr;
+  lds_barrier();
+  // ---- back substitution, level by level
+  for (int l = Lf - 1; l >= 0; --l) {
+    const int ml = level_size(l);
+    const int no = ml >> 1;
+    const int ob0 = P * (m - ml);
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+      if (bl[k] == l) {
+        const int tt = bt[k];
+        T own[P], xl[P], xrt[P];
+        int rl, rr2;
+        const int wl = slot(l + 1, tt, rl);
+        const bool right = 2 * tt + 2 < ml;
+        const int wr = right ? slot(l + 1, tt + 1, rr2) : (rr2 = rl, wl);
+#pragma unroll
+        for (int q = 0; q < P; ++q) {
+          own[q] = R[ob0 + tt + q * no];
+          xl[q] = R[wl + q * rl];
+          const T x = R[wr + q * rr2];
+          xrt[q] = right ? x : T(0);
+        }
+#pragma unroll
+        for (int r = 0; r < P; ++r) {
+          T s = T(0);
+#pragma unroll
+          for (int q = 0; q < P; ++q) s = chain_bwd_step(s, od[k][r][q], own[q], ow[k][r][q], xl[q], oz[k][r][q], xrt[q]);
+          R[ob0 + tt + r * no] = s;
+        }
       }
     }
     lds_barrier();
@@ -1329,46 +1652,133 @@ size_t chain_lds_bytes(int P, int n, size_t es, int lds_level) {
   return (size_t)(n - 1) * P * es + (size_t)chain_tail_bytes(P, n, lds_level, es);
 }
 
-static int chain_maxpos(int P) {
-  static constexpr int t[] = {0, ChainShape<1>::MAXPOS, ChainShape<2>::MAXPOS, ChainShape<3>::MAXPOS,
-                              ChainShape<4>::MAXPOS, ChainShape<5>::MAXPOS, ChainShape<6>::MAXPOS,
-                              ChainShape<7>::MAXPOS, ChainShape<8>::MAXPOS, ChainShape<9>::MAXPOS};
-  return P >= 1 && P <= 9 ? t[P] : 0;
-}
-int chain_max_threads(int P) {
-  static constexpr int t[] = {0, ChainShape<1>::MAXT, ChainShape<2>::MAXT, ChainShape<3>::MAXT,
-                              ChainShape<4>::MAXT, ChainShape<5>::MAXT, ChainShape<6>::MAXT,
-                              ChainShape<7>::MAXT, ChainShape<8>::MAXT, ChainShape<9>::MAXT};
-  return P >= 1 && P <= 9 ? t[P] : 0;
+int chain_max_threads(int P, bool wide) {
+  static constexpr int t[] = {0, ChainShape<1, false>::MAXT, ChainShape<2, false>::MAXT, ChainShape<3, false>::MAXT,
+                              ChainShape<4, false>::MAXT, ChainShape<5, false>::MAXT, ChainShape<6, false>::MAXT,
+                              ChainShape<7, false>::MAXT, ChainShape<8, false>::MAXT, ChainShape<9, false>::MAXT};
+  static constexpr int w[] = {0, ChainShape<1, true>::MAXT, ChainShape<2, true>::MAXT, ChainShape<3, true>::MAXT,
+                              ChainShape<4, true>::MAXT, ChainShape<5, true>::MAXT, ChainShape<6, true>::MAXT,
+                              ChainShape<7, true>::MAXT, ChainShape<8, true>::MAXT, ChainShape<9, true>::MAXT};
+  return P >= 1 && P <= 9 ? (wide ? w[P] : t[P]) : 0;
 }
 
 // Workgroup size: 128 threads for P <= 2 and 256 for larger P (more threads
-// per chain lengthen every phase), raised only as far as the back
-// substitution's MAXPOS positions per thread require.
+// per chain lengthen every phase).
 int chain_threads(int P, int n) {
-  const int64_t bwd = (int64_t)((n - 1) / 2);  // positions of the first backward level
-  int64_t th = P <= 2 ? 128 : 256;
-  while (th < chain_max_threads(P) && bwd > th * chain_maxpos(P)) th += 64;
-  return (int)th;
+  (void)n;
+  return P <= 2 ? 128 : 256;
 }
 
 // XCD-aware chain order pays where the strided right-hand side of horizontal
 // chains dominates (small P); measured neutral to slightly negative for P >= 4.
 int chain_remap(int P) { return P <= 3 ? 1 : 0; }
 
+// Slots per thread of the flat schedule's instances at P (0: none).
+static int chain_flat_k(int P, int need) {
+  static constexpr int ks[6][3] = {{0, 0, 0}, {4, 8, 16}, {2, 4, 0}, {1, 2, 0}, {1, 0, 0}, {1, 0, 0}};
+  if (P < 1 || P > 5) return 0;
+  for (int k : ks[P])
+    if (k >= need) return k;
+  return 0;
+}
+
+static int chain_flat_maxt(int P, int K) { return 3 * K * P * P <= 24 ? 1024 : 512; }  // ChainFlat<P, K>::MAXT
+
+// Workgroup size of the flat schedule (0: none fits): the fewest slots per
+// thread whose workgroup has at most 256 threads, else at most its launch bound.
+int chain_flat_threads(int P, int n) {
+  static constexpr int ks[6][3] = {{0, 0, 0}, {4, 8, 16}, {2, 4, 0}, {1, 2, 0}, {1, 0, 0}, {1, 0, 0}};
+  if (P < 1 || P > 5) return 0;
+  const int m = n - 1;
+  int fallback = 0;
+  for (int k : ks[P]) {
+    if (k == 0) continue;
+    const int th = std::max(64, ((m + k - 1) / k + 63) / 64 * 64);
+    if (th <= 256) return th;
+    if (!fallback && th <= chain_flat_maxt(P, k)) fallback = th;
+  }
+  return fallback;
+}
+
+// Launch shape (ChainArgs::shape): 0 chooses, 1 lean, 2 wide (P = 3 ... 5,
+// else lean), 3 flat (P <= 5, when the chain's factors fit the registers of at
+// most 1024 threads; else chosen).  The choice: flat for meshes with at most 4
+// chains per CU (2n <= 1024) and for P = 2; else wide for P = 3, 4 (within 128
+// registers either way), lean otherwise (measured on MI355X at n = 256, k = 4
+// and n = 1024, k = 3).
+int chain_shape_kind(int P, int n, int shape) {
+  const int th = chain_flat_threads(P, n);
+  const bool flat_ok = th > 0;
+  if (shape == 3 && flat_ok) return 3;  // else as chosen below
+  if (shape == 2) return P >= 3 && P <= 5 ? 2 : 1;
+  if (shape == 1) return 1;
+  if (flat_ok && (P == 2 || 2LL * n <= 1024)) return 3;
+  return P >= 3 && P <= 4 ? 2 : 1;
+}
+
+template <int P, typename T, int K>
+static hipError_t launch_chain_flat_t(const ChainArgs& a, int64_t nch, int threads, size_t lds, hipStream_t s) {
+  if (threads > ChainFlat<P, K>::MAXT) return hipErrorInvalidValue;
+  if (lds > 65536 && hipFuncSetAttribute(reinterpret_cast<const void*>(&k_chain_flat<P, T, K>),
+                                         hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds) != hipSuccess)
+    return hipErrorInvalidValue;
+  hipLaunchKernelGGL((k_chain_flat<P, T, K>), dim3((unsigned)nch), dim3(threads), lds, s, a);
+  return hipGetLastError();
+}
+
+template <typename T>
+static hipError_t launch_chain_flat(int P, const ChainArgs& a, int64_t nch, int threads, hipStream_t s) {
+  const int m = a.n - 1;
+  const int K = chain_flat_k(P, (m + threads - 1) / threads);
+  const size_t lds = (size_t)m * P * sizeof(T);  // the right-hand side only
+  if ((int64_t)lds > (a.lds_cap > 0 ? a.lds_cap : 65536)) return hipErrorInvalidValue;
+  switch (P * 32 + K) {
+    case 1 * 32 + 4: return launch_chain_flat_t<1, T, 4>(a, nch, threads, lds, s);
+    case 1 * 32 + 8: return launch_chain_flat_t<1, T, 8>(a, nch, threads, lds, s);
+    case 1 * 32 + 16: return launch_chain_flat_t<1, T, 16>(a, nch, threads, lds, s);
+    case 2 * 32 + 2: return launch_chain_flat_t<2, T, 2>(a, nch, threads, lds, s);
+    case 2 * 32 + 4: return launch_chain_flat_t<2, T, 4>(a, nch, threads, lds, s);
+    case 3 * 32 + 1: return launch_chain_flat_t<3, T, 1>(a, nch, threads, lds, s);
+    case 3 * 32 + 2: return launch_chain_flat_t<3, T, 2>(a, nch, threads, lds, s);
+    case 4 * 32 + 1: return launch_chain_flat_t<4, T, 1>(a, nch, threads, lds, s);
+    case 5 * 32 + 1: return launch_chain_flat_t<5, T, 1>(a, nch, threads, lds, s);
+    default: return hipErrorInvalidValue;
+  }
+}
+
+template <int P, typename T, bool WIDE>
+static hipError_t launch_chain_t(const ChainArgs& a, int64_t nch, int threads, size_t lds, hipStream_t s) {
+  constexpr bool W = ChainShape<P, WIDE>::W;  // other P have one shape
+  // beyond 64 KiB a kernel's dynamic LDS is raised explicitly
+  if (lds > 65536 && hipFuncSetAttribute(reinterpret_cast<const void*>(&k_chain<P, T, W>),
+                                         hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds) != hipSuccess)
+    return hipErrorInvalidValue;
+  hipLaunchKernelGGL((k_chain<P, T, W>), dim3((unsigned)nch), dim3(threads), lds, s, a);
+  return hipGetLastError();
+}
+
 hipError_t launch_chain_solve(Prec pr, int P, const ChainArgs& a, hipStream_t s) {
   const int64_t nch = 2LL * a.n;
+  const int kind = chain_shape_kind(P, a.n, a.shape);
+  if (kind == 0) return hipErrorInvalidValue;
+  if (kind == 3) {
+    const int threads = a.threads > 0 ? a.threads : chain_flat_threads(P, a.n);
+    if (threads % 64 || threads > 1024) return hipErrorInvalidValue;
+    return pr == Prec::F64 ? launch_chain_flat<double>(P, a, nch, threads, s)
+                           : launch_chain_flat<float>(P, a, nch, threads, s);
+  }
   const int threads = a.threads > 0 ? a.threads : chain_threads(P, a.n);
   const size_t lds = chain_lds_bytes(P, a.n, vec_bytes(pr), a.lds_level);
-  if (lds > 65536) return hipErrorInvalidValue;
-  // the back substitution keeps at most MAXPOS positions per thread
-  if (chain_maxpos(P) == 0 || (int64_t)((a.n - 1) / 2) > (int64_t)threads * chain_maxpos(P) ||
-      threads > chain_max_threads(P) || threads % 64)
+  if ((int64_t)lds > (a.lds_cap > 0 ? a.lds_cap : 65536)) return hipErrorInvalidValue;
+  const bool wide = kind == 2;
+  if (chain_max_threads(P, wide) == 0 || threads > chain_max_threads(P, wide) || threads % 64)
     return hipErrorInvalidValue;
   if (pr == Prec::F64) {
-    HDG_DISPATCH_P(P, hipLaunchKernelGGL((k_chain<PP, double>), dim3((unsigned)nch), dim3(threads), lds, s, a));
+    HDG_DISPATCH_P(P, return wide ? (launch_chain_t<PP, double, true>)(a, nch, threads, lds, s)
+                                  : (launch_chain_t<PP, double, false>)(a, nch, threads, lds, s));
   } else {
-    HDG_DISPATCH_P(P, hipLaunchKernelGGL((k_chain<PP, float>), dim3((unsigned)nch), dim3(threads), lds, s, a));
+    HDG_DISPATCH_P(P, return wide ? (launch_chain_t<PP, float, true>)(a, nch, threads, lds, s)
+                                  : (launch_chain_t<PP, float, false>)(a, nch, threads, lds, s));
   }
   return hipGetLastError();
 }

@@ -109,11 +109,17 @@ struct ChainArgs {
   int threads;          // workgroup size; 0 = chain_threads(P, n)
   int lds_level;        // factors of levels >= lds_level are staged in LDS (chain_lds_level)
   int remap;            // 1: XCD-aware chain order (consecutive chains on one XCD)
+  int64_t lds_cap;      // LDS bytes a workgroup may use on this device (0: 64 KiB)
+  int shape;            // 0 by the mesh, 1 lean, 2 wide, 3 flat (chain_shape_kind)
 };
 int chain_threads(int P, int n);
-int chain_max_threads(int P);  // launch bound of the chain kernel at P
+int chain_flat_threads(int P, int n);            // workgroup size of the flat schedule (0: none at P)
+int chain_shape_kind(int P, int n, int shape);   // the kind ChainArgs::shape selects (0: not available)
+int chain_max_threads(int P, bool wide);         // launch bound of the chain kernel at P
 int chain_remap(int P);
 // first level whose factors (and all later ones) fit in `budget` bytes of LDS
+// LDS of one workgroup on gfx950 (the chain solves keep a whole chain there)
+constexpr int64_t kMaxLdsBytes = 160 * 1024;
 int chain_lds_level(int P, int n, size_t elem_bytes, int64_t budget);
 // dynamic LDS of a chain launch: right-hand side plus the staged factors
 size_t chain_lds_bytes(int P, int n, size_t elem_bytes, int lds_level);
@@ -191,8 +197,11 @@ struct ChainMultiArgs {
   int rc;            // right-hand sides per workgroup (chain_multi_chunk)
   int nchunks;       // ceil(R / rc)
   int threads;       // workgroup size (0: smallest of 256, 512, 1024 that fits the items)
+  int64_t lds_cap;   // LDS bytes a workgroup may use on this device (0: 64 KiB)
 };
-int chain_multi_chunk(int P, int n, int R, size_t elem_bytes);
+// Largest power-of-two chunk of columns for the chain solve; 0 if one column
+// does not fit lds_cap bytes of LDS.
+int chain_multi_chunk(int P, int n, int R, size_t elem_bytes, int64_t lds_cap);
 hipError_t launch_chain_solve_m(Prec pr, int P, const ChainMultiArgs& a, hipStream_t s);
 // out[r] = sum_i x[i][r] y[i][r] (FP64, deterministic); partial needs dots_m_grid(N) * R
 int dots_m_grid(int64_t N);

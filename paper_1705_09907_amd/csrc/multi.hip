@@ -464,9 +464,11 @@ static size_t chain_multi_lds(int P, int n, int rc, size_t es) {
 }
 
 // Largest power-of-two chunk (at most 16 and at most R rounded up to a power
-// of two) whose right-hand sides fit 64 KiB of LDS; 0 if one column does not fit.
-int chain_multi_chunk(int P, int n, int R, size_t es) {
-  if (chain_multi_lds(P, n, 1, es) > 65536) return 0;
+// of two) whose right-hand sides fit 64 KiB of LDS (2 workgroups per CU), or
+// one column up to lds_cap; 0 if one column does not fit lds_cap.
+int chain_multi_chunk(int P, int n, int R, size_t es, int64_t lds_cap) {
+  const int64_t cap = lds_cap > 0 ? lds_cap : 65536;
+  if ((int64_t)chain_multi_lds(P, n, 1, es) > cap) return 0;
   int rc = 1;
   while (rc < 16 && rc < R && chain_multi_lds(P, n, 2 * rc, es) <= 65536) rc *= 2;
   return rc;
@@ -475,7 +477,8 @@ int chain_multi_chunk(int P, int n, int R, size_t es) {
 hipError_t launch_chain_solve_m(Prec pr, int P, const ChainMultiArgs& a, hipStream_t s) {
   if (a.rc < 1 || (a.rc & (a.rc - 1)) || a.nchunks * a.rc < a.R) return hipErrorInvalidValue;
   const size_t lds = chain_multi_lds(P, a.n, a.rc, vec_bytes(pr));
-  if (lds > 65536) return hipErrorInvalidValue;
+  if ((int64_t)lds > (a.lds_cap > 0 ? a.lds_cap : 65536)) return hipErrorInvalidValue;
+  const bool big = lds > 65536;  // beyond 64 KiB a kernel's dynamic LDS is raised explicitly
   // one (position, column) pair per lane: the first forward level has
   // ceil((n-1)/2) positions
   const int64_t items = (int64_t)(a.n / 2) * a.rc;
@@ -484,9 +487,15 @@ hipError_t launch_chain_solve_m(Prec pr, int P, const ChainMultiArgs& a, hipStre
   if (threads > 256 || threads % 64) return hipErrorInvalidValue;
   const dim3 grid((unsigned)(2LL * a.n * a.nchunks));
   if (pr == Prec::F64) {
-    HDG_MDISPATCH_P(P, hipLaunchKernelGGL((k_chain_m<PP, double>), grid, dim3(threads), lds, s, a));
+    HDG_MDISPATCH_P(P, if (big && hipFuncSetAttribute(reinterpret_cast<const void*>(&k_chain_m<PP, double>),
+                                                      hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds) != hipSuccess)
+                         return hipErrorInvalidValue;
+                    hipLaunchKernelGGL((k_chain_m<PP, double>), grid, dim3(threads), lds, s, a));
   } else {
-    HDG_MDISPATCH_P(P, hipLaunchKernelGGL((k_chain_m<PP, float>), grid, dim3(threads), lds, s, a));
+    HDG_MDISPATCH_P(P, if (big && hipFuncSetAttribute(reinterpret_cast<const void*>(&k_chain_m<PP, float>),
+                                                      hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds) != hipSuccess)
+                         return hipErrorInvalidValue;
+                    hipLaunchKernelGGL((k_chain_m<PP, float>), grid, dim3(threads), lds, s, a));
   }
   return hipGetLastError();
 }

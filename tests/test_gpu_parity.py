@@ -393,3 +393,32 @@ def test_full_size_chain_solve_sampled(name, n, k, sigma, seed, autotune):
             assert rel_inf(xc, xd) <= 1e-9, (c, rel_inf(xc, xd))
     finally:
         S.close()
+
+
+@pytest.mark.parametrize("n,k,prec", [(2, 1, "f64"), (16, 1, "f64"), (24, 3, "f64"), (40, 4, "f32"), (7, 8, "f64"),
+                                      (64, 5, "f64"), (130, 2, "f64"), (256, 4, "f64"), (1024, 3, "f64")])
+def test_chain_schedules_are_bitwise_identical(n, k, prec):
+    """The chain solve's launch schedules (lean, wide and flat factor fetches)
+    run the same operations in the same order: one sweep at every level gives
+    bit-identical results whichever schedule runs (each falls back to another
+    where it does not exist at that degree or size)."""
+    print(f"case chain schedules n={n} k={k} {prec}", flush=True)
+    kap = kappa_lognormal(n, 1.0, 8)
+    ref = None
+    for shape in ("auto", "lean", "wide", "flat"):
+        S = H.Solver(n, k, kap, smoother="chain", omega=0.7, chain_shape=shape, precision=prec)
+        try:
+            outs = []
+            for p in range(k + 1):
+                N = S.num_dofs(p)
+                b = dev(normal_vector(N, 40 + p))
+                x = dev(normal_vector(N, 60 + p))
+                S.smooth(p, b, x, 1)
+                outs.append(host(x))
+        finally:
+            S.close()
+        if ref is None:
+            ref = outs
+        else:
+            for p in range(k + 1):
+                assert np.array_equal(outs[p], ref[p]), (shape, p)

@@ -102,12 +102,22 @@ def test_reduced_precision_face_smoother_needs_omega(prec):
     assert not h.value
 
 
-@pytest.mark.parametrize("k,prec,n", [(7, 0, 1018), (3, 0, 2046), (3, 1, 4094)])
-def test_chain_smoother_rejects_chains_beyond_lds(k, prec, n):
-    """One chain's right-hand side plus one factor block must fit 64 KiB of LDS:
-    ((n-1)(k+1) + (k+1)^2) * (8 or 4 bytes) <= 65536; each case is the first n past it."""
+def _first_n_past_lds(k, vb, cap=160 * 1024):
+    P = k + 1
+    n = 2
+    while ((n - 1) * P + P * P) * vb <= cap:
+        n += 1
+    return n
+
+
+@pytest.mark.parametrize("k,prec", [(7, 0), (3, 0), (8, 1), (8, 0)])
+def test_chain_smoother_rejects_chains_beyond_lds(k, prec):
+    """One chain's right-hand side plus one factor block must fit the LDS of one
+    gfx950 workgroup: ((n-1)(k+1) + (k+1)^2) * (8 or 4 bytes) <= 160 KiB; each
+    case is the first n past it, rejected before any device call."""
     P, vb = k + 1, 8 if prec == 0 else 4
-    assert ((n - 1) * P + P * P) * vb > 65536 >= ((n - 2) * P + P * P) * vb
+    n = _first_n_past_lds(k, vb)
+    assert ((n - 1) * P + P * P) * vb > 163840 >= ((n - 2) * P + P * P) * vb
     cfg = H.Config()
     H.lib.hdg_config_default(n, k, ctypes.byref(cfg))
     cfg.precision = prec
