@@ -63,7 +63,9 @@ WORKLOADS = {
 # taken with.  The figure is reported only while csrc/kernels.hip still hashes
 # to that value; after any change to the kernels it is null until re-measured.
 # workload, precision -> (bytes per launch, sha256[:16] of csrc/kernels.hip, profile)
-MEASURED_TRAFFIC = {}
+MEASURED_TRAFFIC = {
+    ("lognormal_n1024_k3", "f64"): (2187578258, "4d277da9041f690d", "profiles/trace_apply_lognormal_n1024_k3.md"),
+}
 
 MAT_BYTES = {"f64": 8, "f32": 4, "bf16": 4}  # the finest level keeps FP32 blocks in the bf16 cycle
 VEC_BYTES = {"f64": 8, "f32": 4, "bf16": 4}
@@ -230,6 +232,32 @@ def pmc_summary(fetch_db, write_db, kernel, calib=None):
                       f"WRITE_MB={wm * 1024 / 1e6:.2f}")
 
 
+def apply_only(args, S, n, k, dev):
+    """Cold applies of the finest level only (each after a 1 GiB cache flush),
+    then optionally the 256 MiB calibration copy; one JSON line."""
+    import torch
+    from workloads import normal_vector
+    N = S.num_dofs()
+    x = torch.tensor(normal_vector(N, 7), device=dev)
+    y = torch.empty_like(x)
+    flush = torch.empty(1 << 27, dtype=torch.float64, device=dev)
+    us = []
+    for i in range(args.warmup + args.steps):
+        flush.zero_()
+        t = S.apply_timed(k, x, y)
+        if i >= args.warmup:
+            us.append(t)
+    if args.calibrate_copy:
+        src = torch.ones(1 << 25, dtype=torch.float64, device=dev)
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+    torch.cuda.synchronize()
+    byts, _ = algorithmic_bytes(n, k)
+    print(json.dumps({"workload": args.workload, "apply_us_cold": float(np.mean(us)),
+                      "algorithmic_bytes": byts, "achieved_GBs": byts / (float(np.mean(us)) * 1e-6) / 1e9,
+                      "calibration_copy_bytes": (1 << 25) * 8 if args.calibrate_copy else None}))
+
+
 def uneven_batch(args):
     """32 meshes n_i = 64 + 32 (i mod 11), k_i = 2 + (i mod 3), K lognormal sigma = 1
     (seed 40 + i): one cold apply of all meshes in one launch, against 32 cold
@@ -307,13 +335,21 @@ def main():
     ap.add_argument("--inner", default="auto",
                     help="K-cycle steps per p-level, e.g. '1:3,0:3'; 'auto' = the workload's tuned "
                          "setting, '' = plain V-cycle")
-    ap.add_argument("--smoother", default="chain", choices=["chain", "face"])
+    ap.add_argument("--smoother", default="chain", choices=["chain", "face", "patch"])
     ap.add_argument("--precision", default="f64", choices=["f64", "f32", "bf16"],
                     help="precision of the multigrid cycle and of the timed apply")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--warm", action="store_true", help="also time back-to-back (cache-warm) applies")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="run one 256 MiB device copy after the timed region (counter calibration)")
+    ap.add_argument("--chain-level", type=int, default=None,
+                    help="only chain Schwarz sweeps at this p-level (3, after set-up): a short run for counter "
+                         "passes of the chain kernels")
+    ap.add_argument("--chain-shape", default="auto", choices=["auto", "lean", "wide", "flat"],
+                    help="chain solve schedule of the handle (with --chain-level)")
+    ap.add_argument("--apply-only", action="store_true",
+                    help="only the cold applies of the workload (warm-up + steps) and, with --calibrate-copy, "
+                         "the copy: a short run for counter passes; prints the apply timing")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py: this build measures one GPU only; multi-GPU runs are not part of it "
@@ -340,9 +376,25 @@ def main():
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
     t0 = time.perf_counter()
-    S = H.Solver(n, k, kap, smoother=args.smoother, precision=args.precision, inner=inner, autotune=True)
+    short = args.apply_only or args.chain_level is not None
+    S = H.Solver(n, k, kap, smoother=args.smoother, precision=args.precision, inner=inner,
+                 autotune=not short, chain_shape=args.chain_shape)
     torch.cuda.synchronize()
     setup_s = time.perf_counter() - t0
+    if args.apply_only:
+        apply_only(args, S, n, k, dev)
+        return
+    if args.chain_level is not None:
+        p = args.chain_level
+        Np = S.num_dofs(p)
+        bp = torch.tensor(normal_vector(Np, 11), device=dev)
+        xp = torch.zeros(Np, dtype=torch.float64, device=dev)
+        for _ in range(3):
+            S.smooth(p, bp, xp, 1)
+        torch.cuda.synchronize()
+        print(json.dumps({"workload": args.workload, "chain_level": p, "P": p + 1, "chain_shape": args.chain_shape,
+                          "launch_shape": S.chain_shape(p)}))
+        return
     N = S.num_dofs()
     nq = S.nq
     t0 = time.perf_counter()
