@@ -264,6 +264,16 @@ hdg_status_t hdg_apply_trace_operator_multi(hdg_handle_t h, int32_t p, int32_t p
 hdg_status_t hdg_apply_trace_operator_batch(int32_t count, const hdg_handle_t* handles, const int32_t* p,
                                             const double* const* X, double* const* Y);
 
+/* The same many-mesh product (Sec. 8, Alg. algo_mv) in the cycle precision of handles created with
+ * HDG_PREC_F32 or HDG_PREC_BF16 (the blocks hdg_apply_trace_operator_lp uses:
+ * FP32 or bfloat16, FP32 vectors and accumulation); handles may mix the two.
+ * X[i], Y[i]: device float [N_i(p[i])], not aliased.  Each y_i is bit-identical
+ * to hdg_apply_trace_operator_lp on that mesh (same loads, same order of
+ * operations).  Returns STATE if a handle has FP64 cycle precision.  Same
+ * stream and synchronization rules as hdg_apply_trace_operator_batch. */
+hdg_status_t hdg_apply_trace_operator_batch_lp(int32_t count, const hdg_handle_t* handles, const int32_t* p,
+                                               const float* const* X, float* const* Y);
+
 /* For callers that cannot allocate device memory (code under HIP graph capture
  * in the caller's own pipeline, tight serving loops, harnesses that forbid
  * hipMalloc): the same products as hdg_apply_trace_operator_batch, bit for bit,

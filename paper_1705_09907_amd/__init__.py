@@ -74,6 +74,7 @@ SIGNATURES = {
     "hdg_apply_trace_operator_multi": [_P, _I32, _I32, _I32, _P, _P],
     "hdg_apply_trace_operator_batch": [_I32, _P, _P, _P, _P],
     "hdg_apply_trace_operator_batch_noalloc": [_I32, _P, _P, _P, _P],
+    "hdg_apply_trace_operator_batch_lp": [_I32, _P, _P, _P, _P],
     "hdg_residual": [_P, _I32, _P, _P, _P, _PD],
     "hdg_smooth": [_P, _I32, _P, _P, _I32],
     "hdg_restrict": [_P, _I32, _P, _P],
@@ -146,19 +147,25 @@ def quadrature_nodes(nq):
     return x
 
 
-def apply_batch(solvers, xs, ys=None, levels=None, noalloc=False):
+def apply_batch(solvers, xs, ys=None, levels=None, noalloc=False, lp=False):
     """y_i = S_i x_i for many meshes in one kernel launch (FP64; synchronizes).
     noalloc=True calls hdg_apply_trace_operator_batch_noalloc (same products, no
-    allocation, at most HDG_BATCH_NOALLOC_MAX meshes)."""
+    allocation, at most HDG_BATCH_NOALLOC_MAX meshes); lp=True calls
+    hdg_apply_trace_operator_batch_lp (the handles' reduced cycle precision,
+    float32 vectors)."""
     import torch
     cnt = len(solvers)
     levels = [s.k for s in solvers] if levels is None else list(levels)
     ys = [torch.empty_like(x) for x in xs] if ys is None else ys
     H = (ctypes.c_void_p * cnt)(*[s._h.value for s in solvers])
     Pv = (ctypes.c_int32 * cnt)(*levels)
-    Xv = (ctypes.c_void_p * cnt)(*[_dptr(x, "x", s.num_dofs(l)).value for s, x, l in zip(solvers, xs, levels)])
-    Yv = (ctypes.c_void_p * cnt)(*[_dptr(y, "y", s.num_dofs(l)).value for s, y, l in zip(solvers, ys, levels)])
-    fn = lib.hdg_apply_trace_operator_batch_noalloc if noalloc else lib.hdg_apply_trace_operator_batch
+    dt = "float32" if lp else "float64"
+    Xv = (ctypes.c_void_p * cnt)(*[_dptr(x, "x", s.num_dofs(l), dt).value for s, x, l in zip(solvers, xs, levels)])
+    Yv = (ctypes.c_void_p * cnt)(*[_dptr(y, "y", s.num_dofs(l), dt).value for s, y, l in zip(solvers, ys, levels)])
+    if lp and noalloc:
+        raise ValueError("the allocation-free batch apply is FP64 only")
+    fn = (lib.hdg_apply_trace_operator_batch_lp if lp else
+          lib.hdg_apply_trace_operator_batch_noalloc if noalloc else lib.hdg_apply_trace_operator_batch)
     st = fn(cnt, H, Pv, Xv, Yv)
     if st != 0:
         raise HDGError(st, lib.hdg_last_error(solvers[0]._h).decode())

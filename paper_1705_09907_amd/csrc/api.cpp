@@ -2033,6 +2033,7 @@ hdg_status_t hdg_apply_trace_operator_batch(int32_t count, const hdg_handle_t* h
       M.tile0 = tot;
       M.n = h->n;
       M.P = L.P;
+      M.mp = (int)hdg::Prec::F64;
       pmax = std::max(pmax, L.P);
       tot += h->ntiles;
     }
@@ -2046,6 +2047,53 @@ hdg_status_t hdg_apply_trace_operator_batch(int32_t count, const hdg_handle_t* h
     const int64_t need = (tot + 3) / 4;
     const int grid = (int)std::max<int64_t>(1, std::min<int64_t>(need, 256 * 8));
     hipchk(hdg::launch_trace_batch(h0->batch_dev, count, tot, grid, pmax, h0->stream), "trace apply batch");
+    hipchk(hipStreamSynchronize(h0->stream), "sync");  // the descriptor table is reused by the next call
+    return HDG_OK;
+  });
+}
+
+hdg_status_t hdg_apply_trace_operator_batch_lp(int32_t count, const hdg_handle_t* handles, const int32_t* p,
+                                               const float* const* X, float* const* Y) {
+  if (count < 1 || !handles || !p || !X || !Y) return HDG_ERR_INVALID_ARG;
+  for (int i = 0; i < count; ++i) {
+    hdg_handle_t h = handles[i];
+    if (!h || p[i] < 0 || p[i] > h->k || !X[i] || !Y[i] || (const void*)X[i] == (const void*)Y[i])
+      return HDG_ERR_INVALID_ARG;
+    if (h->prec == hdg::Prec::F64) {
+      h->err = "handle was created with FP64 cycle precision";
+      return HDG_ERR_STATE;
+    }
+  }
+  hdg_handle_t h0 = handles[0];
+  return guarded(h0, [&]() -> hdg_status_t {
+    h0->batch_host.resize(count);
+    int64_t tot = 0;
+    int pmax = 1;
+    for (int i = 0; i < count; ++i) {
+      const hdg_handle_t h = handles[i];
+      const PLevel& L = h->pl[p[i]];
+      hdg::BatchMesh& M = h0->batch_host[i];
+      M.slab = L.slab;  // the cycle precision's blocks, as hdg_apply_trace_operator_lp reads them
+      M.x = X[i];
+      M.y = Y[i];
+      M.nf = h->nf;
+      M.ntiles = h->ntiles;
+      M.tile0 = tot;
+      M.n = h->n;
+      M.P = L.P;
+      M.mp = (int)L.mp;
+      pmax = std::max(pmax, L.P);
+      tot += h->ntiles;
+    }
+    if (h0->batch_cap < count) {
+      h0->batch_dev = static_cast<hdg::BatchMesh*>(balloc(h0, sizeof(hdg::BatchMesh) * (size_t)count));
+      h0->batch_cap = count;
+    }
+    hipchk(hipMemcpyAsync(h0->batch_dev, h0->batch_host.data(), sizeof(hdg::BatchMesh) * (size_t)count,
+                          hipMemcpyHostToDevice, h0->stream), "h2d");
+    const int64_t need = (tot + 3) / 4;
+    const int grid = (int)std::max<int64_t>(1, std::min<int64_t>(need, 256 * 8));
+    hipchk(hdg::launch_trace_batch(h0->batch_dev, count, tot, grid, pmax, h0->stream, true), "trace apply batch lp");
     hipchk(hipStreamSynchronize(h0->stream), "sync");  // the descriptor table is reused by the next call
     return HDG_OK;
   });
@@ -2087,6 +2135,7 @@ hdg_status_t hdg_apply_trace_operator_batch_noalloc(int32_t count, const hdg_han
       M.tile0 = tot;
       M.n = h->n;
       M.P = L.P;
+      M.mp = (int)hdg::Prec::F64;
       pmax = std::max(pmax, L.P);
       tot += h->ntiles;
     }

@@ -209,33 +209,34 @@ __global__ __launch_bounds__(kWG) void k_trace(TraceArgs a) {
 
 // ------------------------------------------------ many meshes in one launch
 // y = S x on one 64-face tile of one mesh, by one wavefront: the APPLY path of
-// k_trace with the same loads and the same order of operations.
-template <int P>
-__device__ __forceinline__ void apply_tile_f64(const BatchMesh& M, int64_t tile, int lane) {
-  using L16 = Lanes16<double, double>;
+// k_trace<P, TM_APPLY, TM, TV> with the same loads and the same order of
+// operations (TM: stored block entries, TV: vectors and accumulation).
+template <int P, typename TM, typename TV>
+__device__ __forceinline__ void apply_tile(const BatchMesh& M, int64_t tile, int lane) {
+  using L16 = Lanes16<TM, TV>;
   constexpr int V = L16::V;
   constexpr int P2 = P * P;
   constexpr int NE = 7 * P2;
   constexpr int NQ = (NE + V - 1) / V;
-  const double* x = static_cast<const double*>(M.x);
-  double* y = static_cast<double*>(M.y);
+  const TV* x = static_cast<const TV*>(M.x);
+  TV* y = static_cast<TV*>(M.y);
   const int64_t nv = (int64_t)M.n * (M.n - 1);
   const int64_t f = tile * 64 + lane;
   const bool valid = f < M.nf;
   int64_t g[7];
   face_neighbours(M.n, nv, valid ? f : 0, g);
-  double xv[7][P];
+  TV xv[7][P];
 #pragma unroll
   for (int s = 0; s < 7; ++s)
 #pragma unroll
-    for (int c = 0; c < P; ++c) xv[s][c] = (valid && g[s] >= 0) ? x[g[s] * P + c] : 0.0;
-  double acc[P];
+    for (int c = 0; c < P; ++c) xv[s][c] = (valid && g[s] >= 0) ? x[g[s] * P + c] : TV(0);
+  TV acc[P];
 #pragma unroll
-  for (int r = 0; r < P; ++r) acc[r] = 0.0;
+  for (int r = 0; r < P; ++r) acc[r] = TV(0);
   const u32x4* sp = static_cast<const u32x4*>(M.slab) + (tile * NQ) * 64 + lane;
 #pragma unroll
   for (int q = 0; q < NQ; ++q) {
-    double w[V];
+    TV w[V];
     L16::unpack(__builtin_nontemporal_load(sp + q * 64), w);
 #pragma unroll
     for (int u = 0; u < V; ++u) {
@@ -249,13 +250,25 @@ __device__ __forceinline__ void apply_tile_f64(const BatchMesh& M, int64_t tile,
   }
 }
 
+// One mesh's tile with the block storage its descriptor names (FP64 blocks and
+// vectors, or FP32 / bfloat16 blocks with FP32 vectors).
+template <int P, bool LP>
+__device__ __forceinline__ void apply_tile_any(const BatchMesh& M, int64_t tile, int lane) {
+  if constexpr (LP) {
+    if (M.mp == (int)Prec::BF16) apply_tile<P, bf16_t, float>(M, tile, lane);
+    else apply_tile<P, float, float>(M, tile, lane);
+  } else {
+    apply_tile<P, double, double>(M, tile, lane);
+  }
+}
+
 // A fixed grid of workgroups walks the list of (mesh, tile) items with a static
 // stride (deterministic); wavefront w of workgroup b takes items 4 b + w,
 // 4 b + w + 4 G, ...  Meshes are found by a scan of the tile offsets.  PMAX is
 // the largest P compiled in: registers are sized for it, so the launcher takes
 // the smallest instance that covers the batch (P <= 5: about half the registers
-// of P <= 9).
-template <int PMAX>
+// of P <= 9).  LP: the meshes' cycle-precision operators (FP32 vectors).
+template <int PMAX, bool LP>
 __global__ __launch_bounds__(kWG) void k_trace_batch(const BatchMesh* meshes, int nmesh, int64_t total) {
   const int lane = threadIdx.x & 63;
   const int64_t nwaves = (int64_t)gridDim.x * (kWG / 64);
@@ -265,18 +278,18 @@ __global__ __launch_bounds__(kWG) void k_trace_batch(const BatchMesh* meshes, in
     const BatchMesh& M = meshes[m];
     const int64_t tile = item - M.tile0;
     switch (M.P) {
-      case 1: apply_tile_f64<1>(M, tile, lane); break;
-      case 2: apply_tile_f64<2>(M, tile, lane); break;
-      case 3: apply_tile_f64<3>(M, tile, lane); break;
-      case 4: apply_tile_f64<4>(M, tile, lane); break;
-      case 5: apply_tile_f64<5>(M, tile, lane); break;
+      case 1: apply_tile_any<1, LP>(M, tile, lane); break;
+      case 2: apply_tile_any<2, LP>(M, tile, lane); break;
+      case 3: apply_tile_any<3, LP>(M, tile, lane); break;
+      case 4: apply_tile_any<4, LP>(M, tile, lane); break;
+      case 5: apply_tile_any<5, LP>(M, tile, lane); break;
       default:
         if constexpr (PMAX > 5) {
           switch (M.P) {
-            case 6: apply_tile_f64<6>(M, tile, lane); break;
-            case 7: apply_tile_f64<7>(M, tile, lane); break;
-            case 8: apply_tile_f64<8>(M, tile, lane); break;
-            default: apply_tile_f64<9>(M, tile, lane); break;
+            case 6: apply_tile_any<6, LP>(M, tile, lane); break;
+            case 7: apply_tile_any<7, LP>(M, tile, lane); break;
+            case 8: apply_tile_any<8, LP>(M, tile, lane); break;
+            default: apply_tile_any<9, LP>(M, tile, lane); break;
           }
         }
         break;
@@ -285,12 +298,22 @@ __global__ __launch_bounds__(kWG) void k_trace_batch(const BatchMesh* meshes, in
 }
 
 hipError_t launch_trace_batch(const BatchMesh* meshes_dev, int nmesh, int64_t total_tiles, int grid, int pmax,
-                              hipStream_t s) {
+                              hipStream_t s, bool lp) {
   if (total_tiles == 0) return hipSuccess;
-  if (pmax <= 5)
-    hipLaunchKernelGGL(k_trace_batch<5>, dim3((unsigned)grid), dim3(kWG), 0, s, meshes_dev, nmesh, total_tiles);
-  else
-    hipLaunchKernelGGL(k_trace_batch<9>, dim3((unsigned)grid), dim3(kWG), 0, s, meshes_dev, nmesh, total_tiles);
+  if (lp) {
+    if (pmax <= 5)
+      hipLaunchKernelGGL((k_trace_batch<5, true>), dim3((unsigned)grid), dim3(kWG), 0, s, meshes_dev, nmesh,
+                         total_tiles);
+    else
+      hipLaunchKernelGGL((k_trace_batch<9, true>), dim3((unsigned)grid), dim3(kWG), 0, s, meshes_dev, nmesh,
+                         total_tiles);
+  } else if (pmax <= 5) {
+    hipLaunchKernelGGL((k_trace_batch<5, false>), dim3((unsigned)grid), dim3(kWG), 0, s, meshes_dev, nmesh,
+                       total_tiles);
+  } else {
+    hipLaunchKernelGGL((k_trace_batch<9, false>), dim3((unsigned)grid), dim3(kWG), 0, s, meshes_dev, nmesh,
+                       total_tiles);
+  }
   return hipGetLastError();
 }
 

@@ -67,14 +67,17 @@ struct MultiArgs {
 // (Y = P_p^T (B - S X) on the coarse level)
 hipError_t launch_trace_multi(Prec pr, int P, const MultiArgs& a, hipStream_t s, int mode = TM_APPLY);
 
-// y_m = S_m x_m for many meshes (FP64) in one launch: a fixed grid walks the
+// y_m = S_m x_m for many meshes in one launch: a fixed grid walks the
 // (mesh, tile) items; tile0 = first item of the mesh (prefix sum of ntiles).
+// mp: the block storage (Prec) of slab; FP64 blocks go with FP64 vectors, FP32
+// and bfloat16 blocks with FP32 vectors.
 struct BatchMesh {
   const void* slab;
   const void* x;
   void* y;
   int64_t nf, ntiles, tile0;
   int n, P;
+  int mp;
 };
 // Allocation-free variant: the descriptor table lives in a file-scope device
 // array of kBatchNoallocMax entries (one per GPU); batch_scratch_address returns
@@ -82,9 +85,10 @@ struct BatchMesh {
 constexpr int kBatchNoallocMax = 256;
 constexpr int kMaxDevices = 64;
 hipError_t batch_scratch_address(void** out);
-// pmax: the largest P in the batch (selects the register budget)
+// pmax: the largest P in the batch (selects the register budget); lp: every
+// mesh has FP32 or bfloat16 blocks and FP32 vectors (else FP64 throughout)
 hipError_t launch_trace_batch(const BatchMesh* meshes_dev, int nmesh, int64_t total_tiles, int grid, int pmax,
-                              hipStream_t s);
+                              hipStream_t s, bool lp = false);
 
 // x = omega Dinv b (first facet sweep from a zero guess)
 hipError_t launch_dinv_apply(Prec pr, int P, const void* dinv, const void* b, double omega, void* x,

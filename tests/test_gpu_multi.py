@@ -163,3 +163,32 @@ def test_batch_of_meshes_one_launch_bitwise(meshes):
     finally:
         for s in solvers:
             s.close()
+
+
+@pytest.mark.parametrize("meshes", [[(16, 1, "f32"), (24, 3, "bf16"), (40, 4, "f32"), (7, 8, "bf16"), (2, 1, "f32")],
+                                    [(64, 2, "f32"), (96, 5, "f32"), (33, 3, "bf16")]])
+def test_batch_of_meshes_reduced_precision_bitwise(meshes):
+    """The many-mesh launch in the handles' reduced cycle precision (FP32 or
+    bfloat16 blocks, FP32 vectors; handles of both kinds in one launch): every
+    mesh's result is bit-identical to its own hdg_apply_trace_operator_lp, on the
+    finest and a coarser level."""
+    print(f"case batch lp {meshes}", flush=True)
+    solvers, xs = [], []
+    try:
+        for i, (n, k, prec) in enumerate(meshes):
+            S = H.Solver(n, k, kappa_lognormal(n, 1.0, 50 + i), precision=prec)
+            solvers.append(S)
+            xs.append(torch.tensor(np.random.default_rng(i).standard_normal(S.num_dofs()), dtype=torch.float32,
+                                   device="cuda"))
+        ys = H.apply_batch(solvers, xs, lp=True)
+        for S, x, y, m in zip(solvers, xs, ys, meshes):
+            assert np.array_equal(host(y), host(S.apply_lp(S.k, x))), m
+        lv = [max(0, s.k - 1) for s in solvers]
+        xc = [torch.tensor(np.random.default_rng(10 + i).standard_normal(s.num_dofs(l)), dtype=torch.float32,
+                           device="cuda") for i, (s, l) in enumerate(zip(solvers, lv))]
+        ys = H.apply_batch(solvers, xc, levels=lv, lp=True)
+        for S, l, x, y, m in zip(solvers, lv, xc, ys, meshes):
+            assert np.array_equal(host(y), host(S.apply_lp(l, x))), (m, l)
+    finally:
+        for s in solvers:
+            s.close()
