@@ -196,7 +196,8 @@ hdg_status_t hdg_get_params(hdg_handle_t h, double* omega_out /*[k+1]*/,
 
 /* The chain Schwarz launch shape in use at level p (after autotuning, if any):
  * workgroup size, XCD-aware chain order (0/1), first cyclic-reduction level whose
- * factors are staged in LDS.  Each output pointer may be NULL. */
+ * factors are staged in LDS (64: none, as in the flat schedule).  Each output
+ * pointer may be NULL. */
 hdg_status_t hdg_get_chain_shape(hdg_handle_t h, int32_t p, int32_t* threads, int32_t* remap, int32_t* lds_level);
 
 /* Copy the condensed block of element e at level p (4(p+1) x 4(p+1), row major,

@@ -1799,9 +1799,12 @@ hdg_status_t hdg_get_params(hdg_handle_t h, double* omega_out, double* lmax_out)
 hdg_status_t hdg_get_chain_shape(hdg_handle_t h, int32_t p, int32_t* threads, int32_t* remap, int32_t* lds_level) {
   if (!h || p < 0 || p > h->k) return HDG_ERR_INVALID_ARG;
   const PLevel& L = h->pl[p];
-  if (threads) *threads = L.chain_threads > 0 ? L.chain_threads : hdg::chain_threads(L.P, h->n);
+  const bool flat = hdg::chain_shape_kind(L.P, h->n, L.chain_shape) == HDG_CHAIN_FLAT;
+  if (threads)
+    *threads = L.chain_threads > 0 ? L.chain_threads
+                                   : (flat ? hdg::chain_flat_threads(L.P, h->n) : hdg::chain_threads(L.P, h->n));
   if (remap) *remap = L.chain_remap >= 0 ? L.chain_remap : hdg::chain_remap(L.P);
-  if (lds_level) *lds_level = L.chain_lds_level;
+  if (lds_level) *lds_level = flat ? 64 : L.chain_lds_level;  // the flat schedule stages no factors
   return HDG_OK;
 }
 
