@@ -46,7 +46,7 @@ HBM_PEAK_GBS = 8000.0
 
 WORKLOADS = {
     "lognormal_n256_k4": dict(n=256, k=4, sigma=1.0, seed=2, inner="1:2,0:2"),
-    "lognormal_n1024_k3": dict(n=1024, k=3, sigma=2.0, seed=3, inner="1:3,0:8"),
+    "lognormal_n1024_k3": dict(n=1024, k=3, sigma=2.0, seed=3, inner="2:3,1:3,0:8"),
     "poisson_sin_n16_k1": dict(n=16, k=1, sigma=None, seed=None, inner=""),
     # misfit gradient: theta ~ N(0,1) (seed 5); data U(theta + 0.5 N(0,1) (seed 6)) plus
     # 1% noise (seed 7); each step adds one gradient (forward + adjoint solve) to the solve
