@@ -67,6 +67,8 @@ enum { HDG_MULTI_AUTO = 0, HDG_MULTI_VECTOR = 1, HDG_MULTI_MATRIX = 2 };
 
 /* Launch schedules of the chain Schwarz solve (hdg_config_t.chain_shape). */
 enum { HDG_CHAIN_AUTO = 0, HDG_CHAIN_LEAN = 1, HDG_CHAIN_WIDE = 2, HDG_CHAIN_FLAT = 3 };
+/* Launch schedule of a Q1 level visit (hdg_config_t.q1_schedule). */
+enum { HDG_Q1_FUSED = 0, HDG_Q1_SEPARATE = 1 };
 /* Precision of the multigrid cycle (the preconditioner).  The outer solver, its
  * residuals and the finest-level operator it applies stay FP64 in every mode.
  *   HDG_PREC_F64:  every level, vector and block in FP64 (the paper's setting).
@@ -146,7 +148,12 @@ typedef struct {
                             (WIDE: every row of a position per batch, P = 3 ... 5); FLAT: every
                             factor of a sweep requested at once into registers (P <= 5, while
                             they fit).  Same operations in the same order, identical results. */
-  int32_t reserved[2];
+  int32_t q1_schedule;   /* Q1 level visits of the single-vector cycle: HDG_Q1_FUSED (default)
+                            runs the pre-smoothing steps, residual and restriction of a level as
+                            one launch and the prolongation and post-smoothing as a second, on
+                            tiles with redundant halos (when nu1, nu2 <= 6); HDG_Q1_SEPARATE
+                            launches each step on its own.  Identical results.               */
+  int32_t reserved[1];
 } hdg_config_t;
 
 /* Defaults: tau 1, V(2,2), chain smoother, Galerkin p-levels, omega/lmax estimated,

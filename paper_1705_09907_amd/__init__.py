@@ -26,6 +26,7 @@ MODES = {"pcg": 0, "vcycle": 1, "fcg": 2}
 CYCLES = {"V": 0, "W": 1, "WH": 2}
 MULTI_KERNELS = {"auto": 0, "vector": 1, "matrix": 2}
 CHAIN_SHAPES = {"auto": 0, "lean": 1, "wide": 2, "flat": 3}
+Q1_SCHEDULES = {"fused": 0, "separate": 1}
 PRECISIONS = {"f64": 0, "f32": 1, "bf16": 2}
 STATUS = {0: "ok", -1: "invalid argument", -2: "out of memory", -3: "HIP error",
           -4: "not converged", -5: "non-finite value", -6: "invalid state",
@@ -43,7 +44,8 @@ class Config(ctypes.Structure):
                 ("precision", ctypes.c_int32), ("inner_steps", ctypes.c_int32 * (HDG_MAX_DEGREE + 1)),
                 ("graph", ctypes.c_int32), ("autotune", ctypes.c_int32), ("cycle", ctypes.c_int32),
                 ("multi_kernel", ctypes.c_int32), ("setup_on_host", ctypes.c_int32),
-                ("chain_shape", ctypes.c_int32), ("reserved", ctypes.c_int32 * 2)]
+                ("chain_shape", ctypes.c_int32), ("q1_schedule", ctypes.c_int32),
+                ("reserved", ctypes.c_int32 * 1)]
 
 
 _P = ctypes.c_void_p
@@ -178,7 +180,7 @@ class Solver:
     def __init__(self, n, k, kappa, tau=1.0, nu1=2, nu2=2, smoother="chain", coarse="galerkin",
                  omega=None, cheb_lmax=None, cheb=(0.1, 1.1), coarse_max=2000, nq=None, stream=None,
                  precision="f64", inner=None, graph=False, autotune=False, cycle="V", multi_kernel="auto",
-                 host_setup=False, chain_shape="auto"):
+                 host_setup=False, chain_shape="auto", q1_schedule="fused"):
         import torch
         cfg = Config()
         lib.hdg_config_default(n, k, ctypes.byref(cfg))
@@ -204,6 +206,7 @@ class Solver:
         cfg.multi_kernel = MULTI_KERNELS[multi_kernel]
         cfg.setup_on_host = 1 if host_setup else 0
         cfg.chain_shape = CHAIN_SHAPES[chain_shape]
+        cfg.q1_schedule = Q1_SCHEDULES[q1_schedule]
         self.n, self.k, self.nq, self.precision = n, k, cfg.nq, precision
         kap, kp = _host(kappa, "kappa", n * n)
         if stream is None:

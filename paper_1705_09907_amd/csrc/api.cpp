@@ -641,29 +641,51 @@ void smooth(hdg_ctx* h, int p, const void* b, void* x, int nu, bool zero) {
   }
 }
 
-// Chebyshev on Q1 level Q; result in Q.x.  zero: initial guess 0.
-void chebyshev(hdg_ctx* h, QLevel& Q, const void* b, int nu, bool zero) {
+// Coefficients of the Chebyshev three-term recurrence on [cheb_lo, cheb_hi] x
+// lmax of level Q: step s updates d = c1[s] d + c2[s] Dinv (b - A x), x += d.
+void chebyshev_coeffs(const hdg_ctx* h, const QLevel& Q, int nu, double* c1, double* c2) {
   const double a = h->cfg.cheb_lo * Q.lmax, c = h->cfg.cheb_hi * Q.lmax;
   const double theta = 0.5 * (c + a), delta = 0.5 * (c - a), sigma = theta / delta;
   double rho = 1.0 / sigma;
+  for (int s = 0; s < nu; ++s) {
+    if (s == 0) {
+      c1[s] = 0.0;
+      c2[s] = 1.0 / theta;
+    } else {
+      const double rn = 1.0 / (2.0 * sigma - rho);
+      c1[s] = rn * rho;
+      c2[s] = 2.0 * rn / delta;
+      rho = rn;
+    }
+  }
+}
+
+// Chebyshev on Q1 level Q; result in Q.x.  zero: initial guess 0.
+void chebyshev(hdg_ctx* h, QLevel& Q, const void* b, int nu, bool zero) {
+  std::vector<double> c1(nu), c2(nu);
+  chebyshev_coeffs(h, Q, nu, c1.data(), c2.data());
   void* cur = Q.x;
   void* nxt = Q.t;
   for (int s = 0; s < nu; ++s) {
-    double c1, c2;
-    if (s == 0) {
-      c1 = 0.0;
-      c2 = 1.0 / theta;
-    } else {
-      const double rn = 1.0 / (2.0 * sigma - rho);
-      c1 = rn * rho;
-      c2 = 2.0 * rn / delta;
-      rho = rn;
-    }
     const void* xin = (zero && s == 0) ? nullptr : cur;
-    hipchk(hdg::launch_q1_cheb(h->prec, Q.st, Q.dinv, b, xin, Q.d, nxt, c1, c2, Q.m, h->stream), "chebyshev");
+    hipchk(hdg::launch_q1_cheb(h->prec, Q.st, Q.dinv, b, xin, Q.d, nxt, c1[s], c2[s], Q.m, h->stream), "chebyshev");
     std::swap(cur, nxt);
   }
   if (cur != Q.x) hipchk(hdg::launch_copy(h->prec, cur, Q.x, Q.Nv, h->stream), "copy");
+}
+
+// Arguments of a fused visit of level Q with nu steps (the Q1 kernels' LDS
+// regions hold the level's iterates; x_in, x_out, ec, bc set by the caller).
+hdg::Q1FusedArgs q1_fused_args(const hdg_ctx* h, const QLevel& Q, int nu) {
+  hdg::Q1FusedArgs a;
+  a.st = Q.st;
+  a.dinv = Q.dinv;
+  a.b = Q.b;
+  a.m = Q.m;
+  a.nu = nu;
+  a.tile = hdg::q1_fused_tile(Q.m);
+  chebyshev_coeffs(h, Q, nu, a.c1, a.c2);
+  return a;
 }
 
 // Cycle at Q1 level l for A_l x = b (b in Q.b, x in Q.x); zero: x == 0 on
@@ -675,14 +697,34 @@ void qcycle(hdg_ctx* h, int l, bool zero = true) {
     hipchk(hdg::launch_dense_gemv(pr, Q.inv, Q.b, Q.x, (int)Q.Nv, h->stream), "coarse solve");
     return;
   }
-  chebyshev(h, Q, Q.b, h->cfg.nu1, zero);
-  hipchk(hdg::launch_q1_resid(pr, Q.st, Q.b, Q.x, Q.r, Q.m, h->stream), "q1 resid");
   QLevel& C = h->ql[l + 1];
-  hipchk(hdg::launch_q1_restrict(pr, Q.r, C.b, Q.m, h->stream), "q1 restrict");
+  const bool fused = h->cfg.q1_schedule == HDG_Q1_FUSED && h->cfg.nu1 <= hdg::kQ1MaxNu &&
+                     h->cfg.nu2 <= hdg::kQ1MaxNu;
+  if (fused) {
+    // pre-smoothing, residual and restriction in one launch; the iterate goes
+    // to Q.t (its neighbours' halos still read Q.x), and back to Q.x below
+    hdg::Q1FusedArgs a = q1_fused_args(h, Q, h->cfg.nu1);
+    a.x_in = zero ? nullptr : Q.x;
+    a.x_out = Q.t;
+    a.bc = C.b;
+    hipchk(hdg::launch_q1_pre(pr, a, h->stream), "q1 pre");
+  } else {
+    chebyshev(h, Q, Q.b, h->cfg.nu1, zero);
+    hipchk(hdg::launch_q1_resid(pr, Q.st, Q.b, Q.x, Q.r, Q.m, h->stream), "q1 resid");
+    hipchk(hdg::launch_q1_restrict(pr, Q.r, C.b, Q.m, h->stream), "q1 restrict");
+  }
   qcycle(h, l + 1, true);
   if (h->cfg.cycle != HDG_CYCLE_V && !C.coarsest) qcycle(h, l + 1, false);
-  hipchk(hdg::launch_q1_prolong_add(pr, C.x, Q.x, Q.m, h->stream), "q1 prolong");
-  chebyshev(h, Q, Q.b, h->cfg.nu2, false);
+  if (fused) {
+    hdg::Q1FusedArgs a = q1_fused_args(h, Q, h->cfg.nu2);
+    a.x_in = Q.t;
+    a.ec = C.x;
+    a.x_out = Q.x;
+    hipchk(hdg::launch_q1_post(pr, a, h->stream), "q1 post");
+  } else {
+    hipchk(hdg::launch_q1_prolong_add(pr, C.x, Q.x, Q.m, h->stream), "q1 prolong");
+    chebyshev(h, Q, Q.b, h->cfg.nu2, false);
+  }
 }
 
 void krylov_correction(hdg_ctx* h, int p, void* r, void* e, int m);
@@ -1507,6 +1549,8 @@ void validate_config(const hdg_config_t* c) {
   if (c->setup_on_host != 0 && c->setup_on_host != 1) throw ArgError("setup_on_host must be 0 or 1");
   if (c->chain_shape < HDG_CHAIN_AUTO || c->chain_shape > HDG_CHAIN_FLAT)
     throw ArgError("chain_shape must be HDG_CHAIN_AUTO, _LEAN, _WIDE or _FLAT");
+  if (c->q1_schedule != HDG_Q1_FUSED && c->q1_schedule != HDG_Q1_SEPARATE)
+    throw ArgError("q1_schedule must be HDG_Q1_FUSED or HDG_Q1_SEPARATE");
   if (c->multi_kernel != HDG_MULTI_AUTO && c->multi_kernel != HDG_MULTI_VECTOR && c->multi_kernel != HDG_MULTI_MATRIX)
     throw ArgError("multi_kernel must be HDG_MULTI_AUTO, HDG_MULTI_VECTOR or HDG_MULTI_MATRIX");
   for (int p = 0; p <= HDG_MAX_DEGREE; ++p) {

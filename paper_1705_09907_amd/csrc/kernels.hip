@@ -1807,20 +1807,79 @@ hipError_t launch_chain_solve(Prec pr, int P, const ChainArgs& a, hipStream_t s)
 }
 
 // ------------------------------------------------------------------ Q1 levels
-template <typename T>
-__device__ __forceinline__ T q1_apply(const T* st, const T* x, int m, int64_t Nv, int i, int j, int64_t v) {
+// The per-vertex arithmetic of the Q1 levels is written once, with fused
+// multiply-adds in a fixed order, and shared by the one-operation kernels and
+// the fused level kernels below, whose results are therefore bit-identical.
+//
+// 9-point stencil sum at interior vertex (i, j) (index v): dj outer, di inner;
+// xat(ic, jc) returns x at a clamped (existing) vertex, zeroed here for
+// neighbours outside the interior, so no load sits under a branch (the stencil
+// entries are finite).
+template <typename T, typename XAt>
+__device__ __forceinline__ T q1_stencil_sum(const T* st, int m, int64_t Nv, int i, int j, int64_t v, XAt xat) {
   T s = T(0);
 #pragma unroll
   for (int dj = -1; dj <= 1; ++dj)
 #pragma unroll
     for (int di = -1; di <= 1; ++di) {
-      // neighbours outside the interior read a clamped (existing) vertex and are
-      // zeroed: no load sits under a branch, and the stencil entries are finite
       const int ii = i + di, jj = j + dj;
       const bool ok = ii >= 1 && jj >= 1 && ii <= m - 1 && jj <= m - 1;
       const int ic = min(max(ii, 1), m - 1), jc = min(max(jj, 1), m - 1);
-      const T xv = x[(ic - 1) + (int64_t)(m - 1) * (jc - 1)];
-      s += st[(int64_t)((di + 1) + 3 * (dj + 1)) * Nv + v] * (ok ? xv : T(0));
+      const T xv = xat(ic, jc);
+      s = fma_t(st[(int64_t)((di + 1) + 3 * (dj + 1)) * Nv + v], ok ? xv : T(0), s);
+    }
+  return s;
+}
+
+template <typename T>
+__device__ __forceinline__ T q1_apply(const T* st, const T* x, int m, int64_t Nv, int i, int j, int64_t v) {
+  return q1_stencil_sum(st, m, Nv, i, j, v,
+                        [&](int ic, int jc) { return x[(ic - 1) + (int64_t)(m - 1) * (jc - 1)]; });
+}
+
+// One Chebyshev step at a vertex: z = Dinv (b - A x), d' = c1 d + c2 z (c1 = 0
+// on the first step: d is not read), x' = x + d'.
+template <typename T>
+__device__ __forceinline__ T q1_cheb_dir(T dinv, T b, T ax, T d, double c1, double c2) {
+#pragma clang fp contract(off)
+  const T z = dinv * (b - ax);
+  const T cz = T(c2) * z;
+  return c1 != 0.0 ? fma_t(T(c1), d, cz) : cz;
+}
+
+// Full weighting at coarse vertex (I, J): fine (2I + di, 2J + dj), weight
+// w(di) w(dj), dj outer, di inner (the fine vertices are always interior).
+template <typename T, typename RAt>
+__device__ __forceinline__ T q1_restrict_sum(int I, int J, RAt rat) {
+  T s = T(0);
+#pragma unroll
+  for (int dj = -1; dj <= 1; ++dj)
+#pragma unroll
+    for (int di = -1; di <= 1; ++di) {
+      const T w = T((di == 0 ? 1.0 : 0.5) * (dj == 0 ? 1.0 : 0.5));
+      s = fma_t(w, rat(2 * I + di, 2 * J + dj), s);
+    }
+  return s;
+}
+
+// Bilinear interpolation at fine vertex (I, J) from the 2 x 2 coarse vertices
+// around it: an even index has one parent (the second weight is 0); parents
+// outside the interior read a clamped vertex and are zeroed.
+template <typename T>
+__device__ __forceinline__ T q1_prolong_sum(const T* ec, int mc, int I, int J) {
+  const int xi[2] = {I / 2, I / 2 + (I & 1)}, yi[2] = {J / 2, J / 2 + (J & 1)};
+  const T wx[2] = {(I & 1) ? T(0.5) : T(1), (I & 1) ? T(0.5) : T(0)};
+  const T wy[2] = {(J & 1) ? T(0.5) : T(1), (J & 1) ? T(0.5) : T(0)};
+  T s = T(0);
+#pragma unroll
+  for (int bb = 0; bb < 2; ++bb)
+#pragma unroll
+    for (int aa = 0; aa < 2; ++aa) {
+      const int ci = xi[aa], cj = yi[bb];
+      const bool ok = ci >= 1 && cj >= 1 && ci <= mc - 1 && cj <= mc - 1;
+      const int cic = min(max(ci, 1), mc - 1), cjc = min(max(cj, 1), mc - 1);
+      const T e = ec[((cic - 1) + (int64_t)(mc - 1) * (cjc - 1))];
+      s = fma_t(wx[aa] * wy[bb], ok ? e : T(0), s);
     }
   return s;
 }
@@ -1837,13 +1896,13 @@ __global__ __launch_bounds__(kWG) void k_q1_resid(const T* st, const T* b, const
 template <typename T>
 __global__ __launch_bounds__(kWG) void k_q1_cheb(const T* st, const T* dinv, const T* b, const T* x, T* d, T* xo,
                                                  double c1, double c2, int m) {
+#pragma clang fp contract(off)
   const int64_t Nv = (int64_t)(m - 1) * (m - 1);
   const int64_t v = (int64_t)blockIdx.x * kWG + threadIdx.x;
   if (v >= Nv) return;
   const int i = (int)(v % (m - 1)) + 1, j = (int)(v / (m - 1)) + 1;
   const T ax = x ? q1_apply(st, x, m, Nv, i, j, v) : T(0);
-  const T z = dinv[v] * (b[v] - ax);
-  const T dn = (c1 != 0.0 ? T(c1) * d[v] : T(0)) + T(c2) * z;
+  const T dn = q1_cheb_dir(dinv[v], b[v], ax, c1 != 0.0 ? d[v] : T(0), c1, c2);
   d[v] = dn;
   xo[v] = (x ? x[v] : T(0)) + dn;
 }
@@ -1856,16 +1915,7 @@ __global__ __launch_bounds__(kWG) void k_q1_restrict(const T* rf, T* rc, int mf)
   const int64_t v = (int64_t)blockIdx.x * kWG + threadIdx.x;
   if (v >= Nc) return;
   const int I = (int)(v % (mc - 1)) + 1, J = (int)(v / (mc - 1)) + 1;
-  T s = T(0);
-#pragma unroll
-  for (int dj = -1; dj <= 1; ++dj)
-#pragma unroll
-    for (int di = -1; di <= 1; ++di) {
-      const T w = T((di == 0 ? 1.0 : 0.5) * (dj == 0 ? 1.0 : 0.5));
-      const int fi = 2 * I + di, fj = 2 * J + dj;  // always interior of the fine mesh
-      s += w * rf[(fi - 1) + (int64_t)(mf - 1) * (fj - 1)];
-    }
-  rc[v] = s;
+  rc[v] = q1_restrict_sum<T>(I, J, [&](int fi, int fj) { return rf[(fi - 1) + (int64_t)(mf - 1) * (fj - 1)]; });
 }
 
 template <typename T>
@@ -1875,24 +1925,152 @@ __global__ __launch_bounds__(kWG) void k_q1_prolong_add(const T* ec, T* xf, int 
   const int64_t v = (int64_t)blockIdx.x * kWG + threadIdx.x;
   if (v >= Nf) return;
   const int I = (int)(v % (mf - 1)) + 1, J = (int)(v / (mf - 1)) + 1;
-  // bilinear weights over the 2 x 2 coarse vertices around (I, J): an even index
-  // has one parent (the second weight is 0); parents outside the interior read
-  // a clamped vertex and are zeroed, so no load sits under a branch
-  const int xi[2] = {I / 2, I / 2 + (I & 1)}, yi[2] = {J / 2, J / 2 + (J & 1)};
-  const T wx[2] = {(I & 1) ? T(0.5) : T(1), (I & 1) ? T(0.5) : T(0)};
-  const T wy[2] = {(J & 1) ? T(0.5) : T(1), (J & 1) ? T(0.5) : T(0)};
-  T s = T(0);
-#pragma unroll
-  for (int bb = 0; bb < 2; ++bb)
-#pragma unroll
-    for (int aa = 0; aa < 2; ++aa) {
-      const int ci = xi[aa], cj = yi[bb];
-      const bool ok = ci >= 1 && cj >= 1 && ci <= mc - 1 && cj <= mc - 1;
-      const int cic = min(max(ci, 1), mc - 1), cjc = min(max(cj, 1), mc - 1);
-      const T e = ec[((cic - 1) + (int64_t)(mc - 1) * (cjc - 1))];
-      s += wx[aa] * wy[bb] * (ok ? e : T(0));
-    }
-  xf[v] += s;
+  xf[v] += q1_prolong_sum(ec, mc, I, J);
+}
+
+// Fused level visits of the Q1 hierarchy (Sec. 7: Chebyshev smoothing on the
+// Q1 levels).  One launch does the pre-smoothing steps, the residual and the
+// full-weighting restriction of a level; a second the bilinear prolongation of
+// the coarse correction and the post-smoothing steps.  Each workgroup owns a
+// TS x TS tile of interior vertices and works on the tile grown by a halo
+// (redundantly with its neighbours): a step on the tile grown by h needs the
+// previous iterate on the tile grown by h + 1, so the halo shrinks by one
+// vertex per step and no workgroup waits for another.  The iterates, the
+// Chebyshev directions and the residual live in LDS; only the level's inputs,
+// its new iterate and the restricted residual touch global memory.
+//
+// Region R_h: the tile's vertices [t0 + 1, t0 + TS] in each direction grown by
+// h and clipped to the interior [1, m - 1].  LDS arrays cover the tile grown by
+// the kernel's full halo H, with origin t0 + 1 - H.
+struct Q1Tile {
+  int m;
+  int ti0, tj0;  // first vertex of the tile in each direction
+  int i0, j0;    // origin of the LDS region
+  int RW;        // LDS region width
+  int TS;
+};
+
+// Workgroup -> tile: the tiles of one contiguous band go to one XCD (dispatch
+// deals workgroups to the XCDs round robin), so the halo rows that adjacent
+// tiles share are read through the same L2.
+__device__ __forceinline__ bool q1_tile(int m, int TS, int H, Q1Tile& t) {
+  const int nt = (m - 1 + TS - 1) / TS;
+  const int ntot = nt * nt, per = (ntot + 7) / 8;
+  const int tile = (int)(blockIdx.x % 8) * per + (int)(blockIdx.x / 8);
+  if (tile >= ntot) return false;
+  t.m = m;
+  t.TS = TS;
+  t.ti0 = (tile % nt) * TS + 1;
+  t.tj0 = (tile / nt) * TS + 1;
+  t.i0 = t.ti0 - H;
+  t.j0 = t.tj0 - H;
+  t.RW = TS + 2 * H;
+  return true;
+}
+
+// f(i, j, v, l) for every vertex of R_h: (i, j) the vertex, v its global index,
+// l its LDS index.
+template <typename F>
+__device__ __forceinline__ void q1_for_region(const Q1Tile& t, int h, F f) {
+  const int lo_i = max(1, t.ti0 - h), hi_i = min(t.m - 1, t.ti0 + t.TS - 1 + h);
+  const int lo_j = max(1, t.tj0 - h), hi_j = min(t.m - 1, t.tj0 + t.TS - 1 + h);
+  const int w = hi_i - lo_i + 1, cnt = w * (hi_j - lo_j + 1);
+  for (int q = threadIdx.x; q < cnt; q += kQ1Threads) {
+    const int i = lo_i + q % w, j = lo_j + q / w;
+    f(i, j, (int64_t)(i - 1) + (int64_t)(t.m - 1) * (j - 1), (i - t.i0) + t.RW * (j - t.j0));
+  }
+}
+
+// nu Chebyshev steps in LDS, the last on R_hend (step s on R_{hend + nu - 1 - s});
+// xa holds the iterate on R_{hend + nu} on entry (unread when zero) and the
+// result on exit; xb and dd are work arrays.
+template <typename T>
+__device__ __forceinline__ void q1_cheb_steps(const Q1Tile& t, const T* st, const T* dinv, const T* b, int nu,
+                                              int hend, bool zero, const Q1FusedArgs& a, T*& xa, T*& xb, T* dd) {
+#pragma clang fp contract(off)
+  const int64_t Nv = (int64_t)(t.m - 1) * (t.m - 1);
+  for (int s = 0; s < nu; ++s) {
+    const bool z0 = zero && s == 0;
+    const double c1 = a.c1[s], c2 = a.c2[s];
+    const T* xr = xa;
+    T* xw = xb;
+    q1_for_region(t, hend + nu - 1 - s, [&](int i, int j, int64_t v, int l) {
+      const T ax = z0 ? T(0) : q1_stencil_sum(st, t.m, Nv, i, j, v, [&](int ic, int jc) {
+        return xr[(ic - t.i0) + t.RW * (jc - t.j0)];
+      });
+      const T dn = q1_cheb_dir(dinv[v], b[v], ax, c1 != 0.0 ? dd[l] : T(0), c1, c2);
+      dd[l] = dn;
+      xw[l] = (z0 ? T(0) : xr[l]) + dn;
+    });
+    __syncthreads();
+    xa = xw;
+    xb = const_cast<T*>(xr);
+  }
+}
+
+// Pre-smoothing visit: nu1 steps from x_in (zero when null), x_out = the new
+// iterate, bc = full-weighting restriction of b - A x_out to the coarse level.
+template <typename T>
+__global__ __launch_bounds__(kQ1Threads) void k_q1_pre(Q1FusedArgs a) {
+  extern __shared__ unsigned char lds_raw[];
+  const int m = a.m, nu = a.nu, H = nu + 2;
+  Q1Tile t;
+  if (!q1_tile(m, a.tile, H, t)) return;
+  T* xa = reinterpret_cast<T*>(lds_raw);
+  T* xb = xa + t.RW * t.RW;
+  T* dd = xb + t.RW * t.RW;
+  const T* st = static_cast<const T*>(a.st);
+  const T* dinv = static_cast<const T*>(a.dinv);
+  const T* b = static_cast<const T*>(a.b);
+  const T* xin = static_cast<const T*>(a.x_in);
+  T* xout = static_cast<T*>(a.x_out);
+  const bool zero = xin == nullptr;
+  if (!zero) {
+    q1_for_region(t, H, [&](int, int, int64_t v, int l) { xa[l] = xin[v]; });
+    __syncthreads();
+  }
+  q1_cheb_steps(t, st, dinv, b, nu, 2, zero, a, xa, xb, dd);
+  const int64_t Nv = (int64_t)(m - 1) * (m - 1);
+  q1_for_region(t, 0, [&](int, int, int64_t v, int l) { xout[v] = xa[l]; });
+  q1_for_region(t, 1, [&](int i, int j, int64_t v, int l) {
+    xb[l] = b[v] - q1_stencil_sum(st, m, Nv, i, j, v, [&](int ic, int jc) {
+      return xa[(ic - t.i0) + t.RW * (jc - t.j0)];
+    });
+  });
+  __syncthreads();
+  // coarse vertices (I, J) whose fine vertex (2I, 2J) lies in the tile; their
+  // fine neighbours lie in R_1
+  const int mc = m / 2, hs = t.TS / 2;
+  const int I0 = (t.ti0 + 1) / 2, J0 = (t.tj0 + 1) / 2;
+  const int nI = min(hs, mc - I0), nJ = min(hs, mc - J0);
+  T* bc = static_cast<T*>(a.bc);
+  for (int q = threadIdx.x; q < nI * nJ; q += kQ1Threads) {
+    const int I = I0 + q % nI, J = J0 + q / nI;
+    bc[(I - 1) + (int64_t)(mc - 1) * (J - 1)] =
+        q1_restrict_sum<T>(I, J, [&](int fi, int fj) { return xb[(fi - t.i0) + t.RW * (fj - t.j0)]; });
+  }
+}
+
+// Post-smoothing visit: x = x_in + P e (e the coarse correction in a.ec), then
+// nu2 steps; x_out = the result (x_out != x_in: neighbouring tiles read x_in).
+template <typename T>
+__global__ __launch_bounds__(kQ1Threads) void k_q1_post(Q1FusedArgs a) {
+  extern __shared__ unsigned char lds_raw[];
+  const int m = a.m, nu = a.nu, H = nu;
+  Q1Tile t;
+  if (!q1_tile(m, a.tile, H, t)) return;
+  T* xa = reinterpret_cast<T*>(lds_raw);
+  T* xb = xa + t.RW * t.RW;
+  T* dd = xb + t.RW * t.RW;
+  const T* xin = static_cast<const T*>(a.x_in);
+  const T* ec = static_cast<const T*>(a.ec);
+  const int mc = m / 2;
+  q1_for_region(t, H, [&](int i, int j, int64_t v, int l) { xa[l] = xin[v] + q1_prolong_sum(ec, mc, i, j); });
+  __syncthreads();
+  q1_cheb_steps(t, static_cast<const T*>(a.st), static_cast<const T*>(a.dinv), static_cast<const T*>(a.b), nu, 0,
+                false, a, xa, xb, dd);
+  T* xout = static_cast<T*>(a.x_out);
+  q1_for_region(t, 0, [&](int, int, int64_t v, int l) { xout[v] = xa[l]; });
 }
 
 // P_J^T: vertex (i, j) gathers its four incident interior faces, weight 1/2
@@ -1974,6 +2152,30 @@ hipError_t launch_q1_prolong_add(Prec pr, const void* ec, void* xf, int mf, hipS
                                         0, s, (const TT*)ec, (TT*)xf, mf));
   return hipGetLastError();
 }
+// The largest tile that still gives at least 16 x 16 tiles (one workgroup per
+// CU or more); below that 8 x 8.
+int q1_fused_tile(int m) {
+  if (m - 1 > 15 * 32) return 32;
+  if (m - 1 > 15 * 16) return 16;
+  return 8;
+}
+static hipError_t launch_q1_fused(Prec pr, bool pre, const Q1FusedArgs& a, hipStream_t s) {
+  if (a.nu < 1 || a.nu > kQ1MaxNu || (a.m % 2) != 0 || a.m < 4 || (a.tile != 8 && a.tile != 16 && a.tile != 32) ||
+      a.c1[0] != 0.0 || !a.st || !a.dinv || !a.b || !a.x_out || (pre ? !a.bc : (!a.x_in || !a.ec)) ||
+      a.x_in == a.x_out)
+    return hipErrorInvalidValue;
+  const int H = pre ? a.nu + 2 : a.nu, RW = a.tile + 2 * H;
+  const int nt = (a.m - 1 + a.tile - 1) / a.tile, per = (nt * nt + 7) / 8;
+  const size_t lds = (size_t)3 * RW * RW * (pr == Prec::F64 ? sizeof(double) : sizeof(float));
+  if (pre) {
+    HDG_DISPATCH_T(pr, hipLaunchKernelGGL(k_q1_pre<TT>, dim3(8 * per), dim3(kQ1Threads), lds, s, a));
+  } else {
+    HDG_DISPATCH_T(pr, hipLaunchKernelGGL(k_q1_post<TT>, dim3(8 * per), dim3(kQ1Threads), lds, s, a));
+  }
+  return hipGetLastError();
+}
+hipError_t launch_q1_pre(Prec pr, const Q1FusedArgs& a, hipStream_t s) { return launch_q1_fused(pr, true, a, s); }
+hipError_t launch_q1_post(Prec pr, const Q1FusedArgs& a, hipStream_t s) { return launch_q1_fused(pr, false, a, s); }
 hipError_t launch_pj_restrict(Prec pr, const void* rface, void* rv, int n, hipStream_t s) {
   HDG_DISPATCH_T(pr, hipLaunchKernelGGL(k_pj_restrict<TT>, grid_for((int64_t)(n - 1) * (n - 1)), dim3(kWG), 0, s,
                                         (const TT*)rface, (TT*)rv, n));

@@ -138,6 +138,31 @@ hipError_t launch_q1_cheb(Prec pr, const void* st, const void* dinv, const void*
                           void* d, void* xo, double c1, double c2, int m, hipStream_t s);
 hipError_t launch_q1_restrict(Prec pr, const void* rf, void* rc, int m_fine, hipStream_t s);
 hipError_t launch_q1_prolong_add(Prec pr, const void* ec, void* xf, int m_fine, hipStream_t s);
+
+// Fused Q1 level visits: launch_q1_pre does nu Chebyshev steps from x_in (null:
+// zero), writes the iterate to x_out and the restricted residual to bc;
+// launch_q1_post adds the prolonged coarse correction ec to x_in, does nu steps
+// and writes x_out.  x_out must not alias x_in.  m even, 1 <= nu <= kQ1MaxNu,
+// tile from q1_fused_tile(m).  Same arithmetic as the one-operation kernels.
+constexpr int kQ1MaxNu = 6;
+constexpr int kQ1Threads = 256;
+struct Q1FusedArgs {
+  const void* st = nullptr;
+  const void* dinv = nullptr;
+  const void* b = nullptr;
+  const void* x_in = nullptr;
+  void* x_out = nullptr;
+  const void* ec = nullptr;
+  void* bc = nullptr;
+  int m = 0;
+  int nu = 0;
+  int tile = 0;
+  double c1[kQ1MaxNu] = {};
+  double c2[kQ1MaxNu] = {};
+};
+int q1_fused_tile(int m);
+hipError_t launch_q1_pre(Prec pr, const Q1FusedArgs& a, hipStream_t s);
+hipError_t launch_q1_post(Prec pr, const Q1FusedArgs& a, hipStream_t s);
 // p = 0 faces <-> Q1 vertices of the same mesh
 hipError_t launch_pj_restrict(Prec pr, const void* rface, void* rv, int n, hipStream_t s);
 hipError_t launch_pj_prolong_add(Prec pr, const void* ev, void* xface, int n, hipStream_t s);
