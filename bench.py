@@ -232,6 +232,24 @@ def pmc_summary(fetch_db, write_db, kernel, calib=None):
                       f"WRITE_MB={wm * 1024 / 1e6:.2f}")
 
 
+def solve_only(args, S, b, N, dev):
+    """Warm-up + timed solves of the workload, nothing else (kernel traces of the solve)."""
+    import torch
+    lam = torch.zeros(N, dtype=torch.float64, device=dev)
+    ms = []
+    for s in range(args.warmup + args.steps):
+        lam.zero_()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        _, it, rr, _ = S.solve(b, lam, rtol=1e-10, maxit=500, mode=args.mode, raise_on_fail=False)
+        e1.record()
+        torch.cuda.synchronize()
+        if s >= args.warmup:
+            ms.append(e0.elapsed_time(e1))
+    print(json.dumps({"workload": args.workload, "solve_only": True, "q1_schedule": args.q1_schedule,
+                      "solve_ms": sum(ms) / len(ms), "solve_iters": it, "solve_relres": rr}))
+
+
 def apply_only(args, S, n, k, dev):
     """Cold applies of the finest level only (each after a 1 GiB cache flush),
     then optionally the 256 MiB calibration copy; one JSON line."""
@@ -347,6 +365,11 @@ def main():
                          "passes of the chain kernels")
     ap.add_argument("--chain-shape", default="auto", choices=["auto", "lean", "wide", "flat"],
                     help="chain solve schedule of the handle (with --chain-level)")
+    ap.add_argument("--solve-only", action="store_true",
+                    help="only the workload's solves (warm-up + steps) after set-up: a short run for kernel "
+                         "traces of one solve; prints the solve timing")
+    ap.add_argument("--q1-schedule", default="fused", choices=["fused", "separate"],
+                    help="Q1 level visits of the handle: fused launches or one launch per step")
     ap.add_argument("--apply-only", action="store_true",
                     help="only the cold applies of the workload (warm-up + steps) and, with --calibrate-copy, "
                          "the copy: a short run for counter passes; prints the apply timing")
@@ -378,7 +401,7 @@ def main():
     t0 = time.perf_counter()
     short = args.apply_only or args.chain_level is not None
     S = H.Solver(n, k, kap, smoother=args.smoother, precision=args.precision, inner=inner,
-                 autotune=not short, chain_shape=args.chain_shape)
+                 autotune=not short, chain_shape=args.chain_shape, q1_schedule=args.q1_schedule)
     torch.cuda.synchronize()
     setup_s = time.perf_counter() - t0
     if args.apply_only:
@@ -400,6 +423,9 @@ def main():
     t0 = time.perf_counter()
     b = S.assemble_rhs(np.ones((n * n, nq * nq)))
     rhs_s = time.perf_counter() - t0
+    if args.solve_only:
+        solve_only(args, S, b, N, dev)
+        return
     x = torch.tensor(normal_vector(N, 7), device=dev)
     if lp:
         x = x.float()

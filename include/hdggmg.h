@@ -66,7 +66,7 @@ enum { HDG_CYCLE_V = 0, HDG_CYCLE_W = 1, HDG_CYCLE_WH = 2 };
 enum { HDG_MULTI_AUTO = 0, HDG_MULTI_VECTOR = 1, HDG_MULTI_MATRIX = 2 };
 
 /* Launch schedules of the chain Schwarz solve (hdg_config_t.chain_shape). */
-enum { HDG_CHAIN_AUTO = 0, HDG_CHAIN_LEAN = 1, HDG_CHAIN_WIDE = 2, HDG_CHAIN_FLAT = 3 };
+enum { HDG_CHAIN_AUTO = 0, HDG_CHAIN_LEAN = 1, HDG_CHAIN_WIDE = 2, HDG_CHAIN_FLAT = 3, HDG_CHAIN_TRI = 4 };
 /* Launch schedule of a Q1 level visit (hdg_config_t.q1_schedule). */
 enum { HDG_Q1_FUSED = 0, HDG_Q1_SEPARATE = 1 };
 /* Precision of the multigrid cycle (the preconditioner).  The outer solver, its
@@ -147,7 +147,11 @@ typedef struct {
                             LEAN / WIDE: factors fetched level by level in register batches
                             (WIDE: every row of a position per batch, P = 3 ... 5); FLAT: every
                             factor of a sweep requested at once into registers (P <= 5, while
-                            they fit).  Same operations in the same order, identical results. */
+                            they fit).  These three run the block cyclic reduction with the
+                            same operations in the same order: identical results.  TRI (the
+                            default at P = 1 for 5 <= n <= 2049, ignored at other P): the
+                            partitioned tridiagonal solve, one wavefront per chain, one chain
+                            segment per lane; the same chain solve up to rounding.          */
   int32_t q1_schedule;   /* Q1 level visits of the single-vector cycle: HDG_Q1_FUSED (default)
                             runs the pre-smoothing steps, residual and restriction of a level as
                             one launch and the prolongation and post-smoothing as a second, on
@@ -202,9 +206,10 @@ hdg_status_t hdg_get_params(hdg_handle_t h, double* omega_out /*[k+1]*/,
                             double* lmax_out /*[num_hlevels]*/);
 
 /* The chain Schwarz launch shape in use at level p (after autotuning, if any):
- * workgroup size, XCD-aware chain order (0/1), first cyclic-reduction level whose
- * factors are staged in LDS (64: none, as in the flat schedule).  Each output
- * pointer may be NULL. */
+ * workgroup size (partitioned solve: 64 x chains per workgroup), XCD-aware chain
+ * order (0/1), first cyclic-reduction level whose factors are staged in LDS (64:
+ * none, as in the flat and partitioned schedules).  Each output pointer may be
+ * NULL. */
 hdg_status_t hdg_get_chain_shape(hdg_handle_t h, int32_t p, int32_t* threads, int32_t* remap, int32_t* lds_level);
 
 /* Copy the condensed block of element e at level p (4(p+1) x 4(p+1), row major,

@@ -25,7 +25,7 @@ COARSE = {"galerkin": 0, "rediscretize": 1}
 MODES = {"pcg": 0, "vcycle": 1, "fcg": 2}
 CYCLES = {"V": 0, "W": 1, "WH": 2}
 MULTI_KERNELS = {"auto": 0, "vector": 1, "matrix": 2}
-CHAIN_SHAPES = {"auto": 0, "lean": 1, "wide": 2, "flat": 3}
+CHAIN_SHAPES = {"auto": 0, "lean": 1, "wide": 2, "flat": 3, "tri": 4}
 Q1_SCHEDULES = {"fused": 0, "separate": 1}
 PRECISIONS = {"f64": 0, "f32": 1, "bf16": 2}
 STATUS = {0: "ok", -1: "invalid argument", -2: "out of memory", -3: "HIP error",

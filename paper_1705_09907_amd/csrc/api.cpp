@@ -34,6 +34,7 @@ struct PLevel {
   double* slab64 = nullptr;
   void* dinv = nullptr;                                           // facet Schwarz
   void* chain = nullptr;                                          // chain Schwarz factors
+  void* tri = nullptr;                                            // P = 1: partitioned chain solve factors
   void* pslab = nullptr;                                          // element-patch Schwarz inverses (slab layout)
   int64_t cstride = 0;
   void* pmat = nullptr;                                           // P_p (p >= 1)
@@ -416,6 +417,28 @@ void build_face_data(hdg_ctx* h, PLevel& L, const Vec& blocks) {
     }
   });
   L.chain = upload_vec(h, fac);
+  if (P == 1 && hdg::chain_tri_lmax(n) > 0) {
+    // the partitioned solve's factors come from the same device routine as in
+    // the device set-up, on a temporary copy of these blocks
+    L.tri = valloc(h, nch * hdg::chain_tri_stride(n));
+    void* tmp = nullptr;
+    const size_t eb_bytes = blocks.size() * sizeof(double);
+    if (hipMalloc(&tmp, eb_bytes + 256) != hipSuccess) {
+      (void)hipGetLastError();
+      throw std::bad_alloc();
+    }
+    int* dfail = reinterpret_cast<int*>(static_cast<char*>(tmp) + eb_bytes);
+    int failed = 0;
+    hipError_t e = hipMemcpy(tmp, blocks.data(), eb_bytes, hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = hipMemset(dfail, 0, sizeof(int));
+    if (e == hipSuccess)
+      e = hdg::launch_chain_tri_factor(h->prec, static_cast<const double*>(tmp), n, L.tri, dfail, h->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(h->stream);
+    if (e == hipSuccess) e = hipMemcpy(&failed, dfail, sizeof(int), hipMemcpyDeviceToHost);
+    (void)hipFree(tmp);
+    hipchk(e, "partitioned chain factors");
+    if (failed) throw std::runtime_error("a chain pivot is not positive");
+  }
   // stage the small levels' factors in LDS: at most 8 KiB beside the chain
   const size_t es = hdg::vec_bytes(h->prec);
   const int64_t rhs_bytes = (int64_t)(n - 1) * P * (int64_t)es;
@@ -624,6 +647,7 @@ void smooth(hdg_ctx* h, int p, const void* b, void* x, int nu, bool zero) {
       c.shape = L.chain_shape;
       c.remap = L.chain_remap >= 0 ? L.chain_remap : hdg::chain_remap(L.P);
       c.factors = L.chain;
+      c.tri = L.tri;
       c.cstride = L.cstride;
       c.omega = L.omega;
       c.n = h->n;
@@ -1125,6 +1149,10 @@ void device_levels(hdg_ctx* h, SetupClock& clk, bool update) {
       for (int64_t c0 = 0; c0 < nch; c0 += batch)
         hipchk(hdg::launch_chain_factor(h->prec, P, EBcur, n, c0, (int)std::min<int64_t>(batch, nch - c0), work,
                                         L.chain, L.cstride, fail, s), "chain factors");
+      if (P == 1 && hdg::chain_tri_lmax(n) > 0) {
+        if (!update) L.tri = valloc(h, nch * hdg::chain_tri_stride(n));
+        hipchk(hdg::launch_chain_tri_factor(h->prec, EBcur, n, L.tri, fail, s), "partitioned chain factors");
+      }
     }
     clk.mark("face data and smoother factors p=" + std::to_string(p));
     if (p == 0) {
@@ -1209,6 +1237,45 @@ void tune_chain(hdg_ctx* h, int p) {
   float best = 1e30f;
   int bt = 0, br = -1, bl = lds_default, bw = L.chain_shape;
   const bool log = std::getenv("HDG_TUNE_LOG") != nullptr;  // a diagnostic: every candidate's time
+  if (hdg::chain_shape_kind(L.P, h->n, h->cfg.chain_shape) == HDG_CHAIN_TRI) {
+    // the partitioned solve (P = 1): chains per workgroup only, timed as the
+    // smoother runs it after the first sweep (iterate staged with the residual)
+    hipchk(hdg::launch_zero(pr, L.t, L.N, h->stream), "zero");
+    for (int g : {1, 2, 4, 8}) {
+      hdg::ChainArgs c{};
+      c.lds_cap = h->lds_cap;
+      c.shape = HDG_CHAIN_TRI;
+      c.tri = L.tri;
+      c.omega = L.omega;
+      c.n = h->n;
+      c.r = L.r;
+      c.x = L.t;
+      c.out = L.t;
+      c.threads = 64 * g;
+      if (hdg::launch_chain_solve(pr, L.P, c, h->stream) != hipSuccess) {
+        (void)hipGetLastError();
+        continue;
+      }
+      float t = 1e30f;
+      for (int rep = 0; rep < 3; ++rep) {
+        hipchk(hipEventRecord(e0, h->stream), "event");
+        hipchk(hdg::launch_chain_solve(pr, L.P, c, h->stream), "chain tune");
+        hipchk(hipEventRecord(e1, h->stream), "event");
+        hipchk(hipEventSynchronize(e1), "event sync");
+        float ms = 0.f;
+        hipchk(hipEventElapsedTime(&ms, e0, e1), "elapsed");
+        t = std::min(t, ms);
+      }
+      if (log) std::fprintf(stderr, "chain tune p=%d shape=partitioned chains/workgroup=%d: %.2f us\n", p, g, 1e3 * t);
+      if (t < best) {
+        best = t;
+        bt = 64 * g;
+      }
+    }
+    L.chain_threads = bt;
+    L.chain_shape = HDG_CHAIN_TRI;
+    return;
+  }
   for (int wd : {1, 2, 3})
   for (int th : {64, 128, 256, 512, 1024}) {
     if (h->cfg.chain_shape != HDG_CHAIN_AUTO && wd != h->cfg.chain_shape) continue;  // the caller's schedule
@@ -1221,6 +1288,7 @@ void tune_chain(hdg_ctx* h, int p) {
         c.lds_cap = h->lds_cap;
         c.shape = wd;
         c.factors = L.chain;
+        c.tri = L.tri;
         c.cstride = L.cstride;
         c.omega = L.omega;
         c.n = h->n;
@@ -1547,8 +1615,8 @@ void validate_config(const hdg_config_t* c) {
   if (c->cycle != HDG_CYCLE_V && c->cycle != HDG_CYCLE_W && c->cycle != HDG_CYCLE_WH)
     throw ArgError("cycle must be HDG_CYCLE_V, HDG_CYCLE_W or HDG_CYCLE_WH");
   if (c->setup_on_host != 0 && c->setup_on_host != 1) throw ArgError("setup_on_host must be 0 or 1");
-  if (c->chain_shape < HDG_CHAIN_AUTO || c->chain_shape > HDG_CHAIN_FLAT)
-    throw ArgError("chain_shape must be HDG_CHAIN_AUTO, _LEAN, _WIDE or _FLAT");
+  if (c->chain_shape < HDG_CHAIN_AUTO || c->chain_shape > HDG_CHAIN_TRI)
+    throw ArgError("chain_shape must be HDG_CHAIN_AUTO, _LEAN, _WIDE, _FLAT or _TRI");
   if (c->q1_schedule != HDG_Q1_FUSED && c->q1_schedule != HDG_Q1_SEPARATE)
     throw ArgError("q1_schedule must be HDG_Q1_FUSED or HDG_Q1_SEPARATE");
   if (c->multi_kernel != HDG_MULTI_AUTO && c->multi_kernel != HDG_MULTI_VECTOR && c->multi_kernel != HDG_MULTI_MATRIX)
@@ -1843,12 +1911,14 @@ hdg_status_t hdg_get_params(hdg_handle_t h, double* omega_out, double* lmax_out)
 hdg_status_t hdg_get_chain_shape(hdg_handle_t h, int32_t p, int32_t* threads, int32_t* remap, int32_t* lds_level) {
   if (!h || p < 0 || p > h->k) return HDG_ERR_INVALID_ARG;
   const PLevel& L = h->pl[p];
-  const bool flat = hdg::chain_shape_kind(L.P, h->n, L.chain_shape) == HDG_CHAIN_FLAT;
+  const int kind = hdg::chain_shape_kind(L.P, h->n, L.chain_shape);
+  const bool flat = kind == HDG_CHAIN_FLAT, tri = kind == HDG_CHAIN_TRI;
   if (threads)
-    *threads = L.chain_threads > 0 ? L.chain_threads
-                                   : (flat ? hdg::chain_flat_threads(L.P, h->n) : hdg::chain_threads(L.P, h->n));
-  if (remap) *remap = L.chain_remap >= 0 ? L.chain_remap : hdg::chain_remap(L.P);
-  if (lds_level) *lds_level = flat ? 64 : L.chain_lds_level;  // the flat schedule stages no factors
+    *threads = L.chain_threads > 0
+                   ? L.chain_threads
+                   : (tri ? 256 : (flat ? hdg::chain_flat_threads(L.P, h->n) : hdg::chain_threads(L.P, h->n)));
+  if (remap) *remap = tri ? 0 : (L.chain_remap >= 0 ? L.chain_remap : hdg::chain_remap(L.P));
+  if (lds_level) *lds_level = flat || tri ? 64 : L.chain_lds_level;  // these schedules stage no factors
   return HDG_OK;
 }
 

@@ -1732,6 +1732,8 @@ int chain_flat_threads(int P, int n) {
 int chain_shape_kind(int P, int n, int shape) {
   const int th = chain_flat_threads(P, n);
   const bool flat_ok = th > 0;
+  const bool tri_ok = P == 1 && chain_tri_lmax(n) > 0;
+  if ((shape == 4 || shape == 0) && tri_ok) return 4;  // P = 1: the partitioned solve by default
   if (shape == 3 && flat_ok) return 3;  // else as chosen below
   if (shape == 2) return P >= 3 && P <= 5 ? 2 : 1;
   if (shape == 1) return 1;
@@ -1780,10 +1782,179 @@ static hipError_t launch_chain_t(const ChainArgs& a, int64_t nch, int threads, s
   return hipGetLastError();
 }
 
+// ------------------------------------------ partitioned chain solve (P = 1)
+// One wavefront per chain; lane k owns segment k (positions o .. o + L - 1, L
+// >= 2) of the scalar tridiagonal chain matrix and keeps it in registers:
+//  1. the segment interior is solved for the right-hand side with the stored
+//     elimination (ch, ip): its end values y_1, y_{L-2} give the right-hand
+//     sides gF, gL of the segment's first and last rows in the tridiagonal
+//     system that remains on the segment ends;
+//  2. eliminating the first ends (one shuffle) leaves one row per lane, solved
+//     by parallel cyclic reduction across the lanes (6 levels of shuffles with
+//     stored multipliers): the last ends x_l, then the first ends x_o;
+//  3. the interior is solved again with x_o and x_l moved to its right-hand side.
+// No barrier inside the solve; a workgroup of G wavefronts (G chains) stages the
+// right-hand sides and the results in LDS so that global memory is accessed
+// along the faces' storage order: a vertical chain's faces are consecutive, a
+// horizontal chain's are n apart and G adjacent chains share each 8 G-byte run.
+__device__ __forceinline__ int tri_pad(int i) { return i + (i >> 4); }
+
+template <typename T, int LMAX>
+__global__ __launch_bounds__(512) void k_chain_tri(ChainArgs a) {
+  extern __shared__ unsigned char lds_raw[];
+  const int n = a.n, m = n - 1;
+  const int G = (int)(blockDim.x >> 6);
+  const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int nvw = (n + G - 1) / G;
+  const bool vert = (int)blockIdx.x < nvw;
+  const int c0 = vert ? G * (int)blockIdx.x : n + G * ((int)blockIdx.x - nvw);
+  const int cend = vert ? n : 2 * n;
+  const int c = c0 + w;
+  const bool act = c < cend;
+  const int ld = m + (m >> 4) + 1;
+  T* buf = reinterpret_cast<T*>(lds_raw);
+  T* mine = buf + w * ld;
+  const T* r = static_cast<const T*>(a.r);
+  const T* xin = static_cast<const T*>(a.x);
+  T* out = static_cast<T*>(a.out);
+  const int64_t nv = (int64_t)n * m;
+  const T* rec = static_cast<const T*>(a.tri) + (int64_t)(act ? c : c0) * ((2 * LMAX + kTriScalars) * 64);
+  const int nseg = min(64, m / 2), base = m / nseg, extra = m % nseg;
+  const int L = lane < nseg ? base + (lane < extra ? 1 : 0) : 0;
+  const int o = lane * base + min(lane, extra);
+  // the lane's factors first, then the right-hand sides into LDS
+  T ch[LMAX], ip[LMAX], sc[kTriScalars];
+  ch[0] = ip[0] = ch[LMAX - 1] = ip[LMAX - 1] = T(0);
+#pragma unroll
+  for (int j = 1; j < LMAX - 1; ++j) {
+    ch[j] = rec[j * 64 + lane];
+    ip[j] = rec[(LMAX + j) * 64 + lane];
+  }
+#pragma unroll
+  for (int q = 0; q < kTriScalars; ++q) sc[q] = rec[(2 * LMAX + q) * 64 + lane];
+  // The faces this thread stages and writes: positions pos0 + 64 t (t < LMAX,
+  // which covers m <= 64 LMAX) of one chain; vertical: the wavefront's own chain
+  // (pos0 = lane), horizontal: chain tid mod G of the G (pos0 = tid / G), so that
+  // G consecutive threads touch G adjacent faces.  Position pos0 + 64 t is face
+  // f0 + df t and LDS slot s0 + 68 t (tri_pad adds one slot per 16 positions).
+  const int w2 = vert ? w : (int)threadIdx.x % G;
+  const int pos0 = vert ? lane : (int)threadIdx.x / G;
+  const bool own = vert ? act : c0 + w2 < cend;
+  const int64_t f0 = vert ? (int64_t)m * c + lane : nv + (c0 - n + w2) + (int64_t)n * pos0;
+  const int64_t df = vert ? 64 : 64 * (int64_t)n;
+  const int s0 = w2 * ld + pos0 + (pos0 >> 4);
+  // the iterate is requested first, so that its round trip overlaps the
+  // right-hand side's and the factors' (while the registers allow)
+  constexpr bool XPRE = LMAX * sizeof(T) <= 128;
+  T xr[LMAX];
+  if (XPRE && xin) {
+#pragma unroll
+    for (int t = 0; t < LMAX; ++t) xr[t] = own && pos0 + 64 * t < m ? xin[f0 + df * t] : T(0);
+  }
+#pragma unroll
+  for (int t = 0; t < LMAX; ++t)
+    if (own && pos0 + 64 * t < m) buf[s0 + 68 * t] = r[f0 + df * t];
+  __syncthreads();
+  // 1. interior solve (slots outside the interior hold ch = ip = 0); only the
+  //    end values of the backward sweep are kept
+  const T r0 = L > 0 ? mine[tri_pad(o)] : T(0);
+  T u[LMAX], rl = r0;
+  u[0] = T(0);
+#pragma unroll
+  for (int j = 1; j < LMAX; ++j) {
+    const T rj = j < L ? mine[tri_pad(o + j)] : T(0);
+    u[j] = fma_t(-ch[j - 1], u[j - 1], rj);
+    rl = j == L - 1 ? rj : rl;
+  }
+  T yn = T(0), y1 = T(0), yl = T(0);
+#pragma unroll
+  for (int j = LMAX - 2; j >= 1; --j) {
+    yn = fma_t(-ch[j], yn, u[j] * ip[j]);
+    yl = j == L - 2 ? yn : yl;
+    y1 = yn;
+  }
+  // 2. the segment ends
+  const T gF = fma_t(-sc[0], y1, r0);
+  const T gL = fma_t(-sc[1], yl, rl);
+  const T gF1 = __shfl_down(gF, 1, 64);
+  T g = fma_t(-sc[3], gF1, fma_t(-sc[2], gF, gL));
+#pragma unroll
+  for (int h = 0; h < 6; ++h) {
+    const T gm = __shfl_up(g, 1 << h, 64), gp = __shfl_down(g, 1 << h, 64);
+    g = fma_t(-sc[8 + 2 * h], gp, fma_t(-sc[7 + 2 * h], gm, g));
+  }
+  const T xL = g * sc[19];
+  const T xLm = __shfl_up(xL, 1, 64);
+  const T xF = fma_t(-sc[6], xL, fma_t(-sc[5], xLm, gF)) * sc[4];
+  // 3. interior with the ends known: the forward sweep is linear, so x_o enters
+  //    as x_o phi_j (phi_1 = -E_o, phi_{j+1} = -ch_j phi_j) and x_l at the last
+  //    interior position; then the backward sweep in place
+  T phi = -sc[0];
+#pragma unroll
+  for (int j = 1; j < LMAX; ++j) {
+    u[j] = fma_t(xF, phi, u[j]);
+    u[j] = j == L - 2 ? fma_t(-sc[1], xL, u[j]) : u[j];
+    phi = -ch[j] * phi;
+  }
+  u[LMAX - 1] = T(0);
+#pragma unroll
+  for (int j = LMAX - 2; j >= 1; --j) u[j] = fma_t(-ch[j], u[j + 1], u[j] * ip[j]);
+#pragma unroll
+  for (int j = 0; j < LMAX; ++j)
+    if (j < L) mine[tri_pad(o + j)] = j == 0 ? xF : (j == L - 1 ? xL : u[j]);
+  __syncthreads();
+  const T om = T(a.omega);
+#pragma unroll
+  for (int t = 0; t < LMAX; ++t)
+    if (own && pos0 + 64 * t < m)
+      out[f0 + df * t] = (xin ? (XPRE ? xr[t] : xin[f0 + df * t]) : T(0)) + om * buf[s0 + 68 * t];
+}
+
+int chain_tri_lmax(int n) {
+  const int m = n - 1;
+  if (m < 4) return 0;
+  const int nseg = std::min(64, m / 2);
+  const int lmax = (m + nseg - 1) / nseg;
+  for (int b : {4, 8, 16, 32})
+    if (lmax <= b) return b;
+  return 0;
+}
+int64_t chain_tri_stride(int n) { return (int64_t)(2 * chain_tri_lmax(n) + kTriScalars) * 64; }
+size_t chain_tri_lds_bytes(int n, int G, size_t es) {
+  const int m = n - 1;
+  return (size_t)G * (m + (m >> 4) + 1) * es;
+}
+
+template <typename T, int LMAX>
+static hipError_t launch_chain_tri_t(const ChainArgs& a, int G, hipStream_t s) {
+  const size_t lds = chain_tri_lds_bytes(a.n, G, sizeof(T));
+  if ((int64_t)lds > (a.lds_cap > 0 ? a.lds_cap : 65536)) return hipErrorInvalidValue;
+  if (lds > 65536 && hipFuncSetAttribute(reinterpret_cast<const void*>(&k_chain_tri<T, LMAX>),
+                                         hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds) != hipSuccess)
+    return hipErrorInvalidValue;
+  const int nvw = (a.n + G - 1) / G;
+  hipLaunchKernelGGL((k_chain_tri<T, LMAX>), dim3((unsigned)(2 * nvw)), dim3(64 * G), lds, s, a);
+  return hipGetLastError();
+}
+
+template <typename T>
+static hipError_t launch_chain_tri(const ChainArgs& a, hipStream_t s) {
+  const int G = a.threads > 0 ? a.threads / 64 : 4;
+  if (a.threads % 64 || G < 1 || G > 8 || !a.tri) return hipErrorInvalidValue;
+  switch (chain_tri_lmax(a.n)) {
+    case 4: return launch_chain_tri_t<T, 4>(a, G, s);
+    case 8: return launch_chain_tri_t<T, 8>(a, G, s);
+    case 16: return launch_chain_tri_t<T, 16>(a, G, s);
+    case 32: return launch_chain_tri_t<T, 32>(a, G, s);
+    default: return hipErrorInvalidValue;
+  }
+}
+
 hipError_t launch_chain_solve(Prec pr, int P, const ChainArgs& a, hipStream_t s) {
   const int64_t nch = 2LL * a.n;
   const int kind = chain_shape_kind(P, a.n, a.shape);
   if (kind == 0) return hipErrorInvalidValue;
+  if (kind == 4) return pr == Prec::F64 ? launch_chain_tri<double>(a, s) : launch_chain_tri<float>(a, s);
   if (kind == 3) {
     const int threads = a.threads > 0 ? a.threads : chain_flat_threads(P, a.n);
     if (threads % 64 || threads > 1024) return hipErrorInvalidValue;
@@ -2113,14 +2284,24 @@ __global__ __launch_bounds__(kWG) void k_pj_prolong_add(const T* ev, T* xface, i
   xface[f] += T(0.5) * s;
 }
 
-// one wavefront per row, lanes stride the columns, fixed shuffle-tree sum (FP64)
+// one wavefront per row, lanes stride the columns with four independent
+// partial sums (four loads in flight per lane), fixed shuffle-tree sum (FP64)
 template <typename T>
 __global__ __launch_bounds__(kWG) void k_dense_gemv(const double* A, const T* b, T* y, int m) {
   const int row = blockIdx.x * (kWG / 64) + (threadIdx.x >> 6);
   const int lane = threadIdx.x & 63;
   if (row >= m) return;
-  double s = 0.0;
-  for (int c = lane; c < m; c += 64) s += A[(int64_t)row * m + c] * (double)b[c];
+  const double* Ar = A + (int64_t)row * m;
+  double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
+  int c = lane;
+  for (; c + 192 < m; c += 256) {
+    s0 = fma(Ar[c], (double)b[c], s0);
+    s1 = fma(Ar[c + 64], (double)b[c + 64], s1);
+    s2 = fma(Ar[c + 128], (double)b[c + 128], s2);
+    s3 = fma(Ar[c + 192], (double)b[c + 192], s3);
+  }
+  for (; c < m; c += 64) s0 = fma(Ar[c], (double)b[c], s0);
+  double s = (s0 + s1) + (s2 + s3);
   for (int off = 32; off >= 1; off >>= 1) s += __shfl_xor(s, off, 64);
   if (lane == 0) y[row] = T(s);
 }
@@ -2152,11 +2333,12 @@ hipError_t launch_q1_prolong_add(Prec pr, const void* ec, void* xf, int mf, hipS
                                         0, s, (const TT*)ec, (TT*)xf, mf));
   return hipGetLastError();
 }
-// The largest tile that still gives at least 16 x 16 tiles (one workgroup per
-// CU or more); below that 8 x 8.
+// The largest tile that still gives at least 32 x 32 tiles (four workgroups
+// per CU: a workgroup's phases are a chain of memory round trips, which other
+// resident workgroups hide); below that 8 x 8.
 int q1_fused_tile(int m) {
-  if (m - 1 > 15 * 32) return 32;
-  if (m - 1 > 15 * 16) return 16;
+  if (m - 1 > 31 * 32) return 32;
+  if (m - 1 > 31 * 16) return 16;
   return 8;
 }
 static hipError_t launch_q1_fused(Prec pr, bool pre, const Q1FusedArgs& a, hipStream_t s) {

@@ -114,7 +114,8 @@ struct ChainArgs {
   int lds_level;        // factors of levels >= lds_level are staged in LDS (chain_lds_level)
   int remap;            // 1: XCD-aware chain order (consecutive chains on one XCD)
   int64_t lds_cap;      // LDS bytes a workgroup may use on this device (0: 64 KiB)
-  int shape;            // 0 by the mesh, 1 lean, 2 wide, 3 flat (chain_shape_kind)
+  int shape;            // 0 by the mesh, 1 lean, 2 wide, 3 flat, 4 partitioned (chain_shape_kind)
+  const void* tri;      // shape 4: the partitioned solve's factors
 };
 int chain_threads(int P, int n);
 int chain_flat_threads(int P, int n);            // workgroup size of the flat schedule (0: none at P)
@@ -128,6 +129,17 @@ int chain_lds_level(int P, int n, size_t elem_bytes, int64_t budget);
 // dynamic LDS of a chain launch: right-hand side plus the staged factors
 size_t chain_lds_bytes(int P, int n, size_t elem_bytes, int lds_level);
 hipError_t launch_chain_solve(Prec pr, int P, const ChainArgs& a, hipStream_t s);
+// Partitioned tridiagonal solve of the P = 1 chains (ChainArgs::shape 4): one
+// wavefront per chain, one segment of >= 2 positions per lane; its factors
+// (ChainArgs::tri, chain_tri_stride(n) entries per chain) come from
+// launch_chain_tri_factor.  chain_tri_lmax: register bound of a segment's
+// length (4, 8, 16 or 32), 0 where the schedule is not available (n < 5 or
+// n > 2049).
+constexpr int kTriScalars = 20;
+int chain_tri_lmax(int n);
+int64_t chain_tri_stride(int n);
+size_t chain_tri_lds_bytes(int n, int chains_per_wg, size_t elem_bytes);
+hipError_t launch_chain_tri_factor(Prec vp, const double* EB, int n, void* tri, int* fail, hipStream_t s);
 
 // Q1 levels (vector precision): 9-point stencil st[9][Nv] on the interior
 // vertices of an m x m mesh.

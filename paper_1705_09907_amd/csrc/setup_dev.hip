@@ -573,6 +573,145 @@ hipError_t launch_chain_factor(Prec vp, int P, const double* EB, int n, int64_t 
   return hipGetLastError();
 }
 
+// ------------------------------------- partitioned chain solve (P = 1)
+// At P = 1 a chain matrix is scalar tridiagonal and SPD: diagonal D_i and
+// coupling E_i between positions i and i + 1 (symmetric; E_i is taken from the
+// element on the chain's high side, as in the cyclic reduction above).  The
+// chain is split into nseg <= 64 segments of >= 2 positions, one per lane of
+// the solving wavefront.  Each segment's interior (all but its first and last
+// position) is factored by Gaussian elimination: pivots piv_j, stored as
+// ip_j = 1 / piv_j and ch_j = E_j ip_j.  Eliminating the interiors leaves a
+// tridiagonal system on the segment ends (first F_k, last L_k of segment k);
+// eliminating the F_k leaves a tridiagonal system on the L_k, one per lane,
+// solved by parallel cyclic reduction over the lanes (6 levels).  Everything
+// that depends on the matrix only is computed here, per lane:
+//   0 eF = E_o, 1 eL = E_{l-1} (o, l: the segment's first and last position),
+//   2 muF, 3 nuF (the F-elimination's multipliers of gF_k, gF_{k+1}),
+//   4 1 / betaF, 5 alphaF, 6 gammaF (row F_k: alphaF L_{k-1} + betaF F_k + gammaF L_k),
+//   7 + 2 h, 8 + 2 h: the cyclic reduction's multipliers of level h (lanes k - 2^h, k + 2^h),
+//   19 1 / b (the decoupled L_k rows).
+// Record of a chain: ch[LMAX][64], ip[LMAX][64], scalars[20][64], lane-minor.
+template <typename TV>
+__global__ __launch_bounds__(64) void k_chain_tri_factor(const double* __restrict__ EB, int n, TV* __restrict__ tri,
+                                                         int lmax, int64_t tstride, int* fail) {
+  const int64_t c = blockIdx.x;
+  const int m = n - 1, k = threadIdx.x;
+  const bool vert = c < n;
+  const int nseg = min(64, m / 2), base = m / nseg, extra = m % nseg;
+  const int L = k < nseg ? base + (k < extra ? 1 : 0) : 0;
+  const int o = k * base + min(k, extra), l = o + L - 1;
+  TV* R = tri + c * tstride;
+  // D_i and E_i of position i (E_{m-1} = 0)
+  auto entries = [&](int i, double& D, double& E) {
+    int64_t lo, hi;
+    int llo, lhi, lsup;
+    if (vert) {  // row c: between (i, c) and (i+1, c); next face = hi's right
+      lo = i + (int64_t)n * c;
+      hi = lo + 1;
+      llo = 1, lhi = 0, lsup = 1;
+    } else {     // column c - n: between (c', i) and (c', i+1); next face = hi's top
+      lo = (c - n) + (int64_t)n * i;
+      hi = lo + n;
+      llo = 3, lhi = 2, lsup = 3;
+    }
+    D = EB[(lo * 4 + llo) * 4 + llo] + EB[(hi * 4 + lhi) * 4 + lhi];
+    E = i + 1 < m ? EB[(hi * 4 + lhi) * 4 + lsup] : 0.0;
+  };
+  __shared__ double sa[64], sb[64], sc[64], saF[64], sbF[64], sgF[64];
+  double ch[32], ip[32];
+  for (int j = 0; j < 32; ++j) ch[j] = ip[j] = 0.0;
+  double aF = 0.0, bF = 1.0, gF = 0.0, aL = 0.0, bL = 1.0, gL = 0.0, eF = 0.0, eL = 0.0;
+  bool bad = false;
+  if (L >= 2) {
+    double Do, Dl, El, dummy;
+    entries(o, Do, eF);
+    entries(l, Dl, El);
+    entries(l - 1, dummy, eL);
+    if (k > 0) entries(o - 1, dummy, aF);
+    gL = El;
+    if (L == 2) {
+      bF = Do, gF = eF, aL = eF, bL = Dl;
+    } else {
+      // interior LU, then the spikes' end values: sigma = T_J^{-1} (E_o e_1),
+      // tau = T_J^{-1} (E_{l-1} e_{L-2})
+      double Eprev = eF;
+      for (int j = 1; j <= L - 2; ++j) {
+        double Dj, Ej;
+        entries(o + j, Dj, Ej);
+        const double piv = j == 1 ? Dj : Dj - Eprev * ch[j - 1];
+        if (!(piv > 0.0) || !isfinite(piv)) bad = true;
+        ip[j] = 1.0 / piv;
+        ch[j] = j <= L - 3 ? Ej * ip[j] : 0.0;
+        Eprev = Ej;
+      }
+      double s[32];
+      s[1] = eF;
+      for (int j = 2; j <= L - 2; ++j) s[j] = -ch[j - 1] * s[j - 1];
+      double sig = s[L - 2] * ip[L - 2];
+      const double sigL = sig;
+      for (int j = L - 3; j >= 1; --j) sig = s[j] * ip[j] - ch[j] * sig;
+      double tau = eL * ip[L - 2];
+      const double tauL = tau;
+      for (int j = L - 3; j >= 1; --j) tau = -ch[j] * tau;
+      bF = Do - eF * sig;
+      gF = -eF * tau;
+      aL = -eL * sigL;
+      bL = Dl - eL * tauL;
+    }
+    if (!(bF > 0.0) || !isfinite(bF)) bad = true;
+  }
+  saF[k] = aF, sbF[k] = bF, sgF[k] = gF;
+  __syncthreads();
+  const bool nxt = k + 1 < nseg;
+  const double muF = L >= 2 ? aL / bF : 0.0;
+  const double nuF = L >= 2 && nxt ? gL / sbF[k + 1] : 0.0;
+  double a = L >= 2 ? -muF * aF : 0.0;
+  double b = L >= 2 ? bL - muF * gF - (nxt ? nuF * saF[k + 1] : 0.0) : 1.0;
+  double cc = L >= 2 && nxt ? -nuF * sgF[k + 1] : 0.0;
+  double pm[6], pn[6];
+  for (int h = 0; h < 6; ++h) {
+    const int d = 1 << h;
+    sa[k] = a, sb[k] = b, sc[k] = cc;
+    __syncthreads();
+    const bool lo_ok = L >= 2 && k - d >= 0, hi_ok = L >= 2 && k + d < nseg;
+    const double mu = lo_ok ? a / sb[k - d] : 0.0;
+    const double nu = hi_ok ? cc / sb[k + d] : 0.0;
+    const double na = lo_ok ? -mu * sa[k - d] : 0.0;
+    const double nc = hi_ok ? -nu * sc[k + d] : 0.0;
+    const double nb = b - (lo_ok ? mu * sc[k - d] : 0.0) - (hi_ok ? nu * sa[k + d] : 0.0);
+    __syncthreads();
+    pm[h] = mu, pn[h] = nu;
+    a = na, b = nb, cc = nc;
+  }
+  if (L >= 2 && (!(b > 0.0) || !isfinite(b))) bad = true;
+  if (bad) *fail = 1;
+  for (int j = 0; j < lmax; ++j) {
+    R[(int64_t)j * 64 + k] = (TV)ch[j];
+    R[(int64_t)(lmax + j) * 64 + k] = (TV)ip[j];
+  }
+  TV* S = R + (int64_t)2 * lmax * 64;
+  const double sv[7] = {eF, eL, muF, nuF, L >= 2 ? 1.0 / bF : 0.0, aF, gF};
+  for (int q = 0; q < 7; ++q) S[q * 64 + k] = (TV)sv[q];
+  for (int h = 0; h < 6; ++h) {
+    S[(7 + 2 * h) * 64 + k] = (TV)pm[h];
+    S[(8 + 2 * h) * 64 + k] = (TV)pn[h];
+  }
+  S[19 * 64 + k] = (TV)(L >= 2 ? 1.0 / b : 0.0);
+}
+
+hipError_t launch_chain_tri_factor(Prec vp, const double* EB, int n, void* tri, int* fail, hipStream_t s) {
+  const int lmax = chain_tri_lmax(n);
+  if (lmax == 0) return hipErrorInvalidValue;
+  const int64_t ts = chain_tri_stride(n);
+  if (vp == Prec::F64)
+    hipLaunchKernelGGL((k_chain_tri_factor<double>), dim3((unsigned)(2 * n)), dim3(64), 0, s, EB, n, (double*)tri,
+                       lmax, ts, fail);
+  else
+    hipLaunchKernelGGL((k_chain_tri_factor<float>), dim3((unsigned)(2 * n)), dim3(64), 0, s, EB, n, (float*)tri,
+                       lmax, ts, fail);
+  return hipGetLastError();
+}
+
 // ---------------------------------------------------------------- Q1 levels
 // Stencil of P_J^T S0 P_J on the interior vertices of the n x n mesh from the
 // p = 0 element blocks (4 x 4): a vertex gathers, from its 4 elements in order,

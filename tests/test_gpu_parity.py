@@ -408,14 +408,17 @@ def test_full_size_chain_solve_sampled(name, n, k, sigma, seed, autotune):
 @pytest.mark.parametrize("n,k,prec", [(2, 1, "f64"), (16, 1, "f64"), (24, 3, "f64"), (40, 4, "f32"), (7, 8, "f64"),
                                       (64, 5, "f64"), (130, 2, "f64"), (256, 4, "f64"), (1024, 3, "f64")])
 def test_chain_schedules_are_bitwise_identical(n, k, prec):
-    """The chain solve's launch schedules (lean, wide and flat factor fetches)
-    run the same operations in the same order: one sweep at every level gives
-    bit-identical results whichever schedule runs (each falls back to another
-    where it does not exist at that degree or size)."""
+    """The chain solve's block cyclic reduction schedules (lean, wide and flat
+    factor fetches) run the same operations in the same order: one sweep at
+    every level gives bit-identical results whichever schedule runs (each falls
+    back to another where it does not exist at that degree or size).  The
+    default picks one of them at P >= 2; at P = 1 it is the partitioned solve
+    (test_partitioned_chain_solve_*), compared here only where that does not
+    exist (n < 5)."""
     print(f"case chain schedules n={n} k={k} {prec}", flush=True)
     kap = kappa_lognormal(n, 1.0, 8)
     ref = None
-    for shape in ("auto", "lean", "wide", "flat"):
+    for shape in ("lean", "auto", "wide", "flat"):
         S = H.Solver(n, k, kap, smoother="chain", omega=0.7, chain_shape=shape, precision=prec)
         try:
             outs = []
@@ -431,4 +434,90 @@ def test_chain_schedules_are_bitwise_identical(n, k, prec):
             ref = outs
         else:
             for p in range(k + 1):
+                if shape == "auto" and p == 0 and n >= 5:
+                    continue
                 assert np.array_equal(outs[p], ref[p]), (shape, p)
+
+
+def _sampled_chain_check(n, k, kap, xg, b, sample, P=1):
+    import scipy.sparse.linalg as spla
+    chains = mg.chains(n)
+    for c in sample:
+        faces = chains[c]
+        idx = np.concatenate([np.arange(f * P, (f + 1) * P) for f in faces])
+        T = _oracle_chain_matrix(n, k, kap, faces)
+        xc, bc = xg[idx], b[idx]
+        berr = np.abs(T @ xc - bc).max() / (abs(T).sum(axis=1).max() * np.abs(xc).max() + np.abs(bc).max())
+        assert berr <= 1e-14, (c, berr)
+        xd = spla.spsolve(T.tocsc(), bc)
+        assert rel_inf(xc, xd) <= 1e-9, (c, rel_inf(xc, xd))
+
+
+@pytest.mark.parametrize("n", [5, 6, 16, 33, 130, 258, 528, 1024, 2048])
+def test_partitioned_chain_solve_matches_oracle(n):
+    """P = 1 (k = 0): the partitioned chain solve (one wavefront per chain, one
+    segment of >= 2 faces per lane; segment lengths 2 ... 32 over these n) is
+    the default there.  One sweep from x = 0 gives omega M^{-1} b; sampled
+    chains (first, middle, last; vertical and horizontal) against the chain
+    matrix rebuilt from the oracle's element blocks: backward error <= 1e-14,
+    dense solve <= 1e-9 relative."""
+    print(f"case partitioned chain solve n={n}", flush=True)
+    kap = kappa_lognormal(n, 2.0, 4)
+    omega = 0.7
+    S = H.Solver(n, 0, kap, smoother="chain", omega=omega)
+    try:
+        th, _, lds = S.chain_shape(0)
+        assert lds == 64 and th % 64 == 0 and 64 <= th <= 512
+        N = S.num_dofs()
+        b = normal_vector(N, 29)
+        x = torch.zeros(N, dtype=torch.float64, device="cuda")
+        S.smooth(0, dev(b), x, 1)
+        xg = host(x) / omega
+        sample = {0, n // 2, n - 1, n, n + n // 3, 2 * n - 1} if n <= 528 else {0, n + n // 3, 2 * n - 1}
+        _sampled_chain_check(n, 0, kap, xg, b, sorted(sample))
+    finally:
+        S.close()
+
+
+@pytest.mark.parametrize("n,k,prec,tol", [(16, 2, "f64", 1e-11), (130, 1, "f64", 1e-11), (1024, 3, "f64", 1e-11),
+                                          (64, 2, "f32", 2e-4), (528, 0, "f32", 2e-4)])
+def test_partitioned_chain_solve_matches_cyclic_reduction(n, k, prec, tol):
+    """At the p = 0 level (Galerkin blocks from degree k): two sweeps, the second
+    from a non-zero iterate (residual, solve, update), with the partitioned
+    solve and with the lean cyclic reduction agree to rounding (tol relative)."""
+    print(f"case partitioned vs cyclic reduction n={n} k={k} {prec}", flush=True)
+    kap = kappa_lognormal(n, 1.0, 9)
+    outs = {}
+    for shape in ("tri", "lean"):
+        S = H.Solver(n, k, kap, smoother="chain", omega=0.7, chain_shape=shape, precision=prec)
+        try:
+            N = S.num_dofs(0)
+            b = dev(normal_vector(N, 31))
+            x = torch.zeros(N, dtype=torch.float64, device="cuda")
+            S.smooth(0, b, x, 2)
+            outs[shape] = host(x)
+        finally:
+            S.close()
+    assert rel_inf(outs["tri"], outs["lean"]) <= tol
+
+
+def test_partitioned_chain_solve_autotuned_is_bitwise_default():
+    """The autotuner varies only the chains per workgroup of the partitioned
+    solve (1, 2, 4, 8), which leaves each chain's arithmetic unchanged: the tuned
+    handle's p = 0 sweep equals the default handle's bit for bit (n = 1024,
+    k = 3, the benchmark's workload)."""
+    n, k = 1024, 3
+    print(f"case partitioned autotune n={n} k={k}", flush=True)
+    kap = kappa_lognormal(n, 2.0, 3)
+    outs = []
+    for tune in (False, True):
+        S = H.Solver(n, k, kap, smoother="chain", omega=0.7, autotune=tune)
+        try:
+            N = S.num_dofs(0)
+            b = dev(normal_vector(N, 5))
+            x = dev(normal_vector(N, 6))
+            S.smooth(0, b, x, 1)
+            outs.append(host(x))
+        finally:
+            S.close()
+    assert np.array_equal(outs[0], outs[1])

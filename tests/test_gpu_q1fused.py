@@ -45,7 +45,8 @@ def _cycles(S, b, ncyc):
     (512, 1, 1.0, 2, 2, "V", "f32", 2000)])
 def test_fused_q1_visits_are_bitwise_identical(n, k, sigma, nu1, nu2, cycle, prec, cmax):
     """coarse_max = 8 puts every Q1 level down to 2 x 2 or 3 x 3 elements under
-    the fused kernels; m = 256 and 512 take the 16 x 16 and 32 x 32 tiles."""
+    the fused kernels; m = 512 takes the 16 x 16 tiles (the full-size case below
+    the 32 x 32 ones), smaller levels 8 x 8."""
     print(f"case q1 fused vs separate n={n} k={k} nu=({nu1},{nu2}) {cycle} {prec} cmax={cmax}", flush=True)
     kap = kappa_lognormal(n, sigma, 5)
     N = ms.n_trace_dofs(n, k)
