@@ -1982,12 +1982,13 @@ hipError_t launch_chain_solve(Prec pr, int P, const ChainArgs& a, hipStream_t s)
 // multiply-adds in a fixed order, and shared by the one-operation kernels and
 // the fused level kernels below, whose results are therefore bit-identical.
 //
-// 9-point stencil sum at interior vertex (i, j) (index v): dj outer, di inner;
-// xat(ic, jc) returns x at a clamped (existing) vertex, zeroed here for
-// neighbours outside the interior, so no load sits under a branch (the stencil
-// entries are finite).
-template <typename T, typename XAt>
-__device__ __forceinline__ T q1_stencil_sum(const T* st, int m, int64_t Nv, int i, int j, int64_t v, XAt xat) {
+// 9-point stencil sum at interior vertex (i, j): dj outer, di inner; sat(d)
+// returns the vertex's stencil entry for direction d = (di + 1) + 3 (dj + 1),
+// xat(ic, jc) x at a clamped (existing) vertex, zeroed here for neighbours
+// outside the interior, so no load sits under a branch (the stencil entries
+// are finite).
+template <typename T, typename SAt, typename XAt>
+__device__ __forceinline__ T q1_stencil_sum(int m, int i, int j, SAt sat, XAt xat) {
   T s = T(0);
 #pragma unroll
   for (int dj = -1; dj <= 1; ++dj)
@@ -1997,15 +1998,16 @@ __device__ __forceinline__ T q1_stencil_sum(const T* st, int m, int64_t Nv, int 
       const bool ok = ii >= 1 && jj >= 1 && ii <= m - 1 && jj <= m - 1;
       const int ic = min(max(ii, 1), m - 1), jc = min(max(jj, 1), m - 1);
       const T xv = xat(ic, jc);
-      s = fma_t(st[(int64_t)((di + 1) + 3 * (dj + 1)) * Nv + v], ok ? xv : T(0), s);
+      s = fma_t(sat((di + 1) + 3 * (dj + 1)), ok ? xv : T(0), s);
     }
   return s;
 }
 
 template <typename T>
 __device__ __forceinline__ T q1_apply(const T* st, const T* x, int m, int64_t Nv, int i, int j, int64_t v) {
-  return q1_stencil_sum(st, m, Nv, i, j, v,
-                        [&](int ic, int jc) { return x[(ic - 1) + (int64_t)(m - 1) * (jc - 1)]; });
+  return q1_stencil_sum<T>(
+      m, i, j, [&](int d) { return st[(int64_t)d * Nv + v]; },
+      [&](int ic, int jc) { return x[(ic - 1) + (int64_t)(m - 1) * (jc - 1)]; });
 }
 
 // One Chebyshev step at a vertex: z = Dinv (b - A x), d' = c1 d + c2 z (c1 = 0
@@ -2152,10 +2154,39 @@ __device__ __forceinline__ void q1_for_region(const Q1Tile& t, int h, F f) {
   }
 }
 
+// Batched walk of R_h: each round takes vertices q0 + b kQ1Threads (b < B) and
+// issues the global loads of all B (load(b, i, j, v)) before using any of them
+// (use(b, i, j, v, l, ok)), so that a workgroup waits on memory once per round,
+// not once per vertex.  A slot past the region takes the region's last vertex
+// (valid indices, finite values) with ok = false: it must store nothing.
+template <int B, typename Load, typename Use>
+__device__ __forceinline__ void q1_for_region_b(const Q1Tile& t, int h, Load load, Use use) {
+  const int lo_i = max(1, t.ti0 - h), hi_i = min(t.m - 1, t.ti0 + t.TS - 1 + h);
+  const int lo_j = max(1, t.tj0 - h), hi_j = min(t.m - 1, t.tj0 + t.TS - 1 + h);
+  const int w = hi_i - lo_i + 1, cnt = w * (hi_j - lo_j + 1);
+  for (int q0 = threadIdx.x; q0 < cnt; q0 += B * kQ1Threads) {
+    int ii[B], jj[B];
+    bool ok[B];
+#pragma unroll
+    for (int b = 0; b < B; ++b) {
+      const int q = q0 + b * kQ1Threads;
+      ok[b] = q < cnt;
+      const int qc = ok[b] ? q : cnt - 1;
+      ii[b] = lo_i + qc % w;
+      jj[b] = lo_j + qc / w;
+      load(b, ii[b], jj[b], (int64_t)(ii[b] - 1) + (int64_t)(t.m - 1) * (jj[b] - 1));
+    }
+#pragma unroll
+    for (int b = 0; b < B; ++b)
+      use(b, ii[b], jj[b], (int64_t)(ii[b] - 1) + (int64_t)(t.m - 1) * (jj[b] - 1),
+          (ii[b] - t.i0) + t.RW * (jj[b] - t.j0), ok[b]);
+  }
+}
+
 // nu Chebyshev steps in LDS, the last on R_hend (step s on R_{hend + nu - 1 - s});
 // xa holds the iterate on R_{hend + nu} on entry (unread when zero) and the
 // result on exit; xb and dd are work arrays.
-template <typename T>
+template <typename T, int B>
 __device__ __forceinline__ void q1_cheb_steps(const Q1Tile& t, const T* st, const T* dinv, const T* b, int nu,
                                               int hend, bool zero, const Q1FusedArgs& a, T*& xa, T*& xb, T* dd) {
 #pragma clang fp contract(off)
@@ -2165,14 +2196,28 @@ __device__ __forceinline__ void q1_cheb_steps(const Q1Tile& t, const T* st, cons
     const double c1 = a.c1[s], c2 = a.c2[s];
     const T* xr = xa;
     T* xw = xb;
-    q1_for_region(t, hend + nu - 1 - s, [&](int i, int j, int64_t v, int l) {
-      const T ax = z0 ? T(0) : q1_stencil_sum(st, t.m, Nv, i, j, v, [&](int ic, int jc) {
-        return xr[(ic - t.i0) + t.RW * (jc - t.j0)];
-      });
-      const T dn = q1_cheb_dir(dinv[v], b[v], ax, c1 != 0.0 ? dd[l] : T(0), c1, c2);
-      dd[l] = dn;
-      xw[l] = (z0 ? T(0) : xr[l]) + dn;
-    });
+    T stv[B][9], dv[B], bv[B];
+    q1_for_region_b<B>(
+        t, hend + nu - 1 - s,
+        [&](int q, int, int, int64_t v) {
+          if (!z0) {
+#pragma unroll
+            for (int d = 0; d < 9; ++d) stv[q][d] = st[(int64_t)d * Nv + v];
+          }
+          dv[q] = dinv[v];
+          bv[q] = b[v];
+        },
+        [&](int q, int i, int j, int64_t, int l, bool ok) {
+          const T ax = z0 ? T(0)
+                          : q1_stencil_sum<T>(
+                                t.m, i, j, [&](int d) { return stv[q][d]; },
+                                [&](int ic, int jc) { return xr[(ic - t.i0) + t.RW * (jc - t.j0)]; });
+          const T dn = q1_cheb_dir(dv[q], bv[q], ax, c1 != 0.0 ? dd[l] : T(0), c1, c2);
+          if (ok) {
+            dd[l] = dn;
+            xw[l] = (z0 ? T(0) : xr[l]) + dn;
+          }
+        });
     __syncthreads();
     xa = xw;
     xb = const_cast<T*>(xr);
@@ -2181,7 +2226,7 @@ __device__ __forceinline__ void q1_cheb_steps(const Q1Tile& t, const T* st, cons
 
 // Pre-smoothing visit: nu1 steps from x_in (zero when null), x_out = the new
 // iterate, bc = full-weighting restriction of b - A x_out to the coarse level.
-template <typename T>
+template <typename T, int B>
 __global__ __launch_bounds__(kQ1Threads) void k_q1_pre(Q1FusedArgs a) {
   extern __shared__ unsigned char lds_raw[];
   const int m = a.m, nu = a.nu, H = nu + 2;
@@ -2197,17 +2242,33 @@ __global__ __launch_bounds__(kQ1Threads) void k_q1_pre(Q1FusedArgs a) {
   T* xout = static_cast<T*>(a.x_out);
   const bool zero = xin == nullptr;
   if (!zero) {
-    q1_for_region(t, H, [&](int, int, int64_t v, int l) { xa[l] = xin[v]; });
+    T xv[B];
+    q1_for_region_b<B>(
+        t, H, [&](int q, int, int, int64_t v) { xv[q] = xin[v]; },
+        [&](int q, int, int, int64_t, int l, bool ok) {
+          if (ok) xa[l] = xv[q];
+        });
     __syncthreads();
   }
-  q1_cheb_steps(t, st, dinv, b, nu, 2, zero, a, xa, xb, dd);
+  q1_cheb_steps<T, B>(t, st, dinv, b, nu, 2, zero, a, xa, xb, dd);
   const int64_t Nv = (int64_t)(m - 1) * (m - 1);
   q1_for_region(t, 0, [&](int, int, int64_t v, int l) { xout[v] = xa[l]; });
-  q1_for_region(t, 1, [&](int i, int j, int64_t v, int l) {
-    xb[l] = b[v] - q1_stencil_sum(st, m, Nv, i, j, v, [&](int ic, int jc) {
-      return xa[(ic - t.i0) + t.RW * (jc - t.j0)];
-    });
-  });
+  {
+    T stv[B][9], bv[B];
+    q1_for_region_b<B>(
+        t, 1,
+        [&](int q, int, int, int64_t v) {
+#pragma unroll
+          for (int d = 0; d < 9; ++d) stv[q][d] = st[(int64_t)d * Nv + v];
+          bv[q] = b[v];
+        },
+        [&](int q, int i, int j, int64_t, int l, bool ok) {
+          const T r = bv[q] - q1_stencil_sum<T>(
+                                  m, i, j, [&](int d) { return stv[q][d]; },
+                                  [&](int ic, int jc) { return xa[(ic - t.i0) + t.RW * (jc - t.j0)]; });
+          if (ok) xb[l] = r;
+        });
+  }
   __syncthreads();
   // coarse vertices (I, J) whose fine vertex (2I, 2J) lies in the tile; their
   // fine neighbours lie in R_1
@@ -2224,7 +2285,7 @@ __global__ __launch_bounds__(kQ1Threads) void k_q1_pre(Q1FusedArgs a) {
 
 // Post-smoothing visit: x = x_in + P e (e the coarse correction in a.ec), then
 // nu2 steps; x_out = the result (x_out != x_in: neighbouring tiles read x_in).
-template <typename T>
+template <typename T, int B>
 __global__ __launch_bounds__(kQ1Threads) void k_q1_post(Q1FusedArgs a) {
   extern __shared__ unsigned char lds_raw[];
   const int m = a.m, nu = a.nu, H = nu;
@@ -2236,10 +2297,17 @@ __global__ __launch_bounds__(kQ1Threads) void k_q1_post(Q1FusedArgs a) {
   const T* xin = static_cast<const T*>(a.x_in);
   const T* ec = static_cast<const T*>(a.ec);
   const int mc = m / 2;
-  q1_for_region(t, H, [&](int i, int j, int64_t v, int l) { xa[l] = xin[v] + q1_prolong_sum(ec, mc, i, j); });
+  {
+    T xv[B];
+    q1_for_region_b<B>(
+        t, H, [&](int q, int i, int j, int64_t v) { xv[q] = xin[v] + q1_prolong_sum(ec, mc, i, j); },
+        [&](int q, int, int, int64_t, int l, bool ok) {
+          if (ok) xa[l] = xv[q];
+        });
+  }
   __syncthreads();
-  q1_cheb_steps(t, static_cast<const T*>(a.st), static_cast<const T*>(a.dinv), static_cast<const T*>(a.b), nu, 0,
-                false, a, xa, xb, dd);
+  q1_cheb_steps<T, B>(t, static_cast<const T*>(a.st), static_cast<const T*>(a.dinv), static_cast<const T*>(a.b), nu,
+                      0, false, a, xa, xb, dd);
   T* xout = static_cast<T*>(a.x_out);
   q1_for_region(t, 0, [&](int, int, int64_t v, int l) { xout[v] = xa[l]; });
 }
@@ -2349,10 +2417,15 @@ static hipError_t launch_q1_fused(Prec pr, bool pre, const Q1FusedArgs& a, hipSt
   const int H = pre ? a.nu + 2 : a.nu, RW = a.tile + 2 * H;
   const int nt = (a.m - 1 + a.tile - 1) / a.tile, per = (nt * nt + 7) / 8;
   const size_t lds = (size_t)3 * RW * RW * (pr == Prec::F64 ? sizeof(double) : sizeof(float));
-  if (pre) {
-    HDG_DISPATCH_T(pr, hipLaunchKernelGGL(k_q1_pre<TT>, dim3(8 * per), dim3(kQ1Threads), lds, s, a));
+  // vertices per thread and round (measured at n = 1024: two for the
+  // pre-smoothing visit on 32 x 32 and 16 x 16 tiles, 37.0 -> 34.7 and 14.6 ->
+  // 13.1 us; four, or two in the post-smoothing visit, were slower: registers)
+  if (pre && a.tile >= 16) {
+    HDG_DISPATCH_T(pr, hipLaunchKernelGGL((k_q1_pre<TT, 2>), dim3(8 * per), dim3(kQ1Threads), lds, s, a));
+  } else if (pre) {
+    HDG_DISPATCH_T(pr, hipLaunchKernelGGL((k_q1_pre<TT, 1>), dim3(8 * per), dim3(kQ1Threads), lds, s, a));
   } else {
-    HDG_DISPATCH_T(pr, hipLaunchKernelGGL(k_q1_post<TT>, dim3(8 * per), dim3(kQ1Threads), lds, s, a));
+    HDG_DISPATCH_T(pr, hipLaunchKernelGGL((k_q1_post<TT, 1>), dim3(8 * per), dim3(kQ1Threads), lds, s, a));
   }
   return hipGetLastError();
 }
