@@ -520,7 +520,7 @@ void build_hlevels(hdg_ctx* h, const Vec& b0) {
     Vec dinv(Q.Nv);
     for (int64_t v = 0; v < Q.Nv; ++v) dinv[v] = 1.0 / st[(size_t)4 * Q.Nv + v];
     Q.lmax = h->cfg.cheb_lmax[lev] > 0 ? h->cfg.cheb_lmax[lev] : hdg::lanczos_lmax(A, dinv, 30);
-    Q.st = upload_vec(h, st);
+    Q.st = upload_vec(h, Vec(st.begin() + 4 * Q.Nv, st.begin() + 9 * Q.Nv));  // directions 4 ... 8
     Q.dinv = upload_vec(h, dinv);
     for (void** p : {&Q.x, &Q.b, &Q.r, &Q.d, &Q.t}) *p = valloc(h, Q.Nv);
     h->ql.push_back(Q);
@@ -1011,7 +1011,7 @@ double estimate_q1_lmax(hdg_ctx* h, const double* st, const double* dinv, int m,
   std::vector<double> al, be;
   double bprev = 0.0;
   for (int it = 0; it < steps && it < N; ++it) {
-    hipchk(hdg::launch_q1_resid(hdg::Prec::F64, st, zero, z, r, m, s), "q1 apply");  // r = -A z
+    hipchk(hdg::launch_q1_resid9(st, zero, z, r, m, s), "q1 apply");  // r = -A z
     hipchk(hdg::launch_fill(0.0, w, N, s), "fill");
     hipchk(hdg::launch_axpy(-1.0, r, w, N, s), "axpy");
     const double alpha = dot(h, w, z, N);
@@ -1052,7 +1052,7 @@ void device_hlevels(hdg_ctx* h, const double* EB0, bool update, DevScratch& tmp)
       break;
     }
     if (!update) {
-      Q.st = valloc(h, 9 * Q.Nv);
+      Q.st = valloc(h, 5 * Q.Nv);
       Q.dinv = valloc(h, Q.Nv);
       for (void** q : {&Q.x, &Q.b, &Q.r, &Q.d, &Q.t}) *q = valloc(h, Q.Nv);
     }

@@ -2003,11 +2003,39 @@ __device__ __forceinline__ T q1_stencil_sum(int m, int i, int j, SAt sat, XAt xa
   return s;
 }
 
+// The cycle's Q1 operators are symmetric (Galerkin products R A P with R =
+// P^T), and their stencils are kept by five entries per vertex: directions 4
+// ... 8 (centre, east, north-west, north, north-east) at st[(d - 4) Nv + v].  The
+// other four are the mirrored entries of the neighbour, A[v, v + e] =
+// A[v + e, v], read at a clamped vertex where the neighbour is outside the
+// interior (the caller masks that term).  HBM traffic per stencil sweep: 5
+// entries per vertex instead of 9.
+template <typename T>
+__device__ __forceinline__ T q1_sym_entry(const T* st, int64_t Nv, int m, int i, int j, int64_t v, int d) {
+  if (d >= 4) return st[(int64_t)(d - 4) * Nv + v];
+  const int di = d % 3 - 1, dj = d / 3 - 1;
+  const int ic = min(max(i + di, 1), m - 1), jc = min(max(j + dj, 1), m - 1);
+  return st[(int64_t)(4 - d) * Nv + (ic - 1) + (int64_t)(m - 1) * (jc - 1)];
+}
+
 template <typename T>
 __device__ __forceinline__ T q1_apply(const T* st, const T* x, int m, int64_t Nv, int i, int j, int64_t v) {
   return q1_stencil_sum<T>(
-      m, i, j, [&](int d) { return st[(int64_t)d * Nv + v]; },
+      m, i, j, [&](int d) { return q1_sym_entry(st, Nv, m, i, j, v, d); },
       [&](int ic, int jc) { return x[(ic - 1) + (int64_t)(m - 1) * (jc - 1)]; });
+}
+
+// r = b - A x with the full 9-entry FP64 stencil st[9][Nv] of the set-up (the
+// Lanczos estimate of lambda_max runs before the cycle copy exists).
+__global__ __launch_bounds__(kWG) void k_q1_resid9(const double* st, const double* b, const double* x, double* r,
+                                                   int m) {
+  const int64_t Nv = (int64_t)(m - 1) * (m - 1);
+  const int64_t v = (int64_t)blockIdx.x * kWG + threadIdx.x;
+  if (v >= Nv) return;
+  const int i = (int)(v % (m - 1)) + 1, j = (int)(v / (m - 1)) + 1;
+  r[v] = b[v] - q1_stencil_sum<double>(
+                    m, i, j, [&](int d) { return st[(int64_t)d * Nv + v]; },
+                    [&](int ic, int jc) { return x[(ic - 1) + (int64_t)(m - 1) * (jc - 1)]; });
 }
 
 // One Chebyshev step at a vertex: z = Dinv (b - A x), d' = c1 d + c2 z (c1 = 0
@@ -2199,10 +2227,10 @@ __device__ __forceinline__ void q1_cheb_steps(const Q1Tile& t, const T* st, cons
     T stv[B][9], dv[B], bv[B];
     q1_for_region_b<B>(
         t, hend + nu - 1 - s,
-        [&](int q, int, int, int64_t v) {
+        [&](int q, int i, int j, int64_t v) {
           if (!z0) {
 #pragma unroll
-            for (int d = 0; d < 9; ++d) stv[q][d] = st[(int64_t)d * Nv + v];
+            for (int d = 0; d < 9; ++d) stv[q][d] = q1_sym_entry(st, Nv, t.m, i, j, v, d);
           }
           dv[q] = dinv[v];
           bv[q] = b[v];
@@ -2257,9 +2285,9 @@ __global__ __launch_bounds__(kQ1Threads) void k_q1_pre(Q1FusedArgs a) {
     T stv[B][9], bv[B];
     q1_for_region_b<B>(
         t, 1,
-        [&](int q, int, int, int64_t v) {
+        [&](int q, int i, int j, int64_t v) {
 #pragma unroll
-          for (int d = 0; d < 9; ++d) stv[q][d] = st[(int64_t)d * Nv + v];
+          for (int d = 0; d < 9; ++d) stv[q][d] = q1_sym_entry(st, Nv, m, i, j, v, d);
           bv[q] = b[v];
         },
         [&](int q, int i, int j, int64_t, int l, bool ok) {
@@ -2381,6 +2409,10 @@ __global__ __launch_bounds__(kWG) void k_dense_gemv(const double* A, const T* b,
 hipError_t launch_q1_resid(Prec pr, const void* st, const void* b, const void* x, void* r, int m, hipStream_t s) {
   HDG_DISPATCH_T(pr, hipLaunchKernelGGL(k_q1_resid<TT>, grid_for((int64_t)(m - 1) * (m - 1)), dim3(kWG), 0, s,
                                         (const TT*)st, (const TT*)b, (const TT*)x, (TT*)r, m));
+  return hipGetLastError();
+}
+hipError_t launch_q1_resid9(const double* st, const double* b, const double* x, double* r, int m, hipStream_t s) {
+  hipLaunchKernelGGL(k_q1_resid9, grid_for((int64_t)(m - 1) * (m - 1)), dim3(kWG), 0, s, st, b, x, r, m);
   return hipGetLastError();
 }
 hipError_t launch_q1_cheb(Prec pr, const void* st, const void* dinv, const void* b, const void* x, void* d,

@@ -150,6 +150,9 @@ hipError_t launch_q1_cheb(Prec pr, const void* st, const void* dinv, const void*
                           void* d, void* xo, double c1, double c2, int m, hipStream_t s);
 hipError_t launch_q1_restrict(Prec pr, const void* rf, void* rc, int m_fine, hipStream_t s);
 hipError_t launch_q1_prolong_add(Prec pr, const void* ec, void* xf, int m_fine, hipStream_t s);
+// the cycle kernels above read the symmetric 5-entry stencil st[5][Nv]
+// (directions 4 ... 8, launch_q1_finish); this one the set-up's FP64 st[9][Nv]
+hipError_t launch_q1_resid9(const double* st, const double* b, const double* x, double* r, int m, hipStream_t s);
 
 // Fused Q1 level visits: launch_q1_pre does nu Chebyshev steps from x_in (null:
 // zero), writes the iterate to x_out and the restricted residual to bc;

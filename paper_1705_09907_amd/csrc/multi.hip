@@ -103,7 +103,12 @@ __device__ __forceinline__ T q1_apply_m(const T* st, const T* x, int m, int64_t 
       const bool ok = ii >= 1 && jj >= 1 && ii <= m - 1 && jj <= m - 1;
       const int ic = min(max(ii, 1), m - 1), jc = min(max(jj, 1), m - 1);
       const T xv = x[((ic - 1) + (int64_t)(m - 1) * (jc - 1)) * R + r];
-      s += st[(int64_t)((di + 1) + 3 * (dj + 1)) * Nv + v] * (ok ? xv : T(0));
+      // symmetric 5-entry stencil: directions 4 ... 8 at the vertex, the others
+      // mirrored from the (clamped) neighbour
+      const int d = (di + 1) + 3 * (dj + 1);
+      const T a = d >= 4 ? st[(int64_t)(d - 4) * Nv + v]
+                         : st[(int64_t)(4 - d) * Nv + (ic - 1) + (int64_t)(m - 1) * (jc - 1)];
+      s += a * (ok ? xv : T(0));
     }
   return s;
 }

@@ -818,8 +818,9 @@ __global__ __launch_bounds__(kSW) void k_q1_finish(const double* __restrict__ st
                                                    TV* __restrict__ dinv, double* __restrict__ dinv64) {
   const int64_t v = (int64_t)blockIdx.x * kSW + threadIdx.x;
   if (v >= Nv) return;
+  // the cycle keeps the symmetric operator's five entries of directions 4 ... 8
 #pragma unroll
-  for (int s = 0; s < 9; ++s) st[s * Nv + v] = (TV)st64[s * Nv + v];
+  for (int s = 0; s < 5; ++s) st[s * Nv + v] = (TV)st64[(4 + s) * Nv + v];
   const double d = 1.0 / st64[4 * Nv + v];
   dinv[v] = (TV)d;
   dinv64[v] = d;
