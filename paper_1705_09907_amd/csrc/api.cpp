@@ -857,8 +857,13 @@ void krylov_correction(hdg_ctx* h, int p, void* r, void* e, int m) {
       hipchk(hdg::launch_copy(pr, L.kz, L.kd, N, h->stream), "copy");
       device_dots(h, pr, 1, {L.kz, r}, N, sc);
     } else {
-      device_dots(h, pr, 3, {L.kz, L.kq, L.kz, r, L.kd, r}, N, sc + 2);
-      hipchk(hdg::launch_fcg_scalars(sc, h->stream), "fcg scalars");
+      hdg::DotArgs d{};
+      d.ndots = 3;
+      d.x[0] = L.kz, d.y[0] = L.kq;
+      d.x[1] = L.kz, d.y[1] = r;
+      d.x[2] = L.kd, d.y[2] = r;
+      hipchk(hdg::launch_dots(pr, d, N, h->partial, h->stream), "dots");
+      hipchk(hdg::launch_sum_partials_fcg(h->partial, hdg::reduce_grid(N), sc, h->stream), "sum, fcg scalars");
       hipchk(hdg::launch_xpby_dev(pr, L.kz, sc, 2, 1, -1.0, L.kd, N, h->stream), "xpby");
     }
     hdg::TraceArgs ta = targs(h, L, pr);
@@ -867,8 +872,7 @@ void krylov_correction(hdg_ctx* h, int p, void* r, void* e, int m) {
     ta.partial = h->partial;
     hipchk(hdg::launch_trace(L.mp, L.P, hdg::TM_APPLY_DOT, ta, h->stream), "apply dot");
     hipchk(hdg::launch_sum_partials(h->partial, hdg::trace_partials(h->ntiles), sc + 1, h->stream), "sum");
-    hipchk(hdg::launch_axpy_dev(pr, sc, 0, 1, 1.0, L.kd, e, N, h->stream), "axpy");
-    if (step + 1 < m) hipchk(hdg::launch_axpy_dev(pr, sc, 0, 1, -1.0, L.kq, r, N, h->stream), "axpy");
+    hipchk(hdg::launch_fcg_update(pr, sc, L.kd, e, L.kq, step + 1 < m ? r : nullptr, N, h->stream), "fcg update");
   }
 }
 

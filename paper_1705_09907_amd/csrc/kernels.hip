@@ -2708,24 +2708,39 @@ __global__ __launch_bounds__(kWG) void k_dot_partials(const double* a, const dou
   if (threadIdx.x == 0) partial[blockIdx.x] = t;
 }
 
-// Sum of np values by one workgroup in a fixed order: each thread keeps 8 loads
-// in flight (8 running sums, added in order at the end), then the fixed tree.
-__device__ __forceinline__ double thread_sum8(const double* v, int np) {
+// Sums of np values by one workgroup in a fixed order: each thread keeps 8 loads
+// in flight (8 running sums, added in order at the end), then a fixed tree.
+// The summing kernels run one workgroup of kSumT threads (a fixed order again):
+// a sum of 32K partials is then 4 rounds of 8 loads per thread instead of 16.
+constexpr int kSumT = 1024;
+__device__ __forceinline__ double thread_sum8_wide(const double* v, int np) {
   double s[8] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
   int i = threadIdx.x;
-  for (; i + 7 * kWG < np; i += 8 * kWG) {
+  for (; i + 7 * kSumT < np; i += 8 * kSumT) {
 #pragma unroll
-    for (int u = 0; u < 8; ++u) s[u] += v[i + u * kWG];
+    for (int u = 0; u < 8; ++u) s[u] += v[i + u * kSumT];
   }
-  for (; i < np; i += kWG) s[0] += v[i];
+  for (; i < np; i += kSumT) s[0] += v[i];
   double t = 0.0;
 #pragma unroll
   for (int u = 0; u < 8; ++u) t += s[u];
   return t;
 }
+// Deterministic sum over the kSumT threads (fixed shuffle tree, then the wave
+// sums in order); valid in thread 0.  ws: kSumT / 64 shared slots.
+__device__ __forceinline__ double block_sum_wide(double v, double* ws) {
+  for (int off = 32; off >= 1; off >>= 1) v += __shfl_xor(v, off, 64);
+  if ((threadIdx.x & 63) == 0) ws[threadIdx.x >> 6] = v;
+  __syncthreads();
+  double s = 0.0;
+  if (threadIdx.x == 0)
+    for (int w = 0; w < kSumT / 64; ++w) s += ws[w];
+  return s;
+}
 
-__global__ __launch_bounds__(kWG) void k_sum_partials(const double* partial, int np, double* out) {
-  const double t = block_sum(thread_sum8(partial, np));
+__global__ __launch_bounds__(kSumT) void k_sum_partials(const double* partial, int np, double* out) {
+  __shared__ double ws[kSumT / 64];
+  const double t = block_sum_wide(thread_sum8_wide(partial, np), ws);
   if (threadIdx.x == 0) *out = t;
 }
 
@@ -2745,8 +2760,9 @@ __global__ __launch_bounds__(kWG) void k_dots_partials(DotArgs a, int64_t n, dou
     __syncthreads();  // block_sum's shared slots are reused by the next dot
   }
 }
-__global__ __launch_bounds__(kWG) void k_sum_partials_multi(const double* partial, int np, double* out) {
-  const double t = block_sum(thread_sum8(partial + (int64_t)blockIdx.x * np, np));
+__global__ __launch_bounds__(kSumT) void k_sum_partials_multi(const double* partial, int np, double* out) {
+  __shared__ double ws[kSumT / 64];
+  const double t = block_sum_wide(thread_sum8_wide(partial + (int64_t)blockIdx.x * np, np), ws);
   if (threadIdx.x == 0) out[blockIdx.x] = t;
 }
 
@@ -2799,7 +2815,7 @@ hipError_t launch_dot_partials(const double* a, const double* b, int64_t n, doub
   return hipGetLastError();
 }
 hipError_t launch_sum_partials(const double* partial, int np, double* out, hipStream_t s) {
-  hipLaunchKernelGGL(k_sum_partials, dim3(1), dim3(kWG), 0, s, partial, np, out);
+  hipLaunchKernelGGL(k_sum_partials, dim3(1), dim3(kSumT), 0, s, partial, np, out);
   return hipGetLastError();
 }
 hipError_t launch_dots(Prec pr, const DotArgs& a, int64_t n, double* partial, hipStream_t s) {
@@ -2809,7 +2825,7 @@ hipError_t launch_dots(Prec pr, const DotArgs& a, int64_t n, double* partial, hi
   return hipGetLastError();
 }
 hipError_t launch_sum_partials_multi(const double* partial, int np, int ndots, double* out, hipStream_t s) {
-  hipLaunchKernelGGL(k_sum_partials_multi, dim3(ndots), dim3(kWG), 0, s, partial, np, out);
+  hipLaunchKernelGGL(k_sum_partials_multi, dim3(ndots), dim3(kSumT), 0, s, partial, np, out);
   return hipGetLastError();
 }
 hipError_t launch_axpy(double alpha, const double* x, double* y, int64_t n, hipStream_t s) {
@@ -2838,6 +2854,16 @@ __global__ __launch_bounds__(kWG) void k_axpy_dev(const double* sc, int num, int
   const int64_t i = (int64_t)blockIdx.x * kWG + threadIdx.x;
   if (i < n) y[i] += T(sign * ratio_or_zero(sc[num], sc[den])) * x[i];
 }
+// The end of a flexible CG step: e += alpha d and (r != null) r -= alpha q,
+// alpha = sc[0] / sc[1], in one pass (the same operations as two k_axpy_dev).
+template <typename T>
+__global__ __launch_bounds__(kWG) void k_fcg_update(const double* sc, const T* d, T* e, const T* q, T* r, int64_t n) {
+  const int64_t i = (int64_t)blockIdx.x * kWG + threadIdx.x;
+  if (i >= n) return;
+  const double al = ratio_or_zero(sc[0], sc[1]);
+  e[i] += T(1.0 * al) * d[i];
+  if (r) r[i] += T(-1.0 * al) * q[i];
+}
 template <typename T>
 __global__ __launch_bounds__(kWG) void k_xpby_dev(const T* x, const double* sc, int num, int den, double sign,
                                                   T* y, int64_t n) {
@@ -2846,6 +2872,24 @@ __global__ __launch_bounds__(kWG) void k_xpby_dev(const T* x, const double* sc, 
 }
 __global__ void k_fcg_scalars(double* sc) {
   if (threadIdx.x == 0) sc[0] = sc[3] - ratio_or_zero(sc[2], sc[1]) * sc[4];
+}
+// The three dot products of a flexible CG step (partials of dot j at
+// partial[j np ...]) summed by one workgroup into sc[2], sc[3], sc[4], and then
+// sc[0] = sc[3] - (sc[2] / sc[1]) sc[4] as k_fcg_scalars: one launch for both.
+__global__ __launch_bounds__(kSumT) void k_sum_partials_fcg(const double* partial, int np, double* sc) {
+  __shared__ double ws[kSumT / 64];
+  double t[3];
+#pragma unroll
+  for (int j = 0; j < 3; ++j) {
+    t[j] = block_sum_wide(thread_sum8_wide(partial + (int64_t)j * np, np), ws);
+    __syncthreads();  // the shared slots are reused by the next dot
+  }
+  if (threadIdx.x == 0) {
+    sc[2] = t[0];
+    sc[3] = t[1];
+    sc[4] = t[2];
+    sc[0] = t[1] - ratio_or_zero(t[0], sc[1]) * t[2];
+  }
 }
 hipError_t launch_axpy_dev(Prec pr, const double* sc, int num, int den, double sign, const void* x, void* y,
                            int64_t n, hipStream_t s) {
@@ -2861,8 +2905,19 @@ hipError_t launch_xpby_dev(Prec pr, const void* x, const double* sc, int num, in
                                         sign, (TT*)y, n));
   return hipGetLastError();
 }
+hipError_t launch_fcg_update(Prec pr, const double* sc, const void* d, void* e, const void* q, void* r, int64_t n,
+                             hipStream_t s) {
+  if (n == 0) return hipSuccess;
+  HDG_DISPATCH_T(pr, hipLaunchKernelGGL(k_fcg_update<TT>, grid_for(n), dim3(kWG), 0, s, sc, (const TT*)d, (TT*)e,
+                                        (const TT*)q, (TT*)r, n));
+  return hipGetLastError();
+}
 hipError_t launch_fcg_scalars(double* sc, hipStream_t s) {
   hipLaunchKernelGGL(k_fcg_scalars, dim3(1), dim3(64), 0, s, sc);
+  return hipGetLastError();
+}
+hipError_t launch_sum_partials_fcg(const double* partial, int np, double* sc, hipStream_t s) {
+  hipLaunchKernelGGL(k_sum_partials_fcg, dim3(1), dim3(kSumT), 0, s, partial, np, sc);
   return hipGetLastError();
 }
 

@@ -327,6 +327,12 @@ hipError_t launch_xpby_dev(Prec pr, const void* x, const double* sc, int num, in
 // Flexible-CG direction scalars on the device: with sc[1] = d.q, sc[2] = z.q,
 // sc[3] = z.r, sc[4] = d.r:  sc[0] = sc[3] - (sc[2] / sc[1]) sc[4]  (the new d.r)
 hipError_t launch_fcg_scalars(double* sc, hipStream_t s);
+// e += (sc[0] / sc[1]) d and, when r is not null, r -= (sc[0] / sc[1]) q
+hipError_t launch_fcg_update(Prec pr, const double* sc, const void* d, void* e, const void* q, void* r, int64_t n,
+                             hipStream_t s);
+// the three dots of a flexible CG step (sums into sc[2..4]) and sc[0] as
+// launch_fcg_scalars, in one launch
+hipError_t launch_sum_partials_fcg(const double* partial, int np, double* sc, hipStream_t s);
 // r -= alpha q and per-workgroup sum of squares of the new r
 hipError_t launch_axpy_norm(double alpha, const double* q, double* r, int64_t n, double* partial,
                             hipStream_t s);
