@@ -1220,10 +1220,11 @@ struct EventPair {
 
 // Autotuner of the chain Schwarz launch shape of level p: workgroup size,
 // XCD-aware chain order, LDS staging depth and (P = 3 ... 5) the lean or wide
-// batch shape of the factor loads.  Every candidate solves each chain
-// with the same operations in the same order, so the choice changes the time
-// only, never the result.  Each candidate is timed (best of 3, after one warm-up
-// launch) on the level's scratch vectors; the fastest is kept.
+// batch shape of the factor loads; at P = 1 the partitioned solve's chains per
+// workgroup.  Every candidate solves each chain with the same operations in the
+// same order, so the choice changes the time only, never the result.  Each
+// candidate is timed (best of 3, after one warm-up launch) on the level's
+// scratch vectors; the fastest is kept.
 void tune_chain(hdg_ctx* h, int p) {
   PLevel& L = h->pl[p];
   const hdg::Prec pr = h->prec;
@@ -1241,10 +1242,31 @@ void tune_chain(hdg_ctx* h, int p) {
   float best = 1e30f;
   int bt = 0, br = -1, bl = lds_default, bw = L.chain_shape;
   const bool log = std::getenv("HDG_TUNE_LOG") != nullptr;  // a diagnostic: every candidate's time
+  // Each candidate is timed as the smoother runs it inside a cycle: with an
+  // iterate (x = out, zero), and with the 256 MB Infinity Cache flushed before
+  // each timed launch (a level's factors fit in it, and back-to-back launches
+  // would time them cache-warm, which the cycle never does between sweeps).
+  hipchk(hdg::launch_zero(pr, L.t, L.N, h->stream), "zero");
+  // The flush reads a 320 MB buffer (a dot product into its own tail), so it
+  // evicts without leaving dirty lines to be written back during the timing.
+  const int64_t flush_n = (int64_t)40 << 20;  // 320 MB of FP64
+  double* flush = nullptr;
+  if (hipMalloc(reinterpret_cast<void**>(&flush), (size_t)(flush_n + 1024) * sizeof(double)) != hipSuccess) {
+    (void)hipGetLastError();
+    flush = nullptr;  // no flush: time cache-warm rather than fail the set-up
+  }
+  struct FlushGuard {
+    void* q;
+    ~FlushGuard() {
+      if (q) (void)hipFree(q);
+    }
+  } flush_guard{flush};
+  if (flush) hipchk(hdg::launch_fill(0.0, flush, flush_n, h->stream), "fill");
+  auto flush_cache = [&]() {
+    if (flush) hipchk(hdg::launch_dot_partials(flush, flush, flush_n, flush + flush_n, h->stream), "cache flush");
+  };
   if (hdg::chain_shape_kind(L.P, h->n, h->cfg.chain_shape) == HDG_CHAIN_TRI) {
-    // the partitioned solve (P = 1): chains per workgroup only, timed as the
-    // smoother runs it after the first sweep (iterate staged with the residual)
-    hipchk(hdg::launch_zero(pr, L.t, L.N, h->stream), "zero");
+    // the partitioned solve (P = 1): chains per workgroup only
     for (int g : {1, 2, 4, 8}) {
       hdg::ChainArgs c{};
       c.lds_cap = h->lds_cap;
@@ -1262,6 +1284,7 @@ void tune_chain(hdg_ctx* h, int p) {
       }
       float t = 1e30f;
       for (int rep = 0; rep < 3; ++rep) {
+        flush_cache();
         hipchk(hipEventRecord(e0, h->stream), "event");
         hipchk(hdg::launch_chain_solve(pr, L.P, c, h->stream), "chain tune");
         hipchk(hipEventRecord(e1, h->stream), "event");
@@ -1297,7 +1320,7 @@ void tune_chain(hdg_ctx* h, int p) {
         c.omega = L.omega;
         c.n = h->n;
         c.r = L.r;
-        c.x = nullptr;
+        c.x = L.t;
         c.out = L.t;
         c.threads = th;
         c.remap = rm;
@@ -1308,6 +1331,7 @@ void tune_chain(hdg_ctx* h, int p) {
         }
         float t = 1e30f;
         for (int rep = 0; rep < 3; ++rep) {
+          flush_cache();
           hipchk(hipEventRecord(e0, h->stream), "event");
           hipchk(hdg::launch_chain_solve(pr, L.P, c, h->stream), "chain tune");
           hipchk(hipEventRecord(e1, h->stream), "event");
