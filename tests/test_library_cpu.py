@@ -70,7 +70,8 @@ def test_quadrature_nodes_match_oracle():
                                               ("nq", 0, -1), ("precision", 3, -1), ("precision", -1, -1),
                                               ("graph", 2, -1), ("autotune", -1, -1), ("cycle", 3, -1),
                                               ("cycle", -1, -1), ("q1_schedule", 2, -1),
-                                              ("q1_schedule", -1, -1)])
+                                              ("q1_schedule", -1, -1), ("chain_shape", 5, -1),
+                                              ("chain_shape", -1, -1)])
 def test_create_rejects_bad_config_before_any_device_call(field, value, code):
     cfg = H.Config()
     assert H.lib.hdg_config_default(8, 2, ctypes.byref(cfg)) == 0
