@@ -610,6 +610,43 @@ double residual_norm(hdg_ctx* h, int p, const double* b, const double* x, double
 void smooth(hdg_ctx* h, int p, const void* b, void* x, int nu, bool zero) {
   PLevel& L = h->pl[p];
   const hdg::Prec pr = h->prec;
+  // The partitioned chain solve (P = 1) computes each sweep's residual in its own
+  // launch from the face slab, which gathers x on neighbouring chains: a sweep
+  // never updates in place.  Sweeps alternate between x and L.t so that the
+  // last one writes x (one copy first where the count does not work out).
+  if (h->cfg.smoother == HDG_SMOOTH_CHAIN && L.P == 1 && L.mp == pr && L.tri &&
+      hdg::chain_shape_kind(1, h->n, L.chain_shape) == HDG_CHAIN_TRI) {
+    void* cur = x;
+    for (int s = 0; s < nu; ++s) {
+      const bool z = zero && s == 0;
+      void* dst = ((nu - 1 - s) % 2 == 0) ? x : L.t;
+      if (!z && cur == dst) {
+        void* other = dst == x ? L.t : x;
+        hipchk(hdg::launch_copy(pr, cur, other, L.N, h->stream), "copy");
+        cur = other;
+      }
+      hdg::ChainArgs c{};
+      c.lds_cap = h->lds_cap;
+      c.threads = L.chain_threads;
+      c.shape = L.chain_shape;
+      c.tri = L.tri;
+      c.omega = L.omega;
+      c.n = h->n;
+      c.out = dst;
+      if (z) {
+        c.r = b;
+        c.x = nullptr;
+      } else {
+        c.r = nullptr;
+        c.b = b;
+        c.slab = L.slab;
+        c.x = cur;
+      }
+      hipchk(hdg::launch_chain_solve(pr, L.P, c, h->stream), "chain solve");
+      cur = dst;
+    }
+    return;
+  }
   for (int s = 0; s < nu; ++s) {
     const bool z = zero && s == 0;
     if (h->cfg.smoother == HDG_SMOOTH_PATCH) {

@@ -1799,7 +1799,11 @@ static hipError_t launch_chain_t(const ChainArgs& a, int64_t nch, int threads, s
 // horizontal chain's are n apart and G adjacent chains share each 8 G-byte run.
 __device__ __forceinline__ int tri_pad(int i) { return i + (i >> 4); }
 
-template <typename T, int LMAX>
+// RES: the right-hand side is the residual b - S x of the chain's faces,
+// gathered from the face slab as the trace kernel does (7 entries per face at
+// P = 1), instead of a residual vector computed by a launch of its own; x is
+// staged in LDS beside it for the final update.
+template <typename T, int LMAX, bool RES>
 __global__ __launch_bounds__(512) void k_chain_tri(ChainArgs a) {
   extern __shared__ unsigned char lds_raw[];
   const int n = a.n, m = n - 1;
@@ -1845,15 +1849,59 @@ __global__ __launch_bounds__(512) void k_chain_tri(ChainArgs a) {
   const int s0 = w2 * ld + pos0 + (pos0 >> 4);
   // the iterate is requested first, so that its round trip overlaps the
   // right-hand side's and the factors' (while the registers allow)
-  constexpr bool XPRE = LMAX * sizeof(T) <= 128;
+  constexpr bool XPRE = !RES && LMAX * sizeof(T) <= 128;
+  T* xbuf = buf + G * ld;  // RES: the iterate of every staged face
   T xr[LMAX];
   if (XPRE && xin) {
 #pragma unroll
     for (int t = 0; t < LMAX; ++t) xr[t] = own && pos0 + 64 * t < m ? xin[f0 + df * t] : T(0);
   }
+  if constexpr (RES) {
+    // two faces per round: slab words, the 7 gathered x values and b of both
+    // are requested before either is summed (missing neighbours and slots past
+    // the chain read face 0 and are zeroed or not stored)
+    using L16 = Lanes16<T, T>;
+    constexpr int V = L16::V, NQ = (7 + V - 1) / V;
+    const u32x4* sp = static_cast<const u32x4*>(a.slab);
+    const T* bvec = static_cast<const T*>(a.b);
 #pragma unroll
-  for (int t = 0; t < LMAX; ++t)
-    if (own && pos0 + 64 * t < m) buf[s0 + 68 * t] = r[f0 + df * t];
+    for (int t0 = 0; t0 < LMAX; t0 += 2) {
+      T wv[2][NQ * V], xv[2][7], bb[2];
+      unsigned okm[2];
+      bool okf[2];
+#pragma unroll
+      for (int u = 0; u < 2; ++u) {
+        const int t = t0 + u;
+        okf[u] = own && pos0 + 64 * t < m;
+        const int64_t f = okf[u] ? f0 + df * t : 0;
+        int64_t g[7];
+        face_neighbours(n, nv, f, g);
+#pragma unroll
+        for (int q = 0; q < NQ; ++q) L16::unpack(sp[((f >> 6) * NQ + q) * 64 + (f & 63)], &wv[u][q * V]);
+        okm[u] = 0;
+#pragma unroll
+        for (int s = 0; s < 7; ++s) {
+          okm[u] |= (g[s] >= 0 ? 1u : 0u) << s;
+          xv[u][s] = xin[g[s] >= 0 ? g[s] : f];
+        }
+        bb[u] = bvec[f];
+      }
+#pragma unroll
+      for (int u = 0; u < 2; ++u) {
+        T acc = T(0);
+#pragma unroll
+        for (int e = 0; e < 7; ++e) acc = fma_t(wv[u][e], (okm[u] >> e) & 1u ? xv[u][e] : T(0), acc);
+        if (okf[u]) {
+          buf[s0 + 68 * (t0 + u)] = bb[u] - acc;
+          xbuf[s0 + 68 * (t0 + u)] = xv[u][0];
+        }
+      }
+    }
+  } else {
+#pragma unroll
+    for (int t = 0; t < LMAX; ++t)
+      if (own && pos0 + 64 * t < m) buf[s0 + 68 * t] = r[f0 + df * t];
+  }
   __syncthreads();
   // 1. interior solve (slots outside the interior hold ch = ip = 0); only the
   //    end values of the backward sweep are kept
@@ -1907,7 +1955,8 @@ __global__ __launch_bounds__(512) void k_chain_tri(ChainArgs a) {
 #pragma unroll
   for (int t = 0; t < LMAX; ++t)
     if (own && pos0 + 64 * t < m)
-      out[f0 + df * t] = (xin ? (XPRE ? xr[t] : xin[f0 + df * t]) : T(0)) + om * buf[s0 + 68 * t];
+      out[f0 + df * t] = (xin ? (RES ? xbuf[s0 + 68 * t] : (XPRE ? xr[t] : xin[f0 + df * t])) : T(0)) +
+                         om * buf[s0 + 68 * t];
 }
 
 int chain_tri_lmax(int n) {
@@ -1925,16 +1974,28 @@ size_t chain_tri_lds_bytes(int n, int G, size_t es) {
   return (size_t)G * (m + (m >> 4) + 1) * es;
 }
 
-template <typename T, int LMAX>
+template <typename T, int LMAX, bool RES>
 static hipError_t launch_chain_tri_t(const ChainArgs& a, int G, hipStream_t s) {
-  const size_t lds = chain_tri_lds_bytes(a.n, G, sizeof(T));
+  const size_t lds = chain_tri_lds_bytes(a.n, G, sizeof(T)) * (RES ? 2 : 1);
   if ((int64_t)lds > (a.lds_cap > 0 ? a.lds_cap : 65536)) return hipErrorInvalidValue;
-  if (lds > 65536 && hipFuncSetAttribute(reinterpret_cast<const void*>(&k_chain_tri<T, LMAX>),
+  if (lds > 65536 && hipFuncSetAttribute(reinterpret_cast<const void*>(&k_chain_tri<T, LMAX, RES>),
                                          hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds) != hipSuccess)
     return hipErrorInvalidValue;
   const int nvw = (a.n + G - 1) / G;
-  hipLaunchKernelGGL((k_chain_tri<T, LMAX>), dim3((unsigned)(2 * nvw)), dim3(64 * G), lds, s, a);
+  hipLaunchKernelGGL((k_chain_tri<T, LMAX, RES>), dim3((unsigned)(2 * nvw)), dim3(64 * G), lds, s, a);
   return hipGetLastError();
+}
+template <typename T, int LMAX>
+static hipError_t launch_chain_tri_r(const ChainArgs& a, int G, hipStream_t s) {
+  // the residual in the launch needs x, b and the slab, and no residual vector
+  const bool res = a.r == nullptr && a.b != nullptr && a.slab != nullptr && a.x != nullptr;
+  if (!res && a.r == nullptr) return hipErrorInvalidValue;
+  if (!res) return launch_chain_tri_t<T, LMAX, false>(a, G, s);
+  // the staged iterate doubles the LDS: fewer chains per workgroup where it
+  // does not fit (each chain's arithmetic does not depend on it)
+  const int64_t cap = a.lds_cap > 0 ? a.lds_cap : 65536;
+  while (G > 1 && (int64_t)(2 * chain_tri_lds_bytes(a.n, G, sizeof(T))) > cap) G /= 2;
+  return launch_chain_tri_t<T, LMAX, true>(a, G, s);
 }
 
 template <typename T>
@@ -1942,10 +2003,10 @@ static hipError_t launch_chain_tri(const ChainArgs& a, hipStream_t s) {
   const int G = a.threads > 0 ? a.threads / 64 : 4;
   if (a.threads % 64 || G < 1 || G > 8 || !a.tri) return hipErrorInvalidValue;
   switch (chain_tri_lmax(a.n)) {
-    case 4: return launch_chain_tri_t<T, 4>(a, G, s);
-    case 8: return launch_chain_tri_t<T, 8>(a, G, s);
-    case 16: return launch_chain_tri_t<T, 16>(a, G, s);
-    case 32: return launch_chain_tri_t<T, 32>(a, G, s);
+    case 4: return launch_chain_tri_r<T, 4>(a, G, s);
+    case 8: return launch_chain_tri_r<T, 8>(a, G, s);
+    case 16: return launch_chain_tri_r<T, 16>(a, G, s);
+    case 32: return launch_chain_tri_r<T, 32>(a, G, s);
     default: return hipErrorInvalidValue;
   }
 }

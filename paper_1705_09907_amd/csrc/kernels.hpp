@@ -116,6 +116,11 @@ struct ChainArgs {
   int64_t lds_cap;      // LDS bytes a workgroup may use on this device (0: 64 KiB)
   int shape;            // 0 by the mesh, 1 lean, 2 wide, 3 flat, 4 partitioned (chain_shape_kind)
   const void* tri;      // shape 4: the partitioned solve's factors
+  // shape 4 with r == null and these set: the right-hand side is the residual
+  // b - S x, computed in the launch from the level's face slab (P = 1, vector
+  // precision) and x
+  const void* b;
+  const void* slab;
 };
 int chain_threads(int P, int n);
 int chain_flat_threads(int P, int n);            // workgroup size of the flat schedule (0: none at P)

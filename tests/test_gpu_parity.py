@@ -480,11 +480,14 @@ def test_partitioned_chain_solve_matches_oracle(n):
 
 
 @pytest.mark.parametrize("n,k,prec,tol", [(16, 2, "f64", 1e-11), (130, 1, "f64", 1e-11), (1024, 3, "f64", 1e-11),
-                                          (64, 2, "f32", 2e-4), (528, 0, "f32", 2e-4)])
+                                          (2048, 0, "f64", 1e-11), (64, 2, "f32", 2e-4), (528, 0, "f32", 2e-4)])
 def test_partitioned_chain_solve_matches_cyclic_reduction(n, k, prec, tol):
     """At the p = 0 level (Galerkin blocks from degree k): two sweeps, the second
-    from a non-zero iterate (residual, solve, update), with the partitioned
-    solve and with the lean cyclic reduction agree to rounding (tol relative)."""
+    from a non-zero iterate (its residual computed inside the partitioned
+    solve's launch from the face slab; a separate residual launch before the
+    cyclic reduction), agree to rounding (tol relative).  n = 2048 runs the
+    32-position segments with fewer chains per workgroup (the staged iterate
+    doubles the LDS)."""
     print(f"case partitioned vs cyclic reduction n={n} k={k} {prec}", flush=True)
     kap = kappa_lognormal(n, 1.0, 9)
     outs = {}
@@ -521,3 +524,26 @@ def test_partitioned_chain_solve_autotuned_is_bitwise_default():
         finally:
             S.close()
     assert np.array_equal(outs[0], outs[1])
+
+
+@pytest.mark.parametrize("sweeps", [1, 2, 3, 4])
+def test_partitioned_chain_solve_sweep_counts(sweeps):
+    """The partitioned solve never updates x in place (its residual gathers x on
+    neighbouring chains): sweeps alternate between x and a scratch vector, with
+    one copy where the count needs it.  Any number of sweeps from a non-zero
+    iterate gives the cyclic reduction's result to rounding."""
+    n, k = 130, 1
+    print(f"case partitioned sweeps={sweeps}", flush=True)
+    kap = kappa_lognormal(n, 1.0, 10)
+    outs = {}
+    for shape in ("tri", "lean"):
+        S = H.Solver(n, k, kap, smoother="chain", omega=0.7, chain_shape=shape)
+        try:
+            N = S.num_dofs(0)
+            b = dev(normal_vector(N, 33))
+            x = dev(normal_vector(N, 34))
+            S.smooth(0, b, x, sweeps)
+            outs[shape] = host(x)
+        finally:
+            S.close()
+    assert rel_inf(outs["tri"], outs["lean"]) <= 1e-11
