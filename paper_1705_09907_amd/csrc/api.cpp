@@ -613,8 +613,10 @@ void smooth(hdg_ctx* h, int p, const void* b, void* x, int nu, bool zero) {
   // The partitioned chain solve (P = 1) computes each sweep's residual in its own
   // launch from the face slab, which gathers x on neighbouring chains: a sweep
   // never updates in place.  Sweeps alternate between x and L.t so that the
-  // last one writes x (one copy first where the count does not work out).
-  if (h->cfg.smoother == HDG_SMOOTH_CHAIN && L.P == 1 && L.mp == pr && L.tri &&
+  // last one writes x (one copy first where the count does not work out).  The
+  // launch reads the slab in the vector precision: FP64 and FP32 cycles only (a
+  // bfloat16 cycle keeps bfloat16 slabs on the coarse levels, FP32 vectors).
+  if (h->cfg.smoother == HDG_SMOOTH_CHAIN && L.P == 1 && pr != hdg::Prec::BF16 && L.mp == pr && L.tri &&
       hdg::chain_shape_kind(1, h->n, L.chain_shape) == HDG_CHAIN_TRI) {
     void* cur = x;
     for (int s = 0; s < nu; ++s) {

@@ -2015,7 +2015,12 @@ hipError_t launch_chain_solve(Prec pr, int P, const ChainArgs& a, hipStream_t s)
   const int64_t nch = 2LL * a.n;
   const int kind = chain_shape_kind(P, a.n, a.shape);
   if (kind == 0) return hipErrorInvalidValue;
-  if (kind == 4) return pr == Prec::F64 ? launch_chain_tri<double>(a, s) : launch_chain_tri<float>(a, s);
+  if (kind == 4) {
+    // the residual in the launch reads the slab as vector-precision words: a
+    // bfloat16 slab has another word layout
+    if (pr == Prec::BF16 && a.r == nullptr) return hipErrorInvalidValue;
+    return pr == Prec::F64 ? launch_chain_tri<double>(a, s) : launch_chain_tri<float>(a, s);
+  }
   if (kind == 3) {
     const int threads = a.threads > 0 ? a.threads : chain_flat_threads(P, a.n);
     if (threads % 64 || threads > 1024) return hipErrorInvalidValue;

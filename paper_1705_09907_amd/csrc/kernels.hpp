@@ -117,8 +117,8 @@ struct ChainArgs {
   int shape;            // 0 by the mesh, 1 lean, 2 wide, 3 flat, 4 partitioned (chain_shape_kind)
   const void* tri;      // shape 4: the partitioned solve's factors
   // shape 4 with r == null and these set: the right-hand side is the residual
-  // b - S x, computed in the launch from the level's face slab (P = 1, vector
-  // precision) and x
+  // b - S x, computed in the launch from the level's face slab (P = 1, stored in
+  // the vector precision: FP64 or FP32 cycles, not bfloat16 slabs) and x
   const void* b;
   const void* slab;
 };
