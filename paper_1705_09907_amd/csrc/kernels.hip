@@ -2765,11 +2765,27 @@ int reduce_grid(int64_t n) {
   return (int)g;
 }
 
+// The dot-product kernels walk the vector with a grid stride; each round loads
+// kDotRounds strides before adding any, so a thread has that many round trips in
+// flight instead of one.  The additions keep index order, so the partials are the
+// same as those of a one-stride loop.
+constexpr int kDotRounds = 4;
 __global__ __launch_bounds__(kWG) void k_dot_partials(const double* a, const double* b, int64_t n,
                                                       double* partial) {
   double s = 0.0;
-  for (int64_t i = (int64_t)blockIdx.x * kWG + threadIdx.x; i < n; i += (int64_t)gridDim.x * kWG)
-    s += a[i] * b[i];
+  const int64_t st = (int64_t)gridDim.x * kWG;
+  int64_t i = (int64_t)blockIdx.x * kWG + threadIdx.x;
+  for (; i + (kDotRounds - 1) * st < n; i += kDotRounds * st) {
+    double av[kDotRounds], bv[kDotRounds];
+#pragma unroll
+    for (int u = 0; u < kDotRounds; ++u) {
+      av[u] = a[i + u * st];
+      bv[u] = b[i + u * st];
+    }
+#pragma unroll
+    for (int u = 0; u < kDotRounds; ++u) s += av[u] * bv[u];
+  }
+  for (; i < n; i += st) s += a[i] * b[i];
   const double t = block_sum(s);
   if (threadIdx.x == 0) partial[blockIdx.x] = t;
 }
@@ -2816,7 +2832,25 @@ __global__ __launch_bounds__(kSumT) void k_sum_partials(const double* partial, i
 template <typename T>
 __global__ __launch_bounds__(kWG) void k_dots_partials(DotArgs a, int64_t n, double* partial) {
   double s[3] = {0.0, 0.0, 0.0};
-  for (int64_t i = (int64_t)blockIdx.x * kWG + threadIdx.x; i < n; i += (int64_t)gridDim.x * kWG)
+  const int64_t st = (int64_t)gridDim.x * kWG;
+  int64_t i = (int64_t)blockIdx.x * kWG + threadIdx.x;
+  for (; i + (kDotRounds - 1) * st < n; i += kDotRounds * st) {
+    double xv[3][kDotRounds], yv[3][kDotRounds];
+#pragma unroll
+    for (int j = 0; j < 3; ++j)
+      if (j < a.ndots)
+#pragma unroll
+        for (int u = 0; u < kDotRounds; ++u) {
+          xv[j][u] = (double)static_cast<const T*>(a.x[j])[i + u * st];
+          yv[j][u] = (double)static_cast<const T*>(a.y[j])[i + u * st];
+        }
+#pragma unroll
+    for (int u = 0; u < kDotRounds; ++u)
+#pragma unroll
+      for (int j = 0; j < 3; ++j)
+        if (j < a.ndots) s[j] += xv[j][u] * yv[j][u];
+  }
+  for (; i < n; i += st)
 #pragma unroll
     for (int j = 0; j < 3; ++j)
       if (j < a.ndots) s[j] += (double)static_cast<const T*>(a.x[j])[i] * (double)static_cast<const T*>(a.y[j])[i];
