@@ -129,7 +129,10 @@ typedef struct {
   int32_t autotune;     /* 1: at setup, time the chain Schwarz launch shapes (schedule, workgroup
                            size, XCD-aware chain order, LDS staging depth) of every level and keep
                            the fastest; 0 (default): measured fixed defaults.  Results are
-                           identical either way (same operations in the same order).     */
+                           identical either way (same operations in the same order).  The
+                           choices are kept for the life of the process per (device, n, level
+                           degree, precision, chain_shape, LDS limit): a further handle of the
+                           same sizes takes them without timing again.                   */
   int32_t cycle;        /* HDG_CYCLE_V (default): each coarse correction is one cycle of the
                            coarser level; HDG_CYCLE_W: two, the second started from the
                            first's result (the W schedule the paper also reports, Sec. 7);

@@ -10,8 +10,10 @@
 #include <cstring>
 #include <map>
 #include <memory>
+#include <mutex>
 #include <stdexcept>
 #include <string>
+#include <tuple>
 #include <vector>
 
 #include "../../include/hdggmg.h"
@@ -1264,7 +1266,46 @@ struct EventPair {
 // same order, so the choice changes the time only, never the result.  Each
 // candidate is timed (best of 3, after one warm-up launch) on the level's
 // scratch vectors; the fastest is kept.
+// The autotuner's choices, kept for the life of the process: the fastest shape
+// depends on the launch's sizes (device, mesh, P, precision, the caller's
+// schedule, the LDS cap), not on the coefficients, so a further handle of the
+// same sizes takes the shape found by the first instead of timing again.
+struct ChainTuneKey {
+  int dev, n, P, prec, shape;
+  int64_t lds_cap;
+  bool operator<(const ChainTuneKey& o) const {
+    return std::tie(dev, n, P, prec, shape, lds_cap) < std::tie(o.dev, o.n, o.P, o.prec, o.shape, o.lds_cap);
+  }
+};
+struct ChainTuneVal {
+  int threads, remap, lds_level, shape;
+};
+std::mutex g_chain_tune_mu;
+std::map<ChainTuneKey, ChainTuneVal> g_chain_tune;
+
+void tune_chain_timed(hdg_ctx* h, int p);
 void tune_chain(hdg_ctx* h, int p) {
+  PLevel& L = h->pl[p];
+  int dev = 0;
+  hipchk(hipGetDevice(&dev), "device");
+  const ChainTuneKey key{dev, h->n, L.P, (int)h->prec, h->cfg.chain_shape, (int64_t)h->lds_cap};
+  {
+    std::lock_guard<std::mutex> lk(g_chain_tune_mu);
+    const auto it = g_chain_tune.find(key);
+    if (it != g_chain_tune.end()) {
+      L.chain_threads = it->second.threads;
+      L.chain_remap = it->second.remap;
+      L.chain_lds_level = it->second.lds_level;
+      L.chain_shape = it->second.shape;
+      return;
+    }
+  }
+  tune_chain_timed(h, p);
+  std::lock_guard<std::mutex> lk(g_chain_tune_mu);
+  g_chain_tune[key] = ChainTuneVal{L.chain_threads, L.chain_remap, L.chain_lds_level, L.chain_shape};
+}
+
+void tune_chain_timed(hdg_ctx* h, int p) {
   PLevel& L = h->pl[p];
   const hdg::Prec pr = h->prec;
   hipchk(hdg::launch_zero(pr, L.r, L.N, h->stream), "zero");

@@ -526,6 +526,33 @@ def test_partitioned_chain_solve_autotuned_is_bitwise_default():
     assert np.array_equal(outs[0], outs[1])
 
 
+def test_autotuned_shapes_are_kept_for_further_handles():
+    """The autotuner's choices depend on the launch sizes, not on the
+    coefficients: a second handle of the same mesh, degree and precision with
+    another coefficient field takes the first handle's shapes at every level,
+    and its sweeps equal those of an untuned handle bit for bit."""
+    n, k = 200, 3
+    print(f"case tuning kept n={n} k={k}", flush=True)
+    shapes, outs = [], []
+    for seed, tune in ((21, True), (22, True), (22, False)):
+        S = H.Solver(n, k, kappa_lognormal(n, 1.0, seed), smoother="chain", omega=0.7, autotune=tune)
+        try:
+            if tune:
+                shapes.append([S.chain_shape(p) for p in range(k + 1)])
+            if seed == 22:
+                N = S.num_dofs(k)
+                b = dev(normal_vector(N, 23))
+                x = dev(normal_vector(N, 24))
+                S.smooth(k, b, x, 2)
+                y = dev(normal_vector(S.num_dofs(0), 25))
+                S.smooth(0, dev(normal_vector(S.num_dofs(0), 26)), y, 2)
+                outs.append((host(x), host(y)))
+        finally:
+            S.close()
+    assert shapes[0] == shapes[1]
+    assert np.array_equal(outs[0][0], outs[1][0]) and np.array_equal(outs[0][1], outs[1][1])
+
+
 @pytest.mark.parametrize("sweeps", [1, 2, 3, 4])
 def test_partitioned_chain_solve_sweep_counts(sweeps):
     """The partitioned solve never updates x in place (its residual gathers x on
