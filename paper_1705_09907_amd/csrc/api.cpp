@@ -1389,8 +1389,11 @@ void tune_chain_timed(hdg_ctx* h, int p) {
     if (hdg::chain_shape_kind(L.P, h->n, wd) != wd) continue;  // that shape does not exist at P
     if (wd != 3 && th > hdg::chain_max_threads(L.P, wd == 2)) continue;
     for (int rm : {0, 1})
-      for (int ll : {lds_default, lds_staged, lds_half, lds_full, 64}) {
+      for (int li = 0; li < 5; ++li) {
+        const int lls[5] = {lds_default, lds_staged, lds_half, lds_full, 64};
+        const int ll = lls[li];
         if (wd == 3 && ll != lds_default) continue;  // the flat schedule stages no factors
+        if (std::find(lls, lls + li, ll) != lls + li) continue;  // the same staging depth: timed already
         hdg::ChainArgs c{};
         c.lds_cap = h->lds_cap;
         c.shape = wd;
