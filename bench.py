@@ -74,6 +74,7 @@ WORKLOADS = {
 MEASURED_TRAFFIC = {
     ("lognormal_n1024_k3", "f64"): (2187748980, "ff198bc957bd5114", "profiles/trace_apply_lognormal_n1024_k3.md"),
     ("lognormal_n256_k4", "f64"): (204873138, "ff198bc957bd5114", "profiles/trace_apply_lognormal_n256_k4.md"),
+    ("lognormal_n1024_k3", "f32"): (1092495104, "ff198bc957bd5114", "profiles/trace_apply_lognormal_n1024_k3_f32.md"),
 }
 
 MAT_BYTES = {"f64": 8, "f32": 4, "bf16": 4}  # the finest level keeps FP32 blocks in the bf16 cycle
@@ -266,6 +267,8 @@ def apply_only(args, S, n, k, dev):
     from workloads import normal_vector
     N = S.num_dofs()
     x = torch.tensor(normal_vector(N, 7), device=dev)
+    if args.precision != "f64":  # the apply of the cycle precision, as in the full run
+        x = x.float()
     y = torch.empty_like(x)
     flush = torch.empty(1 << 27, dtype=torch.float64, device=dev)
     us = []
@@ -279,8 +282,8 @@ def apply_only(args, S, n, k, dev):
         dst = torch.empty_like(src)
         dst.copy_(src)
     torch.cuda.synchronize()
-    byts, _ = algorithmic_bytes(n, k)
-    print(json.dumps({"workload": args.workload, "apply_us_cold": float(np.mean(us)),
+    byts, _ = algorithmic_bytes(n, k, args.precision)
+    print(json.dumps({"workload": args.workload, "precision": args.precision, "apply_us_cold": float(np.mean(us)),
                       "algorithmic_bytes": byts, "achieved_GBs": byts / (float(np.mean(us)) * 1e-6) / 1e9,
                       "calibration_copy_bytes": (1 << 25) * 8 if args.calibrate_copy else None}))
 
